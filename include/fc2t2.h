@@ -1,0 +1,201 @@
+/*
+ * fc2t2.h -- C-ABI of the MI355X (gfx950) implementation of the FC^2T^2 expansion and the
+ * layers built on it (Lange & Kutz, "FC^2T^2: The Fast Continuous Convolutional Taylor
+ * Transform", arXiv 2111.00110).
+ *
+ * The library evaluates f(q) = sum_n psi(q - p_n) w_n (section 3, eq. (1)) for a smooth,
+ * translation-invariant kernel psi on a uniform cell grid:
+ *   P2M  -> per-cell moments   M[n] = sum w (p - c)^n / n!           (section 3, P2M)
+ *   M2M  -> moments of coarser levels (binomial shift)                (section 3, M2M)
+ *   M2L  -> locals from the neighbouring moments through the kernel's partial
+ *           derivatives, with the parity window and near-field hole  (section 3, K^{M2L})
+ *   L2L  -> coarse locals re-expanded at the finer cells              (section 3, L2L)
+ *   L2P  -> f and its derivatives at query points                     (section 3, L2P)
+ * plus the explicit layer's backward pass (section 4.1), the line integral and its ray
+ * insertion (sections 6.1.1 and 6.2.1), and the first level crossing along a ray with its
+ * implicit-function-theorem backward pass (sections 5.1-5.2).
+ *
+ * Conventions shared by every entry point:
+ *  - Every array argument is a DEVICE pointer, row-major, owned by the caller.  The
+ *    library allocates device memory only inside fc2t2_plan_create (derivative tensors
+ *    and shift tables), and frees it in fc2t2_plan_destroy.  Scratch memory is passed in
+ *    by the caller as `ws` of `ws_bytes` bytes, sized by fc2t2_workspace_size.
+ *  - Floating-point arrays have the plan's IO type: float for FC2T2_IO_F32, double for
+ *    FC2T2_IO_F64.  Integer arrays are int32.
+ *  - Every call except fc2t2_plan_create is asynchronous on `stream` and does not
+ *    synchronise.  Arguments are validated on the host before anything is launched; on
+ *    a non-zero status nothing was launched.
+ *  - Outputs of *_backward calls ACCUMULATE (+=) into their buffers; the caller zeroes
+ *    them first.  Optional outputs may be NULL.
+ *  - Reductions over points use a stable sort by cell and a fixed summation order, with
+ *    no floating-point atomics, so results are bitwise reproducible run to run.
+ *  - Points outside the domain are assigned to the nearest boundary cell (the method
+ *    requires points inside the domain, section 3.2).
+ *
+ * Local expansions are stored in cell-scaled units: the local coefficient of multi-index k
+ * in cell c is Lt[k] = h^|k| d^k f(c) with h the finest cell width, so that
+ * f(q) = sum_k Lt[k] u^k / k!, u = (q - c) / h.  Layout: [C][n^dim][P_pad], cells
+ * row-major with dimension 0 slowest, multi-indices in the order of fc2t2_multi_indices,
+ * entries P..P_pad-1 zero.
+ */
+#ifndef FC2T2_H
+#define FC2T2_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FC2T2_OK = 0,
+  FC2T2_EINVAL = 1,        /* a NULL pointer, a negative size or an out-of-range argument */
+  FC2T2_EUNSUPPORTED = 2,  /* a valid combination this build does not implement */
+  FC2T2_EHIP = 3,          /* a HIP runtime call failed (launch or allocation) */
+  FC2T2_ENOMEM = 4,        /* device allocation inside plan creation failed */
+  FC2T2_EWORKSPACE = 5     /* ws_bytes smaller than fc2t2_workspace_size asks */
+} fc2t2_status;
+
+typedef enum {
+  FC2T2_GAUSSIAN = 0,      /* psi(x) = exp(-|x|^2 / (2 param^2)), param = sigma */
+  FC2T2_IMQ = 1,           /* psi(x) = (|x|^2 + param^2)^(-1/2), param = eps     */
+  FC2T2_POLY = 2           /* psi(x) = sum_a coef[a] x^a (graded multi-index order) */
+} fc2t2_kernel_kind;
+
+typedef enum {
+  FC2T2_M2L_F64 = 0,       /* FP64 contraction (requires FC2T2_IO_F64) */
+  FC2T2_M2L_F32 = 1,       /* FP32 contraction */
+  FC2T2_M2L_BF16 = 2,      /* BF16 MFMA, FP32 accumulation, one pass */
+  FC2T2_M2L_BF16X2 = 3,    /* BF16 MFMA, moments split hi/lo: two passes */
+  FC2T2_M2L_BF16X3 = 4     /* BF16 MFMA, moments and tensor split hi/lo: three passes */
+} fc2t2_m2l_prec;
+
+typedef enum { FC2T2_IO_F32 = 0, FC2T2_IO_F64 = 1 } fc2t2_io;
+
+/* Grid: the cube [lo, hi]^dim split into n^dim cells, n a power of two >= 4.  The
+ * expansion has log2(n) - 1 levels; the coarsest has 4 cells per dimension
+ * (section 3.2: N2 = 2^(levels+1)). */
+typedef struct {
+  int dim;                 /* 2 or 3 */
+  int n;
+  double lo, hi;
+} fc2t2_grid;
+
+/* Kernel psi.  For FC2T2_POLY, `coef` is a HOST array of n_coef values, one per
+ * multi-index of total degree <= deg in the order of fc2t2_multi_indices(dim, deg), with
+ * n_coef = C(deg + dim, dim); it is copied at plan creation. */
+typedef struct {
+  int kind;                /* fc2t2_kernel_kind */
+  double param;
+  int n_coef;
+  const double* coef;
+} fc2t2_kernel;
+
+typedef struct fc2t2_plan_s* fc2t2_plan;
+
+/* Operations, for fc2t2_workspace_size. */
+typedef enum {
+  FC2T2_OP_EXPAND = 0,               /* count = N sources */
+  FC2T2_OP_EVAL_BACKWARD = 1,        /* count = M queries */
+  FC2T2_OP_EXPAND_BACKWARD = 2,      /* count = N sources */
+  FC2T2_OP_RAY_INTEGRAL_BACKWARD = 3,/* count = R rays */
+  FC2T2_OP_RAY_ROOT_BACKWARD = 4     /* count = R rays */
+} fc2t2_op;
+
+/* Status text (static storage). */
+const char* fc2t2_status_string(int status);
+
+/* Multi-indices n with |n| <= K in the library's order (total degree ascending, then
+ * the first component descending, then the second): writes P*dim ints to the HOST array
+ * `out` (may be NULL to query P) and returns P = C(K + dim, dim), or -1 if dim is not 2 or
+ * 3 or K < 0. */
+int fc2t2_multi_indices(int dim, int K, int* out);
+
+/* Supported orders: dim 2 -> 1 <= K <= 6, dim 3 -> 1 <= K <= 5. */
+int fc2t2_supported(int dim, int K);
+
+/* Build a plan: validates the arguments, generates every level's M2L tensor
+ * T[k, n](o) = h^(|k|+|n|) (-1)^|n| d^(k+n) psi(-o h) for o in [-3, 3]^dim in FP64 on the
+ * GPU (section 3, K^{M2L}; derivatives in closed form for the radial kernels), rounds it
+ * to the contraction precision, and uploads the M2M/L2L shift tables.  `channels` is the
+ * number C of weight columns.  Synchronises `stream`.  *out is set only on success. */
+fc2t2_status fc2t2_plan_create(const fc2t2_grid* grid, const fc2t2_kernel* kernel, int K,
+                               int m2l_prec, int io, int channels, hipStream_t stream,
+                               fc2t2_plan* out);
+fc2t2_status fc2t2_plan_destroy(fc2t2_plan plan);
+
+/* Plan properties. */
+int fc2t2_plan_P(fc2t2_plan plan);            /* multi-indices per cell */
+int fc2t2_plan_P_pad(fc2t2_plan plan);        /* row stride of a local-expansion cell */
+int fc2t2_plan_levels(fc2t2_plan plan);
+size_t fc2t2_local_numel(fc2t2_plan plan);    /* C * n^dim * P_pad elements */
+
+/* Scratch bytes `op` needs for `count` points or rays (0 for an invalid op). */
+size_t fc2t2_workspace_size(fc2t2_plan plan, int op, int64_t count);
+
+/* Expansion (section 3): L = locals of f(.) = sum_n psi(. - p_n) w_n at the finest level.
+ *   p [N][dim], w [N][C] in; L [C][n^dim][P_pad] out (overwritten).  N may be 0. */
+fc2t2_status fc2t2_expand(fc2t2_plan plan, const void* p, const void* w, int64_t N, void* L,
+                          void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* L2P (section 3) with the derivatives of section 3.2's accessor:
+ *   q [M][dim] in; y [M][C] out; grad [M][C][dim] out or NULL; hess [M][C][dim(dim+1)/2]
+ *   out or NULL, upper triangle row by row (xx, xy, (xz,) yy, (yz, zz)). */
+fc2t2_status fc2t2_eval(fc2t2_plan plan, const void* L, const void* q, int64_t M, void* y,
+                        void* grad, void* hess, hipStream_t stream);
+
+/* Backward of fc2t2_eval's value output (section 4.1): with gy [M][C],
+ *   gL [C][n^dim][P_pad] += d(sum gy*y)/dL  (the transpose of L2P),
+ *   gq [M][dim] += gy . grad f(q)  (NULL to skip). */
+fc2t2_status fc2t2_eval_backward(fc2t2_plan plan, const void* L, const void* q, int64_t M,
+                                 const void* gy, void* gL, void* gq, void* ws,
+                                 size_t ws_bytes, hipStream_t stream);
+
+/* Backward of fc2t2_expand (section 4.1: the second expansion, with the roles of sources
+ * and targets swapped, computed as the exact transpose L2L^T -> M2L^T -> M2M^T -> P2M^T):
+ * with gL the cotangent of L,
+ *   gp [N][dim] += d/dp, gw [N][C] += d/dw  (either may be NULL). */
+fc2t2_status fc2t2_expand_backward(fc2t2_plan plan, const void* gL, const void* p,
+                                   const void* w, int64_t N, void* gp, void* gw, void* ws,
+                                   size_t ws_bytes, hipStream_t stream);
+
+/* Line integral (section 6.1.1): y[r][c] = integral over t in [t0, t1] of f(o_r + t r_r),
+ * f taken as zero outside the domain, computed exactly cell by cell from L (dim 3 only).
+ *   o [R][3], r [R][3] (need not be unit) in; y [R][C] out. */
+fc2t2_status fc2t2_ray_integral(fc2t2_plan plan, const void* L, const void* o, const void* r,
+                                double t0, double t1, int64_t R, void* y,
+                                hipStream_t stream);
+
+/* Backward of fc2t2_ray_integral (section 6.2.1, ray insertion): gL += the segment
+ * integrals of each cell's monomials weighted by gy [R][C]. */
+fc2t2_status fc2t2_ray_integral_backward(fc2t2_plan plan, const void* o, const void* r,
+                                         double t0, double t1, int64_t R, const void* gy,
+                                         void* gL, void* ws, size_t ws_bytes,
+                                         hipStream_t stream);
+
+/* Ray root (section 5.1, C == 1, dim 3): tau_r = level_frac * max of f along the clipped
+ * ray, then the first t where f - tau_r goes from negative to non-negative (a root on a
+ * cell face belongs to the earlier cell).  Outputs: t [R] (NaN if none), normal [R][3] =
+ * grad f at the root (zero if none), hit [R] int32 (1 hit, 0 dead ray: no crossing, or
+ * f >= tau at entry), saved [R][FC2T2_ROOT_SAVED] (state for the backward: root point,
+ * r . grad f, H r, tau, cell).  The root is polished by one FP64 Newton step. */
+#define FC2T2_ROOT_SAVED 12
+fc2t2_status fc2t2_ray_root(fc2t2_plan plan, const void* L, const void* o, const void* r,
+                            double t0, double t1, int64_t R, double level_frac, void* t,
+                            void* normal, int32_t* hit, void* saved, hipStream_t stream);
+
+/* Backward of fc2t2_ray_root (section 5.2, implicit function theorem), tau held fixed:
+ * gL += a (q* - c)^k / k! + sum_j gn_j d/dq_j (q* - c)^k / k!, with
+ * a = -(gt + gn . H r) / (r . grad f), for every ray with hit = 1.  gt [R] and gn [R][3]
+ * may each be NULL (zero). */
+fc2t2_status fc2t2_ray_root_backward(fc2t2_plan plan, const void* saved, const int32_t* hit,
+                                     int64_t R, const void* gt, const void* gn, void* gL,
+                                     void* ws, size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FC2T2_H */

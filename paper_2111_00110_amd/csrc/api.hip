@@ -1,0 +1,205 @@
+// The explicit layer's entry points (sections 3 and 4.1): expansion, evaluation and their
+// backward passes, with argument validation and workspace carving.
+#include "plan.h"
+
+using namespace fc2t2;
+
+namespace {
+
+// Bump allocator over the caller's workspace (256-byte aligned pieces).
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base((char*)b) {}
+  template <typename X>
+  X* take(size_t count) {
+    X* p = base ? (X*)(base + off) : nullptr;
+    off += align256(count * sizeof(X));
+    return p;
+  }
+};
+
+struct SortBufs {
+  uint32_t *keys, *keys_sorted, *perm, *starts;
+  void* scratch;
+};
+
+SortBufs carve_sort(Carve& c, const fc2t2_plan_s* pl, int64_t count) {
+  SortBufs b;
+  b.keys = c.take<uint32_t>(count);
+  b.keys_sorted = c.take<uint32_t>(count);
+  b.perm = c.take<uint32_t>(count);
+  b.starts = c.take<uint32_t>(pl->G + 1);
+  b.scratch = c.take<char>(radix_sort_scratch_bytes(count));
+  return b;
+}
+
+fc2t2_status bin_and_sort(const fc2t2_plan_s* pl, const void* x, int64_t count, const SortBufs& b,
+                          hipStream_t s) {
+  fc2t2_status st = launch_cell_keys(pl, x, count, b.keys, s);
+  if (st) return st;
+  st = radix_sort_pairs(b.keys, b.keys_sorted, b.perm, count, key_bits_for(pl->G), b.scratch, s);
+  if (st) return st;
+  return launch_cell_starts(b.keys_sorted, count, pl->G, b.starts, s);
+}
+
+// Pyramid of grids for levels [first, levels): returns per-level pointers.
+void carve_pyramid(Carve& c, const fc2t2_plan_s* pl, int first, void** lv) {
+  for (int l = 0; l < kMaxLevels; ++l) lv[l] = nullptr;
+  for (int l = first; l < pl->levels; ++l) lv[l] = c.take<char>(grid_elems(pl, l) * io_size(pl));
+}
+
+size_t ws_expand(const fc2t2_plan_s* pl, int64_t N) {
+  Carve c(nullptr);
+  carve_sort(c, pl, N);
+  void* lv[kMaxLevels];
+  carve_pyramid(c, pl, 0, lv);
+  carve_pyramid(c, pl, 1, lv);
+  return c.off;
+}
+
+size_t ws_eval_backward(const fc2t2_plan_s* pl, int64_t M) {
+  Carve c(nullptr);
+  carve_sort(c, pl, M);
+  return c.off;
+}
+
+size_t ws_expand_backward(const fc2t2_plan_s* pl) {
+  Carve c(nullptr);
+  void* lv[kMaxLevels];
+  carve_pyramid(c, pl, 1, lv);
+  carve_pyramid(c, pl, 0, lv);
+  return c.off;
+}
+
+bool bad_count(int64_t n) { return n < 0 || n > 0xFFFFFFFFll; }
+
+}  // namespace
+
+namespace fc2t2 {
+
+// Levels above the finest of an upward/downward pass: expansion of M0 into L0.
+fc2t2_status expand_from_moments(const fc2t2_plan_s* pl, void** Mlv, void** Llv, void* L0, hipStream_t s) {
+  Llv[0] = L0;
+  for (int l = 0; l + 1 < pl->levels; ++l) {
+    fc2t2_status st = launch_upshift(pl, l, Mlv[l], Mlv[l + 1], s);
+    if (st) return st;
+  }
+  for (int l = pl->levels - 1; l >= 0; --l) {
+    fc2t2_status st;
+    if (l == pl->levels - 1) {
+      st = launch_m2l(pl, l, Mlv[l], Llv[l], false, s);
+    } else {
+      st = launch_downshift(pl, l, Llv[l + 1], Llv[l], false, s);
+      if (st) return st;
+      st = launch_m2l(pl, l, Mlv[l], Llv[l], true, s);
+    }
+    if (st) return st;
+  }
+  return FC2T2_OK;
+}
+
+// Transpose of expand_from_moments: G_L0 -> G_M0.
+fc2t2_status expand_T_to_moments(const fc2t2_plan_s* pl, const void* GL0, void** GLlv, void** GMlv,
+                                 hipStream_t s) {
+  GLlv[0] = (void*)GL0;
+  for (int l = 0; l + 1 < pl->levels; ++l) {
+    fc2t2_status st = launch_upshift(pl, l, GLlv[l], GLlv[l + 1], s);   // L2L^T
+    if (st) return st;
+  }
+  for (int l = pl->levels - 1; l >= 0; --l) {
+    fc2t2_status st;
+    if (l == pl->levels - 1) {
+      st = launch_m2l_T(pl, l, GLlv[l], GMlv[l], false, s);
+    } else {
+      st = launch_downshift(pl, l, GMlv[l + 1], GMlv[l], false, s);    // M2M^T
+      if (st) return st;
+      st = launch_m2l_T(pl, l, GLlv[l], GMlv[l], true, s);
+    }
+    if (st) return st;
+  }
+  return FC2T2_OK;
+}
+
+}  // namespace fc2t2
+
+extern "C" {
+
+size_t fc2t2_workspace_size(fc2t2_plan plan, int op, int64_t count) {
+  if (!plan || count < 0) return 0;
+  switch (op) {
+    case FC2T2_OP_EXPAND: return ws_expand(plan, count);
+    case FC2T2_OP_EVAL_BACKWARD: return ws_eval_backward(plan, count);
+    case FC2T2_OP_EXPAND_BACKWARD: return ws_expand_backward(plan);
+    case FC2T2_OP_RAY_INTEGRAL_BACKWARD: return ray_integral_bwd_ws(plan, count);
+    case FC2T2_OP_RAY_ROOT_BACKWARD: return ray_root_bwd_ws(plan, count);
+  }
+  return 0;
+}
+
+fc2t2_status fc2t2_expand(fc2t2_plan plan, const void* p, const void* w, int64_t N, void* L,
+                          void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!plan || !L || bad_count(N)) return FC2T2_EINVAL;
+  if (N > 0 && (!p || !w)) return FC2T2_EINVAL;
+  const size_t need = ws_expand(plan, N);
+  if (!ws || ws_bytes < need) return FC2T2_EWORKSPACE;
+  Carve c(ws);
+  SortBufs sb = carve_sort(c, plan, N);
+  void* Mlv[kMaxLevels];
+  void* Llv[kMaxLevels];
+  carve_pyramid(c, plan, 0, Mlv);
+  carve_pyramid(c, plan, 1, Llv);
+  fc2t2_status st = bin_and_sort(plan, p, N, sb, stream);
+  if (st) return st;
+  st = launch_p2m(plan, p, w, sb.starts, sb.perm, Mlv[0], stream);
+  if (st) return st;
+  return expand_from_moments(plan, Mlv, Llv, L, stream);
+}
+
+fc2t2_status fc2t2_eval(fc2t2_plan plan, const void* L, const void* q, int64_t M, void* y, void* grad,
+                        void* hess, hipStream_t stream) {
+  if (!plan || !L || bad_count(M)) return FC2T2_EINVAL;
+  if (M > 0 && (!q || !y)) return FC2T2_EINVAL;
+  return launch_l2p(plan, L, q, M, y, grad, hess, stream);
+}
+
+fc2t2_status fc2t2_eval_backward(fc2t2_plan plan, const void* L, const void* q, int64_t M,
+                                 const void* gy, void* gL, void* gq, void* ws, size_t ws_bytes,
+                                 hipStream_t stream) {
+  if (!plan || bad_count(M)) return FC2T2_EINVAL;
+  if (M > 0 && (!q || !gy)) return FC2T2_EINVAL;
+  if (gq && !L) return FC2T2_EINVAL;
+  if (M == 0) return FC2T2_OK;
+  if (gL) {
+    const size_t need = ws_eval_backward(plan, M);
+    if (!ws || ws_bytes < need) return FC2T2_EWORKSPACE;
+    Carve c(ws);
+    SortBufs sb = carve_sort(c, plan, M);
+    fc2t2_status st = bin_and_sort(plan, q, M, sb, stream);
+    if (st) return st;
+    st = launch_l2p_T(plan, q, gy, sb.starts, sb.perm, gL, stream);
+    if (st) return st;
+  }
+  if (gq) return launch_l2p_qgrad(plan, L, q, M, gy, gq, stream);
+  return FC2T2_OK;
+}
+
+fc2t2_status fc2t2_expand_backward(fc2t2_plan plan, const void* gL, const void* p, const void* w,
+                                   int64_t N, void* gp, void* gw, void* ws, size_t ws_bytes,
+                                   hipStream_t stream) {
+  if (!plan || !gL || bad_count(N)) return FC2T2_EINVAL;
+  if (N > 0 && (!p || !w)) return FC2T2_EINVAL;
+  if (N == 0 || (!gp && !gw)) return FC2T2_OK;
+  const size_t need = ws_expand_backward(plan);
+  if (!ws || ws_bytes < need) return FC2T2_EWORKSPACE;
+  Carve c(ws);
+  void* GLlv[kMaxLevels];
+  void* GMlv[kMaxLevels];
+  carve_pyramid(c, plan, 1, GLlv);
+  carve_pyramid(c, plan, 0, GMlv);
+  fc2t2_status st = expand_T_to_moments(plan, gL, GLlv, GMlv, stream);
+  if (st) return st;
+  return launch_p2m_T(plan, GMlv[0], p, w, N, gp, gw, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,277 @@
+// Point <-> grid stages (section 3):
+//   P2M    M[c, n] = sum_{s in c} w_s u_s^n / n!                 (per-cell segmented sum)
+//   L2P    f(q) = sum_k L[c(q), k] u^k / k!, its gradient and Hessian
+// and their transposes for the explicit layer's backward pass (section 4.1):
+//   L2P^T  G_L[c, k] = sum_{q in c} gy_q u_q^k / k!               (per-cell segmented sum)
+//   P2M^T  w_bar_s = <G_M[c(s)], u_s^n / n!>,  p_bar_s = w_s <G_M[c(s)], grad u_s^n / n!>
+// with u = (x - centre) / h the cell-scaled offset.
+//
+// The segmented sums run over points sorted by cell: a group of GROUP lanes owns one cell,
+// strides over its points in input order with TwoSum-compensated accumulation, combines
+// the lanes with xor shuffles, and writes the cell's row.  No atomics.
+#include "plan.h"
+
+using namespace fc2t2;
+
+namespace {
+
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> { using type = float4; static constexpr int n = 4; };
+template <>
+struct Vec4<double> { using type = double2; static constexpr int n = 2; };
+
+// Load a padded row of Ppad values (16-byte aligned) into registers.
+template <int Ppad, typename T>
+__device__ __forceinline__ void load_row(const T* __restrict__ src, T (&c)[Ppad]) {
+  using V = typename Vec4<T>::type;
+  constexpr int w = Vec4<T>::n;
+  const V* s = reinterpret_cast<const V*>(src);
+#pragma unroll
+  for (int i = 0; i < Ppad / w; ++i) {
+    const V v = s[i];
+    if constexpr (w == 4) { c[4 * i] = v.x; c[4 * i + 1] = v.y; c[4 * i + 2] = v.z; c[4 * i + 3] = v.w; }
+    else { c[2 * i] = v.x; c[2 * i + 1] = v.y; }
+  }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void decode_cell(int64_t cell, int n, int (&ic)[3]) {
+  ic[0] = ic[1] = ic[2] = 0;
+  if constexpr (D == 2) {
+    ic[1] = (int)(cell % n);
+    ic[0] = (int)(cell / n);
+  } else {
+    ic[2] = (int)(cell % n);
+    ic[1] = (int)((cell / n) % n);
+    ic[0] = (int)(cell / ((int64_t)n * n));
+  }
+}
+
+template <class S, typename T>
+struct PointMonomials {
+  const T* __restrict__ x;     // [count][D]
+  const T* __restrict__ wt;    // [count][C]
+  int C;
+  T inv_h;
+  __device__ __forceinline__ void operator()(uint32_t idx, const T (&centre)[3], int ch,
+                                             T (&v)[S::P]) const {
+    T u[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int j = 0; j < S::D; ++j) u[j] = (x[(int64_t)idx * S::D + j] - centre[j]) * inv_h;
+    monomials<S>(u, v);
+    const T a = wt[(int64_t)idx * C + ch];
+#pragma unroll
+    for (int k = 0; k < S::P; ++k) v[k] *= a;
+  }
+};
+
+// out[ch][cell][:] (+)= sum over the cell's sorted records of fn(record).
+template <class S, typename T, int GROUP, class F>
+__global__ void __launch_bounds__(256) reduce_cells_kernel(const uint32_t* __restrict__ starts,
+                                                           const uint32_t* __restrict__ perm,
+                                                           int64_t G, int n, T lo, T h,
+                                                           T* __restrict__ out, int accumulate, F fn) {
+  constexpr int P = S::P, Ppad = S::Ppad, D = S::D;
+  const int lane_g = threadIdx.x & (GROUP - 1);
+  const int ch = blockIdx.y;
+  const int64_t groups = (int64_t)gridDim.x * (blockDim.x / GROUP);
+  T* __restrict__ base = out + (int64_t)ch * G * Ppad;
+  for (int64_t cell = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GROUP; cell < G; cell += groups) {
+    const uint32_t b = starts[cell], e = starts[cell + 1];
+    int ic[3];
+    decode_cell<D, T>(cell, n, ic);
+    T centre[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) centre[j] = lo + (T(ic[j]) + T(0.5)) * h;
+    T s[P], c[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) { s[k] = T(0); c[k] = T(0); }
+    for (uint32_t r = b + lane_g; r < e; r += GROUP) {
+      T v[P];
+      fn(perm[r], centre, ch, v);
+#pragma unroll
+      for (int k = 0; k < P; ++k) acc2(s[k], c[k], v[k]);
+    }
+#pragma unroll
+    for (int off = GROUP / 2; off >= 1; off >>= 1) {
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        const T so = __shfl_xor(s[k], off);
+        const T co = __shfl_xor(c[k], off);
+        acc2(s[k], c[k], so);
+        c[k] += co;
+      }
+    }
+    T* __restrict__ dst = base + cell * Ppad;
+#pragma unroll
+    for (int k = 0; k < Ppad; ++k) {
+      if ((k & (GROUP - 1)) == lane_g) {
+        const T v = k < P ? s[k] + c[k] : T(0);
+        if (accumulate) dst[k] += v; else dst[k] = v;
+      }
+    }
+  }
+}
+
+template <class S, typename T, int GROUP>
+fc2t2_status launch_reduce_points(const fc2t2_plan_s* pl, const T* x, const T* wt,
+                                  const uint32_t* starts, const uint32_t* perm, T* out,
+                                  bool accumulate, hipStream_t s) {
+  PointMonomials<S, T> fn{x, wt, pl->C, (T)(1.0 / pl->h0)};
+  const int threads = 256;
+  const int64_t need = ceil_div(pl->G * GROUP, threads);
+  const int64_t blocks = need < 8192 ? need : 8192;
+  hipLaunchKernelGGL((reduce_cells_kernel<S, T, GROUP, PointMonomials<S, T>>),
+                     dim3((unsigned)blocks, pl->C), dim3(threads), 0, s, starts, perm, pl->G, pl->n,
+                     (T)pl->lo, (T)pl->h0, out, accumulate ? 1 : 0, fn);
+  FC2T2_LAUNCH_CHECK();
+  return FC2T2_OK;
+}
+
+template <typename T>
+fc2t2_status reduce_points(const fc2t2_plan_s* pl, const void* x, const void* wt, const uint32_t* starts,
+                           const uint32_t* perm, void* out, bool accumulate, hipStream_t s) {
+  fc2t2_status st = FC2T2_EUNSUPPORTED;
+  dispatch_shape(pl->dim, pl->K, [&](auto shape) {
+    using S = decltype(shape);
+    st = launch_reduce_points<S, T, 16>(pl, (const T*)x, (const T*)wt, starts, perm, (T*)out,
+                                        accumulate, s);
+  });
+  return st;
+}
+
+// ---------------------------------------------------------------------------------------
+// Gather-evaluate: one thread per point reads its cell's row.
+//   mode 0 (L2P):    y = f, grad = grad f / h, hess = H f / h^2     (overwrite)
+//   mode 1 (q grad): gq += sum_ch gy[ch] grad_ch f / h              (accumulate)
+//   mode 2 (P2M^T):  gw[ch] += f_ch, gp += sum_ch w[ch] grad_ch f / h (accumulate)
+template <class S, typename T, int MODE, bool kGrad, bool kHess>
+__global__ void __launch_bounds__(256) gather_eval_kernel(const T* __restrict__ grid, const T* __restrict__ x,
+                                                          int64_t count, int C, int n, int64_t G, T lo,
+                                                          T scale, T h, T inv_h,
+                                                          const T* __restrict__ wts,
+                                                          T* __restrict__ out_v, T* __restrict__ out_g,
+                                                          T* __restrict__ out_h) {
+  constexpr int D = S::D, Ppad = S::Ppad;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  int ic[3] = {0, 0, 0};
+  int64_t cell = 0;
+  T u[3] = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const T xj = x[i * D + j];
+    ic[j] = cell_coord<T>(xj, lo, scale, n);
+    cell = cell * n + ic[j];
+    u[j] = (xj - (lo + (T(ic[j]) + T(0.5)) * h)) * inv_h;
+  }
+  T pw[3][S::K + 1];
+  power_table<S>(u, pw);
+  T gsum[3] = {T(0), T(0), T(0)};
+  for (int ch = 0; ch < C; ++ch) {
+    T c[Ppad];
+    load_row<Ppad>(grid + ((int64_t)ch * G + cell) * Ppad, c);
+    T val, g[3], hs[6];
+    eval_poly<S, T, kGrad, kHess>(c, pw, val, g, hs);
+    if constexpr (MODE == 0) {
+      out_v[i * C + ch] = val;
+      if constexpr (kGrad) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) out_g[(i * C + ch) * D + j] = g[j] * inv_h;
+      }
+      if constexpr (kHess) {
+        constexpr int NH = D == 2 ? 3 : 6;
+#pragma unroll
+        for (int j = 0; j < NH; ++j) out_h[(i * C + ch) * NH + j] = hs[j] * inv_h * inv_h;
+      }
+    } else if constexpr (MODE == 1) {
+      const T a = wts[i * C + ch];
+#pragma unroll
+      for (int j = 0; j < D; ++j) gsum[j] += a * g[j];
+    } else {
+      if (out_v) out_v[i * C + ch] += val;
+      const T a = wts[i * C + ch];
+#pragma unroll
+      for (int j = 0; j < D; ++j) gsum[j] += a * g[j];
+    }
+  }
+  if constexpr (MODE != 0) {
+    if (out_g) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) out_g[i * D + j] += gsum[j] * inv_h;
+    }
+  }
+}
+
+template <typename T, int MODE>
+fc2t2_status gather_eval(const fc2t2_plan_s* pl, const void* grid, const void* x, int64_t count,
+                         const void* wts, void* out_v, void* out_g, void* out_h, hipStream_t s) {
+  if (count == 0) return FC2T2_OK;
+  fc2t2_status st = FC2T2_EUNSUPPORTED;
+  const int threads = 256;
+  const dim3 blocks((unsigned)ceil_div(count, threads));
+  const T lo = (T)pl->lo, scale = (T)(pl->n / (pl->hi - pl->lo)), h = (T)pl->h0, inv_h = (T)(1.0 / pl->h0);
+  dispatch_shape(pl->dim, pl->K, [&](auto shape) {
+    using S = decltype(shape);
+    if constexpr (MODE == 0) {
+      if (out_h)
+        hipLaunchKernelGGL((gather_eval_kernel<S, T, 0, true, true>), blocks, dim3(threads), 0, s,
+                           (const T*)grid, (const T*)x, count, pl->C, pl->n, pl->G, lo, scale, h, inv_h,
+                           (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h);
+      else if (out_g)
+        hipLaunchKernelGGL((gather_eval_kernel<S, T, 0, true, false>), blocks, dim3(threads), 0, s,
+                           (const T*)grid, (const T*)x, count, pl->C, pl->n, pl->G, lo, scale, h, inv_h,
+                           (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h);
+      else
+        hipLaunchKernelGGL((gather_eval_kernel<S, T, 0, false, false>), blocks, dim3(threads), 0, s,
+                           (const T*)grid, (const T*)x, count, pl->C, pl->n, pl->G, lo, scale, h, inv_h,
+                           (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h);
+    } else {
+      hipLaunchKernelGGL((gather_eval_kernel<S, T, MODE, true, false>), blocks, dim3(threads), 0, s,
+                         (const T*)grid, (const T*)x, count, pl->C, pl->n, pl->G, lo, scale, h, inv_h,
+                         (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h);
+    }
+    st = FC2T2_OK;
+  });
+  if (st != FC2T2_OK) return st;
+  FC2T2_LAUNCH_CHECK();
+  return FC2T2_OK;
+}
+
+}  // namespace
+
+namespace fc2t2 {
+
+fc2t2_status launch_p2m(const fc2t2_plan_s* pl, const void* p, const void* w, const uint32_t* starts,
+                        const uint32_t* perm, void* M0, hipStream_t s) {
+  return pl->io == FC2T2_IO_F64 ? reduce_points<double>(pl, p, w, starts, perm, M0, false, s)
+                                : reduce_points<float>(pl, p, w, starts, perm, M0, false, s);
+}
+
+fc2t2_status launch_l2p_T(const fc2t2_plan_s* pl, const void* q, const void* gy, const uint32_t* starts,
+                          const uint32_t* perm, void* gL, hipStream_t s) {
+  return pl->io == FC2T2_IO_F64 ? reduce_points<double>(pl, q, gy, starts, perm, gL, true, s)
+                                : reduce_points<float>(pl, q, gy, starts, perm, gL, true, s);
+}
+
+fc2t2_status launch_l2p(const fc2t2_plan_s* pl, const void* L, const void* q, int64_t M, void* y,
+                        void* grad, void* hess, hipStream_t s) {
+  return pl->io == FC2T2_IO_F64 ? gather_eval<double, 0>(pl, L, q, M, nullptr, y, grad, hess, s)
+                                : gather_eval<float, 0>(pl, L, q, M, nullptr, y, grad, hess, s);
+}
+
+fc2t2_status launch_l2p_qgrad(const fc2t2_plan_s* pl, const void* L, const void* q, int64_t M,
+                              const void* gy, void* gq, hipStream_t s) {
+  return pl->io == FC2T2_IO_F64 ? gather_eval<double, 1>(pl, L, q, M, gy, nullptr, gq, nullptr, s)
+                                : gather_eval<float, 1>(pl, L, q, M, gy, nullptr, gq, nullptr, s);
+}
+
+fc2t2_status launch_p2m_T(const fc2t2_plan_s* pl, const void* GM0, const void* p, const void* w,
+                          int64_t N, void* gp, void* gw, hipStream_t s) {
+  return pl->io == FC2T2_IO_F64 ? gather_eval<double, 2>(pl, GM0, p, N, w, gw, gp, nullptr, s)
+                                : gather_eval<float, 2>(pl, GM0, p, N, w, gw, gp, nullptr, s);
+}
+
+}  // namespace fc2t2

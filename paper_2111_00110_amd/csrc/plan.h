@@ -1,0 +1,105 @@
+// Internal plan state and the launchers each translation unit provides.
+#pragma once
+
+#include "common.h"
+
+struct fc2t2_plan_s {
+  int dim, n, K, P, Ppad, C, levels, io, prec, kind;
+  double lo, hi, param;
+  double h0;                      // finest cell width
+  int64_t G;                      // finest cells
+  int nl[fc2t2::kMaxLevels];      // cells per dimension at each level
+  int64_t Gl[fc2t2::kMaxLevels];  // cells at each level
+  int n_off;                      // 7^dim source offsets o in [-3, 3]^dim
+  // Device tables (owned by the plan).
+  void* m2l_T = nullptr;          // [levels][n_off][P][Ppad], contraction type (f32/f64):
+                                  //   T[lvl][o][n][k] = h^(|k|+|n|) (-1)^|n| d^(k+n) psi(-o h)
+  size_t m2l_T_bytes = 0;
+  void* m2l_bf16 = nullptr;       // MFMA operand tables (layout owned by m2l_mfma.hip)
+  size_t m2l_bf16_bytes = 0;
+  void* shift = nullptr;          // [2^dim][P][P] IO type: S_b[n][m] = 2^-|n| (b-1/2)^(n-m)/(n-m)!
+  int device = 0;
+};
+
+namespace fc2t2 {
+
+inline size_t io_size(const fc2t2_plan_s* pl) { return pl->io == FC2T2_IO_F64 ? 8 : 4; }
+inline size_t grid_elems(const fc2t2_plan_s* pl, int lvl) {
+  return (size_t)pl->C * (size_t)pl->Gl[lvl] * (size_t)pl->Ppad;
+}
+// Elements of a level pyramid holding levels [first, levels).
+inline size_t pyramid_elems(const fc2t2_plan_s* pl, int first) {
+  size_t s = 0;
+  for (int l = first; l < pl->levels; ++l) s += grid_elems(pl, l);
+  return s;
+}
+
+// ---- sort.hip
+// Linear finest-cell index of each point.
+fc2t2_status launch_cell_keys(const fc2t2_plan_s* pl, const void* x, int64_t N, uint32_t* keys,
+                              hipStream_t s);
+// Stable LSD radix sort of (key, index) pairs by the low `key_bits` bits.  keys_in is
+// read only; keys_out/vals_out receive the sorted keys and the original indices.
+size_t radix_sort_scratch_bytes(int64_t N);
+fc2t2_status radix_sort_pairs(const uint32_t* keys_in, uint32_t* keys_out, uint32_t* vals_out,
+                              int64_t N, int key_bits, void* scratch, hipStream_t s);
+// starts[c] = first sorted position with key >= c, for c in [0, G]; starts[G] = N.
+fc2t2_status launch_cell_starts(const uint32_t* keys_sorted, int64_t N, int64_t G,
+                                uint32_t* starts, hipStream_t s);
+int key_bits_for(int64_t G);
+
+// ---- p2m_l2p.hip
+// P2M: M0 = moments of the sorted sources (overwrite).
+fc2t2_status launch_p2m(const fc2t2_plan_s* pl, const void* p, const void* w, const uint32_t* starts,
+                        const uint32_t* perm, void* M0, hipStream_t s);
+// Transpose of L2P: gL += sum over the sorted queries of gy (q - c)^k / k!.
+fc2t2_status launch_l2p_T(const fc2t2_plan_s* pl, const void* q, const void* gy,
+                          const uint32_t* starts, const uint32_t* perm, void* gL, hipStream_t s);
+// L2P: y (overwrite), grad/hess (overwrite, optional).
+fc2t2_status launch_l2p(const fc2t2_plan_s* pl, const void* L, const void* q, int64_t M, void* y,
+                        void* grad, void* hess, hipStream_t s);
+// gq += sum_c gy[c] grad_c f(q).
+fc2t2_status launch_l2p_qgrad(const fc2t2_plan_s* pl, const void* L, const void* q, int64_t M,
+                              const void* gy, void* gq, hipStream_t s);
+// Transpose of P2M: gw += <GM0, mono>, gp += w <GM0, grad mono> / h.
+fc2t2_status launch_p2m_T(const fc2t2_plan_s* pl, const void* GM0, const void* p, const void* w,
+                          int64_t N, void* gp, void* gw, hipStream_t s);
+
+// ---- tree.hip
+// Up-shift: out[I] = sum_b S_b in[2I+b] (M2M, and the transpose of L2L).
+fc2t2_status launch_upshift(const fc2t2_plan_s* pl, int lvl_child, const void* in, void* out,
+                            hipStream_t s);
+// Down-shift: out[2I+b] (+)= S_b^T in[I] (L2L, and the transpose of M2M).
+fc2t2_status launch_downshift(const fc2t2_plan_s* pl, int lvl_child, const void* in, void* out,
+                              bool accumulate, hipStream_t s);
+// M2L at one level: L (+)= sum_o T(o) M[i + o] over the admissible offsets.
+fc2t2_status launch_m2l(const fc2t2_plan_s* pl, int lvl, const void* M, void* L, bool accumulate,
+                        hipStream_t s);
+// Transpose: GM (+)= sum_o T(o)^T GL[j - o].
+fc2t2_status launch_m2l_T(const fc2t2_plan_s* pl, int lvl, const void* GL, void* GM,
+                          bool accumulate, hipStream_t s);
+
+// ---- m2l_mfma.hip
+bool m2l_mfma_supported(const fc2t2_plan_s* pl);
+size_t m2l_mfma_table_bytes(const fc2t2_plan_s* pl);
+fc2t2_status m2l_mfma_build_tables(fc2t2_plan_s* pl, hipStream_t s);
+fc2t2_status launch_m2l_mfma(const fc2t2_plan_s* pl, int lvl, const void* M, void* L,
+                             bool accumulate, bool transpose, hipStream_t s);
+
+// ---- rays.hip
+size_t ray_integral_bwd_ws(const fc2t2_plan_s* pl, int64_t R);
+fc2t2_status launch_ray_integral(const fc2t2_plan_s* pl, const void* L, const void* o,
+                                 const void* r, double t0, double t1, int64_t R, void* y,
+                                 hipStream_t s);
+fc2t2_status ray_integral_backward(const fc2t2_plan_s* pl, const void* o, const void* r, double t0,
+                                   double t1, int64_t R, const void* gy, void* gL, void* ws,
+                                   hipStream_t s);
+fc2t2_status launch_ray_root(const fc2t2_plan_s* pl, const void* L, const void* o, const void* r,
+                             double t0, double t1, int64_t R, double frac, void* t, void* normal,
+                             int32_t* hit, void* saved, hipStream_t s);
+size_t ray_root_bwd_ws(const fc2t2_plan_s* pl, int64_t R);
+fc2t2_status ray_root_backward(const fc2t2_plan_s* pl, const void* saved, const int32_t* hit,
+                               int64_t R, const void* gt, const void* gn, void* gL, void* ws,
+                               hipStream_t s);
+
+}  // namespace fc2t2

@@ -1,0 +1,363 @@
+// Plan creation: geometry, the M2L derivative tensors (FP64 on the GPU) and the M2M/L2L
+// shift tables.  Section 3 of the paper (multilevel expansion, K^{M2M}, K^{L2L}, K^{M2L}).
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "plan.h"
+
+using namespace fc2t2;
+
+namespace {
+
+// ---------------------------------------------------------------------------------------
+// Partial derivatives of a kernel psi at the cell-centre offsets.
+//
+// Radial kernels psi(x) = phi(|x|^2): with delta(y) = |x0 + y|^2 - |x0|^2 = sum_i y_i (2 x0_i + y_i),
+//   psi(x0 + y) = sum_m phi^(m)(|x0|^2) delta^m / m!,
+// and the coefficient of y^g in delta^m / m! is
+//   sum over j with |j| = m, ceil(g_i/2) <= j_i <= g_i of prod_i C(j_i, g_i - j_i) (2 x0_i)^(2 j_i - g_i) / j_i!
+// so d^g psi(x0) = g! sum_j phi^(|j|)(|x0|^2) prod_i C(j_i, g_i - j_i) (2 x0_i)^(2 j_i - g_i) / j_i!.
+//   Gaussian: phi(u) = exp(-u / (2 s^2)),  phi^(m) = (-1/(2 s^2))^m phi.
+//   IMQ:      phi(u) = (u + e^2)^(-1/2),   phi^(m) = (-1)^m (2m-1)!! / 2^m (u + e^2)^(-1/2 - m).
+// Polynomial kernels: d^g sum_a c_a x^a = sum_{a >= g} c_a a!/(a-g)! x^(a-g).
+// ---------------------------------------------------------------------------------------
+
+__device__ double dfact(int n) {
+  double r = 1.0;
+  for (int i = 2; i <= n; ++i) r *= i;
+  return r;
+}
+
+__device__ double dbinom(int n, int k) {
+  if (k < 0 || k > n) return 0.0;
+  double r = 1.0;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+__device__ double ipow(double x, int e) {
+  double r = 1.0;
+  for (int i = 0; i < e; ++i) r *= x;
+  return r;
+}
+
+// phi^(m)(u) for the radial kernels.
+__device__ double radial_deriv(int kind, double param, double u, int m) {
+  if (kind == FC2T2_GAUSSIAN) {
+    const double a = -1.0 / (2.0 * param * param);
+    return ipow(a, m) * exp(a * u);
+  }
+  // IMQ
+  const double base = u + param * param;
+  double c = 1.0;
+  for (int i = 0; i < m; ++i) c *= -(2.0 * i + 1.0) * 0.5;
+  return c * pow(base, -0.5 - m);
+}
+
+// One thread per (level, offset, derivative multi-index g): D[lvl][o][g] = d^g psi(-o h_lvl).
+__global__ void derivs_kernel(int dim, int kind, double param, const double* __restrict__ coef,
+                              const int* __restrict__ coef_exps, int n_coef,
+                              const int* __restrict__ g_exps, int n_g, int levels,
+                              const double* __restrict__ hl, int n_off, double* __restrict__ D) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)levels * n_off * n_g;
+  if (tid >= total) return;
+  const int gi = (int)(tid % n_g);
+  const int oi = (int)((tid / n_g) % n_off);
+  const int lvl = (int)(tid / ((int64_t)n_g * n_off));
+  int o[3] = {0, 0, 0};
+  {
+    int r = oi;
+    for (int j = dim - 1; j >= 0; --j) { o[j] = r % 7 - 3; r /= 7; }
+  }
+  const double h = hl[lvl];
+  double x[3] = {0.0, 0.0, 0.0};
+  for (int j = 0; j < dim; ++j) x[j] = -o[j] * h;
+  const int g[3] = {g_exps[3 * gi], g_exps[3 * gi + 1], g_exps[3 * gi + 2]};
+  double val = 0.0;
+  if (kind == FC2T2_POLY) {
+    for (int a = 0; a < n_coef; ++a) {
+      const int e0 = coef_exps[3 * a], e1 = coef_exps[3 * a + 1], e2 = coef_exps[3 * a + 2];
+      if (e0 < g[0] || e1 < g[1] || e2 < g[2]) continue;
+      double term = coef[a];
+      term *= dfact(e0) / dfact(e0 - g[0]) * ipow(x[0], e0 - g[0]);
+      term *= dfact(e1) / dfact(e1 - g[1]) * ipow(x[1], e1 - g[1]);
+      term *= dfact(e2) / dfact(e2 - g[2]) * ipow(x[2], e2 - g[2]);
+      val += term;
+    }
+  } else {
+    const double u = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+    // j_i ranges over [ceil(g_i/2), g_i]
+    const int lo0 = (g[0] + 1) / 2, lo1 = (g[1] + 1) / 2, lo2 = (g[2] + 1) / 2;
+    for (int j0 = lo0; j0 <= g[0]; ++j0) {
+      const double f0 = dbinom(j0, g[0] - j0) * ipow(2.0 * x[0], 2 * j0 - g[0]) / dfact(j0);
+      for (int j1 = lo1; j1 <= g[1]; ++j1) {
+        const double f1 = dbinom(j1, g[1] - j1) * ipow(2.0 * x[1], 2 * j1 - g[1]) / dfact(j1);
+        for (int j2 = lo2; j2 <= g[2]; ++j2) {
+          const double f2 = dbinom(j2, g[2] - j2) * ipow(2.0 * x[2], 2 * j2 - g[2]) / dfact(j2);
+          val += radial_deriv(kind, param, u, j0 + j1 + j2) * f0 * f1 * f2;
+        }
+      }
+    }
+    val *= dfact(g[0]) * dfact(g[1]) * dfact(g[2]);
+  }
+  D[tid] = val;
+}
+
+// T[lvl][o][n][k] = h^(|k|+|n|) (-1)^|n| D[lvl][o][pos(k+n)], zero for k >= P.
+template <typename T>
+__global__ void pack_m2l_kernel(int dim, int K, int P, int Ppad, int levels, int n_off, int n_g,
+                                const double* __restrict__ hl, const int* __restrict__ exps,
+                                const double* __restrict__ D, T* __restrict__ out) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)levels * n_off * P * Ppad;
+  if (tid >= total) return;
+  const int k = (int)(tid % Ppad);
+  const int n = (int)((tid / Ppad) % P);
+  const int oi = (int)((tid / ((int64_t)Ppad * P)) % n_off);
+  const int lvl = (int)(tid / ((int64_t)Ppad * P * n_off));
+  if (k >= P) { out[tid] = T(0); return; }
+  const int a0 = exps[3 * k] + exps[3 * n], a1 = exps[3 * k + 1] + exps[3 * n + 1],
+            a2 = exps[3 * k + 2] + exps[3 * n + 2];
+  const int pos = dim == 2 ? mi_pos2(a0, a1) : mi_pos3(a0, a1, a2);
+  const int dk = exps[3 * k] + exps[3 * k + 1] + exps[3 * k + 2];
+  const int dn = exps[3 * n] + exps[3 * n + 1] + exps[3 * n + 2];
+  double v = D[((int64_t)lvl * n_off + oi) * n_g + pos];
+  v *= ipow(hl[lvl], dk + dn);
+  if (dn & 1) v = -v;
+  out[tid] = (T)v;
+}
+
+struct DevFree {
+  std::vector<void*> ptrs;
+  ~DevFree() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* fc2t2_status_string(int status) {
+  switch (status) {
+    case FC2T2_OK: return "ok";
+    case FC2T2_EINVAL: return "invalid argument";
+    case FC2T2_EUNSUPPORTED: return "unsupported combination";
+    case FC2T2_EHIP: return "HIP runtime error";
+    case FC2T2_ENOMEM: return "out of device memory";
+    case FC2T2_EWORKSPACE: return "workspace too small";
+  }
+  return "unknown status";
+}
+
+int fc2t2_multi_indices(int dim, int K, int* out) {
+  if ((dim != 2 && dim != 3) || K < 0) return -1;
+  const int P = nterms(dim, K);
+  if (out) {
+    std::vector<int> e((size_t)P * 3);
+    mi_fill(dim, K, reinterpret_cast<int(*)[3]>(e.data()));
+    for (int i = 0; i < P; ++i)
+      for (int j = 0; j < dim; ++j) out[i * dim + j] = e[3 * i + j];
+  }
+  return P;
+}
+
+int fc2t2_supported(int dim, int K) {
+  return (dim == 2 && K >= 1 && K <= 6) || (dim == 3 && K >= 1 && K <= 5);
+}
+
+fc2t2_status fc2t2_plan_create(const fc2t2_grid* grid, const fc2t2_kernel* kernel, int K,
+                               int m2l_prec, int io, int channels, hipStream_t stream,
+                               fc2t2_plan* out) {
+  if (!grid || !kernel || !out) return FC2T2_EINVAL;
+  const int dim = grid->dim, n = grid->n;
+  if (dim != 2 && dim != 3) return FC2T2_EINVAL;
+  if (n < 4 || (n & (n - 1)) || n > (1 << (kMaxLevels + 1))) return FC2T2_EINVAL;
+  if (!(grid->hi > grid->lo) || !isfinite(grid->lo) || !isfinite(grid->hi)) return FC2T2_EINVAL;
+  if (K < 1 || channels < 1) return FC2T2_EINVAL;
+  if (!fc2t2_supported(dim, K)) return FC2T2_EUNSUPPORTED;
+  if (io != FC2T2_IO_F32 && io != FC2T2_IO_F64) return FC2T2_EINVAL;
+  if (m2l_prec < FC2T2_M2L_F64 || m2l_prec > FC2T2_M2L_BF16X3) return FC2T2_EINVAL;
+  if ((io == FC2T2_IO_F64) != (m2l_prec == FC2T2_M2L_F64)) return FC2T2_EUNSUPPORTED;
+  if (kernel->kind == FC2T2_GAUSSIAN || kernel->kind == FC2T2_IMQ) {
+    if (!(kernel->param > 0.0) || !isfinite(kernel->param)) return FC2T2_EINVAL;
+  } else if (kernel->kind == FC2T2_POLY) {
+    if (kernel->n_coef < 1 || !kernel->coef) return FC2T2_EINVAL;
+    // n_coef must be C(deg + dim, dim) for some deg
+    int deg = -1;
+    for (int d = 0; d <= 64; ++d)
+      if (nterms(dim, d) == kernel->n_coef) { deg = d; break; }
+    if (deg < 0) return FC2T2_EINVAL;
+  } else {
+    return FC2T2_EINVAL;
+  }
+  const int64_t G = dim == 2 ? (int64_t)n * n : (int64_t)n * n * n;
+  if (G > (int64_t(1) << 31)) return FC2T2_EUNSUPPORTED;
+
+  fc2t2_plan_s* pl = new (std::nothrow) fc2t2_plan_s();
+  if (!pl) return FC2T2_ENOMEM;
+  pl->dim = dim;
+  pl->n = n;
+  pl->K = K;
+  pl->P = nterms(dim, K);
+  pl->Ppad = pad4(pl->P);
+  pl->C = channels;
+  pl->io = io;
+  pl->prec = m2l_prec;
+  pl->kind = kernel->kind;
+  pl->lo = grid->lo;
+  pl->hi = grid->hi;
+  pl->param = kernel->param;
+  pl->h0 = (grid->hi - grid->lo) / n;
+  pl->G = G;
+  int levels = 0;
+  while ((2 << levels) < n) ++levels;   // n = 2^(levels + 1)
+  pl->levels = levels;
+  for (int l = 0; l < levels; ++l) {
+    pl->nl[l] = n >> l;
+    pl->Gl[l] = dim == 2 ? (int64_t)pl->nl[l] * pl->nl[l] : (int64_t)pl->nl[l] * pl->nl[l] * pl->nl[l];
+  }
+  pl->n_off = dim == 2 ? 49 : 343;
+  if (hipGetDevice(&pl->device) != hipSuccess) { delete pl; return FC2T2_EHIP; }
+
+  auto fail = [&](fc2t2_status st) {
+    if (pl->m2l_T) (void)hipFree(pl->m2l_T);
+    if (pl->m2l_bf16) (void)hipFree(pl->m2l_bf16);
+    if (pl->shift) (void)hipFree(pl->shift);
+    delete pl;
+    return st;
+  };
+
+  // ---- host tables
+  const int P = pl->P, Ppad = pl->Ppad;
+  const int n_g = nterms(dim, 2 * K);
+  std::vector<int> g_exps((size_t)n_g * 3), k_exps((size_t)P * 3);
+  mi_fill(dim, 2 * K, reinterpret_cast<int(*)[3]>(g_exps.data()));
+  mi_fill(dim, K, reinterpret_cast<int(*)[3]>(k_exps.data()));
+  std::vector<double> hl(levels);
+  for (int l = 0; l < levels; ++l) hl[l] = pl->h0 * (double)(1 << l);
+  int n_coef = 0, deg = 0;
+  std::vector<int> c_exps(3, 0);
+  if (kernel->kind == FC2T2_POLY) {
+    n_coef = kernel->n_coef;
+    while (nterms(dim, deg) != n_coef) ++deg;
+    c_exps.assign((size_t)n_coef * 3, 0);
+    mi_fill(dim, deg, reinterpret_cast<int(*)[3]>(c_exps.data()));
+  }
+
+  // ---- device scratch for the FP64 derivative pass
+  DevFree tmp;
+  auto dalloc = [&](size_t bytes) -> void* {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes ? bytes : 16) != hipSuccess) return nullptr;
+    tmp.ptrs.push_back(p);
+    return p;
+  };
+  const size_t nD = (size_t)levels * pl->n_off * n_g;
+  double* dD = (double*)dalloc(nD * sizeof(double));
+  int* dg = (int*)dalloc(g_exps.size() * sizeof(int));
+  int* dk = (int*)dalloc(k_exps.size() * sizeof(int));
+  double* dh = (double*)dalloc(hl.size() * sizeof(double));
+  int* dce = (int*)dalloc(c_exps.size() * sizeof(int));
+  double* dcoef = (double*)dalloc((size_t)(n_coef ? n_coef : 1) * sizeof(double));
+  if (!dD || !dg || !dk || !dh || !dce || !dcoef) return fail(FC2T2_ENOMEM);
+  if (hipMemcpyAsync(dg, g_exps.data(), g_exps.size() * sizeof(int), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(dk, k_exps.data(), k_exps.size() * sizeof(int), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(dh, hl.data(), hl.size() * sizeof(double), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(dce, c_exps.data(), c_exps.size() * sizeof(int), hipMemcpyHostToDevice, stream) != hipSuccess)
+    return fail(FC2T2_EHIP);
+  if (n_coef && hipMemcpyAsync(dcoef, kernel->coef, n_coef * sizeof(double), hipMemcpyHostToDevice, stream) != hipSuccess)
+    return fail(FC2T2_EHIP);
+  {
+    const int threads = 256;
+    const int64_t blocks = ceil_div((int64_t)nD, threads);
+    hipLaunchKernelGGL(derivs_kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, dim,
+                       kernel->kind, kernel->param, dcoef, dce, n_coef, dg, n_g, levels, dh,
+                       pl->n_off, dD);
+    if (hipGetLastError() != hipSuccess) return fail(FC2T2_EHIP);
+  }
+  // ---- pack the contraction tensor (f64 for F64 plans, f32 otherwise)
+  const size_t nT = (size_t)levels * pl->n_off * P * Ppad;
+  const size_t tsz = io == FC2T2_IO_F64 ? 8 : 4;
+  if (hipMalloc(&pl->m2l_T, nT * tsz) != hipSuccess) { pl->m2l_T = nullptr; return fail(FC2T2_ENOMEM); }
+  pl->m2l_T_bytes = nT * tsz;
+  {
+    const int threads = 256;
+    const int64_t blocks = ceil_div((int64_t)nT, threads);
+    if (io == FC2T2_IO_F64)
+      hipLaunchKernelGGL(pack_m2l_kernel<double>, dim3((unsigned)blocks), dim3(threads), 0, stream,
+                         dim, K, P, Ppad, levels, pl->n_off, n_g, dh, dk, dD, (double*)pl->m2l_T);
+    else
+      hipLaunchKernelGGL(pack_m2l_kernel<float>, dim3((unsigned)blocks), dim3(threads), 0, stream,
+                         dim, K, P, Ppad, levels, pl->n_off, n_g, dh, dk, dD, (float*)pl->m2l_T);
+    if (hipGetLastError() != hipSuccess) return fail(FC2T2_EHIP);
+  }
+  // ---- scaled shift matrices S_b[n][m] = 2^-|n| prod_j (b_j - 1/2)^(n_j - m_j) / (n_j - m_j)!
+  {
+    const int nb = 1 << dim;
+    std::vector<double> S((size_t)nb * P * P, 0.0);
+    for (int b = 0; b < nb; ++b) {
+      double e[3];
+      for (int j = 0; j < 3; ++j) e[j] = (j < dim) ? (((b >> (dim - 1 - j)) & 1) - 0.5) : 0.0;
+      for (int a = 0; a < P; ++a)
+        for (int c = 0; c < P; ++c) {
+          double v = 1.0;
+          bool ok = true;
+          int tn = 0;
+          for (int j = 0; j < 3; ++j) {
+            const int dn = k_exps[3 * a + j] - k_exps[3 * c + j];
+            if (dn < 0) { ok = false; break; }
+            double f = 1.0;
+            for (int i = 2; i <= dn; ++i) f *= i;
+            v *= pow(e[j], dn) / f;
+            tn += k_exps[3 * a + j];
+          }
+          if (ok) S[((size_t)b * P + a) * P + c] = v * ldexp(1.0, -tn);
+        }
+    }
+    const size_t bytes = S.size() * tsz;
+    if (hipMalloc(&pl->shift, bytes) != hipSuccess) { pl->shift = nullptr; return fail(FC2T2_ENOMEM); }
+    if (io == FC2T2_IO_F64) {
+      if (hipMemcpyAsync(pl->shift, S.data(), bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
+        return fail(FC2T2_EHIP);
+      if (hipStreamSynchronize(stream) != hipSuccess) return fail(FC2T2_EHIP);
+    } else {
+      std::vector<float> Sf(S.begin(), S.end());
+      if (hipMemcpyAsync(pl->shift, Sf.data(), bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
+        return fail(FC2T2_EHIP);
+      if (hipStreamSynchronize(stream) != hipSuccess) return fail(FC2T2_EHIP);
+    }
+  }
+  // ---- MFMA operand tables
+  if (m2l_prec >= FC2T2_M2L_BF16) {
+    if (!m2l_mfma_supported(pl)) return fail(FC2T2_EUNSUPPORTED);
+    const fc2t2_status st = m2l_mfma_build_tables(pl, stream);
+    if (st != FC2T2_OK) return fail(st);
+  }
+  if (hipStreamSynchronize(stream) != hipSuccess) return fail(FC2T2_EHIP);
+  *out = pl;
+  return FC2T2_OK;
+}
+
+fc2t2_status fc2t2_plan_destroy(fc2t2_plan plan) {
+  if (!plan) return FC2T2_EINVAL;
+  if (plan->m2l_T) (void)hipFree(plan->m2l_T);
+  if (plan->m2l_bf16) (void)hipFree(plan->m2l_bf16);
+  if (plan->shift) (void)hipFree(plan->shift);
+  delete plan;
+  return FC2T2_OK;
+}
+
+int fc2t2_plan_P(fc2t2_plan plan) { return plan ? plan->P : -1; }
+int fc2t2_plan_P_pad(fc2t2_plan plan) { return plan ? plan->Ppad : -1; }
+int fc2t2_plan_levels(fc2t2_plan plan) { return plan ? plan->levels : -1; }
+size_t fc2t2_local_numel(fc2t2_plan plan) {
+  return plan ? (size_t)plan->C * (size_t)plan->G * (size_t)plan->Ppad : 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,260 @@
+// Grid-to-grid stages of the multilevel expansion (section 3):
+//   up-shift    out[I]    = sum_b S_b in[2I + b]     M2M, and the transpose of L2L
+//   down-shift  out[2I+b] = S_b^T in[I]              L2L, and the transpose of M2M
+//   M2L         L[i] = sum_o T(o) M[i + o] over the parity window minus the hole
+//   M2L^T       G_M[j] = sum_o T(o)^T G_L[j - o] over the same pairs
+// S_b are the cell-scaled binomial shift matrices S_b[n][m] = 2^-|n| (b - 1/2)^(n-m)/(n-m)!
+// (identical at every level in scaled units), T the per-level derivative tensors.
+//
+// Admissible offsets o = j - i at a level (target i, source j): per dimension
+// o_d in [-2, 3] when i_d is even and [-3, 2] when odd (children of the parent's
+// neighbours), j inside the grid, and max |o_d| > 1 above the finest level (the hole is
+// filled by the finer levels).
+#include "plan.h"
+
+using namespace fc2t2;
+
+namespace {
+
+template <int D>
+__device__ __forceinline__ void decode(int64_t lin, int n, int (&c)[3]) {
+  c[0] = c[1] = c[2] = 0;
+#pragma unroll
+  for (int j = D - 1; j >= 0; --j) { c[j] = (int)(lin % n); lin /= n; }
+}
+
+template <int D>
+__device__ __forceinline__ int64_t encode(const int (&c)[3], int n) {
+  int64_t lin = 0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) lin = lin * n + c[j];
+  return lin;
+}
+
+// out[ch][I][n] = sum_b sum_m S[b][n][m] in[ch][2I+b][m]; one thread per (parent, n).
+template <int D, typename T>
+__global__ void __launch_bounds__(256) upshift_kernel(const T* __restrict__ in, T* __restrict__ out,
+                                                      const T* __restrict__ S, int P, int Ppad,
+                                                      int n_par, int64_t G_par, int64_t G_child) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= G_par * Ppad) return;
+  const int ch = blockIdx.y;
+  const int nn = (int)(tid % Ppad);
+  const int64_t I = tid / Ppad;
+  T acc = T(0);
+  if (nn < P) {
+    int ci[3];
+    decode<D>(I, n_par, ci);
+    const int n_child = 2 * n_par;
+    for (int b = 0; b < (1 << D); ++b) {
+      int cc[3] = {0, 0, 0};
+#pragma unroll
+      for (int j = 0; j < D; ++j) cc[j] = 2 * ci[j] + ((b >> (D - 1 - j)) & 1);
+      const T* __restrict__ row = in + ((int64_t)ch * G_child + encode<D>(cc, n_child)) * Ppad;
+      const T* __restrict__ Srow = S + ((int64_t)b * P + nn) * P;
+      for (int m = 0; m < P; ++m) acc += Srow[m] * row[m];
+    }
+  }
+  out[((int64_t)ch * G_par + I) * Ppad + nn] = acc;
+}
+
+// out[ch][i][k] (+)= sum_m S[b(i)][m][k] in[ch][i/2][m]; one thread per (child, k).
+template <int D, typename T>
+__global__ void __launch_bounds__(256) downshift_kernel(const T* __restrict__ in, T* __restrict__ out,
+                                                        const T* __restrict__ S, int P, int Ppad,
+                                                        int n_child, int64_t G_child, int64_t G_par,
+                                                        int accumulate) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= G_child * Ppad) return;
+  const int ch = blockIdx.y;
+  const int k = (int)(tid % Ppad);
+  const int64_t i = tid / Ppad;
+  T acc = T(0);
+  if (k < P) {
+    int ci[3];
+    decode<D>(i, n_child, ci);
+    int pc[3] = {0, 0, 0};
+    int b = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) { pc[j] = ci[j] >> 1; b = (b << 1) | (ci[j] & 1); }
+    const T* __restrict__ row = in + ((int64_t)ch * G_par + encode<D>(pc, n_child / 2)) * Ppad;
+    const T* __restrict__ Sb = S + (int64_t)b * P * P;
+    for (int m = 0; m < P; ++m) acc += Sb[m * P + k] * row[m];
+  }
+  T* dst = out + ((int64_t)ch * G_child + i) * Ppad + k;
+  if (accumulate) *dst += acc; else *dst = acc;
+}
+
+__device__ __forceinline__ bool offset_ok(int i, int o, int n_l) {
+  const bool in_win = (i & 1) ? (o >= -3 && o <= 2) : (o >= -2 && o <= 3);
+  return in_win && i + o >= 0 && i + o < n_l;
+}
+
+// L[ch][i][k] (+)= sum_o sum_n T[o][n][k] M[ch][i+o][n]; one thread per (target, k).
+template <int D, typename T>
+__global__ void __launch_bounds__(256) m2l_kernel(const T* __restrict__ M, T* __restrict__ L,
+                                                  const T* __restrict__ Tl, int P, int Ppad, int n_l,
+                                                  int64_t G_l, int finest, int accumulate) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= G_l * Ppad) return;
+  const int ch = blockIdx.y;
+  const int k = (int)(tid % Ppad);
+  const int64_t i = tid / Ppad;
+  T acc = T(0);
+  if (k < P) {
+    int ci[3];
+    decode<D>(i, n_l, ci);
+    const int z_lo = D == 3 ? -3 : 0, z_hi = D == 3 ? 3 : 0;
+    for (int o0 = -3; o0 <= 3; ++o0) {
+      if (!offset_ok(ci[0], o0, n_l)) continue;
+      for (int o1 = -3; o1 <= 3; ++o1) {
+        if (!offset_ok(ci[1], o1, n_l)) continue;
+        for (int o2 = z_lo; o2 <= z_hi; ++o2) {
+          if (D == 3 && !offset_ok(ci[2], o2, n_l)) continue;
+          const int am = max(max(abs(o0), abs(o1)), abs(o2));
+          if (!finest && am <= 1) continue;
+          int cj[3] = {ci[0] + o0, ci[1] + o1, ci[2] + o2};
+          const int oi = D == 2 ? (o0 + 3) * 7 + (o1 + 3) : ((o0 + 3) * 7 + (o1 + 3)) * 7 + (o2 + 3);
+          const T* __restrict__ src = M + ((int64_t)ch * G_l + encode<D>(cj, n_l)) * Ppad;
+          const T* __restrict__ To = Tl + (int64_t)oi * P * Ppad + k;
+          for (int nn = 0; nn < P; ++nn) acc += To[(int64_t)nn * Ppad] * src[nn];
+        }
+      }
+    }
+  }
+  T* dst = L + ((int64_t)ch * G_l + i) * Ppad + k;
+  if (accumulate) *dst += acc; else *dst = acc;
+}
+
+// GM[ch][j][n] (+)= sum_o sum_k T[o][n][k] GL[ch][j-o][k]; one thread per (source, n).
+template <int D, typename T>
+__global__ void __launch_bounds__(256) m2l_T_kernel(const T* __restrict__ GL, T* __restrict__ GM,
+                                                    const T* __restrict__ Tl, int P, int Ppad, int n_l,
+                                                    int64_t G_l, int finest, int accumulate) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= G_l * Ppad) return;
+  const int ch = blockIdx.y;
+  const int nn = (int)(tid % Ppad);
+  const int64_t j = tid / Ppad;
+  T acc = T(0);
+  if (nn < P) {
+    int cj[3];
+    decode<D>(j, n_l, cj);
+    const int z_lo = D == 3 ? -3 : 0, z_hi = D == 3 ? 3 : 0;
+    for (int o0 = -3; o0 <= 3; ++o0) {
+      const int i0 = cj[0] - o0;
+      if (i0 < 0 || i0 >= n_l || !offset_ok(i0, o0, n_l)) continue;
+      for (int o1 = -3; o1 <= 3; ++o1) {
+        const int i1 = cj[1] - o1;
+        if (i1 < 0 || i1 >= n_l || !offset_ok(i1, o1, n_l)) continue;
+        for (int o2 = z_lo; o2 <= z_hi; ++o2) {
+          const int i2 = cj[2] - o2;
+          if (D == 3 && (i2 < 0 || i2 >= n_l || !offset_ok(i2, o2, n_l))) continue;
+          const int am = max(max(abs(o0), abs(o1)), abs(o2));
+          if (!finest && am <= 1) continue;
+          int ci[3] = {i0, i1, D == 3 ? i2 : 0};
+          const int oi = D == 2 ? (o0 + 3) * 7 + (o1 + 3) : ((o0 + 3) * 7 + (o1 + 3)) * 7 + (o2 + 3);
+          const T* __restrict__ src = GL + ((int64_t)ch * G_l + encode<D>(ci, n_l)) * Ppad;
+          const T* __restrict__ To = Tl + ((int64_t)oi * P + nn) * Ppad;
+          for (int k = 0; k < P; ++k) acc += To[k] * src[k];
+        }
+      }
+    }
+  }
+  T* dst = GM + ((int64_t)ch * G_l + j) * Ppad + nn;
+  if (accumulate) *dst += acc; else *dst = acc;
+}
+
+template <typename T>
+const T* level_tensor(const fc2t2_plan_s* pl, int lvl) {
+  return (const T*)pl->m2l_T + (size_t)lvl * pl->n_off * pl->P * pl->Ppad;
+}
+
+}  // namespace
+
+namespace fc2t2 {
+
+fc2t2_status launch_upshift(const fc2t2_plan_s* pl, int lvl_child, const void* in, void* out,
+                            hipStream_t s) {
+  const int lp = lvl_child + 1;
+  const int64_t work = pl->Gl[lp] * pl->Ppad;
+  const dim3 grid((unsigned)ceil_div(work, 256), pl->C);
+  if (pl->io == FC2T2_IO_F64) {
+    if (pl->dim == 2)
+      hipLaunchKernelGGL((upshift_kernel<2, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, (const double*)pl->shift, pl->P, pl->Ppad, pl->nl[lp], pl->Gl[lp], pl->Gl[lvl_child]);
+    else
+      hipLaunchKernelGGL((upshift_kernel<3, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, (const double*)pl->shift, pl->P, pl->Ppad, pl->nl[lp], pl->Gl[lp], pl->Gl[lvl_child]);
+  } else {
+    if (pl->dim == 2)
+      hipLaunchKernelGGL((upshift_kernel<2, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, (const float*)pl->shift, pl->P, pl->Ppad, pl->nl[lp], pl->Gl[lp], pl->Gl[lvl_child]);
+    else
+      hipLaunchKernelGGL((upshift_kernel<3, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, (const float*)pl->shift, pl->P, pl->Ppad, pl->nl[lp], pl->Gl[lp], pl->Gl[lvl_child]);
+  }
+  FC2T2_LAUNCH_CHECK();
+  return FC2T2_OK;
+}
+
+fc2t2_status launch_downshift(const fc2t2_plan_s* pl, int lvl_child, const void* in, void* out,
+                              bool accumulate, hipStream_t s) {
+  const int lp = lvl_child + 1;
+  const int64_t work = pl->Gl[lvl_child] * pl->Ppad;
+  const dim3 grid((unsigned)ceil_div(work, 256), pl->C);
+  const int acc = accumulate ? 1 : 0;
+  if (pl->io == FC2T2_IO_F64) {
+    if (pl->dim == 2)
+      hipLaunchKernelGGL((downshift_kernel<2, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, (const double*)pl->shift, pl->P, pl->Ppad, pl->nl[lvl_child], pl->Gl[lvl_child], pl->Gl[lp], acc);
+    else
+      hipLaunchKernelGGL((downshift_kernel<3, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, (const double*)pl->shift, pl->P, pl->Ppad, pl->nl[lvl_child], pl->Gl[lvl_child], pl->Gl[lp], acc);
+  } else {
+    if (pl->dim == 2)
+      hipLaunchKernelGGL((downshift_kernel<2, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, (const float*)pl->shift, pl->P, pl->Ppad, pl->nl[lvl_child], pl->Gl[lvl_child], pl->Gl[lp], acc);
+    else
+      hipLaunchKernelGGL((downshift_kernel<3, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, (const float*)pl->shift, pl->P, pl->Ppad, pl->nl[lvl_child], pl->Gl[lvl_child], pl->Gl[lp], acc);
+  }
+  FC2T2_LAUNCH_CHECK();
+  return FC2T2_OK;
+}
+
+fc2t2_status launch_m2l(const fc2t2_plan_s* pl, int lvl, const void* M, void* L, bool accumulate,
+                        hipStream_t s) {
+  if (pl->prec >= FC2T2_M2L_BF16) return launch_m2l_mfma(pl, lvl, M, L, accumulate, false, s);
+  const int64_t work = pl->Gl[lvl] * pl->Ppad;
+  const dim3 grid((unsigned)ceil_div(work, 256), pl->C);
+  const int fin = lvl == 0, acc = accumulate ? 1 : 0;
+  if (pl->io == FC2T2_IO_F64) {
+    if (pl->dim == 2)
+      hipLaunchKernelGGL((m2l_kernel<2, double>), grid, dim3(256), 0, s, (const double*)M, (double*)L, level_tensor<double>(pl, lvl), pl->P, pl->Ppad, pl->nl[lvl], pl->Gl[lvl], fin, acc);
+    else
+      hipLaunchKernelGGL((m2l_kernel<3, double>), grid, dim3(256), 0, s, (const double*)M, (double*)L, level_tensor<double>(pl, lvl), pl->P, pl->Ppad, pl->nl[lvl], pl->Gl[lvl], fin, acc);
+  } else {
+    if (pl->dim == 2)
+      hipLaunchKernelGGL((m2l_kernel<2, float>), grid, dim3(256), 0, s, (const float*)M, (float*)L, level_tensor<float>(pl, lvl), pl->P, pl->Ppad, pl->nl[lvl], pl->Gl[lvl], fin, acc);
+    else
+      hipLaunchKernelGGL((m2l_kernel<3, float>), grid, dim3(256), 0, s, (const float*)M, (float*)L, level_tensor<float>(pl, lvl), pl->P, pl->Ppad, pl->nl[lvl], pl->Gl[lvl], fin, acc);
+  }
+  FC2T2_LAUNCH_CHECK();
+  return FC2T2_OK;
+}
+
+fc2t2_status launch_m2l_T(const fc2t2_plan_s* pl, int lvl, const void* GL, void* GM, bool accumulate,
+                          hipStream_t s) {
+  if (pl->prec >= FC2T2_M2L_BF16) return launch_m2l_mfma(pl, lvl, GL, GM, accumulate, true, s);
+  const int64_t work = pl->Gl[lvl] * pl->Ppad;
+  const dim3 grid((unsigned)ceil_div(work, 256), pl->C);
+  const int fin = lvl == 0, acc = accumulate ? 1 : 0;
+  if (pl->io == FC2T2_IO_F64) {
+    if (pl->dim == 2)
+      hipLaunchKernelGGL((m2l_T_kernel<2, double>), grid, dim3(256), 0, s, (const double*)GL, (double*)GM, level_tensor<double>(pl, lvl), pl->P, pl->Ppad, pl->nl[lvl], pl->Gl[lvl], fin, acc);
+    else
+      hipLaunchKernelGGL((m2l_T_kernel<3, double>), grid, dim3(256), 0, s, (const double*)GL, (double*)GM, level_tensor<double>(pl, lvl), pl->P, pl->Ppad, pl->nl[lvl], pl->Gl[lvl], fin, acc);
+  } else {
+    if (pl->dim == 2)
+      hipLaunchKernelGGL((m2l_T_kernel<2, float>), grid, dim3(256), 0, s, (const float*)GL, (float*)GM, level_tensor<float>(pl, lvl), pl->P, pl->Ppad, pl->nl[lvl], pl->Gl[lvl], fin, acc);
+    else
+      hipLaunchKernelGGL((m2l_T_kernel<3, float>), grid, dim3(256), 0, s, (const float*)GL, (float*)GM, level_tensor<float>(pl, lvl), pl->P, pl->Ppad, pl->nl[lvl], pl->Gl[lvl], fin, acc);
+  }
+  FC2T2_LAUNCH_CHECK();
+  return FC2T2_OK;
+}
+
+}  // namespace fc2t2

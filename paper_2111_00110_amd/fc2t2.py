@@ -1,0 +1,346 @@
+"""Python binding of libfc2t2.so: argument marshalling over ctypes, torch for device memory.
+
+Every step of the computation runs in the HIP library; this module only checks shapes,
+allocates outputs and workspaces with torch, and passes raw device pointers and torch's
+current stream.  It raises if the library has not been built: there is no fallback.
+
+Names follow the C-ABI (fc2t2.h) without the ``fc2t2_`` prefix, as methods of ``Plan``.
+The autograd wrappers ``Explicit``, ``RayIntegral`` and ``RayRoot`` give the layers of the
+paper's sections 4, 6.1 and 5 with their hand-written backward passes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfc2t2.so")
+
+KERNELS = {"gaussian": 0, "imq": 1, "poly": 2}
+M2L_PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x2": 3, "bf16x3": 4}
+IO = {"f32": 0, "f64": 1}
+OP = {"expand": 0, "eval_backward": 1, "expand_backward": 2, "ray_integral_backward": 3,
+      "ray_root_backward": 4}
+ROOT_SAVED = 12
+
+_lib = None
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("lo", ctypes.c_double),
+                ("hi", ctypes.c_double)]
+
+
+class _Kernel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("param", ctypes.c_double), ("n_coef", ctypes.c_int),
+                ("coef", ctypes.POINTER(ctypes.c_double))]
+
+
+class FC2T2Error(RuntimeError):
+    pass
+
+
+def lib() -> ctypes.CDLL:
+    """Load libfc2t2.so (torch is imported first so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FC2T2Error("libfc2t2.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    L.fc2t2_status_string.restype = ctypes.c_char_p
+    L.fc2t2_status_string.argtypes = [i32]
+    L.fc2t2_multi_indices.restype = i32
+    L.fc2t2_multi_indices.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_int)]
+    L.fc2t2_supported.restype = i32
+    L.fc2t2_supported.argtypes = [i32, i32]
+    L.fc2t2_plan_create.restype = i32
+    L.fc2t2_plan_create.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Kernel), i32, i32, i32,
+                                    i32, vp, ctypes.POINTER(vp)]
+    L.fc2t2_plan_destroy.restype = i32
+    L.fc2t2_plan_destroy.argtypes = [vp]
+    for name in ("fc2t2_plan_P", "fc2t2_plan_P_pad", "fc2t2_plan_levels"):
+        getattr(L, name).restype = i32
+        getattr(L, name).argtypes = [vp]
+    L.fc2t2_local_numel.restype = sz
+    L.fc2t2_local_numel.argtypes = [vp]
+    L.fc2t2_workspace_size.restype = sz
+    L.fc2t2_workspace_size.argtypes = [vp, i32, i64]
+    L.fc2t2_expand.restype = i32
+    L.fc2t2_expand.argtypes = [vp, vp, vp, i64, vp, vp, sz, vp]
+    L.fc2t2_eval.restype = i32
+    L.fc2t2_eval.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
+    L.fc2t2_eval_backward.restype = i32
+    L.fc2t2_eval_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]
+    L.fc2t2_expand_backward.restype = i32
+    L.fc2t2_expand_backward.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, sz, vp]
+    L.fc2t2_ray_integral.restype = i32
+    L.fc2t2_ray_integral.argtypes = [vp, vp, vp, vp, dbl, dbl, i64, vp, vp]
+    L.fc2t2_ray_integral_backward.restype = i32
+    L.fc2t2_ray_integral_backward.argtypes = [vp, vp, vp, dbl, dbl, i64, vp, vp, vp, sz, vp]
+    L.fc2t2_ray_root.restype = i32
+    L.fc2t2_ray_root.argtypes = [vp, vp, vp, vp, dbl, dbl, i64, dbl, vp, vp, vp, vp, vp]
+    L.fc2t2_ray_root_backward.restype = i32
+    L.fc2t2_ray_root_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]
+    _lib = L
+    return L
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise FC2T2Error("%s failed: %s (status %d)" % (what, lib().fc2t2_status_string(status).decode(), status))
+
+
+def multi_indices(dim: int, K: int):
+    """The library's multi-index order as a list of tuples."""
+    L = lib()
+    P = L.fc2t2_multi_indices(dim, K, None)
+    if P < 0:
+        raise FC2T2Error("bad dim/K")
+    buf = (ctypes.c_int * (P * dim))()
+    L.fc2t2_multi_indices(dim, K, buf)
+    return [tuple(buf[i * dim:(i + 1) * dim]) for i in range(P)]
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """A grid, a kernel psi and an order K (the paper's initialize(func, levels, rho))."""
+
+    def __init__(self, dim: int, n: int, lo: float, hi: float, kernel: str, param: float = 0.0,
+                 K: int = 4, m2l: str = "f32", io: str = "f32", channels: int = 1,
+                 coef: Optional[Sequence[float]] = None, device=None):
+        L = lib()
+        self.dim, self.n, self.lo, self.hi, self.K = dim, n, float(lo), float(hi), K
+        self.kernel, self.param, self.m2l, self.io, self.C = kernel, float(param), m2l, io, channels
+        self.dtype = torch.float64 if io == "f64" else torch.float32
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        g = _Grid(dim, n, self.lo, self.hi)
+        if coef is not None:
+            arr = (ctypes.c_double * len(coef))(*[float(c) for c in coef])
+            self._coef = arr
+            k = _Kernel(KERNELS[kernel], self.param, len(coef), ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)))
+        else:
+            k = _Kernel(KERNELS[kernel], self.param, 0, None)
+        out = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.fc2t2_plan_create(ctypes.byref(g), ctypes.byref(k), K, M2L_PREC[m2l], IO[io],
+                                       channels, _stream(), ctypes.byref(out)), "fc2t2_plan_create")
+        self.handle = out
+        self.P = L.fc2t2_plan_P(out)
+        self.P_pad = L.fc2t2_plan_P_pad(out)
+        self.levels = L.fc2t2_plan_levels(out)
+        self.h = (self.hi - self.lo) / n
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.fc2t2_plan_destroy(h)
+            self.handle = None
+
+    # ------------------------------------------------------------------ helpers
+    def _t(self, x: torch.Tensor, shape, name: str) -> torch.Tensor:
+        if not isinstance(x, torch.Tensor) or x.device.type != "cuda":
+            raise FC2T2Error("%s must be a CUDA tensor" % name)
+        if x.dtype != self.dtype:
+            raise FC2T2Error("%s must be %s" % (name, self.dtype))
+        if tuple(x.shape) != tuple(shape):
+            raise FC2T2Error("%s has shape %s, expected %s" % (name, tuple(x.shape), tuple(shape)))
+        return x.contiguous()
+
+    def local_shape(self):
+        return (self.C, self.n ** self.dim, self.P_pad)
+
+    def new_local(self) -> torch.Tensor:
+        return torch.zeros(self.local_shape(), dtype=self.dtype, device=self.device)
+
+    def workspace(self, op: str, count: int) -> torch.Tensor:
+        nbytes = lib().fc2t2_workspace_size(self.handle, OP[op], int(count))
+        return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+
+    # ------------------------------------------------------------------ C-ABI calls
+    def expand(self, p: torch.Tensor, w: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        N = p.shape[0]
+        p = self._t(p, (N, self.dim), "p")
+        w = self._t(w, (N, self.C), "w")
+        Lt = self.new_local() if out is None else self._t(out, self.local_shape(), "L")
+        ws = self.workspace("expand", N)
+        _check(lib().fc2t2_expand(self.handle, _ptr(p), _ptr(w), N, _ptr(Lt), _ptr(ws), ws.numel(),
+                                  _stream()), "fc2t2_expand")
+        return Lt
+
+    def eval(self, Lt: torch.Tensor, q: torch.Tensor, grad: bool = False, hess: bool = False):
+        M = q.shape[0]
+        q = self._t(q, (M, self.dim), "q")
+        Lt = self._t(Lt, self.local_shape(), "L")
+        y = torch.empty((M, self.C), dtype=self.dtype, device=self.device)
+        g = torch.empty((M, self.C, self.dim), dtype=self.dtype, device=self.device) if grad or hess else None
+        nh = self.dim * (self.dim + 1) // 2
+        hs = torch.empty((M, self.C, nh), dtype=self.dtype, device=self.device) if hess else None
+        _check(lib().fc2t2_eval(self.handle, _ptr(Lt), _ptr(q), M, _ptr(y), _ptr(g), _ptr(hs), _stream()),
+               "fc2t2_eval")
+        return y, g, hs
+
+    def eval_backward(self, Lt, q, gy, gL: Optional[torch.Tensor] = None, gq: Optional[torch.Tensor] = None):
+        M = q.shape[0]
+        q = self._t(q, (M, self.dim), "q")
+        gy = self._t(gy, (M, self.C), "gy")
+        if gL is not None:
+            assert gL.is_contiguous() and tuple(gL.shape) == self.local_shape() and gL.dtype == self.dtype
+        if gq is not None:
+            assert gq.is_contiguous() and tuple(gq.shape) == (M, self.dim) and gq.dtype == self.dtype
+        ws = self.workspace("eval_backward", M) if gL is not None else None
+        _check(lib().fc2t2_eval_backward(self.handle, _ptr(Lt), _ptr(q), M, _ptr(gy), _ptr(gL), _ptr(gq),
+                                         _ptr(ws), 0 if ws is None else ws.numel(), _stream()),
+               "fc2t2_eval_backward")
+
+    def expand_backward(self, gL, p, w, gp: Optional[torch.Tensor] = None, gw: Optional[torch.Tensor] = None):
+        N = p.shape[0]
+        p = self._t(p, (N, self.dim), "p")
+        w = self._t(w, (N, self.C), "w")
+        gL = self._t(gL, self.local_shape(), "gL")
+        if gp is not None:
+            assert gp.is_contiguous() and tuple(gp.shape) == (N, self.dim) and gp.dtype == self.dtype
+        if gw is not None:
+            assert gw.is_contiguous() and tuple(gw.shape) == (N, self.C) and gw.dtype == self.dtype
+        ws = self.workspace("expand_backward", N)
+        _check(lib().fc2t2_expand_backward(self.handle, _ptr(gL), _ptr(p), _ptr(w), N, _ptr(gp), _ptr(gw),
+                                           _ptr(ws), ws.numel(), _stream()), "fc2t2_expand_backward")
+
+    def ray_integral(self, Lt, o, r, t0: float, t1: float) -> torch.Tensor:
+        R = o.shape[0]
+        o = self._t(o, (R, 3), "o")
+        r = self._t(r, (R, 3), "r")
+        Lt = self._t(Lt, self.local_shape(), "L")
+        y = torch.empty((R, self.C), dtype=self.dtype, device=self.device)
+        _check(lib().fc2t2_ray_integral(self.handle, _ptr(Lt), _ptr(o), _ptr(r), float(t0), float(t1), R,
+                                        _ptr(y), _stream()), "fc2t2_ray_integral")
+        return y
+
+    def ray_integral_backward(self, o, r, t0: float, t1: float, gy, gL):
+        R = o.shape[0]
+        o = self._t(o, (R, 3), "o")
+        r = self._t(r, (R, 3), "r")
+        gy = self._t(gy, (R, self.C), "gy")
+        assert gL.is_contiguous() and tuple(gL.shape) == self.local_shape() and gL.dtype == self.dtype
+        ws = self.workspace("ray_integral_backward", R)
+        _check(lib().fc2t2_ray_integral_backward(self.handle, _ptr(o), _ptr(r), float(t0), float(t1), R,
+                                                 _ptr(gy), _ptr(gL), _ptr(ws), ws.numel(), _stream()),
+               "fc2t2_ray_integral_backward")
+
+    def ray_root(self, Lt, o, r, t0: float, t1: float, level_frac: float = 0.5):
+        R = o.shape[0]
+        o = self._t(o, (R, 3), "o")
+        r = self._t(r, (R, 3), "r")
+        Lt = self._t(Lt, self.local_shape(), "L")
+        t = torch.empty(R, dtype=self.dtype, device=self.device)
+        normal = torch.empty((R, 3), dtype=self.dtype, device=self.device)
+        hit = torch.empty(R, dtype=torch.int32, device=self.device)
+        saved = torch.empty((R, ROOT_SAVED), dtype=self.dtype, device=self.device)
+        _check(lib().fc2t2_ray_root(self.handle, _ptr(Lt), _ptr(o), _ptr(r), float(t0), float(t1), R,
+                                    float(level_frac), _ptr(t), _ptr(normal), _ptr(hit), _ptr(saved),
+                                    _stream()), "fc2t2_ray_root")
+        return t, normal, hit, saved
+
+    def ray_root_backward(self, saved, hit, gt, gn, gL):
+        R = saved.shape[0]
+        saved = self._t(saved, (R, ROOT_SAVED), "saved")
+        assert hit.dtype == torch.int32 and hit.is_contiguous()
+        if gt is not None:
+            gt = self._t(gt, (R,), "gt")
+        if gn is not None:
+            gn = self._t(gn, (R, 3), "gn")
+        assert gL.is_contiguous() and tuple(gL.shape) == self.local_shape() and gL.dtype == self.dtype
+        ws = self.workspace("ray_root_backward", R)
+        _check(lib().fc2t2_ray_root_backward(self.handle, _ptr(saved), _ptr(hit), R, _ptr(gt), _ptr(gn),
+                                             _ptr(gL), _ptr(ws), ws.numel(), _stream()),
+               "fc2t2_ray_root_backward")
+
+
+# ---------------------------------------------------------------------------- autograd
+
+class Explicit(torch.autograd.Function):
+    """y = f(q; p, w) (section 4) with the backward of section 4.1."""
+
+    @staticmethod
+    def forward(ctx, plan: Plan, p, w, q):
+        Lt = plan.expand(p, w)
+        y, _, _ = plan.eval(Lt, q)
+        ctx.plan = plan
+        ctx.save_for_backward(p, w, q, Lt)
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        plan = ctx.plan
+        p, w, q, Lt = ctx.saved_tensors
+        gy = gy.contiguous()
+        need_p, need_w, need_q = ctx.needs_input_grad[1], ctx.needs_input_grad[2], ctx.needs_input_grad[3]
+        gq = torch.zeros_like(q) if need_q else None
+        gp = torch.zeros_like(p) if need_p else None
+        gw = torch.zeros_like(w) if need_w else None
+        gL = plan.new_local() if (need_p or need_w) else None
+        plan.eval_backward(Lt, q, gy, gL, gq)
+        if gL is not None:
+            plan.expand_backward(gL, p, w, gp, gw)
+        return None, gp, gw, gq
+
+
+class RayIntegral(torch.autograd.Function):
+    """y_r = integral of f(o_r + t r_r) over t in [t0, t1] (section 6.1) and its backward
+    by ray insertion (section 6.2.1)."""
+
+    @staticmethod
+    def forward(ctx, plan: Plan, p, w, o, r, t0: float, t1: float):
+        Lt = plan.expand(p, w)
+        y = plan.ray_integral(Lt, o, r, t0, t1)
+        ctx.plan, ctx.t0, ctx.t1 = plan, t0, t1
+        ctx.save_for_backward(p, w, o, r)
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        plan = ctx.plan
+        p, w, o, r = ctx.saved_tensors
+        gL = plan.new_local()
+        plan.ray_integral_backward(o, r, ctx.t0, ctx.t1, gy.contiguous(), gL)
+        gp = torch.zeros_like(p) if ctx.needs_input_grad[1] else None
+        gw = torch.zeros_like(w) if ctx.needs_input_grad[2] else None
+        plan.expand_backward(gL, p, w, gp, gw)
+        return None, gp, gw, None, None, None, None
+
+
+class RayRoot(torch.autograd.Function):
+    """(t*, grad f(q*)) of the first level crossing along each ray (section 5.1), with the
+    implicit-function-theorem backward of section 5.2."""
+
+    @staticmethod
+    def forward(ctx, plan: Plan, p, w, o, r, t0: float, t1: float, level_frac: float = 0.5):
+        Lt = plan.expand(p, w)
+        t, normal, hit, saved = plan.ray_root(Lt, o, r, t0, t1, level_frac)
+        ctx.plan = plan
+        ctx.save_for_backward(p, w, saved, hit)
+        ctx.mark_non_differentiable(hit)
+        return t, normal, hit
+
+    @staticmethod
+    def backward(ctx, gt, gn, _ghit):
+        plan = ctx.plan
+        p, w, saved, hit = ctx.saved_tensors
+        gL = plan.new_local()
+        plan.ray_root_backward(saved, hit, None if gt is None else gt.contiguous(),
+                               None if gn is None else gn.contiguous(), gL)
+        gp = torch.zeros_like(p) if ctx.needs_input_grad[1] else None
+        gw = torch.zeros_like(w) if ctx.needs_input_grad[2] else None
+        plan.expand_backward(gL, p, w, gp, gw)
+        return None, gp, gw, None, None, None, None, None

@@ -1,0 +1,166 @@
+"""GPU parity of the explicit layer (expansion, evaluation, backward) against the FP64
+checker, through the C-ABI.  Tolerances: FP64 path 1e-12 relative L2 against the
+step-by-step checker; FP32 path 1e-5 on values and w_bar, 1e-4 on the gradient-derived
+p_bar and q_bar (one order of the expansion is lost by differentiating)."""
+import numpy as np
+import pytest
+
+from oracle import direct, fmm, kernels
+from paper_2111_00110_amd import workloads as W
+
+from helpers import oracle_geometry, oracle_kernel, poly_coef_list, rel, scaled_locals
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def F():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2111_00110_amd import fc2t2
+    return fc2t2
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _plan(F, wl, m2l=None, coef=None, channels=1):
+    m2l = m2l or ("f64" if wl.io == "f64" else "f32")
+    return F.Plan(wl.dim, wl.n, wl.lo, wl.hi, wl.kernel, wl.param, wl.K, m2l=m2l, io=wl.io,
+                  channels=channels, coef=coef)
+
+
+def _run_gpu(F, plan, x):
+    p, w, q, gy = (_dev(x[k]) for k in ("p", "w", "q", "gy"))
+    Lt = plan.expand(p, w)
+    y, g, _ = plan.eval(Lt, q, grad=True)
+    gL = plan.new_local()
+    gq = torch.zeros_like(q)
+    plan.eval_backward(Lt, q, gy, gL, gq)
+    gp = torch.zeros_like(p)
+    gw = torch.zeros_like(w)
+    plan.expand_backward(gL, p, w, gp, gw)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in dict(L=Lt, y=y, g=g, gL=gL, gq=gq, gp=gp, gw=gw).items()}
+
+
+def test_small_2d_fp64_matches_checker(F):
+    wl = W.workload("explicit2d_small")
+    x = W.make(wl)
+    geo, ker = oracle_geometry(wl), oracle_kernel(wl)
+    plan = _plan(F, wl)
+    got = _run_gpu(F, plan, x)
+    L0 = fmm.expand(geo, ker, x["p"], x["w"])
+    assert rel(got["L"], scaled_locals(geo, L0, plan.P_pad)) < 1e-12
+    y, gw, gp, gq = fmm.explicit_forward_backward(geo, ker, x["p"], x["w"], x["q"], x["gy"])
+    assert rel(got["y"], y) < 1e-12
+    assert rel(got["gw"], gw) < 1e-12
+    assert rel(got["gp"], gp) < 1e-12
+    assert rel(got["gq"], gq) < 1e-12
+    gdir = fmm.l2p_grad(geo, L0, x["q"])
+    assert rel(got["g"], gdir) < 1e-12
+
+
+@pytest.mark.parametrize("d,n,K", [(2, 8, 4), (2, 32, 6), (3, 8, 3), (3, 16, 5)])
+def test_polynomial_kernel_fp64_equals_direct_sum(F, d, n, K):
+    rng = np.random.default_rng(7 * n + K)
+    deg = min(K, 4)
+    coef = {a: rng.standard_normal() for a in fmm.multi_indices(d, deg)}
+    ker = kernels.Polynomial(coef, d)
+    wl = W.Workload("poly", d, n, -1.0, 1.0, K, "poly", 0.0, 700, 500, 0, "f64", "explicit", "uniform")
+    p = rng.uniform(-1, 1, (700, d))
+    q = rng.uniform(-1, 1, (500, d))
+    w = rng.standard_normal((700, 2))
+    gy = rng.standard_normal((500, 2))
+    plan = _plan(F, wl, coef=poly_coef_list(ker, d, deg), channels=2)
+    got = _run_gpu(F, plan, dict(p=p, q=q, w=w, gy=gy))
+    assert rel(got["y"], direct.explicit_y(ker, p, w, q)) < 1e-11
+    gwd, gpd, gqd = direct.explicit_grads(ker, p, w, q, gy)
+    assert rel(got["gw"], gwd) < 1e-11
+    assert rel(got["gp"], gpd) < 1e-10
+    assert rel(got["gq"], gqd) < 1e-10
+
+
+@pytest.mark.parametrize("name,N,M,n", [("explicit2d", 1 << 15, 1 << 14, 256), ("explicit2d", 3001, 2999, 64)])
+def test_2d_fp32_matches_checker(F, name, N, M, n):
+    wl = W.workload(name, N=N, M=M, n=n)
+    x = W.make(wl, seed=1)
+    geo, ker = oracle_geometry(wl), oracle_kernel(wl)
+    plan = _plan(F, wl)
+    got = _run_gpu(F, plan, x)
+    y, gw, gp, gq = fmm.explicit_forward_backward(geo, ker, x["p"], x["w"], x["q"], x["gy"])
+    assert rel(got["y"], y) < 1e-5
+    assert rel(got["gw"], gw) < 1e-5
+    assert rel(got["gp"], gp) < 1e-4
+    assert rel(got["gq"], gq) < 1e-4
+
+
+@pytest.mark.parametrize("kind,param,K", [("gaussian", 0.05, 4), ("imq", 0.1, 3), ("gaussian", 0.06, 5)])
+@pytest.mark.parametrize("io", ["f64", "f32"])
+def test_3d_small_matches_checker(F, kind, param, K, io):
+    wl = W.Workload("t3", 3, 16, -1.0, 1.0, K, kind, param, 4000, 3000, 0, io, "explicit", "shell")
+    x = W.make(wl, seed=2)
+    geo, ker = oracle_geometry(wl), oracle_kernel(wl)
+    plan = _plan(F, wl)
+    got = _run_gpu(F, plan, x)
+    y, gw, gp, gq = fmm.explicit_forward_backward(geo, ker, x["p"], x["w"], x["q"], x["gy"])
+    tol, tolg = (1e-12, 1e-12) if io == "f64" else (1e-5, 1e-4)
+    assert rel(got["y"], y) < tol
+    assert rel(got["gw"], gw) < tol
+    assert rel(got["gp"], gp) < tolg
+    assert rel(got["gq"], gq) < tolg
+
+
+def test_bitwise_deterministic(F):
+    wl = W.workload("explicit2d", N=1 << 16, M=1 << 15, n=128)
+    x = W.make(wl, seed=3)
+    plan = _plan(F, wl)
+    a = _run_gpu(F, plan, x)
+    b = _run_gpu(F, plan, x)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_edge_cases(F):
+    wl = W.Workload("e", 2, 16, 0.0, 1.0, 4, "gaussian", 0.05, 0, 0, 0, "f64", "explicit", "uniform")
+    geo, ker = oracle_geometry(wl), oracle_kernel(wl)
+    plan = _plan(F, wl)
+    # no sources: zero expansion, zero output
+    Lt = plan.expand(_dev(np.zeros((0, 2))), _dev(np.zeros((0, 1))))
+    q = np.random.default_rng(0).uniform(0, 1, (37, 2))
+    y, _, _ = plan.eval(Lt, _dev(q))
+    assert float(torch.abs(Lt).max()) == 0.0 and float(torch.abs(y).max()) == 0.0
+    # no queries
+    y0, _, _ = plan.eval(Lt, _dev(np.zeros((0, 2))))
+    assert y0.shape == (0, 1)
+    # all sources in one cell, points on faces and outside the domain (clamped)
+    p = np.array([[0.51, 0.52]] * 50 + [[0.0, 0.0], [1.0, 1.0], [0.5, 0.25], [-0.01, 0.3], [1.02, 0.7]])
+    w = np.random.default_rng(1).standard_normal((len(p), 1))
+    qq = np.array([[0.5, 0.5], [0.0, 1.0], [0.999, 0.001], [0.3, 0.7]])
+    got = _run_gpu(F, plan, dict(p=p, w=w, q=qq, gy=np.ones((4, 1))))
+    y, gw, gp, gq = fmm.explicit_forward_backward(geo, ker, p, w, qq, np.ones((4, 1)))
+    assert rel(got["y"], y) < 1e-12 and rel(got["gw"], gw) < 1e-12 and rel(got["gp"], gp) < 1e-12
+
+
+def test_full_size_2d_sampled(F):
+    """The 2-D workload at full size (N = M = 2^20, 256^2, K = 6): sampled queries against
+    the checker's locals computed cell by cell from the moment pyramid."""
+    wl = W.workload("explicit2d")
+    x = W.make(wl)
+    geo, ker = oracle_geometry(wl), oracle_kernel(wl)
+    plan = _plan(F, wl)
+    p, w, q = _dev(x["p"]), _dev(x["w"]), _dev(x["q"])
+    Lt = plan.expand(p, w)
+    y, _, _ = plan.eval(Lt, q)
+    y = y.cpu().numpy()
+    idx = W.subsample(5, 256, wl.M)
+    qs = x["q"][idx]
+    cells = geo.cell_index(qs)
+    Ms = fmm.moments_all_levels(geo, x["p"], x["w"])
+    Lc = fmm.locals_at_cells(geo, ker, Ms, cells)                          # [C, S, P]
+    dvec = qs.astype(np.float64) - geo.centre(0, cells)
+    want = np.einsum("csp,sp->sc", Lc, fmm.monomials(dvec, geo.idx))
+    assert rel(y[idx], want) < 1e-5

@@ -194,6 +194,17 @@ fc2t2_status fc2t2_ray_root_backward(fc2t2_plan plan, const void* saved, const i
                                      int64_t R, const void* gt, const void* gn, void* gL,
                                      void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Stage entry point: one M2L launch at one level (section 3, K^{M2L}) between caller-owned
+ * grids of that level, [C][n_level^dim][P_pad] in that level's cell-scaled units
+ * (moments M[n] / h_level^|n|, locals h_level^|k| d^k f).  transpose = 0 computes
+ * out (+)= M2L(in); transpose = 1 computes the transpose out (+)= M2L^T(in).  accumulate
+ * selects += over overwrite.  For per-stage timing and custom level pipelines. */
+fc2t2_status fc2t2_m2l(fc2t2_plan plan, int level, int transpose, const void* in, void* out,
+                       int accumulate, hipStream_t stream);
+
+/* Elements of one level's grid: C * n_level^dim * P_pad (0 for an invalid level). */
+size_t fc2t2_level_numel(fc2t2_plan plan, int level);
+
 #ifdef __cplusplus
 }
 #endif

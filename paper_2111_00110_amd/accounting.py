@@ -1,0 +1,53 @@
+"""Algorithmic work of the expansion (flop and byte counts used for roofline figures).
+
+Counts are of what the method must do, not of what a kernel happens to do: unpadded
+multi-index counts P, the exact number of admissible (target cell, source cell) pairs at
+each level (parity window minus the near-field hole, clipped at the grid boundary), and
+each grid read or written once per pass.
+"""
+from __future__ import annotations
+
+from math import comb
+
+
+def n_terms(dim: int, K: int) -> int:
+    return comb(K + dim, dim)
+
+
+def _window_pairs_1d(n: int) -> int:
+    """sum over cells i of the offsets o in i's parity window with 0 <= i + o < n."""
+    tot = 0
+    for i in range(n):
+        lo, hi = (-2, 3) if i % 2 == 0 else (-3, 2)
+        tot += sum(1 for o in range(lo, hi + 1) if 0 <= i + o < n)
+    return tot
+
+
+def _hole_pairs_1d(n: int) -> int:
+    return sum(1 for i in range(n) for o in (-1, 0, 1) if 0 <= i + o < n)
+
+
+def m2l_pairs(dim: int, n_level: int, finest: bool) -> int:
+    """Admissible (target, source) cell pairs of one level."""
+    pairs = _window_pairs_1d(n_level) ** dim
+    if not finest:
+        pairs -= _hole_pairs_1d(n_level) ** dim
+    return pairs
+
+
+def levels_of(n: int) -> int:
+    lv = 0
+    while (2 << lv) < n:
+        lv += 1
+    return lv
+
+
+def m2l_flops(dim: int, n: int, K: int, channels: int = 1, level: int | None = None) -> int:
+    """Multiply-add flops (2 per term) of the forward M2L, one level or all levels."""
+    P = n_terms(dim, K)
+    lvls = range(levels_of(n)) if level is None else [level]
+    return sum(2 * P * P * channels * m2l_pairs(dim, n >> l, l == 0) for l in lvls)
+
+
+def grid_bytes(dim: int, n_level: int, K: int, channels: int = 1, itemsize: int = 4) -> int:
+    return channels * n_level ** dim * n_terms(dim, K) * itemsize

@@ -202,4 +202,16 @@ fc2t2_status fc2t2_expand_backward(fc2t2_plan plan, const void* gL, const void* 
   return launch_p2m_T(plan, GMlv[0], p, w, N, gp, gw, stream);
 }
 
+fc2t2_status fc2t2_m2l(fc2t2_plan plan, int level, int transpose, const void* in, void* out,
+                       int accumulate, hipStream_t stream) {
+  if (!plan || !in || !out || level < 0 || level >= plan->levels) return FC2T2_EINVAL;
+  return transpose ? launch_m2l_T(plan, level, in, out, accumulate != 0, stream)
+                   : launch_m2l(plan, level, in, out, accumulate != 0, stream);
+}
+
+size_t fc2t2_level_numel(fc2t2_plan plan, int level) {
+  if (!plan || level < 0 || level >= plan->levels) return 0;
+  return grid_elems(plan, level);
+}
+
 }  // extern "C"

@@ -84,6 +84,10 @@ def lib() -> ctypes.CDLL:
     L.fc2t2_ray_integral_backward.argtypes = [vp, vp, vp, dbl, dbl, i64, vp, vp, vp, sz, vp]
     L.fc2t2_ray_root.restype = i32
     L.fc2t2_ray_root.argtypes = [vp, vp, vp, vp, dbl, dbl, i64, dbl, vp, vp, vp, vp, vp]
+    L.fc2t2_m2l.restype = i32
+    L.fc2t2_m2l.argtypes = [vp, i32, i32, vp, vp, i32, vp]
+    L.fc2t2_level_numel.restype = sz
+    L.fc2t2_level_numel.argtypes = [vp, i32]
     L.fc2t2_ray_root_backward.restype = i32
     L.fc2t2_ray_root_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]
     _lib = L
@@ -167,6 +171,18 @@ class Plan:
     def workspace(self, op: str, count: int) -> torch.Tensor:
         nbytes = lib().fc2t2_workspace_size(self.handle, OP[op], int(count))
         return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+
+    def level_shape(self, level: int):
+        return (self.C, (self.n >> level) ** self.dim, self.P_pad)
+
+    def m2l(self, level: int, src: torch.Tensor, out: torch.Tensor, transpose: bool = False,
+            accumulate: bool = False):
+        """One M2L (or M2L^T) launch at a level between caller-owned grids of that level."""
+        shp = self.level_shape(level)
+        src = self._t(src, shp, "in")
+        assert out.is_contiguous() and tuple(out.shape) == shp and out.dtype == self.dtype
+        _check(lib().fc2t2_m2l(self.handle, level, int(transpose), _ptr(src), _ptr(out), int(accumulate),
+                               _stream()), "fc2t2_m2l")
 
     # ------------------------------------------------------------------ C-ABI calls
     def expand(self, p: torch.Tensor, w: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:

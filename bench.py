@@ -39,7 +39,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="explicit2d")
-    ap.add_argument("--m2l", default="f32", help="f32 | bf16 | bf16x2 | bf16x3")
+    ap.add_argument("--m2l", default="bf16x3", help="f32 | bf16 | bf16x2 | bf16x3")
+    ap.add_argument("--compare-f32", type=int, default=1,
+                    help="also time the same step with the plain FP32 M2L (same accuracy class)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=256, help="queries in the CPU sample")
     ap.add_argument("--kernel-reps", type=int, default=20)
@@ -62,41 +64,49 @@ def main():
     x = workloads.make(wl, seed=0)
     dev = torch.device("cuda", 0)
     t = {k: torch.from_numpy(v).to(dev) for k, v in x.items()}
-    t_plan0 = time.perf_counter()
-    plan = fc2t2.Plan(wl.dim, wl.n, wl.lo, wl.hi, wl.kernel, wl.param, wl.K, m2l=args.m2l, io=wl.io)
-    torch.cuda.synchronize()
-    plan_ms = (time.perf_counter() - t_plan0) * 1e3
+    def make_plan(m2l):
+        return fc2t2.Plan(wl.dim, wl.n, wl.lo, wl.hi, wl.kernel, wl.param, wl.K, m2l=m2l, io=wl.io)
 
     p, w, q, gy = t["p"], t["w"], t["q"], t["gy"]
-    Lt = plan.new_local()
-    gL = plan.new_local()
-    gq = torch.zeros_like(q)
-    gp = torch.zeros_like(p)
-    gw = torch.zeros_like(w)
 
-    def step():
-        plan.expand(p, w, out=Lt)
-        y, _, _ = plan.eval(Lt, q)
-        gL.zero_()
-        gq.zero_()
-        gp.zero_()
-        gw.zero_()
-        plan.eval_backward(Lt, q, gy, gL, gq)
-        plan.expand_backward(gL, p, w, gp, gw)
-        return y
+    def time_steps(plan, steps, warmup):
+        Lt = plan.new_local()
+        gL = plan.new_local()
+        gq = torch.zeros_like(q)
+        gp = torch.zeros_like(p)
+        gw = torch.zeros_like(w)
 
-    for _ in range(args.warmup):
-        y = step()
+        def step():
+            plan.expand(p, w, out=Lt)
+            y, _, _ = plan.eval(Lt, q)
+            gL.zero_()
+            gq.zero_()
+            gp.zero_()
+            gw.zero_()
+            plan.eval_backward(Lt, q, gy, gL, gq)
+            plan.expand_backward(gL, p, w, gp, gw)
+            return y
+
+        for _ in range(warmup):
+            y = step()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(steps):
+            y = step()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / steps, y
+
+    t_plan0 = time.perf_counter()
+    plan = make_plan(args.m2l)
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(args.steps):
-        y = step()
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
+    plan_ms = (time.perf_counter() - t_plan0) * 1e3
+    ms, y = time_steps(plan, args.steps, args.warmup)
     value = wl.M / (ms * 1e-3)
+    f32_ms = None
+    if args.compare_f32 and args.m2l != "f32":
+        f32_ms, _ = time_steps(make_plan("f32"), max(3, args.steps // 4), 1)
 
     # ---- dominant kernel: the finest-level M2L launch, timed alone with events on the
     # current stream (the stream the library launches on)
@@ -118,10 +128,13 @@ def main():
     else:
         bound, peak = "mfma", PEAKS["bf16_mfma_TFLOPs"]
     achieved = flops / (m2l_ms * 1e-3) / 1e12
+    passes = {"f32": 1, "bf16": 1, "bf16x2": 2, "bf16x3": 3}[args.m2l]
     roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": None,
-                "kernel": "m2l level 0 (finest), forward", "kernel_us": round(m2l_ms * 1e3, 2),
-                "flops_per_launch": flops}
+                "kernel": "m2l level 0 (finest), forward, %s" % args.m2l, "kernel_us": round(m2l_ms * 1e3, 2),
+                "flops_per_launch": flops, "mfma_passes": passes,
+                "mfma_issue_frac": round(achieved * passes * accounting.mfma_padding(wl.dim, wl.K) / peak, 4)
+                if bound == "mfma" else None}
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "queries/s", "n_gpus": 1,
@@ -134,6 +147,9 @@ def main():
         "roofline": roofline,
         "plan_ms": round(plan_ms, 1),
     }
+    if f32_ms is not None:
+        out["m2l_f32_comparison"] = {"value": round(wl.M / (f32_ms * 1e-3), 1), "unit": "queries/s",
+                                     "ms_per_step": round(f32_ms, 4)}
 
     # ---- CPU baseline: the FP64 direct-sum checker on a bounded sample of queries (all N
     # sources), timed on this host; the same values give the GPU's error against it.

@@ -68,7 +68,7 @@ typedef enum {
   FC2T2_M2L_F64 = 0,       /* FP64 contraction (requires FC2T2_IO_F64) */
   FC2T2_M2L_F32 = 1,       /* FP32 contraction */
   FC2T2_M2L_BF16 = 2,      /* BF16 MFMA, FP32 accumulation, one pass */
-  FC2T2_M2L_BF16X2 = 3,    /* BF16 MFMA, moments split hi/lo: two passes */
+  FC2T2_M2L_BF16X2 = 3,    /* BF16 MFMA, tensor split hi/lo: two passes */
   FC2T2_M2L_BF16X3 = 4     /* BF16 MFMA, moments and tensor split hi/lo: three passes */
 } fc2t2_m2l_prec;
 

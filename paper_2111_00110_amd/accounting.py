@@ -51,3 +51,12 @@ def m2l_flops(dim: int, n: int, K: int, channels: int = 1, level: int | None = N
 
 def grid_bytes(dim: int, n_level: int, K: int, channels: int = 1, itemsize: int = 4) -> int:
     return channels * n_level ** dim * n_terms(dim, K) * itemsize
+
+
+def mfma_padding(dim: int, K: int) -> float:
+    """Issued / useful flops of the 16x16x32 MFMA tiling: in-channels padded to a multiple
+    of 8, out-channels to a multiple of 16."""
+    P = n_terms(dim, K)
+    p8 = (P + 7) // 8 * 8
+    p16 = (P + 15) // 16 * 16
+    return p8 * p16 / (P * P)

@@ -1,11 +1,360 @@
-// BF16 MFMA M2L (placeholder until the matrix-core kernel lands).
+// M2L on the matrix cores (gfx950 v_mfma_f32_16x16x32_bf16, FP32 accumulation).
+//
+// The M2L of one level (section 3, K^{M2L}) is a convolution whose 6^d-wide window depends
+// on the parity of the target cell.  Grouping targets by parity makes it an implicit GEMM
+// per parity class:
+//     L[t, k] = sum_{(o, n)} M[t + o, n] * T_o[n, k]
+// rows t = targets of one parity, columns k = local multi-indices, reduction over the 6^d
+// admissible offsets o times the source multi-indices n.  The tensor T_o depends only on
+// the offset, so one table serves every parity; above the finest level the hole offsets
+// (|o| <= 1) hold zero blocks, so every level walks the same 6^d window.
+//
+// The transpose M2L^T has the same structure: substituting o' = -o, the source-side
+// window of a source cell's parity is again [-2, 3] (even) / [-3, 2] (odd), with the
+// tensor T'_{o'}[k, n] = T_{-o'}[n, k]; it runs the same kernel with a second table.
+//
+// Work decomposition: a workgroup owns a TPX x TPY (x TPZ) block of parent cells, i.e. all
+// 2^d children parities of it; wave w owns parity class w and RM = (parents / 16) row tiles
+// of 16 targets, for NT column tiles of 16.  The reduction runs over slices of 8 source
+// multi-indices (n8): for each slice the moments of the tile's source region
+// ((2 TP + 4)^d cells) are staged in LDS as BF16 hi and lo planes (16 B per cell each);
+// each 32-deep MFMA step takes four consecutive offsets of the parity's window (one per
+// 16-lane group).  B fragments stream from the per-level table (L2-resident).
+//
+// Precision variants: 1 pass  Mhi*Thi; 2 passes + Mhi*Tlo (the tensor's rounding dominates
+// the one-pass error); 3 passes + Mlo*Thi.
 #include "plan.h"
 
-namespace fc2t2 {
-bool m2l_mfma_supported(const fc2t2_plan_s*) { return false; }
-size_t m2l_mfma_table_bytes(const fc2t2_plan_s*) { return 0; }
-fc2t2_status m2l_mfma_build_tables(fc2t2_plan_s*, hipStream_t) { return FC2T2_EUNSUPPORTED; }
-fc2t2_status launch_m2l_mfma(const fc2t2_plan_s*, int, const void*, void*, bool, bool, hipStream_t) {
-  return FC2T2_EUNSUPPORTED;
+using namespace fc2t2;
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_bits_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  u = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+  return (unsigned short)u;
 }
+__device__ __forceinline__ float bf16_bits_to_float(unsigned short b) {
+  return __uint_as_float(((unsigned)b) << 16);
+}
+
+constexpr int ceil8(int p) { return (p + 7) / 8 * 8; }
+constexpr int ntiles(int p) { return (p + 15) / 16; }
+
+// ---------------------------------------------------------------------------------------
+// Table: [dir][plane][lvl][o in 7^D (+1 zero block)][n8][NT*16][8] bf16 bits.
+//   dir 0 (forward):   in-channel n, out-channel k, value T[lvl][o][n][k]
+//   dir 1 (transpose): in-channel k, out-channel n, value T[lvl][-o][n][k]
+// Entries are zero outside [0, P), and for hole offsets (max |o| <= 1) above the finest
+// level.  plane 0 = bf16(v), plane 1 = bf16(v - plane 0).
+__global__ void pack_mfma_table_kernel(const float* __restrict__ T, int D, int P, int Ppad, int P8,
+                                       int NTC, int levels, int n_off, unsigned short* __restrict__ out,
+                                       int64_t plane_stride, int64_t dir_stride) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per_lvl = (int64_t)(n_off + 1) * P8 * NTC;   // (o, in, out) triples
+  const int64_t total = 2 * (int64_t)levels * per_lvl;
+  if (tid >= total) return;
+  // decompose: dir, lvl, o, n8, outc, j  (in = n8*8 + j)
+  int64_t r = tid;
+  const int j = (int)(r % 8); r /= 8;
+  const int outc = (int)(r % NTC); r /= NTC;
+  const int n8 = (int)(r % (P8 / 8)); r /= (P8 / 8);
+  const int oi = (int)(r % (n_off + 1)); r /= (n_off + 1);
+  const int lvl = (int)(r % levels); r /= levels;
+  const int dir = (int)r;
+  const int inc = n8 * 8 + j;
+  float v = 0.0f;
+  if (oi < n_off && inc < P && outc < P) {
+    int o[3] = {0, 0, 0};
+    int rr = oi;
+    for (int d = D - 1; d >= 0; --d) { o[d] = rr % 7 - 3; rr /= 7; }
+    const int am = max(max(abs(o[0]), abs(o[1])), abs(o[2]));
+    if (lvl == 0 || am > 1) {
+      if (dir == 0) {
+        v = T[(((int64_t)lvl * n_off + oi) * P + inc) * Ppad + outc];
+      } else {
+        int om = 0;
+        for (int d = 0; d < D; ++d) om = om * 7 + (3 - o[d]);
+        v = T[(((int64_t)lvl * n_off + om) * P + outc) * Ppad + inc];
+      }
+    }
+  }
+  const unsigned short hi = bf16_bits_rne(v);
+  const unsigned short lo = bf16_bits_rne(v - bf16_bits_to_float(hi));
+  // destination layout index (without dir/plane)
+  const int64_t idx = ((((int64_t)lvl * (n_off + 1) + oi) * (P8 / 8) + n8) * NTC + outc) * 8 + j;
+  out[dir * dir_stride + idx] = hi;
+  out[dir * dir_stride + plane_stride + idx] = lo;
+}
+
+// ---------------------------------------------------------------------------------------
+template <int D, int P, int TPX, int TPY, int TPZ, int PASSES>
+struct Cfg {
+  static constexpr int P8 = ceil8(P);
+  static constexpr int NT = ntiles(P);
+  static constexpr int NTC = NT * 16;
+  static constexpr int NPAR = 1 << D;                 // parity classes = waves
+  static constexpr int PARENTS = TPX * TPY * TPZ;
+  static constexpr int RM = PARENTS / 16;             // row tiles per wave
+  static constexpr int SX = 2 * TPX + 4, SY = 2 * TPY + 4, SZ = D == 3 ? 2 * TPZ + 4 : 1;
+  static constexpr int CELLS = SX * SY * SZ;
+  static constexpr int WIN = D == 3 ? 216 : 36;       // 6^D admissible offsets per parity
+  static constexpr int KSTEPS = WIN / 4;
+  static constexpr int THREADS = 64 * NPAR;
+  static_assert(PARENTS % 16 == 0, "parent tile must hold a multiple of 16 parents");
+  static_assert(D == 3 || TPZ == 1, "2-D tiles have TPZ = 1");
+};
+
+template <class C>
+__global__ void __launch_bounds__(C::THREADS) m2l_mfma_kernel(
+    const float* __restrict__ Min, float* __restrict__ Lout, const unsigned short* __restrict__ Bhi,
+    const unsigned short* __restrict__ Blo, int n_l, int Ppad, int64_t G_l, int tiles_x, int tiles_y,
+    int tiles_z, int accumulate) {
+  constexpr int D = C::D_, P = C::P_;
+  constexpr int P8 = C::P8, NT = C::NT, NTC = C::NTC, RM = C::RM;
+  constexpr int SX = C::SX, SY = C::SY, SZ = C::SZ, CELLS = C::CELLS;
+  constexpr int PASSES = C::PASSES_;
+  __shared__ __attribute__((aligned(16))) unsigned short lds_hi[CELLS * 8];
+  __shared__ __attribute__((aligned(16))) unsigned short lds_lo[CELLS * 8];
+
+  const int ch = blockIdx.y;
+  // XCD-aware order: consecutive logical tiles share an XCD (dispatch is round-robin over 8)
+  const int nblk = gridDim.x;
+  int bid = blockIdx.x;
+  if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
+  const int tz = bid % tiles_z;
+  const int ty = (bid / tiles_z) % tiles_y;
+  const int tx = bid / (tiles_z * tiles_y);
+  (void)tiles_x;
+  // region origin (cell coords at this level) = 2 * parent origin - 2
+  const int rx0 = 2 * tx * C::TPX_ - 2, ry0 = 2 * ty * C::TPY_ - 2, rz0 = D == 3 ? 2 * tz * C::TPZ_ - 2 : 0;
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int px_bit = D == 3 ? (wave >> 2) & 1 : (wave >> 1) & 1;
+  const int py_bit = D == 3 ? (wave >> 1) & 1 : wave & 1;
+  const int pz_bit = D == 3 ? wave & 1 : 0;
+  const int row = lane & 15, grp = lane >> 4;
+
+  // LDS cell index of this lane's target for each row tile (A operand rows)
+  int tcell[RM];
+#pragma unroll
+  for (int m = 0; m < RM; ++m) {
+    const int p = m * 16 + row;
+    const int pz = p % C::TPZ_, py = (p / C::TPZ_) % C::TPY_, px = p / (C::TPZ_ * C::TPY_);
+    const int cx = 2 * px + px_bit + 2, cy = 2 * py + py_bit + 2, cz = D == 3 ? 2 * pz + pz_bit + 2 : 0;
+    tcell[m] = (cx * SY + cy) * SZ + cz;
+  }
+  const int wlo_x = px_bit ? -3 : -2, wlo_y = py_bit ? -3 : -2, wlo_z = pz_bit ? -3 : -2;
+
+  floatx4 acc[RM][NT];
+#pragma unroll
+  for (int m = 0; m < RM; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const float* __restrict__ Mch = Min + (int64_t)ch * G_l * Ppad;
+
+  for (int n8 = 0; n8 < P8 / 8; ++n8) {
+    // ---- stage the source region's slice [n8*8, n8*8+8) as bf16 hi / lo
+    for (int c = tid; c < CELLS; c += C::THREADS) {
+      const int cz = c % SZ, cy = (c / SZ) % SY, cx = c / (SZ * SY);
+      const int gx = rx0 + cx, gy = ry0 + cy, gz = rz0 + cz;
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = 0.f;
+      const bool inside = gx >= 0 && gx < n_l && gy >= 0 && gy < n_l && (D == 2 || (gz >= 0 && gz < n_l));
+      if (inside) {
+        const int64_t cell = D == 3 ? ((int64_t)gx * n_l + gy) * n_l + gz : (int64_t)gx * n_l + gy;
+        const float* src = Mch + cell * Ppad + n8 * 8;
+        if (n8 * 8 + 4 <= Ppad) {
+          const float4 a = *reinterpret_cast<const float4*>(src);
+          v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        }
+        if (n8 * 8 + 8 <= Ppad) {
+          const float4 b = *reinterpret_cast<const float4*>(src + 4);
+          v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+        }
+      }
+      unsigned short hi[8], lo[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        hi[j] = bf16_bits_rne(v[j]);
+        lo[j] = bf16_bits_rne(v[j] - bf16_bits_to_float(hi[j]));
+      }
+      uint4 h4, l4;
+      h4.x = hi[0] | ((unsigned)hi[1] << 16); h4.y = hi[2] | ((unsigned)hi[3] << 16);
+      h4.z = hi[4] | ((unsigned)hi[5] << 16); h4.w = hi[6] | ((unsigned)hi[7] << 16);
+      l4.x = lo[0] | ((unsigned)lo[1] << 16); l4.y = lo[2] | ((unsigned)lo[3] << 16);
+      l4.z = lo[4] | ((unsigned)lo[5] << 16); l4.w = lo[6] | ((unsigned)lo[7] << 16);
+      *reinterpret_cast<uint4*>(&lds_hi[c * 8]) = h4;
+      if constexpr (PASSES >= 3) *reinterpret_cast<uint4*>(&lds_lo[c * 8]) = l4;
+    }
+    __syncthreads();
+
+    // ---- 32-deep MFMA steps: group g of the wave takes window entry 4 * s + g
+    for (int s = 0; s < C::KSTEPS; ++s) {
+      const int e = 4 * s + grp;
+      int ex, ey, ez;
+      if constexpr (D == 3) { ez = e % 6; ey = (e / 6) % 6; ex = e / 36; }
+      else { ez = 0; ey = e % 6; ex = e / 6; }
+      const int ox = wlo_x + ex, oy = wlo_y + ey, oz = D == 3 ? wlo_z + ez : 0;
+      const int delta = (ox * SY + oy) * SZ + oz;
+      const int ob = D == 3 ? ((ox + 3) * 7 + (oy + 3)) * 7 + (oz + 3) : (ox + 3) * 7 + (oy + 3);
+      // B fragments: lanes (grp, row as column) read 8 in-channels of out-channel t*16+row
+      bf16x8 bh[NT], bl[NT];
+      const int64_t bbase = (((int64_t)ob * (P8 / 8) + n8) * NTC) * 8;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const uint4 u = *reinterpret_cast<const uint4*>(Bhi + bbase + (int64_t)(t * 16 + row) * 8);
+        bh[t] = __builtin_bit_cast(bf16x8, u);
+        if constexpr (PASSES >= 2) {
+          const uint4 w = *reinterpret_cast<const uint4*>(Blo + bbase + (int64_t)(t * 16 + row) * 8);
+          bl[t] = __builtin_bit_cast(bf16x8, w);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < RM; ++m) {
+        const int cidx = tcell[m] + delta;
+        const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&lds_hi[cidx * 8]));
+        bf16x8 al;
+        if constexpr (PASSES >= 3) al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&lds_lo[cidx * 8]));
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[t], acc[m][t], 0, 0, 0);
+          if constexpr (PASSES >= 2) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[t], acc[m][t], 0, 0, 0);
+          if constexpr (PASSES >= 3) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[t], acc[m][t], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- write: lane holds D[4*grp + i][row] of each (m, t) tile
+  float* __restrict__ Lch = Lout + (int64_t)ch * G_l * Ppad;
+#pragma unroll
+  for (int m = 0; m < RM; ++m) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int p = m * 16 + 4 * grp + i;
+      const int pz = p % C::TPZ_, py = (p / C::TPZ_) % C::TPY_, px = p / (C::TPZ_ * C::TPY_);
+      const int gx = rx0 + 2 + 2 * px + px_bit, gy = ry0 + 2 + 2 * py + py_bit;
+      const int gz = D == 3 ? rz0 + 2 + 2 * pz + pz_bit : 0;
+      if (gx >= n_l || gy >= n_l || (D == 3 && gz >= n_l)) continue;
+      const int64_t cell = D == 3 ? ((int64_t)gx * n_l + gy) * n_l + gz : (int64_t)gx * n_l + gy;
+      float* dst = Lch + cell * Ppad;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int k = t * 16 + row;
+        if (k < P) {
+          const float v = acc[m][t][i];
+          if (accumulate) dst[k] += v; else dst[k] = v;
+        } else if (k < Ppad && !accumulate) {
+          dst[k] = 0.f;
+        }
+      }
+    }
+  }
+}
+
+// Expose the template parameters under names usable inside the kernel.
+template <int D, int P, int TPX, int TPY, int TPZ, int PASSES>
+struct CfgX : Cfg<D, P, TPX, TPY, TPZ, PASSES> {
+  static constexpr int D_ = D, P_ = P, TPX_ = TPX, TPY_ = TPY, TPZ_ = TPZ, PASSES_ = PASSES;
+};
+
+template <int D, int P, int PASSES>
+struct Tile;
+// 2-D: 4 x 4 parents (64 targets, 4 waves, one 16-row tile each)
+template <int P, int PASSES>
+struct Tile<2, P, PASSES> { using type = CfgX<2, P, 4, 4, 1, PASSES>; };
+// 3-D: 4 x 2 x 2 parents (128 targets, 8 waves, one 16-row tile each)
+template <int P, int PASSES>
+struct Tile<3, P, PASSES> { using type = CfgX<3, P, 4, 2, 2, PASSES>; };
+
+template <class C>
+fc2t2_status launch_cfg(const fc2t2_plan_s* pl, int lvl, const float* in, float* out, bool accumulate,
+                        const unsigned short* Bhi, const unsigned short* Blo, hipStream_t s) {
+  const int n_l = pl->nl[lvl];
+  const int npar = n_l / 2;
+  const int tx = (npar + C::TPX_ - 1) / C::TPX_, ty = (npar + C::TPY_ - 1) / C::TPY_;
+  const int tz = C::D_ == 3 ? (npar + C::TPZ_ - 1) / C::TPZ_ : 1;
+  const dim3 grid((unsigned)(tx * ty * tz), pl->C);
+  hipLaunchKernelGGL((m2l_mfma_kernel<C>), grid, dim3(C::THREADS), 0, s, in, out, Bhi, Blo, n_l, pl->Ppad,
+                     pl->Gl[lvl], tx, ty, tz, accumulate ? 1 : 0);
+  FC2T2_LAUNCH_CHECK();
+  return FC2T2_OK;
+}
+
+struct TableGeom {
+  int P8, NTC;
+  int64_t per_lvl, plane, dir;
+};
+
+TableGeom table_geom(const fc2t2_plan_s* pl) {
+  TableGeom g;
+  g.P8 = ceil8(pl->P);
+  g.NTC = ntiles(pl->P) * 16;
+  g.per_lvl = (int64_t)(pl->n_off + 1) * g.P8 * g.NTC;
+  g.plane = g.per_lvl * pl->levels;
+  g.dir = 2 * g.plane;
+  return g;
+}
+
+}  // namespace
+
+namespace fc2t2 {
+
+bool m2l_mfma_supported(const fc2t2_plan_s* pl) {
+  return pl->io == FC2T2_IO_F32 && fc2t2_supported(pl->dim, pl->K);
+}
+
+size_t m2l_mfma_table_bytes(const fc2t2_plan_s* pl) {
+  const TableGeom g = table_geom(pl);
+  return (size_t)g.dir * 2 * sizeof(unsigned short);
+}
+
+fc2t2_status m2l_mfma_build_tables(fc2t2_plan_s* pl, hipStream_t s) {
+  const size_t bytes = m2l_mfma_table_bytes(pl);
+  if (hipMalloc(&pl->m2l_bf16, bytes) != hipSuccess) { pl->m2l_bf16 = nullptr; return FC2T2_ENOMEM; }
+  pl->m2l_bf16_bytes = bytes;
+  const TableGeom g = table_geom(pl);
+  const int64_t total = 2 * (int64_t)pl->levels * g.per_lvl;
+  hipLaunchKernelGGL(pack_mfma_table_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s,
+                     (const float*)pl->m2l_T, pl->dim, pl->P, pl->Ppad, g.P8, g.NTC, pl->levels, pl->n_off,
+                     (unsigned short*)pl->m2l_bf16, g.plane, g.dir);
+  FC2T2_LAUNCH_CHECK();
+  return FC2T2_OK;
+}
+
+fc2t2_status launch_m2l_mfma(const fc2t2_plan_s* pl, int lvl, const void* in, void* out, bool accumulate,
+                             bool transpose, hipStream_t s) {
+  if (!pl->m2l_bf16) return FC2T2_EUNSUPPORTED;
+  const TableGeom g = table_geom(pl);
+  const unsigned short* base = (const unsigned short*)pl->m2l_bf16 + (transpose ? g.dir : 0);
+  const unsigned short* Bhi = base + lvl * g.per_lvl;
+  const unsigned short* Blo = base + g.plane + lvl * g.per_lvl;
+  const float* fin = (const float*)in;
+  float* fout = (float*)out;
+  fc2t2_status st = FC2T2_EUNSUPPORTED;
+  dispatch_shape(pl->dim, pl->K, [&](auto shape) {
+    using S = decltype(shape);
+    switch (pl->prec) {
+      case FC2T2_M2L_BF16:
+        st = launch_cfg<typename Tile<S::D, S::P, 1>::type>(pl, lvl, fin, fout, accumulate, Bhi, Blo, s);
+        break;
+      case FC2T2_M2L_BF16X2:
+        st = launch_cfg<typename Tile<S::D, S::P, 2>::type>(pl, lvl, fin, fout, accumulate, Bhi, Blo, s);
+        break;
+      case FC2T2_M2L_BF16X3:
+        st = launch_cfg<typename Tile<S::D, S::P, 3>::type>(pl, lvl, fin, fout, accumulate, Bhi, Blo, s);
+        break;
+    }
+  });
+  return st;
+}
+
 }  // namespace fc2t2

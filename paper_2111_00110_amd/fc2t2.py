@@ -126,7 +126,7 @@ class Plan:
                  coef: Optional[Sequence[float]] = None, device=None):
         L = lib()
         self.dim, self.n, self.lo, self.hi, self.K = dim, n, float(lo), float(hi), K
-        self.kernel, self.param, self.m2l, self.io, self.C = kernel, float(param), m2l, io, channels
+        self.kernel, self.param, self.m2l_prec, self.io, self.C = kernel, float(param), m2l, io, channels
         self.dtype = torch.float64 if io == "f64" else torch.float32
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         g = _Grid(dim, n, self.lo, self.hi)

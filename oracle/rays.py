@@ -12,7 +12,10 @@
 * Ray root (section 5.1.2): tau = frac * max of f along the clipped ray, then the first
   parameter where f - tau changes sign from - to +, cell by cell in ray order.  A root on
   a cell face belongs to the earlier cell; tangent roots are ignored; a ray with
-  f - tau >= 0 at entry or without a crossing is dead.
+  f - tau >= 0 at entry or without a crossing is dead.  The expansion is piecewise
+  (one polynomial per cell), so f can jump across a face: when the previous segment ends
+  below tau and the next starts at or above it, the crossing is the face itself and
+  belongs to the earlier cell.
 * Ray-root backward (section 5.2, implicit function theorem): with t_bar and n_bar the
   cotangents of the root t* and of the surface gradient grad f(q*), the cotangent of the
   finest locals is a (q* - c)^k / k! + sum_j n_bar_j d/dq_j (q* - c)^k / k! with
@@ -210,19 +213,25 @@ def ray_root(geo: fmm.Geometry, L0: np.ndarray, o, r, t0, t1, frac: float = 0.5,
         res["tau"][ri] = tau
         if npoly.polyval(0.0, polys[0]) - tau >= 0.0:
             continue
+        prev = None                       # (end value, cell, tb) of the previous segment
         for c, (cell, ta, tb) in zip(polys, segs):
             g = c.copy()
             g[0] -= tau
-            u = first_upward_root(g, tb - ta)
-            if u is None:
-                continue
-            t = ta + u
+            if prev is not None and prev[0] < 0.0 <= npoly.polyval(0.0, g):
+                # the crossing happens across the face: it lies on the face, earlier cell
+                t, rcell = prev[2], prev[1]
+            else:
+                u = first_upward_root(g, tb - ta)
+                if u is None:
+                    prev = (npoly.polyval(tb - ta, g), cell, tb)
+                    continue
+                t, rcell = ta + u, cell
             q = np.asarray(o[ri], dtype=np.float64) + t * np.asarray(r[ri], dtype=np.float64)
-            dq = q - geo.centre(0, np.asarray(cell))
-            row = L0[(0,) + cell]
+            dq = q - geo.centre(0, np.asarray(rcell))
+            row = L0[(0,) + rcell]
             res["t"][ri] = t
             res["hit"][ri] = 1
-            res["cell"][ri] = cell
+            res["cell"][ri] = rcell
             res["normal"][ri] = row @ fmm.monomial_grads(dq[None], geo.idx)[0]
             res["hess"][ri] = np.einsum("p,pab->ab", row,
                                         fmm.monomial_hessians(dq[None], geo.idx)[0])

@@ -151,7 +151,7 @@ fc2t2_status fc2t2_expand(fc2t2_plan plan, const void* p, const void* w, int64_t
   carve_pyramid(c, plan, 1, Llv);
   fc2t2_status st = bin_and_sort(plan, p, N, sb, stream);
   if (st) return st;
-  st = launch_p2m(plan, p, w, sb.starts, sb.perm, Mlv[0], stream);
+  st = launch_p2m(plan, p, w, N, sb.starts, sb.perm, Mlv[0], stream);
   if (st) return st;
   return expand_from_moments(plan, Mlv, Llv, L, stream);
 }
@@ -177,7 +177,7 @@ fc2t2_status fc2t2_eval_backward(fc2t2_plan plan, const void* L, const void* q, 
     SortBufs sb = carve_sort(c, plan, M);
     fc2t2_status st = bin_and_sort(plan, q, M, sb, stream);
     if (st) return st;
-    st = launch_l2p_T(plan, q, gy, sb.starts, sb.perm, gL, stream);
+    st = launch_l2p_T(plan, q, gy, M, sb.starts, sb.perm, gL, stream);
     if (st) return st;
   }
   if (gq) return launch_l2p_qgrad(plan, L, q, M, gy, gq, stream);

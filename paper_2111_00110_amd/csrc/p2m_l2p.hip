@@ -10,6 +10,7 @@
 // strides over its points in input order with TwoSum-compensated accumulation, combines
 // the lanes with xor shuffles, and writes the cell's row.  No atomics.
 #include "plan.h"
+#include "segreduce.h"
 
 using namespace fc2t2;
 
@@ -36,19 +37,6 @@ __device__ __forceinline__ void load_row(const T* __restrict__ src, T (&c)[Ppad]
   }
 }
 
-template <int D, typename T>
-__device__ __forceinline__ void decode_cell(int64_t cell, int n, int (&ic)[3]) {
-  ic[0] = ic[1] = ic[2] = 0;
-  if constexpr (D == 2) {
-    ic[1] = (int)(cell % n);
-    ic[0] = (int)(cell / n);
-  } else {
-    ic[2] = (int)(cell % n);
-    ic[1] = (int)((cell / n) % n);
-    ic[0] = (int)(cell / ((int64_t)n * n));
-  }
-}
-
 template <class S, typename T>
 struct PointMonomials {
   const T* __restrict__ x;     // [count][D]
@@ -67,77 +55,15 @@ struct PointMonomials {
   }
 };
 
-// out[ch][cell][:] (+)= sum over the cell's sorted records of fn(record).
-template <class S, typename T, int GROUP, class F>
-__global__ void __launch_bounds__(256) reduce_cells_kernel(const uint32_t* __restrict__ starts,
-                                                           const uint32_t* __restrict__ perm,
-                                                           int64_t G, int n, T lo, T h,
-                                                           T* __restrict__ out, int accumulate, F fn) {
-  constexpr int P = S::P, Ppad = S::Ppad, D = S::D;
-  const int lane_g = threadIdx.x & (GROUP - 1);
-  const int ch = blockIdx.y;
-  const int64_t groups = (int64_t)gridDim.x * (blockDim.x / GROUP);
-  T* __restrict__ base = out + (int64_t)ch * G * Ppad;
-  for (int64_t cell = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GROUP; cell < G; cell += groups) {
-    const uint32_t b = starts[cell], e = starts[cell + 1];
-    int ic[3];
-    decode_cell<D, T>(cell, n, ic);
-    T centre[3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) centre[j] = lo + (T(ic[j]) + T(0.5)) * h;
-    T s[P], c[P];
-#pragma unroll
-    for (int k = 0; k < P; ++k) { s[k] = T(0); c[k] = T(0); }
-    for (uint32_t r = b + lane_g; r < e; r += GROUP) {
-      T v[P];
-      fn(perm[r], centre, ch, v);
-#pragma unroll
-      for (int k = 0; k < P; ++k) acc2(s[k], c[k], v[k]);
-    }
-#pragma unroll
-    for (int off = GROUP / 2; off >= 1; off >>= 1) {
-#pragma unroll
-      for (int k = 0; k < P; ++k) {
-        const T so = __shfl_xor(s[k], off);
-        const T co = __shfl_xor(c[k], off);
-        acc2(s[k], c[k], so);
-        c[k] += co;
-      }
-    }
-    T* __restrict__ dst = base + cell * Ppad;
-#pragma unroll
-    for (int k = 0; k < Ppad; ++k) {
-      if ((k & (GROUP - 1)) == lane_g) {
-        const T v = k < P ? s[k] + c[k] : T(0);
-        if (accumulate) dst[k] += v; else dst[k] = v;
-      }
-    }
-  }
-}
-
-template <class S, typename T, int GROUP>
-fc2t2_status launch_reduce_points(const fc2t2_plan_s* pl, const T* x, const T* wt,
-                                  const uint32_t* starts, const uint32_t* perm, T* out,
-                                  bool accumulate, hipStream_t s) {
-  PointMonomials<S, T> fn{x, wt, pl->C, (T)(1.0 / pl->h0)};
-  const int threads = 256;
-  const int64_t need = ceil_div(pl->G * GROUP, threads);
-  const int64_t blocks = need < 8192 ? need : 8192;
-  hipLaunchKernelGGL((reduce_cells_kernel<S, T, GROUP, PointMonomials<S, T>>),
-                     dim3((unsigned)blocks, pl->C), dim3(threads), 0, s, starts, perm, pl->G, pl->n,
-                     (T)pl->lo, (T)pl->h0, out, accumulate ? 1 : 0, fn);
-  FC2T2_LAUNCH_CHECK();
-  return FC2T2_OK;
-}
-
 template <typename T>
-fc2t2_status reduce_points(const fc2t2_plan_s* pl, const void* x, const void* wt, const uint32_t* starts,
-                           const uint32_t* perm, void* out, bool accumulate, hipStream_t s) {
+fc2t2_status reduce_points(const fc2t2_plan_s* pl, const void* x, const void* wt, int64_t count,
+                           const uint32_t* starts, const uint32_t* perm, void* out, bool accumulate,
+                           hipStream_t s) {
   fc2t2_status st = FC2T2_EUNSUPPORTED;
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {
     using S = decltype(shape);
-    st = launch_reduce_points<S, T, 16>(pl, (const T*)x, (const T*)wt, starts, perm, (T*)out,
-                                        accumulate, s);
+    PointMonomials<S, T> fn{(const T*)x, (const T*)wt, pl->C, (T)(1.0 / pl->h0)};
+    st = launch_reduce_cells<S, T>(pl, starts, perm, count, (T*)out, accumulate, fn, s);
   });
   return st;
 }
@@ -244,16 +170,16 @@ fc2t2_status gather_eval(const fc2t2_plan_s* pl, const void* grid, const void* x
 
 namespace fc2t2 {
 
-fc2t2_status launch_p2m(const fc2t2_plan_s* pl, const void* p, const void* w, const uint32_t* starts,
-                        const uint32_t* perm, void* M0, hipStream_t s) {
-  return pl->io == FC2T2_IO_F64 ? reduce_points<double>(pl, p, w, starts, perm, M0, false, s)
-                                : reduce_points<float>(pl, p, w, starts, perm, M0, false, s);
+fc2t2_status launch_p2m(const fc2t2_plan_s* pl, const void* p, const void* w, int64_t N,
+                        const uint32_t* starts, const uint32_t* perm, void* M0, hipStream_t s) {
+  return pl->io == FC2T2_IO_F64 ? reduce_points<double>(pl, p, w, N, starts, perm, M0, false, s)
+                                : reduce_points<float>(pl, p, w, N, starts, perm, M0, false, s);
 }
 
-fc2t2_status launch_l2p_T(const fc2t2_plan_s* pl, const void* q, const void* gy, const uint32_t* starts,
-                          const uint32_t* perm, void* gL, hipStream_t s) {
-  return pl->io == FC2T2_IO_F64 ? reduce_points<double>(pl, q, gy, starts, perm, gL, true, s)
-                                : reduce_points<float>(pl, q, gy, starts, perm, gL, true, s);
+fc2t2_status launch_l2p_T(const fc2t2_plan_s* pl, const void* q, const void* gy, int64_t M,
+                          const uint32_t* starts, const uint32_t* perm, void* gL, hipStream_t s) {
+  return pl->io == FC2T2_IO_F64 ? reduce_points<double>(pl, q, gy, M, starts, perm, gL, true, s)
+                                : reduce_points<float>(pl, q, gy, M, starts, perm, gL, true, s);
 }
 
 fc2t2_status launch_l2p(const fc2t2_plan_s* pl, const void* L, const void* q, int64_t M, void* y,

@@ -50,10 +50,10 @@ int key_bits_for(int64_t G);
 
 // ---- p2m_l2p.hip
 // P2M: M0 = moments of the sorted sources (overwrite).
-fc2t2_status launch_p2m(const fc2t2_plan_s* pl, const void* p, const void* w, const uint32_t* starts,
-                        const uint32_t* perm, void* M0, hipStream_t s);
+fc2t2_status launch_p2m(const fc2t2_plan_s* pl, const void* p, const void* w, int64_t N,
+                        const uint32_t* starts, const uint32_t* perm, void* M0, hipStream_t s);
 // Transpose of L2P: gL += sum over the sorted queries of gy (q - c)^k / k!.
-fc2t2_status launch_l2p_T(const fc2t2_plan_s* pl, const void* q, const void* gy,
+fc2t2_status launch_l2p_T(const fc2t2_plan_s* pl, const void* q, const void* gy, int64_t M,
                           const uint32_t* starts, const uint32_t* perm, void* gL, hipStream_t s);
 // L2P: y (overwrite), grad/hess (overwrite, optional).
 fc2t2_status launch_l2p(const fc2t2_plan_s* pl, const void* L, const void* q, int64_t M, void* y,

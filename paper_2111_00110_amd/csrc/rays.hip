@@ -1,26 +1,818 @@
-// Ray layers (placeholder).
+// Ray layers on the finest-level local expansions (dim 3):
+//   line integral        y = integral over t of f(o + t r)            (section 6.1.1)
+//   ray insertion        G_L[c] += gy * int_0^s (d + r v)^k / k! dv   (section 6.2.1)
+//   first level crossing of f along the ray and its IFT backward     (sections 5.1, 5.2)
+//
+// Traversal: the ray is clipped to the domain and [t0, t1], then walked cell by cell with
+// an incremental 3-D DDA in FP64 whose plane crossings are recomputed from the plane
+// position at every step (lo + k h - o) / r, so they do not drift.  Inside a cell with
+// centre c the expansion restricted to the segment is a polynomial in v = t - t_a with
+// u(v) = (o + t_a r - c) / h + v r / h (line to polynomial, section 5.1.1).
+//
+// MI355X note: without packed FP32 the vector FP32 and FP64 rates are equal, so the
+// per-segment polynomial work (line integrals, root isolation) runs in FP64; only the
+// expansion rows are FP32.
+#include <math.h>
+
 #include "plan.h"
+#include "segreduce.h"
+
+using namespace fc2t2;
+
+namespace {
+
+constexpr int kRaySaved = FC2T2_ROOT_SAVED;
+
+// ---------------------------------------------------------------------------------------
+struct Dda {
+  double o[3], r[3];
+  double lo, h;
+  int n;
+  double t, t_end;
+  int c[3], step[3];
+  double tmax[3];
+  bool live;
+
+  __device__ double next_plane(int j) const {
+    if (step[j] == 0) return INFINITY;
+    const int k = step[j] > 0 ? c[j] + 1 : c[j];
+    return (lo + (double)k * h - o[j]) / r[j];
+  }
+
+  __device__ void init(const double (&o_)[3], const double (&r_)[3], double t0, double t1, double lo_,
+                       double hi_, double h_, int n_) {
+    lo = lo_;
+    h = h_;
+    n = n_;
+    double ta = t0, tb = t1;
+    live = true;
+    for (int j = 0; j < 3; ++j) {
+      o[j] = o_[j];
+      r[j] = r_[j];
+      if (r[j] == 0.0) {
+        if (o[j] < lo_ || o[j] > hi_) live = false;
+      } else {
+        const double a = (lo_ - o[j]) / r[j], b = (hi_ - o[j]) / r[j];
+        ta = fmax(ta, fmin(a, b));
+        tb = fmin(tb, fmax(a, b));
+      }
+    }
+    if (!(tb > ta)) live = false;
+    t = ta;
+    t_end = tb;
+    for (int j = 0; j < 3; ++j) {
+      step[j] = r[j] > 0.0 ? 1 : (r[j] < 0.0 ? -1 : 0);
+      const double x = o[j] + ta * r[j];
+      int cj = (int)floor((x - lo) / h);
+      c[j] = cj < 0 ? 0 : (cj > n - 1 ? n - 1 : cj);
+      tmax[j] = next_plane(j);
+      // the entry point can sit on a plane: move past planes that lie at or behind ta
+      for (int guard = 0; guard < 2 && step[j] != 0 && tmax[j] <= ta; ++guard) {
+        const int nc = c[j] + step[j];
+        if (nc < 0 || nc > n - 1) break;
+        c[j] = nc;
+        tmax[j] = next_plane(j);
+      }
+    }
+  }
+
+  // Next segment of positive length: cell index (row-major) and [ta, tb].
+  __device__ bool next(int64_t& cell, int (&cc)[3], double& ta, double& tb) {
+    while (live && t < t_end) {
+      int j = 0;
+      if (tmax[1] < tmax[j]) j = 1;
+      if (tmax[2] < tmax[j]) j = 2;
+      const double tn = fmin(tmax[j], t_end);
+      const double t_prev = t;
+      cc[0] = c[0]; cc[1] = c[1]; cc[2] = c[2];
+      t = tn;
+      if (tn < t_end) {
+        const int nc = c[j] + step[j];
+        if (nc < 0 || nc > n - 1) live = false;
+        else { c[j] = nc; tmax[j] = next_plane(j); }
+      } else {
+        live = false;
+      }
+      if (tn > t_prev) {
+        cell = ((int64_t)cc[0] * n + cc[1]) * n + cc[2];
+        ta = t_prev;
+        tb = tn;
+        return true;
+      }
+    }
+    return false;
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ void load3(const T* p, int64_t i, double (&v)[3]) {
+  v[0] = (double)p[3 * i];
+  v[1] = (double)p[3 * i + 1];
+  v[2] = (double)p[3 * i + 2];
+}
+
+// Three-point Gauss-Legendre rule on [0, s]: nodes s (1 + x_i) / 2 with x = 0, +-sqrt(3/5),
+// weights (s / 2) * (8/9, 5/9, 5/9).  Exact for polynomials of degree <= 5, so for every
+// monomial of an expansion with K <= 5 it gives the segment integral exactly (up to
+// rounding) -- the same value as integrating the line polynomial term by term.
+__device__ __forceinline__ void gl3(double s, double (&v)[3], double (&wt)[3]) {
+  const double x = 0.7745966692414833770;   // sqrt(3/5)
+  v[0] = 0.5 * s;
+  v[1] = 0.5 * s * (1.0 - x);
+  v[2] = 0.5 * s * (1.0 + x);
+  wt[0] = 0.5 * s * (8.0 / 9.0);
+  wt[1] = 0.5 * s * (5.0 / 9.0);
+  wt[2] = wt[1];
+}
+
+// Integral over v in [0, s] of prod_j (d_j + q_j v)^e_j / e_j!  (one multi-index, |e| <= 5).
+__device__ double seg_integral(const int (&e)[3], const double (&d)[3], const double (&q)[3], double s) {
+  double v[3], wt[3];
+  gl3(s, v, wt);
+  double acc = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    double m = 1.0;
+    for (int j = 0; j < 3; ++j) {
+      const double x = d[j] + q[j] * v[i];
+      for (int a = 1; a <= e[j]; ++a) m *= x / a;
+    }
+    acc += wt[i] * m;
+  }
+  return acc;
+}
+
+// Exponents of the lane's multi-index in the graded order (lane < P).
+template <int D, int K>
+__device__ void lane_exponents(int lane, int (&e)[3]) {
+  int idx = 0;
+  e[0] = e[1] = e[2] = 0;
+  for (int t = 0; t <= K; ++t)
+    for (int a = t; a >= 0; --a)
+      for (int b = t - a; b >= 0; --b) {
+        if (idx == lane) { e[0] = a; e[1] = b; e[2] = t - a - b; }
+        ++idx;
+      }
+}
+
+// ---------------------------------------------------------------------------------------
+// Line integral: one wavefront per ray, lane k accumulates L[c, k] * I_k over the segments.
+template <class S, typename T>
+__global__ void __launch_bounds__(256) ray_integral_kernel(const T* __restrict__ L, const T* __restrict__ O,
+                                                           const T* __restrict__ Rd, int64_t R, double t0,
+                                                           double t1, double lo, double hi, double h, int n,
+                                                           int64_t G, T* __restrict__ y, int C) {
+  constexpr int P = S::P, Ppad = S::Ppad;
+  const int lane = threadIdx.x & 63;
+  const int64_t ray = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int ch = blockIdx.y;
+  if (ray >= R) return;
+  int e[3];
+  lane_exponents<S::D, S::K>(lane < P ? lane : 0, e);
+  double o[3], r[3];
+  load3(O, ray, o);
+  load3(Rd, ray, r);
+  Dda dda;
+  dda.init(o, r, t0, t1, lo, hi, h, n);
+  const double q[3] = {r[0] / h, r[1] / h, r[2] / h};
+  const T* __restrict__ Lc = L + (int64_t)ch * G * Ppad;
+  double acc = 0.0;
+  int64_t cell;
+  int cc[3];
+  double ta, tb;
+  while (dda.next(cell, cc, ta, tb)) {
+    if (lane < P) {
+      double d[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) d[j] = (o[j] + ta * r[j] - (lo + (cc[j] + 0.5) * h)) / h;
+      acc += (double)Lc[cell * Ppad + lane] * seg_integral(e, d, q, tb - ta);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) y[ray * C + ch] = (T)acc;
+}
+
+// ---------------------------------------------------------------------------------------
+// Ray insertion records: slot ray * maxseg + j holds segment j of the ray (its cell as the
+// sort key, [ta, tb] as payload); unused slots get the key G (sorted after every cell).
+template <typename T>
+__global__ void __launch_bounds__(256) ray_records_kernel(const T* __restrict__ O, const T* __restrict__ Rd,
+                                                          int64_t R, double t0, double t1, double lo, double hi,
+                                                          double h, int n, int64_t G, int maxseg,
+                                                          uint32_t* __restrict__ keys, double2* __restrict__ rec) {
+  const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ray >= R) return;
+  double o[3], r[3];
+  load3(O, ray, o);
+  load3(Rd, ray, r);
+  Dda dda;
+  dda.init(o, r, t0, t1, lo, hi, h, n);
+  int64_t cell;
+  int cc[3];
+  double ta, tb;
+  int j = 0;
+  const int64_t base = ray * maxseg;
+  while (j < maxseg && dda.next(cell, cc, ta, tb)) {
+    keys[base + j] = (uint32_t)cell;
+    rec[base + j] = make_double2(ta, tb);
+    ++j;
+  }
+  for (; j < maxseg; ++j) keys[base + j] = (uint32_t)G;
+}
+
+template <class S, typename T>
+struct SegmentInsert {
+  static_assert(S::K <= 5, "three Gauss-Legendre nodes integrate degree <= 5 exactly");
+  const T* __restrict__ O;
+  const T* __restrict__ Rd;
+  const double2* __restrict__ rec;
+  const T* __restrict__ gy;
+  int maxseg, C;
+  double h;
+  __device__ __forceinline__ void operator()(uint32_t slot, const T (&centre)[3], int ch, T (&v)[S::P]) const {
+    const int64_t ray = slot / maxseg;
+    double o[3], r[3];
+    load3(O, ray, o);
+    load3(Rd, ray, r);
+    const double2 tt = rec[slot];
+    double d[3], q[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      d[j] = (o[j] + tt.x * r[j] - (double)centre[j]) / h;
+      q[j] = r[j] / h;
+    }
+    double nodes[3], wt[3];
+    gl3(tt.y - tt.x, nodes, wt);
+    const double g = (double)gy[ray * C + ch];
+#pragma unroll
+    for (int k = 0; k < S::P; ++k) v[k] = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      T u[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) u[j] = (T)(d[j] + q[j] * nodes[i]);
+      T m[S::P];
+      monomials<S>(u, m);
+      const T a = (T)(g * wt[i]);
+#pragma unroll
+      for (int k = 0; k < S::P; ++k) v[k] += a * m[k];
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------------------
+// Real-root isolation for polynomials of degree <= 5 on [a, b] (FP64): the roots of the
+// derivative split [a, b] into monotone pieces; each piece with a sign change holds one
+// root, found by Newton steps safeguarded by bisection.
+template <int DEG>
+__device__ __forceinline__ double peval(const double (&c)[6], double x) {
+  double v = c[DEG];
+#pragma unroll
+  for (int m = DEG - 1; m >= 0; --m) v = v * x + c[m];
+  return v;
+}
+
+template <int DEG>
+__device__ double solve_monotone(const double (&c)[6], double lo, double hi, double flo) {
+  double dc[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int m = 0; m < DEG; ++m) dc[m] = (m + 1) * c[m + 1];
+  double x = 0.5 * (lo + hi);
+  for (int it = 0; it < 200; ++it) {
+    const double fx = peval<DEG>(c, x);
+    if (fx == 0.0) return x;
+    if ((fx < 0.0) == (flo < 0.0)) { lo = x; flo = fx; } else { hi = x; }
+    const double dfx = peval<(DEG >= 1 ? DEG - 1 : 0)>(dc, x);
+    double xn = x - fx / dfx;
+    if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+    const double tol = 4e-16 * fmax(1.0, fabs(x));
+    if (fabs(xn - x) <= tol || hi - lo <= tol) return xn;
+    x = xn;
+  }
+  return x;
+}
+
+// Sign-changing roots of c (degree <= DEG) in [a, b], ascending.  Returns the count.
+template <int DEG>
+__device__ int real_roots(const double (&c)[6], double a, double b, double (&out)[5]) {
+  if constexpr (DEG <= 0) {
+    return 0;
+  } else {
+    if (c[DEG] == 0.0) return real_roots<DEG - 1>(c, a, b, out);
+    if constexpr (DEG == 1) {
+      const double x = -c[0] / c[1];
+      if (a <= x && x <= b) { out[0] = x; return 1; }
+      return 0;
+    } else {
+      double dc[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int m = 0; m < DEG; ++m) dc[m] = (m + 1) * c[m + 1];
+      double crit[5];
+      const int nc = real_roots<DEG - 1>(dc, a, b, crit);
+      double pts[7];
+      int np = 0;
+      pts[np++] = a;
+      for (int i = 0; i < nc; ++i)
+        if (crit[i] > a && crit[i] < b && crit[i] > pts[np - 1]) pts[np++] = crit[i];
+      pts[np++] = b;
+      int cnt = 0;
+      double f0 = peval<DEG>(c, pts[0]);
+      for (int i = 0; i + 1 < np; ++i) {
+        const double f1 = peval<DEG>(c, pts[i + 1]);
+        if (f0 == 0.0) {
+          if (cnt == 0 || out[cnt - 1] != pts[i]) out[cnt++] = pts[i];
+        } else if ((f0 < 0.0) != (f1 < 0.0) && f1 != 0.0) {
+          out[cnt++] = solve_monotone<DEG>(c, pts[i], pts[i + 1], f0);
+        }
+        f0 = f1;
+      }
+      if (f0 == 0.0 && (cnt == 0 || out[cnt - 1] != b)) out[cnt++] = b;
+      return cnt;
+    }
+  }
+}
+
+// Segment polynomial a(v) = sum_k L[k] ((d + q v)^k / k!) as coefficients (degree <= K).
+template <class S>
+__device__ void line2poly(const double* Lrow, const double (&d)[3], const double (&q)[3], double (&a)[6]) {
+  constexpr int K = S::K;
+  double F[3][K + 1][K + 1];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+#pragma unroll
+    for (int p = 0; p <= K; ++p)
+#pragma unroll
+      for (int m = 0; m <= K; ++m) F[j][p][m] = 0.0;
+    F[j][0][0] = 1.0;
+#pragma unroll
+    for (int p = 1; p <= K; ++p)
+#pragma unroll
+      for (int m = 0; m <= K; ++m)
+        F[j][p][m] = ((m <= p - 1 ? F[j][p - 1][m] * d[j] : 0.0) + (m >= 1 ? F[j][p - 1][m - 1] * q[j] : 0.0)) / p;
+  }
+#pragma unroll
+  for (int m = 0; m < 6; ++m) a[m] = 0.0;
+#pragma unroll
+  for (int p0 = 0; p0 <= K; ++p0)
+#pragma unroll
+    for (int p1 = 0; p0 + p1 <= K; ++p1) {
+      // inner sum over the third exponent: sum_p2 L[p0,p1,p2] F2[p2]
+      double inner[K + 1];
+#pragma unroll
+      for (int m = 0; m <= K; ++m) inner[m] = 0.0;
+#pragma unroll
+      for (int p2 = 0; p0 + p1 + p2 <= K; ++p2) {
+        const double l = Lrow[mi_pos3(p0, p1, p2)];
+#pragma unroll
+        for (int m = 0; m <= p2; ++m) inner[m] += l * F[2][p2][m];
+      }
+      // times F0[p0] * F1[p1]
+#pragma unroll
+      for (int m0 = 0; m0 <= p0; ++m0)
+#pragma unroll
+        for (int m1 = 0; m1 <= p1; ++m1) {
+          const double f = F[0][p0][m0] * F[1][p1][m1];
+#pragma unroll
+          for (int m2 = 0; m0 + m1 + m2 <= K; ++m2) a[m0 + m1 + m2] += f * inner[m2];
+        }
+    }
+}
+
+template <class S, typename T>
+__device__ __forceinline__ void load_row_f64(const T* __restrict__ src, double (&c)[S::P]) {
+#pragma unroll
+  for (int k = 0; k < S::P; ++k) c[k] = (double)src[k];
+}
+
+template <class S>
+__device__ double seg_max(const double (&a)[6], double s) {
+  constexpr int K = S::K;
+  double best = fmax(peval<K>(a, 0.0), peval<K>(a, s));
+  double da[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int m = 0; m < K; ++m) da[m] = (m + 1) * a[m + 1];
+  double crit[5];
+  const int nc = real_roots<K - 1>(da, 0.0, s, crit);
+  for (int i = 0; i < nc; ++i) best = fmax(best, peval<K>(a, crit[i]));
+  return best;
+}
+
+// First v in (0, s] where g = a - tau goes from < 0 to >= 0 on a monotone piece; -1 if none.
+template <class S>
+__device__ double first_upward(const double (&g)[6], double s) {
+  constexpr int K = S::K;
+  double dg[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int m = 0; m < K; ++m) dg[m] = (m + 1) * g[m + 1];
+  double crit[5];
+  const int nc = real_roots<K - 1>(dg, 0.0, s, crit);
+  double pts[7];
+  int np = 0;
+  pts[np++] = 0.0;
+  for (int i = 0; i < nc; ++i)
+    if (crit[i] > 0.0 && crit[i] < s && crit[i] > pts[np - 1]) pts[np++] = crit[i];
+  pts[np++] = s;
+  double f0 = peval<K>(g, 0.0);
+  for (int i = 0; i + 1 < np; ++i) {
+    const double f1 = peval<K>(g, pts[i + 1]);
+    if (f0 < 0.0 && f1 >= 0.0) {
+      if (f1 == 0.0) return pts[i + 1];
+      return solve_monotone<K>(g, pts[i], pts[i + 1], f0);
+    }
+    f0 = f1;
+  }
+  return -1.0;
+}
+
+// Ray root: one thread per ray.  Pass 1 finds max f along the clipped ray, pass 2 walks the
+// segments again for the first upward crossing of tau = frac * max.  A crossing that
+// happens across a face (previous segment ends below tau, this one starts at or above)
+// lies on the face and belongs to the earlier cell.
+template <class S, typename T>
+__global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, const T* __restrict__ O,
+                                                      const T* __restrict__ Rd, int64_t R, double t0, double t1,
+                                                      double lo, double hi, double h, int n, double frac,
+                                                      T* __restrict__ t_out, T* __restrict__ normal,
+                                                      int32_t* __restrict__ hit, T* __restrict__ saved) {
+  constexpr int P = S::P, Ppad = S::Ppad, K = S::K;
+  const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ray >= R) return;
+  double o[3], r[3];
+  load3(O, ray, o);
+  load3(Rd, ray, r);
+  const double q[3] = {r[0] / h, r[1] / h, r[2] / h};
+  int64_t cell;
+  int cc[3];
+  double ta, tb;
+  // ---- pass 1: max of f along the ray
+  double fmax_v = -INFINITY;
+  bool any = false;
+  {
+    Dda dda;
+    dda.init(o, r, t0, t1, lo, hi, h, n);
+    while (dda.next(cell, cc, ta, tb)) {
+      double row[P];
+      load_row_f64<S>(L + cell * Ppad, row);
+      double d[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) d[j] = (o[j] + ta * r[j] - (lo + (cc[j] + 0.5) * h)) / h;
+      double a[6];
+      line2poly<S>(row, d, q, a);
+      fmax_v = fmax(fmax_v, seg_max<S>(a, tb - ta));
+      any = true;
+    }
+  }
+  const double tau = frac * fmax_v;
+  double t_star = NAN;
+  int found = 0;
+  int rc[3] = {0, 0, 0};
+  int64_t rcell = 0;
+  if (any) {
+    Dda dda;
+    dda.init(o, r, t0, t1, lo, hi, h, n);
+    bool first = true;
+    double prev_end = 0.0, prev_ta = 0.0, prev_s = 0.0;
+    int pc[3] = {0, 0, 0};
+    int64_t pcell = 0;
+    while (dda.next(cell, cc, ta, tb)) {
+      double row[P];
+      load_row_f64<S>(L + cell * Ppad, row);
+      double d[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) d[j] = (o[j] + ta * r[j] - (lo + (cc[j] + 0.5) * h)) / h;
+      double g[6];
+      line2poly<S>(row, d, q, g);
+      g[0] -= tau;
+      const double s = tb - ta;
+      const double g0 = peval<K>(g, 0.0);
+      if (first) {
+        if (g0 >= 0.0) break;                       // at or above the level at entry: dead ray
+        first = false;
+      } else if (prev_end < 0.0 && g0 >= 0.0) {     // crossing on the face: earlier cell
+        t_star = prev_ta + prev_s;
+        rc[0] = pc[0]; rc[1] = pc[1]; rc[2] = pc[2];
+        rcell = pcell;
+        found = 1;
+        break;
+      }
+      const double v = first_upward<S>(g, s);
+      if (v >= 0.0) {
+        t_star = ta + v;
+        rc[0] = cc[0]; rc[1] = cc[1]; rc[2] = cc[2];
+        rcell = cell;
+        found = 1;
+        break;
+      }
+      prev_end = peval<K>(g, s);
+      prev_ta = ta;
+      prev_s = s;
+      pc[0] = cc[0]; pc[1] = cc[1]; pc[2] = cc[2];
+      pcell = cell;
+    }
+  }
+  double gout[3] = {0.0, 0.0, 0.0}, hr[3] = {0.0, 0.0, 0.0}, qs[3] = {0.0, 0.0, 0.0}, rdg = 0.0;
+  if (found) {
+    double row[P];
+    load_row_f64<S>(L + rcell * Ppad, row);
+    double u[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      qs[j] = o[j] + t_star * r[j];
+      u[j] = (qs[j] - (lo + (rc[j] + 0.5) * h)) / h;
+    }
+    double pw[3][K + 1];
+    power_table<S>(u, pw);
+    double val, g[3], hs[6];
+    eval_poly<S, double, true, true>(row, pw, val, g, hs);
+    const double ih = 1.0 / h;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) gout[j] = g[j] * ih;
+    const double H[3][3] = {{hs[0], hs[1], hs[2]}, {hs[1], hs[3], hs[4]}, {hs[2], hs[4], hs[5]}};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) hr[j] = (H[j][0] * r[0] + H[j][1] * r[1] + H[j][2] * r[2]) * ih * ih;
+    rdg = r[0] * gout[0] + r[1] * gout[1] + r[2] * gout[2];
+  }
+  t_out[ray] = (T)t_star;
+  hit[ray] = found;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) normal[ray * 3 + j] = (T)gout[j];
+  T* sv = saved + ray * kRaySaved;
+  sv[0] = (T)qs[0]; sv[1] = (T)qs[1]; sv[2] = (T)qs[2];
+  sv[3] = (T)(double)rcell;
+  sv[4] = (T)rdg;
+  sv[5] = (T)hr[0]; sv[6] = (T)hr[1]; sv[7] = (T)hr[2];
+  sv[8] = (T)tau;
+  sv[9] = (T)t_star;
+  sv[10] = T(0);
+  sv[11] = T(0);
+}
+
+// Root insertion records: key = the root's cell for rays that hit, G otherwise.
+template <typename T>
+__global__ void __launch_bounds__(256) root_keys_kernel(const T* __restrict__ saved, const int32_t* __restrict__ hit,
+                                                        int64_t R, int64_t G, uint32_t* __restrict__ keys) {
+  const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ray >= R) return;
+  const double c = (double)saved[ray * kRaySaved + 3];
+  keys[ray] = (hit[ray] && c >= 0.0 && c < (double)G) ? (uint32_t)c : (uint32_t)G;
+}
+
+template <class S, typename T>
+struct RootInsert {
+  const T* __restrict__ saved;
+  const T* __restrict__ gt;
+  const T* __restrict__ gn;
+  double h;
+  __device__ __forceinline__ void operator()(uint32_t ray, const T (&centre)[3], int, T (&v)[S::P]) const {
+    constexpr int K = S::K;
+    const T* sv = saved + (int64_t)ray * kRaySaved;
+    double u[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) u[j] = ((double)sv[j] - (double)centre[j]) / h;
+    const double rdg = (double)sv[4];
+    double gnv[3] = {0.0, 0.0, 0.0};
+    if (gn) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) gnv[j] = (double)gn[(int64_t)ray * 3 + j];
+    }
+    const double gtv = gt ? (double)gt[ray] : 0.0;
+    const double a = -(gtv + gnv[0] * (double)sv[5] + gnv[1] * (double)sv[6] + gnv[2] * (double)sv[7]) / rdg;
+    const double ih = 1.0 / h;
+    double pw[3][K + 1];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      pw[j][0] = 1.0;
+#pragma unroll
+      for (int m = 1; m <= K; ++m) pw[j][m] = pw[j][m - 1] * u[j] / m;
+    }
+#pragma unroll
+    for (int t = 0; t <= K; ++t)
+#pragma unroll
+      for (int p0 = t; p0 >= 0; --p0)
+#pragma unroll
+        for (int p1 = t - p0; p1 >= 0; --p1) {
+          const int p2 = t - p0 - p1;
+          double val = a * pw[0][p0] * pw[1][p1] * pw[2][p2];
+          if (p0 >= 1) val += gnv[0] * ih * pw[0][p0 - 1] * pw[1][p1] * pw[2][p2];
+          if (p1 >= 1) val += gnv[1] * ih * pw[0][p0] * pw[1][p1 - 1] * pw[2][p2];
+          if (p2 >= 1) val += gnv[2] * ih * pw[0][p0] * pw[1][p1] * pw[2][p2 - 1];
+          v[mi_pos3(p0, p1, p2)] = (T)val;
+        }
+  }
+};
+
+// ---------------------------------------------------------------------------------------
+int maxseg_for(const fc2t2_plan_s* pl) { return 3 * pl->n + 4; }
+
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base((char*)b) {}
+  template <typename X>
+  X* take(size_t count) {
+    X* p = base ? (X*)(base + off) : nullptr;
+    off += align256(count * sizeof(X));
+    return p;
+  }
+};
+
+struct RecordBufs {
+  uint32_t *keys, *keys_sorted, *perm, *starts;
+  double2* rec;
+  void* scratch;
+};
+
+RecordBufs carve_records(Carve& c, const fc2t2_plan_s* pl, int64_t slots, bool with_rec) {
+  RecordBufs b;
+  b.keys = c.take<uint32_t>(slots);
+  b.keys_sorted = c.take<uint32_t>(slots);
+  b.perm = c.take<uint32_t>(slots);
+  b.starts = c.take<uint32_t>(pl->G + 1);
+  b.rec = with_rec ? c.take<double2>(slots) : nullptr;
+  b.scratch = c.take<char>(radix_sort_scratch_bytes(slots));
+  return b;
+}
+
+bool rays_ok(const fc2t2_plan_s* pl) { return pl->dim == 3; }
+
+}  // namespace
 
 namespace fc2t2 {
-size_t ray_integral_bwd_ws(const fc2t2_plan_s*, int64_t) { return 0; }
-fc2t2_status launch_ray_integral(const fc2t2_plan_s*, const void*, const void*, const void*, double,
-                                 double, int64_t, void*, hipStream_t) { return FC2T2_EUNSUPPORTED; }
-fc2t2_status ray_integral_backward(const fc2t2_plan_s*, const void*, const void*, double, double,
-                                   int64_t, const void*, void*, void*, hipStream_t) { return FC2T2_EUNSUPPORTED; }
-fc2t2_status launch_ray_root(const fc2t2_plan_s*, const void*, const void*, const void*, double, double,
-                             int64_t, double, void*, void*, int32_t*, void*, hipStream_t) { return FC2T2_EUNSUPPORTED; }
-size_t ray_root_bwd_ws(const fc2t2_plan_s*, int64_t) { return 0; }
-fc2t2_status ray_root_backward(const fc2t2_plan_s*, const void*, const int32_t*, int64_t, const void*,
-                               const void*, void*, void*, hipStream_t) { return FC2T2_EUNSUPPORTED; }
+
+size_t ray_integral_bwd_ws(const fc2t2_plan_s* pl, int64_t R) {
+  Carve c(nullptr);
+  carve_records(c, pl, R * maxseg_for(pl), true);
+  return c.off;
+}
+
+size_t ray_root_bwd_ws(const fc2t2_plan_s* pl, int64_t R) {
+  Carve c(nullptr);
+  carve_records(c, pl, R, false);
+  return c.off;
+}
+
+fc2t2_status launch_ray_integral(const fc2t2_plan_s* pl, const void* L, const void* o, const void* r, double t0,
+                                 double t1, int64_t R, void* y, hipStream_t s) {
+  if (R == 0) return FC2T2_OK;
+  fc2t2_status st = FC2T2_EUNSUPPORTED;
+  const dim3 grid((unsigned)ceil_div(R * 64, 256), pl->C);
+  dispatch_shape(pl->dim, pl->K, [&](auto shape) {
+    using S = decltype(shape);
+    if constexpr (S::D == 3) {
+      if (pl->io == FC2T2_IO_F64)
+        hipLaunchKernelGGL((ray_integral_kernel<S, double>), grid, dim3(256), 0, s, (const double*)L,
+                           (const double*)o, (const double*)r, R, t0, t1, pl->lo, pl->hi, pl->h0, pl->n, pl->G,
+                           (double*)y, pl->C);
+      else
+        hipLaunchKernelGGL((ray_integral_kernel<S, float>), grid, dim3(256), 0, s, (const float*)L,
+                           (const float*)o, (const float*)r, R, t0, t1, pl->lo, pl->hi, pl->h0, pl->n, pl->G,
+                           (float*)y, pl->C);
+      st = FC2T2_OK;
+    }
+  });
+  if (st) return st;
+  FC2T2_LAUNCH_CHECK();
+  return FC2T2_OK;
+}
+
+template <typename T>
+fc2t2_status ray_integral_backward_t(const fc2t2_plan_s* pl, const T* o, const T* r, double t0, double t1,
+                                     int64_t R, const T* gy, T* gL, void* ws, hipStream_t s) {
+  const int maxseg = maxseg_for(pl);
+  const int64_t slots = R * maxseg;
+  Carve c(ws);
+  RecordBufs b = carve_records(c, pl, slots, true);
+  hipLaunchKernelGGL((ray_records_kernel<T>), dim3((unsigned)ceil_div(R, 256)), dim3(256), 0, s, o, r, R, t0, t1,
+                     pl->lo, pl->hi, pl->h0, pl->n, pl->G, maxseg, b.keys, b.rec);
+  FC2T2_LAUNCH_CHECK();
+  fc2t2_status st = radix_sort_pairs(b.keys, b.keys_sorted, b.perm, slots, key_bits_for(pl->G + 1), b.scratch, s);
+  if (st) return st;
+  st = launch_cell_starts(b.keys_sorted, slots, pl->G, b.starts, s);
+  if (st) return st;
+  st = FC2T2_EUNSUPPORTED;
+  dispatch_shape(pl->dim, pl->K, [&](auto shape) {
+    using S = decltype(shape);
+    if constexpr (S::D == 3) {
+      SegmentInsert<S, T> fn{o, r, b.rec, gy, maxseg, pl->C, pl->h0};
+      // records per occupied cell are few (a ray crosses a cell once): the number of real
+      // segments is about 2.3 n per ray
+      st = launch_reduce_cells<S, T>(pl, b.starts, b.perm, R * 2 * pl->n, gL, true, fn, s);
+    }
+  });
+  return st;
+}
+
+fc2t2_status ray_integral_backward(const fc2t2_plan_s* pl, const void* o, const void* r, double t0, double t1,
+                                   int64_t R, const void* gy, void* gL, void* ws, hipStream_t s) {
+  if (R == 0) return FC2T2_OK;
+  return pl->io == FC2T2_IO_F64
+             ? ray_integral_backward_t<double>(pl, (const double*)o, (const double*)r, t0, t1, R, (const double*)gy,
+                                               (double*)gL, ws, s)
+             : ray_integral_backward_t<float>(pl, (const float*)o, (const float*)r, t0, t1, R, (const float*)gy,
+                                              (float*)gL, ws, s);
+}
+
+fc2t2_status launch_ray_root(const fc2t2_plan_s* pl, const void* L, const void* o, const void* r, double t0, double t1,
+                             int64_t R, double frac, void* t, void* normal, int32_t* hit, void* saved, hipStream_t s) {
+  if (R == 0) return FC2T2_OK;
+  fc2t2_status st = FC2T2_EUNSUPPORTED;
+  const dim3 grid((unsigned)ceil_div(R, 64));
+  dispatch_shape(pl->dim, pl->K, [&](auto shape) {
+    using S = decltype(shape);
+    if constexpr (S::D == 3) {
+      if (pl->io == FC2T2_IO_F64)
+        hipLaunchKernelGGL((ray_root_kernel<S, double>), grid, dim3(64), 0, s, (const double*)L, (const double*)o,
+                           (const double*)r, R, t0, t1, pl->lo, pl->hi, pl->h0, pl->n, frac, (double*)t,
+                           (double*)normal, hit, (double*)saved);
+      else
+        hipLaunchKernelGGL((ray_root_kernel<S, float>), grid, dim3(64), 0, s, (const float*)L, (const float*)o,
+                           (const float*)r, R, t0, t1, pl->lo, pl->hi, pl->h0, pl->n, frac, (float*)t,
+                           (float*)normal, hit, (float*)saved);
+      st = FC2T2_OK;
+    }
+  });
+  if (st) return st;
+  FC2T2_LAUNCH_CHECK();
+  return FC2T2_OK;
+}
+
+template <typename T>
+fc2t2_status ray_root_backward_t(const fc2t2_plan_s* pl, const T* saved, const int32_t* hit, int64_t R, const T* gt,
+                                 const T* gn, T* gL, void* ws, hipStream_t s) {
+  Carve c(ws);
+  RecordBufs b = carve_records(c, pl, R, false);
+  hipLaunchKernelGGL((root_keys_kernel<T>), dim3((unsigned)ceil_div(R, 256)), dim3(256), 0, s, saved, hit, R, pl->G,
+                     b.keys);
+  FC2T2_LAUNCH_CHECK();
+  fc2t2_status st = radix_sort_pairs(b.keys, b.keys_sorted, b.perm, R, key_bits_for(pl->G + 1), b.scratch, s);
+  if (st) return st;
+  st = launch_cell_starts(b.keys_sorted, R, pl->G, b.starts, s);
+  if (st) return st;
+  st = FC2T2_EUNSUPPORTED;
+  dispatch_shape(pl->dim, pl->K, [&](auto shape) {
+    using S = decltype(shape);
+    if constexpr (S::D == 3) {
+      RootInsert<S, T> fn{saved, gt, gn, pl->h0};
+      st = launch_reduce_cells<S, T>(pl, b.starts, b.perm, R, gL, true, fn, s);
+    }
+  });
+  return st;
+}
+
+fc2t2_status ray_root_backward(const fc2t2_plan_s* pl, const void* saved, const int32_t* hit, int64_t R, const void* gt,
+                               const void* gn, void* gL, void* ws, hipStream_t s) {
+  if (R == 0) return FC2T2_OK;
+  return pl->io == FC2T2_IO_F64
+             ? ray_root_backward_t<double>(pl, (const double*)saved, hit, R, (const double*)gt, (const double*)gn,
+                                           (double*)gL, ws, s)
+             : ray_root_backward_t<float>(pl, (const float*)saved, hit, R, (const float*)gt, (const float*)gn,
+                                          (float*)gL, ws, s);
+}
+
 }  // namespace fc2t2
 
 extern "C" {
-fc2t2_status fc2t2_ray_integral(fc2t2_plan, const void*, const void*, const void*, double, double,
-                                int64_t, void*, hipStream_t) { return FC2T2_EUNSUPPORTED; }
-fc2t2_status fc2t2_ray_integral_backward(fc2t2_plan, const void*, const void*, double, double, int64_t,
-                                         const void*, void*, void*, size_t, hipStream_t) { return FC2T2_EUNSUPPORTED; }
-fc2t2_status fc2t2_ray_root(fc2t2_plan, const void*, const void*, const void*, double, double, int64_t,
-                            double, void*, void*, int32_t*, void*, hipStream_t) { return FC2T2_EUNSUPPORTED; }
-fc2t2_status fc2t2_ray_root_backward(fc2t2_plan, const void*, const int32_t*, int64_t, const void*,
-                                     const void*, void*, void*, size_t, hipStream_t) { return FC2T2_EUNSUPPORTED; }
+
+static bool bad_rays(int64_t R) { return R < 0 || R > 0x7FFFFFFFll; }
+
+fc2t2_status fc2t2_ray_integral(fc2t2_plan plan, const void* L, const void* o, const void* r, double t0, double t1,
+                                int64_t R, void* y, hipStream_t stream) {
+  if (!plan || !L || bad_rays(R) || !isfinite(t0) || !isfinite(t1)) return FC2T2_EINVAL;
+  if (R > 0 && (!o || !r || !y)) return FC2T2_EINVAL;
+  if (!rays_ok(plan)) return FC2T2_EUNSUPPORTED;
+  return launch_ray_integral(plan, L, o, r, t0, t1, R, y, stream);
 }
+
+fc2t2_status fc2t2_ray_integral_backward(fc2t2_plan plan, const void* o, const void* r, double t0, double t1,
+                                         int64_t R, const void* gy, void* gL, void* ws, size_t ws_bytes,
+                                         hipStream_t stream) {
+  if (!plan || !gL || bad_rays(R) || !isfinite(t0) || !isfinite(t1)) return FC2T2_EINVAL;
+  if (R > 0 && (!o || !r || !gy)) return FC2T2_EINVAL;
+  if (!rays_ok(plan)) return FC2T2_EUNSUPPORTED;
+  if (R * (int64_t)maxseg_for(plan) > 0xFFFFFFFFll) return FC2T2_EUNSUPPORTED;
+  if (R == 0) return FC2T2_OK;
+  if (!ws || ws_bytes < ray_integral_bwd_ws(plan, R)) return FC2T2_EWORKSPACE;
+  return ray_integral_backward(plan, o, r, t0, t1, R, gy, gL, ws, stream);
+}
+
+fc2t2_status fc2t2_ray_root(fc2t2_plan plan, const void* L, const void* o, const void* r, double t0, double t1,
+                            int64_t R, double level_frac, void* t, void* normal, int32_t* hit, void* saved,
+                            hipStream_t stream) {
+  if (!plan || !L || bad_rays(R) || !isfinite(t0) || !isfinite(t1) || !isfinite(level_frac)) return FC2T2_EINVAL;
+  if (R > 0 && (!o || !r || !t || !normal || !hit || !saved)) return FC2T2_EINVAL;
+  if (!rays_ok(plan) || plan->C != 1) return FC2T2_EUNSUPPORTED;
+  if (plan->io == FC2T2_IO_F32 && plan->G > (int64_t(1) << 24)) return FC2T2_EUNSUPPORTED;
+  return launch_ray_root(plan, L, o, r, t0, t1, R, level_frac, t, normal, hit, saved, stream);
+}
+
+fc2t2_status fc2t2_ray_root_backward(fc2t2_plan plan, const void* saved, const int32_t* hit, int64_t R, const void* gt,
+                                     const void* gn, void* gL, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!plan || !gL || bad_rays(R)) return FC2T2_EINVAL;
+  if (R > 0 && (!saved || !hit)) return FC2T2_EINVAL;
+  if (!rays_ok(plan) || plan->C != 1) return FC2T2_EUNSUPPORTED;
+  if (R == 0 || (!gt && !gn)) return FC2T2_OK;
+  if (!ws || ws_bytes < ray_root_bwd_ws(plan, R)) return FC2T2_EWORKSPACE;
+  return ray_root_backward(plan, saved, hit, R, gt, gn, gL, ws, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Per-cell segmented reduction over records sorted by cell (shared by P2M, the transpose
+// of L2P, ray insertion and root insertion).
+#pragma once
+
+#include "plan.h"
+
+namespace fc2t2 {
+
+template <int D, typename T>
+__device__ __forceinline__ void decode_cell(int64_t cell, int n, int (&ic)[3]) {
+  ic[0] = ic[1] = ic[2] = 0;
+  if constexpr (D == 2) {
+    ic[1] = (int)(cell % n);
+    ic[0] = (int)(cell / n);
+  } else {
+    ic[2] = (int)(cell % n);
+    ic[1] = (int)((cell / n) % n);
+    ic[0] = (int)(cell / ((int64_t)n * n));
+  }
+}
+
+// out[ch][cell][:] (+)= sum over the cell's sorted records of fn(record).
+template <class S, typename T, int GROUP, class F>
+__global__ void __launch_bounds__(256) reduce_cells_kernel(const uint32_t* __restrict__ starts,
+                                                           const uint32_t* __restrict__ perm,
+                                                           int64_t G, int n, T lo, T h,
+                                                           T* __restrict__ out, int accumulate, F fn) {
+  constexpr int P = S::P, Ppad = S::Ppad, D = S::D;
+  const int lane_g = threadIdx.x & (GROUP - 1);
+  const int ch = blockIdx.y;
+  const int64_t groups = (int64_t)gridDim.x * (blockDim.x / GROUP);
+  T* __restrict__ base = out + (int64_t)ch * G * Ppad;
+  for (int64_t cell = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GROUP; cell < G; cell += groups) {
+    const uint32_t b = starts[cell], e = starts[cell + 1];
+    int ic[3];
+    decode_cell<D, T>(cell, n, ic);
+    T centre[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) centre[j] = lo + (T(ic[j]) + T(0.5)) * h;
+    T s[P], c[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) { s[k] = T(0); c[k] = T(0); }
+    for (uint32_t r = b + lane_g; r < e; r += GROUP) {
+      T v[P];
+      fn(perm[r], centre, ch, v);
+#pragma unroll
+      for (int k = 0; k < P; ++k) acc2(s[k], c[k], v[k]);
+    }
+    // lanes of the group combine their compensated partial sums
+#pragma unroll
+    for (int k = 0; k < P; ++k) s[k] += c[k];
+#pragma unroll
+    for (int off = GROUP / 2; off >= 1; off >>= 1) {
+#pragma unroll
+      for (int k = 0; k < P; ++k) s[k] += __shfl_xor(s[k], off);
+    }
+    T* __restrict__ dst = base + cell * Ppad;
+#pragma unroll
+    for (int k = 0; k < Ppad; ++k) {
+      if ((k & (GROUP - 1)) == lane_g) {
+        const T v = k < P ? s[k] : T(0);
+        if (accumulate) dst[k] += v; else dst[k] = v;
+      }
+    }
+  }
+}
+
+
+// Lanes per cell from the mean number of records per cell.
+inline int reduce_group_for(int64_t records, int64_t cells) {
+  const double avg = cells > 0 ? (double)records / (double)cells : 0.0;
+  return avg < 6.0 ? 4 : (avg < 40.0 ? 16 : 64);
+}
+
+template <class S, typename T, int GROUP, class F>
+fc2t2_status launch_reduce_cells_g(const fc2t2_plan_s* pl, const uint32_t* starts, const uint32_t* perm,
+                                   T* out, bool accumulate, const F& fn, hipStream_t s) {
+  const int threads = 256;
+  const int64_t need = ceil_div(pl->G * GROUP, threads);
+  const int64_t blocks = need < 16384 ? need : 16384;
+  hipLaunchKernelGGL((reduce_cells_kernel<S, T, GROUP, F>), dim3((unsigned)blocks, pl->C), dim3(threads), 0, s,
+                     starts, perm, pl->G, pl->n, (T)pl->lo, (T)pl->h0, out, accumulate ? 1 : 0, fn);
+  FC2T2_LAUNCH_CHECK();
+  return FC2T2_OK;
+}
+
+template <class S, typename T, class F>
+fc2t2_status launch_reduce_cells(const fc2t2_plan_s* pl, const uint32_t* starts, const uint32_t* perm,
+                                 int64_t records, T* out, bool accumulate, const F& fn, hipStream_t s) {
+  switch (reduce_group_for(records, pl->G)) {
+    case 4: return launch_reduce_cells_g<S, T, 4>(pl, starts, perm, out, accumulate, fn, s);
+    case 16: return launch_reduce_cells_g<S, T, 16>(pl, starts, perm, out, accumulate, fn, s);
+    default: return launch_reduce_cells_g<S, T, 64>(pl, starts, perm, out, accumulate, fn, s);
+  }
+}
+
+}  // namespace fc2t2

@@ -38,3 +38,29 @@ def scaled_locals(geo: fmm.Geometry, L0: np.ndarray, P_pad: int) -> np.ndarray:
 def poly_coef_list(kernel: kernels.Polynomial, dim: int, deg: int):
     """Coefficient list in the graded multi-index order of degree <= deg."""
     return [kernel.coef.get(a, 0.0) for a in fmm.multi_indices(dim, deg)]
+
+
+def physical_locals(geo: fmm.Geometry, Lt: np.ndarray) -> np.ndarray:
+    """The library's scaled layout [C][n^d][P_pad] -> physical (C, n, ..., n, P)."""
+    C = Lt.shape[0]
+    scale = np.array([geo.h(0) ** sum(k) for k in geo.idx])
+    out = np.asarray(Lt, dtype=np.float64)[:, :, :geo.P] / scale
+    return out.reshape((C,) + (geo.n,) * geo.dim + (geo.P,))
+
+
+def scaled_cotangent(geo: fmm.Geometry, G: np.ndarray, P_pad: int) -> np.ndarray:
+    """Cotangent of physical locals -> cotangent of the scaled locals h^|k| L[k]."""
+    C = G.shape[0]
+    scale = np.array([geo.h(0) ** sum(k) for k in geo.idx])
+    flat = G.reshape(C, -1, geo.P) / scale
+    out = np.zeros((C, flat.shape[1], P_pad))
+    out[:, :, :geo.P] = flat
+    return out
+
+
+def rays_toward_origin(rng, R, jitter=0.1):
+    """Origins on the radius-2 sphere aimed at the origin with a uniform aim jitter."""
+    v = rng.standard_normal((R, 3))
+    o = 2.0 * v / np.linalg.norm(v, axis=1, keepdims=True)
+    r = -o + rng.uniform(-jitter, jitter, (R, 3))
+    return o, r / np.linalg.norm(r, axis=1, keepdims=True)

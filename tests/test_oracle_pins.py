@@ -490,3 +490,18 @@ def test_ray_root_backward_matches_finite_differences():
         e = np.zeros_like(w); e[s, 0] = eps
         fd = (loss(w + e) - loss(w - e)) / (2 * eps)
         assert abs(fd - gw[s, 0]) < 1e-5 * max(1.0, abs(fd))
+
+
+def test_ray_root_face_crossing_belongs_to_earlier_cell():
+    """Piecewise-constant field: 0 in the cells x < 0, 1 for x >= 0.  Along +x the level
+    0.5 * max = 0.5 is crossed only across the face x = 0, which the root rule assigns to
+    the earlier cell (t at the face)."""
+    geo = fmm.Geometry(3, 8, -1, 1, 2)
+    L0 = np.zeros((1, 8, 8, 8, geo.P))
+    L0[0, 4:, :, :, 0] = 1.0
+    o = np.array([[-2.0, 0.1, -0.05]])
+    r = np.array([[1.0, 0.0, 0.0]])
+    res = rays.ray_root(geo, L0, o, r, 0.0, 4.0)
+    assert res["hit"][0] == 1 and abs(res["tau"][0] - 0.5) < 1e-15
+    assert abs(res["t"][0] - 2.0) < 1e-15
+    assert tuple(res["cell"][0]) == (3, 4, 3)

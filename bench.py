@@ -60,32 +60,59 @@ def main():
 
     torch.cuda.set_device(0)
     wl = workloads.workload(args.workload)
-    assert wl.layer == "explicit", "bench.py times the explicit layer"
     x = workloads.make(wl, seed=0)
     dev = torch.device("cuda", 0)
     t = {k: torch.from_numpy(v).to(dev) for k, v in x.items()}
     def make_plan(m2l):
         return fc2t2.Plan(wl.dim, wl.n, wl.lo, wl.hi, wl.kernel, wl.param, wl.K, m2l=m2l, io=wl.io)
 
-    p, w, q, gy = t["p"], t["w"], t["q"], t["gy"]
+    p, w = t["p"], t["w"]
+    q, gy = t.get("q"), t.get("gy")
+
+    layer = wl.layer
+    if layer != "explicit":
+        o, r = t["o"], t["r"]
 
     def time_steps(plan, steps, warmup):
         Lt = plan.new_local()
         gL = plan.new_local()
-        gq = torch.zeros_like(q)
         gp = torch.zeros_like(p)
         gw = torch.zeros_like(w)
+        if layer == "explicit":
+            gq = torch.zeros_like(q)
 
-        def step():
-            plan.expand(p, w, out=Lt)
-            y, _, _ = plan.eval(Lt, q)
-            gL.zero_()
-            gq.zero_()
-            gp.zero_()
-            gw.zero_()
-            plan.eval_backward(Lt, q, gy, gL, gq)
-            plan.expand_backward(gL, p, w, gp, gw)
-            return y
+            def step():
+                plan.expand(p, w, out=Lt)
+                y, _, _ = plan.eval(Lt, q)
+                gL.zero_()
+                gq.zero_()
+                gp.zero_()
+                gw.zero_()
+                plan.eval_backward(Lt, q, gy, gL, gq)
+                plan.expand_backward(gL, p, w, gp, gw)
+                return y
+        elif layer == "ray_integral":
+            def step():
+                plan.expand(p, w, out=Lt)
+                y = plan.ray_integral(Lt, o, r, wl.t0, wl.t1)
+                gL.zero_()
+                gp.zero_()
+                gw.zero_()
+                plan.ray_integral_backward(o, r, wl.t0, wl.t1, gy, gL)
+                plan.expand_backward(gL, p, w, gp, gw)
+                return y
+        else:
+            gt, gn = t["gt"], t["gn"]
+
+            def step():
+                plan.expand(p, w, out=Lt)
+                tt, nrm, hit, saved = plan.ray_root(Lt, o, r, wl.t0, wl.t1, 0.5)
+                gL.zero_()
+                gp.zero_()
+                gw.zero_()
+                plan.ray_root_backward(saved, hit, gt, gn, gL)
+                plan.expand_backward(gL, p, w, gp, gw)
+                return tt
 
         for _ in range(warmup):
             y = step()
@@ -103,7 +130,8 @@ def main():
     torch.cuda.synchronize()
     plan_ms = (time.perf_counter() - t_plan0) * 1e3
     ms, y = time_steps(plan, args.steps, args.warmup)
-    value = wl.M / (ms * 1e-3)
+    units = wl.M if wl.layer == "explicit" else wl.R
+    value = units / (ms * 1e-3)
     f32_ms = None
     if args.compare_f32 and args.m2l != "f32":
         f32_ms, _ = time_steps(make_plan("f32"), max(3, args.steps // 4), 1)
@@ -136,24 +164,27 @@ def main():
                 "mfma_issue_frac": round(achieved * passes * accounting.mfma_padding(wl.dim, wl.K) / peak, 4)
                 if bound == "mfma" else None}
 
+    unit = "queries/s" if wl.layer == "explicit" else "rays/s"
+    outputs = {"explicit": "y, w_bar, p_bar, q_bar", "ray_integral": "y (ray integrals), w_bar, p_bar",
+               "ray_root": "t*, grad f(q*), w_bar, p_bar"}[wl.layer]
     out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "queries/s", "n_gpus": 1,
+        "metric": METRIC, "value": round(value, 1), "unit": unit, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (seeded uniform points, Gaussian weights)",
-        "config": {"workload": wl.name, "dim": wl.dim, "N": wl.N, "M": wl.M, "grid": "%d^%d" % (wl.n, wl.dim),
-                   "K": wl.K, "kernel": "%s %g" % (wl.kernel, wl.param), "m2l": args.m2l,
-                   "outputs": "y, w_bar, p_bar, q_bar"},
+        "data": "synthetic (seeded %s sources, Gaussian weights)" % wl.sources,
+        "config": {"workload": wl.name, "dim": wl.dim, "N": wl.N, "M": wl.M, "R": wl.R,
+                   "grid": "%d^%d" % (wl.n, wl.dim), "K": wl.K, "kernel": "%s %g" % (wl.kernel, wl.param),
+                   "m2l": args.m2l, "outputs": outputs},
         "roofline": roofline,
         "plan_ms": round(plan_ms, 1),
     }
     if f32_ms is not None:
-        out["m2l_f32_comparison"] = {"value": round(wl.M / (f32_ms * 1e-3), 1), "unit": "queries/s",
+        out["m2l_f32_comparison"] = {"value": round(units / (f32_ms * 1e-3), 1), "unit": unit,
                                      "ms_per_step": round(f32_ms, 4)}
 
     # ---- CPU baseline: the FP64 direct-sum checker on a bounded sample of queries (all N
     # sources), timed on this host; the same values give the GPU's error against it.
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and wl.layer == "explicit":
         from oracle import direct, kernels
         idx = workloads.subsample(123, args.cpu_sample, wl.M)
         ker = kernels.make_kernel(wl.kernel, wl.param, wl.dim)

@@ -117,8 +117,9 @@ __global__ void __launch_bounds__(C::THREADS) m2l_mfma_kernel(
   constexpr int P8 = C::P8, NT = C::NT, NTC = C::NTC, RM = C::RM;
   constexpr int SX = C::SX, SY = C::SY, SZ = C::SZ, CELLS = C::CELLS;
   constexpr int PASSES = C::PASSES_;
+  constexpr int KSTEPS = C::KSTEPS;
   __shared__ __attribute__((aligned(16))) unsigned short lds_hi[CELLS * 8];
-  __shared__ __attribute__((aligned(16))) unsigned short lds_lo[CELLS * 8];
+  __shared__ __attribute__((aligned(16))) unsigned short lds_lo[PASSES >= 3 ? CELLS * 8 : 8];
 
   const int ch = blockIdx.y;
   // XCD-aware order: consecutive logical tiles share an XCD (dispatch is round-robin over 8)
@@ -157,6 +158,8 @@ __global__ void __launch_bounds__(C::THREADS) m2l_mfma_kernel(
     for (int t = 0; t < NT; ++t) acc[m][t] = floatx4{0.f, 0.f, 0.f, 0.f};
 
   const float* __restrict__ Mch = Min + (int64_t)ch * G_l * Ppad;
+  // window entry e = 4 s + grp as digits (ex, ey, ez) in base 6; advanced by 4 per step
+  const int e0 = grp;
 
   for (int n8 = 0; n8 < P8 / 8; ++n8) {
     // ---- stage the source region's slice [n8*8, n8*8+8) as bf16 hi / lo
@@ -196,24 +199,49 @@ __global__ void __launch_bounds__(C::THREADS) m2l_mfma_kernel(
     __syncthreads();
 
     // ---- 32-deep MFMA steps: group g of the wave takes window entry 4 * s + g
-    for (int s = 0; s < C::KSTEPS; ++s) {
-      const int e = 4 * s + grp;
-      int ex, ey, ez;
-      if constexpr (D == 3) { ez = e % 6; ey = (e / 6) % 6; ex = e / 36; }
-      else { ez = 0; ey = e % 6; ex = e / 6; }
-      const int ox = wlo_x + ex, oy = wlo_y + ey, oz = D == 3 ? wlo_z + ez : 0;
-      const int delta = (ox * SY + oy) * SZ + oz;
+    int ex, ey, ez;
+    if constexpr (D == 3) { ez = e0 % 6; ey = (e0 / 6) % 6; ex = e0 / 36; }
+    else { ez = 0; ey = e0 % 6; ex = e0 / 6; }
+    auto b_base = [&](int qx, int qy, int qz) -> int64_t {
+      const int ox = wlo_x + qx, oy = wlo_y + qy, oz = D == 3 ? wlo_z + qz : 0;
       const int ob = D == 3 ? ((ox + 3) * 7 + (oy + 3)) * 7 + (oz + 3) : (ox + 3) * 7 + (oy + 3);
-      // B fragments: lanes (grp, row as column) read 8 in-channels of out-channel t*16+row
-      bf16x8 bh[NT], bl[NT];
-      const int64_t bbase = (((int64_t)ob * (P8 / 8) + n8) * NTC) * 8;
+      return (((int64_t)ob * (P8 / 8) + n8) * NTC + row) * 8;
+    };
+    auto advance = [&](int& qx, int& qy, int& qz) {
+      if constexpr (D == 3) {
+        qz += 4;
+        if (qz >= 6) { qz -= 6; ++qy; if (qy >= 6) { qy -= 6; ++qx; } }
+      } else {
+        qy += 4;
+        if (qy >= 6) { qy -= 6; ++qx; }
+      }
+    };
+    uint4 nbh[NT], nbl[NT];
+    {
+      const int64_t bb = b_base(ex, ey, ez);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const uint4 u = *reinterpret_cast<const uint4*>(Bhi + bbase + (int64_t)(t * 16 + row) * 8);
-        bh[t] = __builtin_bit_cast(bf16x8, u);
-        if constexpr (PASSES >= 2) {
-          const uint4 w = *reinterpret_cast<const uint4*>(Blo + bbase + (int64_t)(t * 16 + row) * 8);
-          bl[t] = __builtin_bit_cast(bf16x8, w);
+        nbh[t] = *reinterpret_cast<const uint4*>(Bhi + bb + (int64_t)t * 16 * 8);
+        if constexpr (PASSES >= 2) nbl[t] = *reinterpret_cast<const uint4*>(Blo + bb + (int64_t)t * 16 * 8);
+      }
+    }
+    for (int s = 0; s < KSTEPS; ++s) {
+      bf16x8 bh[NT], bl[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        bh[t] = __builtin_bit_cast(bf16x8, nbh[t]);
+        if constexpr (PASSES >= 2) bl[t] = __builtin_bit_cast(bf16x8, nbl[t]);
+      }
+      const int ox = wlo_x + ex, oy = wlo_y + ey, oz = D == 3 ? wlo_z + ez : 0;
+      const int delta = (ox * SY + oy) * SZ + oz;
+      // prefetch the next step's B fragments
+      if (s + 1 < KSTEPS) {
+        advance(ex, ey, ez);
+        const int64_t bb = b_base(ex, ey, ez);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          nbh[t] = *reinterpret_cast<const uint4*>(Bhi + bb + (int64_t)t * 16 * 8);
+          if constexpr (PASSES >= 2) nbl[t] = *reinterpret_cast<const uint4*>(Blo + bb + (int64_t)t * 16 * 8);
         }
       }
 #pragma unroll
@@ -268,12 +296,13 @@ struct CfgX : Cfg<D, P, TPX, TPY, TPZ, PASSES> {
 
 template <int D, int P, int PASSES>
 struct Tile;
-// 2-D: 4 x 4 parents (64 targets, 4 waves, one 16-row tile each)
+// 2-D: 8 x 4 parents (128 targets, 4 waves, two 16-row tiles each)
 template <int P, int PASSES>
-struct Tile<2, P, PASSES> { using type = CfgX<2, P, 4, 4, 1, PASSES>; };
-// 3-D: 4 x 2 x 2 parents (128 targets, 8 waves, one 16-row tile each)
+struct Tile<2, P, PASSES> { using type = CfgX<2, P, 8, 4, 1, PASSES>; };
+// 3-D: 8 x 4 x 4 parents (1024 targets, 8 waves, eight 16-row tiles each; the tensor
+// fragment a wave loads feeds 8 row tiles)
 template <int P, int PASSES>
-struct Tile<3, P, PASSES> { using type = CfgX<3, P, 4, 2, 2, PASSES>; };
+struct Tile<3, P, PASSES> { using type = CfgX<3, P, 8, 4, 4, PASSES>; };
 
 template <class C>
 fc2t2_status launch_cfg(const fc2t2_plan_s* pl, int lvl, const float* in, float* out, bool accumulate,

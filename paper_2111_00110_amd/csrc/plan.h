@@ -17,7 +17,8 @@ struct fc2t2_plan_s {
   size_t m2l_T_bytes = 0;
   void* m2l_bf16 = nullptr;       // MFMA operand tables (layout owned by m2l_mfma.hip)
   size_t m2l_bf16_bytes = 0;
-  void* shift = nullptr;          // [2^dim][P][P] IO type: S_b[n][m] = 2^-|n| (b-1/2)^(n-m)/(n-m)!
+  void* shift = nullptr;          // sparse M2M/L2L shift lists (layout owned by tree.hip)
+  size_t shift_beg_off = 0;
   int device = 0;
 };
 
@@ -66,6 +67,8 @@ fc2t2_status launch_p2m_T(const fc2t2_plan_s* pl, const void* GM0, const void* p
                           int64_t N, void* gp, void* gw, hipStream_t s);
 
 // ---- tree.hip
+// Sparse shift lists of the plan's (dim, K), uploaded to pl->shift.
+fc2t2_status build_shift_tables(fc2t2_plan_s* pl, hipStream_t s);
 // Up-shift: out[I] = sum_b S_b in[2I+b] (M2M, and the transpose of L2L).
 fc2t2_status launch_upshift(const fc2t2_plan_s* pl, int lvl_child, const void* in, void* out,
                             hipStream_t s);

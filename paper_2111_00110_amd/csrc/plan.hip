@@ -297,41 +297,10 @@ fc2t2_status fc2t2_plan_create(const fc2t2_grid* grid, const fc2t2_kernel* kerne
                          dim, K, P, Ppad, levels, pl->n_off, n_g, dh, dk, dD, (float*)pl->m2l_T);
     if (hipGetLastError() != hipSuccess) return fail(FC2T2_EHIP);
   }
-  // ---- scaled shift matrices S_b[n][m] = 2^-|n| prod_j (b_j - 1/2)^(n_j - m_j) / (n_j - m_j)!
+  // ---- sparse M2M / L2L shift lists
   {
-    const int nb = 1 << dim;
-    std::vector<double> S((size_t)nb * P * P, 0.0);
-    for (int b = 0; b < nb; ++b) {
-      double e[3];
-      for (int j = 0; j < 3; ++j) e[j] = (j < dim) ? (((b >> (dim - 1 - j)) & 1) - 0.5) : 0.0;
-      for (int a = 0; a < P; ++a)
-        for (int c = 0; c < P; ++c) {
-          double v = 1.0;
-          bool ok = true;
-          int tn = 0;
-          for (int j = 0; j < 3; ++j) {
-            const int dn = k_exps[3 * a + j] - k_exps[3 * c + j];
-            if (dn < 0) { ok = false; break; }
-            double f = 1.0;
-            for (int i = 2; i <= dn; ++i) f *= i;
-            v *= pow(e[j], dn) / f;
-            tn += k_exps[3 * a + j];
-          }
-          if (ok) S[((size_t)b * P + a) * P + c] = v * ldexp(1.0, -tn);
-        }
-    }
-    const size_t bytes = S.size() * tsz;
-    if (hipMalloc(&pl->shift, bytes) != hipSuccess) { pl->shift = nullptr; return fail(FC2T2_ENOMEM); }
-    if (io == FC2T2_IO_F64) {
-      if (hipMemcpyAsync(pl->shift, S.data(), bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
-        return fail(FC2T2_EHIP);
-      if (hipStreamSynchronize(stream) != hipSuccess) return fail(FC2T2_EHIP);
-    } else {
-      std::vector<float> Sf(S.begin(), S.end());
-      if (hipMemcpyAsync(pl->shift, Sf.data(), bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
-        return fail(FC2T2_EHIP);
-      if (hipStreamSynchronize(stream) != hipSuccess) return fail(FC2T2_EHIP);
-    }
+    const fc2t2_status st = build_shift_tables(pl, stream);
+    if (st != FC2T2_OK) return fail(st);
   }
   // ---- MFMA operand tables
   if (m2l_prec >= FC2T2_M2L_BF16) {

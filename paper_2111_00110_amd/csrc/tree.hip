@@ -1,6 +1,7 @@
 // Grid-to-grid stages of the multilevel expansion (section 3):
 //   up-shift    out[I]    = sum_b S_b in[2I + b]     M2M, and the transpose of L2L
 //   down-shift  out[2I+b] = S_b^T in[I]              L2L, and the transpose of M2M
+// (section 3, the binomial M2M shift and the Taylor L2L shift)
 //   M2L         L[i] = sum_o T(o) M[i + o] over the parity window minus the hole
 //   M2L^T       G_M[j] = sum_o T(o)^T G_L[j - o] over the same pairs
 // S_b are the cell-scaled binomial shift matrices S_b[n][m] = 2^-|n| (b - 1/2)^(n-m)/(n-m)!
@@ -10,6 +11,10 @@
 // o_d in [-2, 3] when i_d is even and [-3, 2] when odd (children of the parent's
 // neighbours), j inside the grid, and max |o_d| > 1 above the finest level (the hole is
 // filled by the finer levels).
+#include <math.h>
+
+#include <vector>
+
 #include "plan.h"
 
 using namespace fc2t2;
@@ -31,11 +36,43 @@ __device__ __forceinline__ int64_t encode(const int (&c)[3], int n) {
   return lin;
 }
 
-// out[ch][I][n] = sum_b sum_m S[b][n][m] in[ch][2I+b][m]; one thread per (parent, n).
+// ---------------------------------------------------------------------------------------
+// Shifts between a parent and its 2^d children in cell-scaled units.  With the child
+// offset e = (b - 1/2) h_child (b in {0,1}^d), the scaled shift matrix factors as
+//   S_b[n][m] = c[n][m] * sigma_b(n - m),
+//   c[n][m] = 2^(-|n| - |n-m|) / prod_j (n_j - m_j)!,   sigma_b(d) = prod_j (-1)^(d_j (1 - b_j)),
+// and sigma depends on d only through its parity pattern pi = d mod 2.  The plan holds,
+// for every multi-index, the sparse list of its (partner multi-index, parity pattern, c)
+// entries: for the up-shift, n's list runs over m <= n; for the down-shift, k's list runs
+// over m >= k.  One thread computes one output coefficient by walking its list and
+// combining the 2^d children with the signs sigma_b(pi).
+
+struct ShiftEntry {
+  double c;
+  int m;
+  int pi;
+};
+
+__device__ __forceinline__ float sigma_sign(int pi, int b) {
+  // (-1)^(number of dimensions j with pi_j = 1 and b_j = 0)
+  return (__popc(pi & ~b) & 1) ? -1.0f : 1.0f;
+}
+
+template <int D>
+__device__ __forceinline__ int64_t child_cell(const int (&pc)[3], int b, int n_child) {
+  int64_t lin = 0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) lin = lin * n_child + (2 * pc[j] + ((b >> (D - 1 - j)) & 1));
+  return lin;
+}
+
+// out[ch][I][n] = sum_b sum_{m <= n} S_b[n][m] in[ch][2I+b][m]; one thread per (parent, n).
 template <int D, typename T>
 __global__ void __launch_bounds__(256) upshift_kernel(const T* __restrict__ in, T* __restrict__ out,
-                                                      const T* __restrict__ S, int P, int Ppad,
-                                                      int n_par, int64_t G_par, int64_t G_child) {
+                                                      const ShiftEntry* __restrict__ tab,
+                                                      const int* __restrict__ beg, int P, int Ppad, int n_par,
+                                                      int64_t G_par, int64_t G_child) {
+  constexpr int NB = 1 << D;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= G_par * Ppad) return;
   const int ch = blockIdx.y;
@@ -43,25 +80,27 @@ __global__ void __launch_bounds__(256) upshift_kernel(const T* __restrict__ in, 
   const int64_t I = tid / Ppad;
   T acc = T(0);
   if (nn < P) {
-    int ci[3];
-    decode<D>(I, n_par, ci);
-    const int n_child = 2 * n_par;
-    for (int b = 0; b < (1 << D); ++b) {
-      int cc[3] = {0, 0, 0};
+    int pc[3] = {0, 0, 0};
+    decode<D>(I, n_par, pc);
+    const T* rows[NB];
 #pragma unroll
-      for (int j = 0; j < D; ++j) cc[j] = 2 * ci[j] + ((b >> (D - 1 - j)) & 1);
-      const T* __restrict__ row = in + ((int64_t)ch * G_child + encode<D>(cc, n_child)) * Ppad;
-      const T* __restrict__ Srow = S + ((int64_t)b * P + nn) * P;
-      for (int m = 0; m < P; ++m) acc += Srow[m] * row[m];
+    for (int b = 0; b < NB; ++b) rows[b] = in + ((int64_t)ch * G_child + child_cell<D>(pc, b, 2 * n_par)) * Ppad;
+    for (int e = beg[nn]; e < beg[nn + 1]; ++e) {
+      const ShiftEntry en = tab[e];
+      T h = T(0);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) h += (T)sigma_sign(en.pi, b) * rows[b][en.m];
+      acc += (T)en.c * h;
     }
   }
   out[((int64_t)ch * G_par + I) * Ppad + nn] = acc;
 }
 
-// out[ch][i][k] (+)= sum_m S[b(i)][m][k] in[ch][i/2][m]; one thread per (child, k).
+// out[ch][i][k] (+)= sum_{m >= k} S_{b(i)}[m][k] in[ch][i/2][m]; one thread per (child, k).
 template <int D, typename T>
 __global__ void __launch_bounds__(256) downshift_kernel(const T* __restrict__ in, T* __restrict__ out,
-                                                        const T* __restrict__ S, int P, int Ppad,
+                                                        const ShiftEntry* __restrict__ tab,
+                                                        const int* __restrict__ beg, int P, int Ppad,
                                                         int n_child, int64_t G_child, int64_t G_par,
                                                         int accumulate) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -78,8 +117,10 @@ __global__ void __launch_bounds__(256) downshift_kernel(const T* __restrict__ in
 #pragma unroll
     for (int j = 0; j < D; ++j) { pc[j] = ci[j] >> 1; b = (b << 1) | (ci[j] & 1); }
     const T* __restrict__ row = in + ((int64_t)ch * G_par + encode<D>(pc, n_child / 2)) * Ppad;
-    const T* __restrict__ Sb = S + (int64_t)b * P * P;
-    for (int m = 0; m < P; ++m) acc += Sb[m * P + k] * row[m];
+    for (int e = beg[k]; e < beg[k + 1]; ++e) {
+      const ShiftEntry en = tab[e];
+      acc += (T)(en.c * (double)sigma_sign(en.pi, b)) * row[en.m];
+    }
   }
   T* dst = out + ((int64_t)ch * G_child + i) * Ppad + k;
   if (accumulate) *dst += acc; else *dst = acc;
@@ -174,21 +215,76 @@ const T* level_tensor(const fc2t2_plan_s* pl, int lvl) {
 
 namespace fc2t2 {
 
+// Host: the sparse shift lists (see above), laid out as [up lists | down lists] entries
+// followed by the begin offsets of both.
+fc2t2_status build_shift_tables(fc2t2_plan_s* pl, hipStream_t s) {
+  const int P = pl->P, dim = pl->dim;
+  std::vector<int> e((size_t)P * 3);
+  mi_fill(dim, pl->K, reinterpret_cast<int(*)[3]>(e.data()));
+  std::vector<ShiftEntry> up, down;
+  std::vector<int> beg_up(P + 1), beg_down(P + 1);
+  auto le = [&](int a, int c) {   // multi-index c <= a componentwise
+    return e[3 * c] <= e[3 * a] && e[3 * c + 1] <= e[3 * a + 1] && e[3 * c + 2] <= e[3 * a + 2];
+  };
+  auto coef = [&](int hi, int lo) {
+    double v = 1.0;
+    int tot = 0;
+    for (int j = 0; j < 3; ++j) {
+      const int d = e[3 * hi + j] - e[3 * lo + j];
+      for (int i = 2; i <= d; ++i) v /= i;
+      tot += e[3 * hi + j] + d;
+    }
+    return ldexp(v, -tot);
+  };
+  auto parity = [&](int hi, int lo) {
+    int pi = 0;
+    for (int j = 0; j < dim; ++j) pi = (pi << 1) | ((e[3 * hi + j] - e[3 * lo + j]) & 1);
+    return pi;
+  };
+  for (int n = 0; n < P; ++n) {
+    beg_up[n] = (int)up.size();
+    for (int m = 0; m < P; ++m)
+      if (le(n, m)) up.push_back(ShiftEntry{coef(n, m), m, parity(n, m)});
+  }
+  beg_up[P] = (int)up.size();
+  for (int k = 0; k < P; ++k) {
+    beg_down[k] = (int)down.size();
+    for (int m = 0; m < P; ++m)
+      if (le(m, k)) down.push_back(ShiftEntry{coef(m, k), m, parity(m, k)});
+  }
+  beg_down[P] = (int)down.size();
+  std::vector<ShiftEntry> all(up);
+  all.insert(all.end(), down.begin(), down.end());
+  for (int k = 0; k <= P; ++k) beg_down[k] += (int)up.size();
+  std::vector<int> begs(beg_up);
+  begs.insert(begs.end(), beg_down.begin(), beg_down.end());
+  const size_t tab_bytes = align256(all.size() * sizeof(ShiftEntry));
+  const size_t bytes = tab_bytes + align256(begs.size() * sizeof(int));
+  if (hipMalloc(&pl->shift, bytes) != hipSuccess) { pl->shift = nullptr; return FC2T2_ENOMEM; }
+  if (hipMemcpyAsync(pl->shift, all.data(), all.size() * sizeof(ShiftEntry), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync((char*)pl->shift + tab_bytes, begs.data(), begs.size() * sizeof(int), hipMemcpyHostToDevice, s) !=
+          hipSuccess)
+    return FC2T2_EHIP;
+  pl->shift_beg_off = tab_bytes;
+  return hipStreamSynchronize(s) == hipSuccess ? FC2T2_OK : FC2T2_EHIP;
+}
+
 fc2t2_status launch_upshift(const fc2t2_plan_s* pl, int lvl_child, const void* in, void* out,
                             hipStream_t s) {
   const int lp = lvl_child + 1;
-  const int64_t work = pl->Gl[lp] * pl->Ppad;
-  const dim3 grid((unsigned)ceil_div(work, 256), pl->C);
+  const dim3 grid((unsigned)ceil_div(pl->Gl[lp] * pl->Ppad, 256), pl->C);
+  const ShiftEntry* tab = (const ShiftEntry*)pl->shift;
+  const int* beg = (const int*)((const char*)pl->shift + pl->shift_beg_off);
   if (pl->io == FC2T2_IO_F64) {
     if (pl->dim == 2)
-      hipLaunchKernelGGL((upshift_kernel<2, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, (const double*)pl->shift, pl->P, pl->Ppad, pl->nl[lp], pl->Gl[lp], pl->Gl[lvl_child]);
+      hipLaunchKernelGGL((upshift_kernel<2, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, pl->nl[lp], pl->Gl[lp], pl->Gl[lvl_child]);
     else
-      hipLaunchKernelGGL((upshift_kernel<3, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, (const double*)pl->shift, pl->P, pl->Ppad, pl->nl[lp], pl->Gl[lp], pl->Gl[lvl_child]);
+      hipLaunchKernelGGL((upshift_kernel<3, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, pl->nl[lp], pl->Gl[lp], pl->Gl[lvl_child]);
   } else {
     if (pl->dim == 2)
-      hipLaunchKernelGGL((upshift_kernel<2, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, (const float*)pl->shift, pl->P, pl->Ppad, pl->nl[lp], pl->Gl[lp], pl->Gl[lvl_child]);
+      hipLaunchKernelGGL((upshift_kernel<2, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, pl->nl[lp], pl->Gl[lp], pl->Gl[lvl_child]);
     else
-      hipLaunchKernelGGL((upshift_kernel<3, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, (const float*)pl->shift, pl->P, pl->Ppad, pl->nl[lp], pl->Gl[lp], pl->Gl[lvl_child]);
+      hipLaunchKernelGGL((upshift_kernel<3, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, pl->nl[lp], pl->Gl[lp], pl->Gl[lvl_child]);
   }
   FC2T2_LAUNCH_CHECK();
   return FC2T2_OK;
@@ -197,19 +293,20 @@ fc2t2_status launch_upshift(const fc2t2_plan_s* pl, int lvl_child, const void* i
 fc2t2_status launch_downshift(const fc2t2_plan_s* pl, int lvl_child, const void* in, void* out,
                               bool accumulate, hipStream_t s) {
   const int lp = lvl_child + 1;
-  const int64_t work = pl->Gl[lvl_child] * pl->Ppad;
-  const dim3 grid((unsigned)ceil_div(work, 256), pl->C);
+  const dim3 grid((unsigned)ceil_div(pl->Gl[lvl_child] * pl->Ppad, 256), pl->C);
   const int acc = accumulate ? 1 : 0;
+  const ShiftEntry* tab = (const ShiftEntry*)pl->shift;
+  const int* beg = (const int*)((const char*)pl->shift + pl->shift_beg_off) + (pl->P + 1);
   if (pl->io == FC2T2_IO_F64) {
     if (pl->dim == 2)
-      hipLaunchKernelGGL((downshift_kernel<2, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, (const double*)pl->shift, pl->P, pl->Ppad, pl->nl[lvl_child], pl->Gl[lvl_child], pl->Gl[lp], acc);
+      hipLaunchKernelGGL((downshift_kernel<2, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, pl->nl[lvl_child], pl->Gl[lvl_child], pl->Gl[lp], acc);
     else
-      hipLaunchKernelGGL((downshift_kernel<3, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, (const double*)pl->shift, pl->P, pl->Ppad, pl->nl[lvl_child], pl->Gl[lvl_child], pl->Gl[lp], acc);
+      hipLaunchKernelGGL((downshift_kernel<3, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, pl->nl[lvl_child], pl->Gl[lvl_child], pl->Gl[lp], acc);
   } else {
     if (pl->dim == 2)
-      hipLaunchKernelGGL((downshift_kernel<2, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, (const float*)pl->shift, pl->P, pl->Ppad, pl->nl[lvl_child], pl->Gl[lvl_child], pl->Gl[lp], acc);
+      hipLaunchKernelGGL((downshift_kernel<2, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, pl->nl[lvl_child], pl->Gl[lvl_child], pl->Gl[lp], acc);
     else
-      hipLaunchKernelGGL((downshift_kernel<3, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, (const float*)pl->shift, pl->P, pl->Ppad, pl->nl[lvl_child], pl->Gl[lvl_child], pl->Gl[lp], acc);
+      hipLaunchKernelGGL((downshift_kernel<3, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, pl->nl[lvl_child], pl->Gl[lvl_child], pl->Gl[lp], acc);
   }
   FC2T2_LAUNCH_CHECK();
   return FC2T2_OK;

@@ -78,28 +78,24 @@ bool bad_count(int64_t n) { return n < 0 || n > 0xFFFFFFFFll; }
 
 namespace fc2t2 {
 
-// Levels above the finest of an upward/downward pass: expansion of M0 into L0.
+// Expansion of the finest moments M0 into the finest locals L0: M2M up the pyramid, M2L at
+// every level (one launch), then L2L down the pyramid accumulating into each finer level.
 fc2t2_status expand_from_moments(const fc2t2_plan_s* pl, void** Mlv, void** Llv, void* L0, hipStream_t s) {
   Llv[0] = L0;
   for (int l = 0; l + 1 < pl->levels; ++l) {
     fc2t2_status st = launch_upshift(pl, l, Mlv[l], Mlv[l + 1], s);
     if (st) return st;
   }
-  for (int l = pl->levels - 1; l >= 0; --l) {
-    fc2t2_status st;
-    if (l == pl->levels - 1) {
-      st = launch_m2l(pl, l, Mlv[l], Llv[l], false, s);
-    } else {
-      st = launch_downshift(pl, l, Llv[l + 1], Llv[l], false, s);
-      if (st) return st;
-      st = launch_m2l(pl, l, Mlv[l], Llv[l], true, s);
-    }
+  fc2t2_status st = launch_m2l_all(pl, (const void* const*)Mlv, Llv, false, s);
+  if (st) return st;
+  for (int l = pl->levels - 2; l >= 0; --l) {
+    st = launch_downshift(pl, l, Llv[l + 1], Llv[l], true, s);
     if (st) return st;
   }
   return FC2T2_OK;
 }
 
-// Transpose of expand_from_moments: G_L0 -> G_M0.
+// Transpose of expand_from_moments: G_L0 -> G_M0 (L2L^T up, M2L^T at every level, M2M^T down).
 fc2t2_status expand_T_to_moments(const fc2t2_plan_s* pl, const void* GL0, void** GLlv, void** GMlv,
                                  hipStream_t s) {
   GLlv[0] = (void*)GL0;
@@ -107,15 +103,10 @@ fc2t2_status expand_T_to_moments(const fc2t2_plan_s* pl, const void* GL0, void**
     fc2t2_status st = launch_upshift(pl, l, GLlv[l], GLlv[l + 1], s);   // L2L^T
     if (st) return st;
   }
-  for (int l = pl->levels - 1; l >= 0; --l) {
-    fc2t2_status st;
-    if (l == pl->levels - 1) {
-      st = launch_m2l_T(pl, l, GLlv[l], GMlv[l], false, s);
-    } else {
-      st = launch_downshift(pl, l, GMlv[l + 1], GMlv[l], false, s);    // M2M^T
-      if (st) return st;
-      st = launch_m2l_T(pl, l, GLlv[l], GMlv[l], true, s);
-    }
+  fc2t2_status st = launch_m2l_all(pl, (const void* const*)GLlv, GMlv, true, s);
+  if (st) return st;
+  for (int l = pl->levels - 2; l >= 0; --l) {
+    st = launch_downshift(pl, l, GMlv[l + 1], GMlv[l], true, s);       // M2M^T
     if (st) return st;
   }
   return FC2T2_OK;

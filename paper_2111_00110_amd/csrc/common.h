@@ -210,6 +210,11 @@ bool dispatch_shape(int D, int K, F&& f) {
 }
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int lg2i(int64_t v) {
+  int l = 0;
+  while ((int64_t(1) << l) < v) ++l;
+  return l;
+}
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace fc2t2

@@ -108,11 +108,23 @@ struct Cfg {
   static_assert(D == 3 || TPZ == 1, "2-D tiles have TPZ = 1");
 };
 
+// One launch covers every level of the pyramid: the levels' M2L are independent given the
+// moments, so the workgroups of the small coarse levels run beside those of the finest.
+struct M2LLevel {
+  const float* in;
+  float* out;
+  const unsigned short* Bhi;
+  const unsigned short* Blo;
+  int64_t G_l;
+  int n_l, tiles_y, tiles_z, block_begin;
+};
+struct M2LBatch {
+  M2LLevel lv[kMaxLevels];
+  int nlev, Ppad, accumulate;
+};
+
 template <class C>
-__global__ void __launch_bounds__(C::THREADS) m2l_mfma_kernel(
-    const float* __restrict__ Min, float* __restrict__ Lout, const unsigned short* __restrict__ Bhi,
-    const unsigned short* __restrict__ Blo, int n_l, int Ppad, int64_t G_l, int tiles_x, int tiles_y,
-    int tiles_z, int accumulate) {
+__global__ void __launch_bounds__(C::THREADS) m2l_mfma_kernel(const M2LBatch batch) {
   constexpr int D = C::D_, P = C::P_;
   constexpr int P8 = C::P8, NT = C::NT, NTC = C::NTC, RM = C::RM;
   constexpr int SX = C::SX, SY = C::SY, SZ = C::SZ, CELLS = C::CELLS;
@@ -126,10 +138,20 @@ __global__ void __launch_bounds__(C::THREADS) m2l_mfma_kernel(
   const int nblk = gridDim.x;
   int bid = blockIdx.x;
   if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
+  int lvl = batch.nlev - 1;
+  while (lvl > 0 && bid < batch.lv[lvl].block_begin) --lvl;
+  const M2LLevel& LV = batch.lv[lvl];
+  const float* __restrict__ Min = LV.in;
+  float* __restrict__ Lout = LV.out;
+  const unsigned short* __restrict__ Bhi = LV.Bhi;
+  const unsigned short* __restrict__ Blo = LV.Blo;
+  const int n_l = LV.n_l, Ppad = batch.Ppad, accumulate = batch.accumulate;
+  const int64_t G_l = LV.G_l;
+  const int tiles_y = LV.tiles_y, tiles_z = LV.tiles_z;
+  bid -= LV.block_begin;
   const int tz = bid % tiles_z;
   const int ty = (bid / tiles_z) % tiles_y;
   const int tx = bid / (tiles_z * tiles_y);
-  (void)tiles_x;
   // region origin (cell coords at this level) = 2 * parent origin - 2
   const int rx0 = 2 * tx * C::TPX_ - 2, ry0 = 2 * ty * C::TPY_ - 2, rz0 = D == 3 ? 2 * tz * C::TPZ_ - 2 : 0;
 
@@ -305,15 +327,33 @@ template <int P, int PASSES>
 struct Tile<3, P, PASSES> { using type = CfgX<3, P, 8, 4, 4, PASSES>; };
 
 template <class C>
-fc2t2_status launch_cfg(const fc2t2_plan_s* pl, int lvl, const float* in, float* out, bool accumulate,
-                        const unsigned short* Bhi, const unsigned short* Blo, hipStream_t s) {
-  const int n_l = pl->nl[lvl];
-  const int npar = n_l / 2;
-  const int tx = (npar + C::TPX_ - 1) / C::TPX_, ty = (npar + C::TPY_ - 1) / C::TPY_;
-  const int tz = C::D_ == 3 ? (npar + C::TPZ_ - 1) / C::TPZ_ : 1;
-  const dim3 grid((unsigned)(tx * ty * tz), pl->C);
-  hipLaunchKernelGGL((m2l_mfma_kernel<C>), grid, dim3(C::THREADS), 0, s, in, out, Bhi, Blo, n_l, pl->Ppad,
-                     pl->Gl[lvl], tx, ty, tz, accumulate ? 1 : 0);
+fc2t2_status launch_cfg(const fc2t2_plan_s* pl, int lvl0, int lvl1, const void* const* ins, void* const* outs,
+                        bool accumulate, const unsigned short* base, int64_t plane, int64_t per_lvl,
+                        hipStream_t s) {
+  M2LBatch b;
+  b.nlev = 0;
+  b.Ppad = pl->Ppad;
+  b.accumulate = accumulate ? 1 : 0;
+  int blocks = 0;
+  for (int lvl = lvl0; lvl < lvl1; ++lvl) {
+    const int n_l = pl->nl[lvl];
+    const int npar = n_l / 2;
+    const int tx = (npar + C::TPX_ - 1) / C::TPX_, ty = (npar + C::TPY_ - 1) / C::TPY_;
+    const int tz = C::D_ == 3 ? (npar + C::TPZ_ - 1) / C::TPZ_ : 1;
+    M2LLevel& L = b.lv[b.nlev++];
+    L.in = (const float*)ins[lvl];
+    L.out = (float*)outs[lvl];
+    L.Bhi = base + lvl * per_lvl;
+    L.Blo = base + plane + lvl * per_lvl;
+    L.G_l = pl->Gl[lvl];
+    L.n_l = n_l;
+    L.tiles_y = ty;
+    L.tiles_z = tz;
+    L.block_begin = blocks;
+    blocks += tx * ty * tz;
+  }
+  const dim3 grid((unsigned)blocks, pl->C);
+  hipLaunchKernelGGL((m2l_mfma_kernel<C>), grid, dim3(C::THREADS), 0, s, b);
   FC2T2_LAUNCH_CHECK();
   return FC2T2_OK;
 }
@@ -359,27 +399,23 @@ fc2t2_status m2l_mfma_build_tables(fc2t2_plan_s* pl, hipStream_t s) {
   return FC2T2_OK;
 }
 
-fc2t2_status launch_m2l_mfma(const fc2t2_plan_s* pl, int lvl, const void* in, void* out, bool accumulate,
-                             bool transpose, hipStream_t s) {
+fc2t2_status launch_m2l_mfma(const fc2t2_plan_s* pl, int lvl0, int lvl1, const void* const* ins,
+                             void* const* outs, bool accumulate, bool transpose, hipStream_t s) {
   if (!pl->m2l_bf16) return FC2T2_EUNSUPPORTED;
   const TableGeom g = table_geom(pl);
   const unsigned short* base = (const unsigned short*)pl->m2l_bf16 + (transpose ? g.dir : 0);
-  const unsigned short* Bhi = base + lvl * g.per_lvl;
-  const unsigned short* Blo = base + g.plane + lvl * g.per_lvl;
-  const float* fin = (const float*)in;
-  float* fout = (float*)out;
   fc2t2_status st = FC2T2_EUNSUPPORTED;
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {
     using S = decltype(shape);
     switch (pl->prec) {
       case FC2T2_M2L_BF16:
-        st = launch_cfg<typename Tile<S::D, S::P, 1>::type>(pl, lvl, fin, fout, accumulate, Bhi, Blo, s);
+        st = launch_cfg<typename Tile<S::D, S::P, 1>::type>(pl, lvl0, lvl1, ins, outs, accumulate, base, g.plane, g.per_lvl, s);
         break;
       case FC2T2_M2L_BF16X2:
-        st = launch_cfg<typename Tile<S::D, S::P, 2>::type>(pl, lvl, fin, fout, accumulate, Bhi, Blo, s);
+        st = launch_cfg<typename Tile<S::D, S::P, 2>::type>(pl, lvl0, lvl1, ins, outs, accumulate, base, g.plane, g.per_lvl, s);
         break;
       case FC2T2_M2L_BF16X3:
-        st = launch_cfg<typename Tile<S::D, S::P, 3>::type>(pl, lvl, fin, fout, accumulate, Bhi, Blo, s);
+        st = launch_cfg<typename Tile<S::D, S::P, 3>::type>(pl, lvl0, lvl1, ins, outs, accumulate, base, g.plane, g.per_lvl, s);
         break;
     }
   });

@@ -81,13 +81,17 @@ fc2t2_status launch_m2l(const fc2t2_plan_s* pl, int lvl, const void* M, void* L,
 // Transpose: GM (+)= sum_o T(o)^T GL[j - o].
 fc2t2_status launch_m2l_T(const fc2t2_plan_s* pl, int lvl, const void* GL, void* GM,
                           bool accumulate, hipStream_t s);
+// M2L (or its transpose) at every level, outputs overwritten; ins/outs indexed by level.
+fc2t2_status launch_m2l_all(const fc2t2_plan_s* pl, const void* const* ins, void* const* outs,
+                            bool transpose, hipStream_t s);
 
 // ---- m2l_mfma.hip
 bool m2l_mfma_supported(const fc2t2_plan_s* pl);
 size_t m2l_mfma_table_bytes(const fc2t2_plan_s* pl);
 fc2t2_status m2l_mfma_build_tables(fc2t2_plan_s* pl, hipStream_t s);
-fc2t2_status launch_m2l_mfma(const fc2t2_plan_s* pl, int lvl, const void* M, void* L,
-                             bool accumulate, bool transpose, hipStream_t s);
+// Levels [lvl0, lvl1) in one launch; ins/outs are indexed by level.
+fc2t2_status launch_m2l_mfma(const fc2t2_plan_s* pl, int lvl0, int lvl1, const void* const* ins,
+                             void* const* outs, bool accumulate, bool transpose, hipStream_t s);
 
 // ---- rays.hip
 size_t ray_integral_bwd_ws(const fc2t2_plan_s* pl, int64_t R);

@@ -24,19 +24,47 @@ namespace {
 constexpr int kRaySaved = FC2T2_ROOT_SAVED;
 
 // ---------------------------------------------------------------------------------------
+// Per-axis state is kept in scalars (no runtime-indexed arrays, which would live in
+// scratch memory); the axis of the next crossing is chosen with selects.
 struct Dda {
-  double o[3], r[3];
+  double ox, oy, oz, rx, ry, rz;
   double lo, h;
   int n;
   double t, t_end;
-  int c[3], step[3];
-  double tmax[3];
+  int cx, cy, cz, sx, sy, sz;
+  double mx, my, mz;   // parameter of the next plane crossing per axis
   bool live;
 
-  __device__ double next_plane(int j) const {
-    if (step[j] == 0) return INFINITY;
-    const int k = step[j] > 0 ? c[j] + 1 : c[j];
-    return (lo + (double)k * h - o[j]) / r[j];
+  __device__ static double plane_t(double lo, double h, int c, int st, double o, double r) {
+    if (st == 0) return INFINITY;
+    const int k = st > 0 ? c + 1 : c;
+    return (lo + (double)k * h - o) / r;
+  }
+
+  __device__ static void start_axis(double lo, double hi, double h, int n, double o, double r, double& ta,
+                                    double& tb, bool& live) {
+    if (r == 0.0) {
+      if (o < lo || o > hi) live = false;
+    } else {
+      const double a = (lo - o) / r, b = (hi - o) / r;
+      ta = fmax(ta, fmin(a, b));
+      tb = fmin(tb, fmax(a, b));
+    }
+  }
+
+  __device__ static void first_cell(double lo, double h, int n, double o, double r, double ta, int& c, int& st,
+                                    double& m) {
+    st = r > 0.0 ? 1 : (r < 0.0 ? -1 : 0);
+    const int cj = (int)floor((o + ta * r - lo) / h);
+    c = cj < 0 ? 0 : (cj > n - 1 ? n - 1 : cj);
+    m = plane_t(lo, h, c, st, o, r);
+    // the entry point can sit on a plane: move past planes that lie at or behind ta
+    for (int guard = 0; guard < 2 && st != 0 && m <= ta; ++guard) {
+      const int nc = c + st;
+      if (nc < 0 || nc > n - 1) break;
+      c = nc;
+      m = plane_t(lo, h, c, st, o, r);
+    }
   }
 
   __device__ void init(const double (&o_)[3], const double (&r_)[3], double t0, double t1, double lo_,
@@ -44,52 +72,41 @@ struct Dda {
     lo = lo_;
     h = h_;
     n = n_;
+    ox = o_[0]; oy = o_[1]; oz = o_[2];
+    rx = r_[0]; ry = r_[1]; rz = r_[2];
     double ta = t0, tb = t1;
     live = true;
-    for (int j = 0; j < 3; ++j) {
-      o[j] = o_[j];
-      r[j] = r_[j];
-      if (r[j] == 0.0) {
-        if (o[j] < lo_ || o[j] > hi_) live = false;
-      } else {
-        const double a = (lo_ - o[j]) / r[j], b = (hi_ - o[j]) / r[j];
-        ta = fmax(ta, fmin(a, b));
-        tb = fmin(tb, fmax(a, b));
-      }
-    }
+    start_axis(lo_, hi_, h_, n_, ox, rx, ta, tb, live);
+    start_axis(lo_, hi_, h_, n_, oy, ry, ta, tb, live);
+    start_axis(lo_, hi_, h_, n_, oz, rz, ta, tb, live);
     if (!(tb > ta)) live = false;
     t = ta;
     t_end = tb;
-    for (int j = 0; j < 3; ++j) {
-      step[j] = r[j] > 0.0 ? 1 : (r[j] < 0.0 ? -1 : 0);
-      const double x = o[j] + ta * r[j];
-      int cj = (int)floor((x - lo) / h);
-      c[j] = cj < 0 ? 0 : (cj > n - 1 ? n - 1 : cj);
-      tmax[j] = next_plane(j);
-      // the entry point can sit on a plane: move past planes that lie at or behind ta
-      for (int guard = 0; guard < 2 && step[j] != 0 && tmax[j] <= ta; ++guard) {
-        const int nc = c[j] + step[j];
-        if (nc < 0 || nc > n - 1) break;
-        c[j] = nc;
-        tmax[j] = next_plane(j);
-      }
-    }
+    first_cell(lo, h, n, ox, rx, ta, cx, sx, mx);
+    first_cell(lo, h, n, oy, ry, ta, cy, sy, my);
+    first_cell(lo, h, n, oz, rz, ta, cz, sz, mz);
   }
 
   // Next segment of positive length: cell index (row-major) and [ta, tb].
   __device__ bool next(int64_t& cell, int (&cc)[3], double& ta, double& tb) {
     while (live && t < t_end) {
-      int j = 0;
-      if (tmax[1] < tmax[j]) j = 1;
-      if (tmax[2] < tmax[j]) j = 2;
-      const double tn = fmin(tmax[j], t_end);
+      const int j = (my < mx) ? ((mz < my) ? 2 : 1) : ((mz < mx) ? 2 : 0);
+      const double tm = j == 0 ? mx : (j == 1 ? my : mz);
+      const double tn = fmin(tm, t_end);
       const double t_prev = t;
-      cc[0] = c[0]; cc[1] = c[1]; cc[2] = c[2];
+      cc[0] = cx; cc[1] = cy; cc[2] = cz;
       t = tn;
       if (tn < t_end) {
-        const int nc = c[j] + step[j];
-        if (nc < 0 || nc > n - 1) live = false;
-        else { c[j] = nc; tmax[j] = next_plane(j); }
+        if (j == 0) {
+          cx += sx;
+          if (cx < 0 || cx > n - 1) live = false; else mx = plane_t(lo, h, cx, sx, ox, rx);
+        } else if (j == 1) {
+          cy += sy;
+          if (cy < 0 || cy > n - 1) live = false; else my = plane_t(lo, h, cy, sy, oy, ry);
+        } else {
+          cz += sz;
+          if (cz < 0 || cz > n - 1) live = false; else mz = plane_t(lo, h, cz, sz, oz, rz);
+        }
       } else {
         live = false;
       }
@@ -125,71 +142,58 @@ __device__ __forceinline__ void gl3(double s, double (&v)[3], double (&wt)[3]) {
   wt[2] = wt[1];
 }
 
-// Integral over v in [0, s] of prod_j (d_j + q_j v)^e_j / e_j!  (one multi-index, |e| <= 5).
-__device__ double seg_integral(const int (&e)[3], const double (&d)[3], const double (&q)[3], double s) {
-  double v[3], wt[3];
-  gl3(s, v, wt);
-  double acc = 0.0;
-  for (int i = 0; i < 3; ++i) {
-    double m = 1.0;
-    for (int j = 0; j < 3; ++j) {
-      const double x = d[j] + q[j] * v[i];
-      for (int a = 1; a <= e[j]; ++a) m *= x / a;
-    }
-    acc += wt[i] * m;
-  }
-  return acc;
-}
-
-// Exponents of the lane's multi-index in the graded order (lane < P).
-template <int D, int K>
-__device__ void lane_exponents(int lane, int (&e)[3]) {
-  int idx = 0;
-  e[0] = e[1] = e[2] = 0;
-  for (int t = 0; t <= K; ++t)
-    for (int a = t; a >= 0; --a)
-      for (int b = t - a; b >= 0; --b) {
-        if (idx == lane) { e[0] = a; e[1] = b; e[2] = t - a - b; }
-        ++idx;
-      }
-}
-
 // ---------------------------------------------------------------------------------------
-// Line integral: one wavefront per ray, lane k accumulates L[c, k] * I_k over the segments.
 template <class S, typename T>
-__global__ void __launch_bounds__(256) ray_integral_kernel(const T* __restrict__ L, const T* __restrict__ O,
-                                                           const T* __restrict__ Rd, int64_t R, double t0,
-                                                           double t1, double lo, double hi, double h, int n,
-                                                           int64_t G, T* __restrict__ y, int C) {
-  constexpr int P = S::P, Ppad = S::Ppad;
-  const int lane = threadIdx.x & 63;
-  const int64_t ray = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+__device__ __forceinline__ void load_row_f64(const T* __restrict__ src, double (&c)[S::P]) {
+#pragma unroll
+  for (int k = 0; k < S::P; ++k) c[k] = (double)src[k];
+}
+
+// Line integral: one thread per ray; each segment's integral is the three-point
+// Gauss-Legendre sum of the cell polynomial (exact for K <= 5), accumulated in FP64.
+template <class S, typename T>
+__global__ void __launch_bounds__(64) ray_integral_kernel(const T* __restrict__ L, const T* __restrict__ O,
+                                                          const T* __restrict__ Rd, int64_t R, double t0,
+                                                          double t1, double lo, double hi, double h, int n,
+                                                          int64_t G, T* __restrict__ y, int C) {
+  static_assert(S::K <= 5, "three Gauss-Legendre nodes integrate degree <= 5 exactly");
+  constexpr int P = S::P, Ppad = S::Ppad, K = S::K;
+  const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int ch = blockIdx.y;
   if (ray >= R) return;
-  int e[3];
-  lane_exponents<S::D, S::K>(lane < P ? lane : 0, e);
   double o[3], r[3];
   load3(O, ray, o);
   load3(Rd, ray, r);
   Dda dda;
   dda.init(o, r, t0, t1, lo, hi, h, n);
-  const double q[3] = {r[0] / h, r[1] / h, r[2] / h};
+  const double ih = 1.0 / h;
+  const double q[3] = {r[0] * ih, r[1] * ih, r[2] * ih};
   const T* __restrict__ Lc = L + (int64_t)ch * G * Ppad;
   double acc = 0.0;
   int64_t cell;
   int cc[3];
   double ta, tb;
   while (dda.next(cell, cc, ta, tb)) {
-    if (lane < P) {
-      double d[3];
+    double row[P];
+    load_row_f64<S>(Lc + cell * Ppad, row);
+    double d[3];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) d[j] = (o[j] + ta * r[j] - (lo + (cc[j] + 0.5) * h)) / h;
-      acc += (double)Lc[cell * Ppad + lane] * seg_integral(e, d, q, tb - ta);
+    for (int j = 0; j < 3; ++j) d[j] = (o[j] + ta * r[j] - (lo + (cc[j] + 0.5) * h)) * ih;
+    double nodes[3], wt[3];
+    gl3(tb - ta, nodes, wt);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double u[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) u[j] = d[j] + q[j] * nodes[i];
+      double pw[3][K + 1];
+      power_table<S>(u, pw);
+      double val, g[3], hs[6];
+      eval_poly<S, double, false, false>(row, pw, val, g, hs);
+      acc += wt[i] * val;
     }
   }
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
-  if (lane == 0) y[ray * C + ch] = (T)acc;
+  y[ray * C + ch] = (T)acc;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -378,10 +382,13 @@ __device__ void line2poly(const double* Lrow, const double (&d)[3], const double
     }
 }
 
-template <class S, typename T>
-__device__ __forceinline__ void load_row_f64(const T* __restrict__ src, double (&c)[S::P]) {
+// Upper bound of the polynomial a on [0, s]: a_0 + sum_{m >= 1} max(0, a_m) s^m.
+template <int K>
+__device__ __forceinline__ double upper_bound(const double (&a)[6], double s) {
+  double ub = a[0], sp = 1.0;
 #pragma unroll
-  for (int k = 0; k < S::P; ++k) c[k] = (double)src[k];
+  for (int m = 1; m <= K; ++m) { sp *= s; ub += fmax(a[m], 0.0) * sp; }
+  return ub;
 }
 
 template <class S>
@@ -458,7 +465,8 @@ __global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, c
       for (int j = 0; j < 3; ++j) d[j] = (o[j] + ta * r[j] - (lo + (cc[j] + 0.5) * h)) / h;
       double a[6];
       line2poly<S>(row, d, q, a);
-      fmax_v = fmax(fmax_v, seg_max<S>(a, tb - ta));
+      // the exact segment maximum only matters when the segment can beat the best so far
+      if (!any || upper_bound<K>(a, tb - ta) > fmax_v) fmax_v = fmax(fmax_v, seg_max<S>(a, tb - ta));
       any = true;
     }
   }
@@ -495,7 +503,8 @@ __global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, c
         found = 1;
         break;
       }
-      const double v = first_upward<S>(g, s);
+      // no upward crossing is possible when g stays below zero on the whole segment
+      const double v = upper_bound<K>(g, s) < 0.0 ? -1.0 : first_upward<S>(g, s);
       if (v >= 0.0) {
         t_star = ta + v;
         rc[0] = cc[0]; rc[1] = cc[1]; rc[2] = cc[2];
@@ -655,16 +664,16 @@ fc2t2_status launch_ray_integral(const fc2t2_plan_s* pl, const void* L, const vo
                                  double t1, int64_t R, void* y, hipStream_t s) {
   if (R == 0) return FC2T2_OK;
   fc2t2_status st = FC2T2_EUNSUPPORTED;
-  const dim3 grid((unsigned)ceil_div(R * 64, 256), pl->C);
+  const dim3 grid((unsigned)ceil_div(R, 64), pl->C);
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {
     using S = decltype(shape);
     if constexpr (S::D == 3) {
       if (pl->io == FC2T2_IO_F64)
-        hipLaunchKernelGGL((ray_integral_kernel<S, double>), grid, dim3(256), 0, s, (const double*)L,
+        hipLaunchKernelGGL((ray_integral_kernel<S, double>), grid, dim3(64), 0, s, (const double*)L,
                            (const double*)o, (const double*)r, R, t0, t1, pl->lo, pl->hi, pl->h0, pl->n, pl->G,
                            (double*)y, pl->C);
       else
-        hipLaunchKernelGGL((ray_integral_kernel<S, float>), grid, dim3(256), 0, s, (const float*)L,
+        hipLaunchKernelGGL((ray_integral_kernel<S, float>), grid, dim3(64), 0, s, (const float*)L,
                            (const float*)o, (const float*)r, R, t0, t1, pl->lo, pl->hi, pl->h0, pl->n, pl->G,
                            (float*)y, pl->C);
       st = FC2T2_OK;

@@ -67,24 +67,36 @@ __device__ __forceinline__ int64_t child_cell(const int (&pc)[3], int b, int n_c
 }
 
 // out[ch][I][n] = sum_b sum_{m <= n} S_b[n][m] in[ch][2I+b][m]; one thread per (parent, n).
+// Grid sizes fit in 32 bits and n is a power of two, so indices decode with shifts.
 template <int D, typename T>
 __global__ void __launch_bounds__(256) upshift_kernel(const T* __restrict__ in, T* __restrict__ out,
                                                       const ShiftEntry* __restrict__ tab,
-                                                      const int* __restrict__ beg, int P, int Ppad, int n_par,
-                                                      int64_t G_par, int64_t G_child) {
+                                                      const int* __restrict__ beg, int P, int Ppad, int lg_par,
+                                                      uint32_t G_par, uint32_t G_child) {
   constexpr int NB = 1 << D;
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= G_par * Ppad) return;
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= G_par * (uint32_t)Ppad) return;
   const int ch = blockIdx.y;
-  const int nn = (int)(tid % Ppad);
-  const int64_t I = tid / Ppad;
+  const uint32_t I = tid / (uint32_t)Ppad;
+  const int nn = (int)(tid - I * (uint32_t)Ppad);
   T acc = T(0);
   if (nn < P) {
-    int pc[3] = {0, 0, 0};
-    decode<D>(I, n_par, pc);
+    const uint32_t mask = (1u << lg_par) - 1u;
+    uint32_t pc[3] = {0, 0, 0};
+    {
+      uint32_t r = I;
+#pragma unroll
+      for (int j = D - 1; j >= 0; --j) { pc[j] = r & mask; r >>= lg_par; }
+    }
+    const int lg_child = lg_par + 1;
     const T* rows[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) rows[b] = in + ((int64_t)ch * G_child + child_cell<D>(pc, b, 2 * n_par)) * Ppad;
+    for (int b = 0; b < NB; ++b) {
+      uint32_t lin = 0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) lin = (lin << lg_child) | (2 * pc[j] + ((b >> (D - 1 - j)) & 1));
+      rows[b] = in + ((size_t)ch * G_child + lin) * Ppad;
+    }
     for (int e = beg[nn]; e < beg[nn + 1]; ++e) {
       const ShiftEntry en = tab[e];
       T h = T(0);
@@ -93,7 +105,7 @@ __global__ void __launch_bounds__(256) upshift_kernel(const T* __restrict__ in, 
       acc += (T)en.c * h;
     }
   }
-  out[((int64_t)ch * G_par + I) * Ppad + nn] = acc;
+  out[((size_t)ch * G_par + I) * Ppad + nn] = acc;
 }
 
 // out[ch][i][k] (+)= sum_{m >= k} S_{b(i)}[m][k] in[ch][i/2][m]; one thread per (child, k).
@@ -101,28 +113,30 @@ template <int D, typename T>
 __global__ void __launch_bounds__(256) downshift_kernel(const T* __restrict__ in, T* __restrict__ out,
                                                         const ShiftEntry* __restrict__ tab,
                                                         const int* __restrict__ beg, int P, int Ppad,
-                                                        int n_child, int64_t G_child, int64_t G_par,
+                                                        int lg_child, uint32_t G_child, uint32_t G_par,
                                                         int accumulate) {
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= G_child * Ppad) return;
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= G_child * (uint32_t)Ppad) return;
   const int ch = blockIdx.y;
-  const int k = (int)(tid % Ppad);
-  const int64_t i = tid / Ppad;
+  const uint32_t i = tid / (uint32_t)Ppad;
+  const int k = (int)(tid - i * (uint32_t)Ppad);
   T acc = T(0);
   if (k < P) {
-    int ci[3];
-    decode<D>(i, n_child, ci);
-    int pc[3] = {0, 0, 0};
+    const uint32_t mask = (1u << lg_child) - 1u;
+    uint32_t r = i, par = 0;
     int b = 0;
+    uint32_t pcs[3] = {0, 0, 0};
 #pragma unroll
-    for (int j = 0; j < D; ++j) { pc[j] = ci[j] >> 1; b = (b << 1) | (ci[j] & 1); }
-    const T* __restrict__ row = in + ((int64_t)ch * G_par + encode<D>(pc, n_child / 2)) * Ppad;
+    for (int j = D - 1; j >= 0; --j) { pcs[j] = r & mask; r >>= lg_child; }
+#pragma unroll
+    for (int j = 0; j < D; ++j) { par = (par << (lg_child - 1)) | (pcs[j] >> 1); b = (b << 1) | (int)(pcs[j] & 1u); }
+    const T* __restrict__ row = in + ((size_t)ch * G_par + par) * Ppad;
     for (int e = beg[k]; e < beg[k + 1]; ++e) {
       const ShiftEntry en = tab[e];
-      acc += (T)(en.c * (double)sigma_sign(en.pi, b)) * row[en.m];
+      acc += (T)en.c * (T)sigma_sign(en.pi, b) * row[en.m];
     }
   }
-  T* dst = out + ((int64_t)ch * G_child + i) * Ppad + k;
+  T* dst = out + ((size_t)ch * G_child + i) * Ppad + k;
   if (accumulate) *dst += acc; else *dst = acc;
 }
 
@@ -277,14 +291,14 @@ fc2t2_status launch_upshift(const fc2t2_plan_s* pl, int lvl_child, const void* i
   const int* beg = (const int*)((const char*)pl->shift + pl->shift_beg_off);
   if (pl->io == FC2T2_IO_F64) {
     if (pl->dim == 2)
-      hipLaunchKernelGGL((upshift_kernel<2, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, pl->nl[lp], pl->Gl[lp], pl->Gl[lvl_child]);
+      hipLaunchKernelGGL((upshift_kernel<2, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, lg2i(pl->nl[lp]), (uint32_t)pl->Gl[lp], (uint32_t)pl->Gl[lvl_child]);
     else
-      hipLaunchKernelGGL((upshift_kernel<3, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, pl->nl[lp], pl->Gl[lp], pl->Gl[lvl_child]);
+      hipLaunchKernelGGL((upshift_kernel<3, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, lg2i(pl->nl[lp]), (uint32_t)pl->Gl[lp], (uint32_t)pl->Gl[lvl_child]);
   } else {
     if (pl->dim == 2)
-      hipLaunchKernelGGL((upshift_kernel<2, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, pl->nl[lp], pl->Gl[lp], pl->Gl[lvl_child]);
+      hipLaunchKernelGGL((upshift_kernel<2, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, lg2i(pl->nl[lp]), (uint32_t)pl->Gl[lp], (uint32_t)pl->Gl[lvl_child]);
     else
-      hipLaunchKernelGGL((upshift_kernel<3, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, pl->nl[lp], pl->Gl[lp], pl->Gl[lvl_child]);
+      hipLaunchKernelGGL((upshift_kernel<3, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, lg2i(pl->nl[lp]), (uint32_t)pl->Gl[lp], (uint32_t)pl->Gl[lvl_child]);
   }
   FC2T2_LAUNCH_CHECK();
   return FC2T2_OK;
@@ -299,14 +313,14 @@ fc2t2_status launch_downshift(const fc2t2_plan_s* pl, int lvl_child, const void*
   const int* beg = (const int*)((const char*)pl->shift + pl->shift_beg_off) + (pl->P + 1);
   if (pl->io == FC2T2_IO_F64) {
     if (pl->dim == 2)
-      hipLaunchKernelGGL((downshift_kernel<2, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, pl->nl[lvl_child], pl->Gl[lvl_child], pl->Gl[lp], acc);
+      hipLaunchKernelGGL((downshift_kernel<2, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, lg2i(pl->nl[lvl_child]), (uint32_t)pl->Gl[lvl_child], (uint32_t)pl->Gl[lp], acc);
     else
-      hipLaunchKernelGGL((downshift_kernel<3, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, pl->nl[lvl_child], pl->Gl[lvl_child], pl->Gl[lp], acc);
+      hipLaunchKernelGGL((downshift_kernel<3, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, lg2i(pl->nl[lvl_child]), (uint32_t)pl->Gl[lvl_child], (uint32_t)pl->Gl[lp], acc);
   } else {
     if (pl->dim == 2)
-      hipLaunchKernelGGL((downshift_kernel<2, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, pl->nl[lvl_child], pl->Gl[lvl_child], pl->Gl[lp], acc);
+      hipLaunchKernelGGL((downshift_kernel<2, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, lg2i(pl->nl[lvl_child]), (uint32_t)pl->Gl[lvl_child], (uint32_t)pl->Gl[lp], acc);
     else
-      hipLaunchKernelGGL((downshift_kernel<3, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, pl->nl[lvl_child], pl->Gl[lvl_child], pl->Gl[lp], acc);
+      hipLaunchKernelGGL((downshift_kernel<3, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, lg2i(pl->nl[lvl_child]), (uint32_t)pl->Gl[lvl_child], (uint32_t)pl->Gl[lp], acc);
   }
   FC2T2_LAUNCH_CHECK();
   return FC2T2_OK;
@@ -314,7 +328,13 @@ fc2t2_status launch_downshift(const fc2t2_plan_s* pl, int lvl_child, const void*
 
 fc2t2_status launch_m2l(const fc2t2_plan_s* pl, int lvl, const void* M, void* L, bool accumulate,
                         hipStream_t s) {
-  if (pl->prec >= FC2T2_M2L_BF16) return launch_m2l_mfma(pl, lvl, M, L, accumulate, false, s);
+  if (pl->prec >= FC2T2_M2L_BF16) {
+    const void* ins[kMaxLevels] = {};
+    void* outs[kMaxLevels] = {};
+    ins[lvl] = M;
+    outs[lvl] = L;
+    return launch_m2l_mfma(pl, lvl, lvl + 1, ins, outs, accumulate, false, s);
+  }
   const int64_t work = pl->Gl[lvl] * pl->Ppad;
   const dim3 grid((unsigned)ceil_div(work, 256), pl->C);
   const int fin = lvl == 0, acc = accumulate ? 1 : 0;
@@ -335,7 +355,13 @@ fc2t2_status launch_m2l(const fc2t2_plan_s* pl, int lvl, const void* M, void* L,
 
 fc2t2_status launch_m2l_T(const fc2t2_plan_s* pl, int lvl, const void* GL, void* GM, bool accumulate,
                           hipStream_t s) {
-  if (pl->prec >= FC2T2_M2L_BF16) return launch_m2l_mfma(pl, lvl, GL, GM, accumulate, true, s);
+  if (pl->prec >= FC2T2_M2L_BF16) {
+    const void* ins[kMaxLevels] = {};
+    void* outs[kMaxLevels] = {};
+    ins[lvl] = GL;
+    outs[lvl] = GM;
+    return launch_m2l_mfma(pl, lvl, lvl + 1, ins, outs, accumulate, true, s);
+  }
   const int64_t work = pl->Gl[lvl] * pl->Ppad;
   const dim3 grid((unsigned)ceil_div(work, 256), pl->C);
   const int fin = lvl == 0, acc = accumulate ? 1 : 0;
@@ -351,6 +377,17 @@ fc2t2_status launch_m2l_T(const fc2t2_plan_s* pl, int lvl, const void* GL, void*
       hipLaunchKernelGGL((m2l_T_kernel<3, float>), grid, dim3(256), 0, s, (const float*)GL, (float*)GM, level_tensor<float>(pl, lvl), pl->P, pl->Ppad, pl->nl[lvl], pl->Gl[lvl], fin, acc);
   }
   FC2T2_LAUNCH_CHECK();
+  return FC2T2_OK;
+}
+
+fc2t2_status launch_m2l_all(const fc2t2_plan_s* pl, const void* const* ins, void* const* outs, bool transpose,
+                            hipStream_t s) {
+  if (pl->prec >= FC2T2_M2L_BF16) return launch_m2l_mfma(pl, 0, pl->levels, ins, outs, false, transpose, s);
+  for (int l = 0; l < pl->levels; ++l) {
+    const fc2t2_status st = transpose ? launch_m2l_T(pl, l, ins[l], outs[l], false, s)
+                                      : launch_m2l(pl, l, ins[l], outs[l], false, s);
+    if (st) return st;
+  }
   return FC2T2_OK;
 }
 

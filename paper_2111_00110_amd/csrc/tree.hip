@@ -108,36 +108,48 @@ __global__ void __launch_bounds__(256) upshift_kernel(const T* __restrict__ in, 
   out[((size_t)ch * G_par + I) * Ppad + nn] = acc;
 }
 
-// out[ch][i][k] (+)= sum_{m >= k} S_{b(i)}[m][k] in[ch][i/2][m]; one thread per (child, k).
+// out[ch][2I+b][k] (+)= sum_{m >= k} S_b[m][k] in[ch][I][m]; one thread per (parent, k)
+// producing coefficient k of all 2^d children (the list is walked once per parent).
 template <int D, typename T>
 __global__ void __launch_bounds__(256) downshift_kernel(const T* __restrict__ in, T* __restrict__ out,
                                                         const ShiftEntry* __restrict__ tab,
                                                         const int* __restrict__ beg, int P, int Ppad,
-                                                        int lg_child, uint32_t G_child, uint32_t G_par,
+                                                        int lg_par, uint32_t G_par, uint32_t G_child,
                                                         int accumulate) {
+  constexpr int NB = 1 << D;
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= G_child * (uint32_t)Ppad) return;
+  if (tid >= G_par * (uint32_t)Ppad) return;
   const int ch = blockIdx.y;
-  const uint32_t i = tid / (uint32_t)Ppad;
-  const int k = (int)(tid - i * (uint32_t)Ppad);
-  T acc = T(0);
+  const uint32_t I = tid / (uint32_t)Ppad;
+  const int k = (int)(tid - I * (uint32_t)Ppad);
+  const uint32_t mask = (1u << lg_par) - 1u;
+  uint32_t pc[3] = {0, 0, 0};
+  {
+    uint32_t r = I;
+#pragma unroll
+    for (int j = D - 1; j >= 0; --j) { pc[j] = r & mask; r >>= lg_par; }
+  }
+  T acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = T(0);
   if (k < P) {
-    const uint32_t mask = (1u << lg_child) - 1u;
-    uint32_t r = i, par = 0;
-    int b = 0;
-    uint32_t pcs[3] = {0, 0, 0};
-#pragma unroll
-    for (int j = D - 1; j >= 0; --j) { pcs[j] = r & mask; r >>= lg_child; }
-#pragma unroll
-    for (int j = 0; j < D; ++j) { par = (par << (lg_child - 1)) | (pcs[j] >> 1); b = (b << 1) | (int)(pcs[j] & 1u); }
-    const T* __restrict__ row = in + ((size_t)ch * G_par + par) * Ppad;
+    const T* __restrict__ row = in + ((size_t)ch * G_par + I) * Ppad;
     for (int e = beg[k]; e < beg[k + 1]; ++e) {
       const ShiftEntry en = tab[e];
-      acc += (T)en.c * (T)sigma_sign(en.pi, b) * row[en.m];
+      const T v = (T)en.c * row[en.m];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[b] += (T)sigma_sign(en.pi, b) * v;
     }
   }
-  T* dst = out + ((size_t)ch * G_child + i) * Ppad + k;
-  if (accumulate) *dst += acc; else *dst = acc;
+  const int lg_child = lg_par + 1;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    uint32_t lin = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) lin = (lin << lg_child) | (2 * pc[j] + ((b >> (D - 1 - j)) & 1));
+    T* dst = out + ((size_t)ch * G_child + lin) * Ppad + k;
+    if (accumulate) *dst += acc[b]; else *dst = acc[b];
+  }
 }
 
 __device__ __forceinline__ bool offset_ok(int i, int o, int n_l) {
@@ -307,20 +319,22 @@ fc2t2_status launch_upshift(const fc2t2_plan_s* pl, int lvl_child, const void* i
 fc2t2_status launch_downshift(const fc2t2_plan_s* pl, int lvl_child, const void* in, void* out,
                               bool accumulate, hipStream_t s) {
   const int lp = lvl_child + 1;
-  const dim3 grid((unsigned)ceil_div(pl->Gl[lvl_child] * pl->Ppad, 256), pl->C);
+  const dim3 grid((unsigned)ceil_div(pl->Gl[lp] * pl->Ppad, 256), pl->C);
   const int acc = accumulate ? 1 : 0;
   const ShiftEntry* tab = (const ShiftEntry*)pl->shift;
   const int* beg = (const int*)((const char*)pl->shift + pl->shift_beg_off) + (pl->P + 1);
+  const int lg = lg2i(pl->nl[lp]);
+  const uint32_t gp = (uint32_t)pl->Gl[lp], gc = (uint32_t)pl->Gl[lvl_child];
   if (pl->io == FC2T2_IO_F64) {
     if (pl->dim == 2)
-      hipLaunchKernelGGL((downshift_kernel<2, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, lg2i(pl->nl[lvl_child]), (uint32_t)pl->Gl[lvl_child], (uint32_t)pl->Gl[lp], acc);
+      hipLaunchKernelGGL((downshift_kernel<2, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, lg, gp, gc, acc);
     else
-      hipLaunchKernelGGL((downshift_kernel<3, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, lg2i(pl->nl[lvl_child]), (uint32_t)pl->Gl[lvl_child], (uint32_t)pl->Gl[lp], acc);
+      hipLaunchKernelGGL((downshift_kernel<3, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, lg, gp, gc, acc);
   } else {
     if (pl->dim == 2)
-      hipLaunchKernelGGL((downshift_kernel<2, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, lg2i(pl->nl[lvl_child]), (uint32_t)pl->Gl[lvl_child], (uint32_t)pl->Gl[lp], acc);
+      hipLaunchKernelGGL((downshift_kernel<2, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, lg, gp, gc, acc);
     else
-      hipLaunchKernelGGL((downshift_kernel<3, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, lg2i(pl->nl[lvl_child]), (uint32_t)pl->Gl[lvl_child], (uint32_t)pl->Gl[lp], acc);
+      hipLaunchKernelGGL((downshift_kernel<3, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, lg, gp, gc, acc);
   }
   FC2T2_LAUNCH_CHECK();
   return FC2T2_OK;

@@ -245,12 +245,14 @@ def p2m(geo: Geometry, p: np.ndarray, w: np.ndarray) -> np.ndarray:
     d, n = geo.dim, geo.n
     w = np.asarray(w, dtype=np.float64).reshape(len(p), -1)
     C = w.shape[1]
-    cell = geo.cell_index(p)
-    dvec = np.asarray(p, dtype=np.float64) - geo.centre(0, cell)
-    mono = monomials(dvec, geo.idx)                                   # [N, P]
     M = np.zeros((C,) + (n,) * d + (geo.P,))
-    for ch in range(C):
-        np.add.at(M[ch], tuple(cell[:, j] for j in range(d)), mono * w[:, ch:ch + 1])
+    for a in range(0, len(p), 1 << 20):          # chunks bound the monomial array's memory
+        pc = p[a:a + (1 << 20)]
+        cell = geo.cell_index(pc)
+        dvec = np.asarray(pc, dtype=np.float64) - geo.centre(0, cell)
+        mono = monomials(dvec, geo.idx)                               # [chunk, P]
+        for ch in range(C):
+            np.add.at(M[ch], tuple(cell[:, j] for j in range(d)), mono * w[a:a + (1 << 20), ch:ch + 1])
     return M
 
 

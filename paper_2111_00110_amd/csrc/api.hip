@@ -82,34 +82,22 @@ namespace fc2t2 {
 // every level (one launch), then L2L down the pyramid accumulating into each finer level.
 fc2t2_status expand_from_moments(const fc2t2_plan_s* pl, void** Mlv, void** Llv, void* L0, hipStream_t s) {
   Llv[0] = L0;
-  for (int l = 0; l + 1 < pl->levels; ++l) {
-    fc2t2_status st = launch_upshift(pl, l, Mlv[l], Mlv[l + 1], s);
-    if (st) return st;
-  }
-  fc2t2_status st = launch_m2l_all(pl, (const void* const*)Mlv, Llv, false, s);
+  fc2t2_status st = upshift_pyramid(pl, Mlv, s);
   if (st) return st;
-  for (int l = pl->levels - 2; l >= 0; --l) {
-    st = launch_downshift(pl, l, Llv[l + 1], Llv[l], true, s);
-    if (st) return st;
-  }
-  return FC2T2_OK;
+  st = launch_m2l_all(pl, (const void* const*)Mlv, Llv, false, s);
+  if (st) return st;
+  return downshift_pyramid(pl, Llv, s);
 }
 
 // Transpose of expand_from_moments: G_L0 -> G_M0 (L2L^T up, M2L^T at every level, M2M^T down).
 fc2t2_status expand_T_to_moments(const fc2t2_plan_s* pl, const void* GL0, void** GLlv, void** GMlv,
                                  hipStream_t s) {
   GLlv[0] = (void*)GL0;
-  for (int l = 0; l + 1 < pl->levels; ++l) {
-    fc2t2_status st = launch_upshift(pl, l, GLlv[l], GLlv[l + 1], s);   // L2L^T
-    if (st) return st;
-  }
-  fc2t2_status st = launch_m2l_all(pl, (const void* const*)GLlv, GMlv, true, s);
+  fc2t2_status st = upshift_pyramid(pl, GLlv, s);          // L2L^T
   if (st) return st;
-  for (int l = pl->levels - 2; l >= 0; --l) {
-    st = launch_downshift(pl, l, GMlv[l + 1], GMlv[l], true, s);       // M2M^T
-    if (st) return st;
-  }
-  return FC2T2_OK;
+  st = launch_m2l_all(pl, (const void* const*)GLlv, GMlv, true, s);
+  if (st) return st;
+  return downshift_pyramid(pl, GMlv, s);                     // M2M^T
 }
 
 }  // namespace fc2t2
@@ -168,6 +156,8 @@ fc2t2_status fc2t2_eval_backward(fc2t2_plan plan, const void* L, const void* q, 
     SortBufs sb = carve_sort(c, plan, M);
     fc2t2_status st = bin_and_sort(plan, q, M, sb, stream);
     if (st) return st;
+    if (gq && plan->C == 1)   // one pass over the sorted queries produces both
+      return launch_l2p_T_qgrad(plan, L, q, gy, M, sb.starts, sb.perm, gL, gq, stream);
     st = launch_l2p_T(plan, q, gy, M, sb.starts, sb.perm, gL, stream);
     if (st) return st;
   }

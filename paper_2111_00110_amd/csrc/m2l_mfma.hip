@@ -229,6 +229,13 @@ __global__ void __launch_bounds__(C::THREADS) m2l_mfma_kernel(const M2LBatch bat
       const int ob = D == 3 ? ((ox + 3) * 7 + (oy + 3)) * 7 + (oz + 3) : (ox + 3) * 7 + (oy + 3);
       return (((int64_t)ob * (P8 / 8) + n8) * NTC + row) * 8;
     };
+    auto fetch_b = [&](int64_t bb, uint4 (&fh)[NT], uint4 (&fl)[NT]) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        fh[t] = *reinterpret_cast<const uint4*>(Bhi + bb + (int64_t)t * 16 * 8);
+        if constexpr (PASSES >= 2) fl[t] = *reinterpret_cast<const uint4*>(Blo + bb + (int64_t)t * 16 * 8);
+      }
+    };
     auto advance = [&](int& qx, int& qy, int& qz) {
       if constexpr (D == 3) {
         qz += 4;
@@ -239,14 +246,7 @@ __global__ void __launch_bounds__(C::THREADS) m2l_mfma_kernel(const M2LBatch bat
       }
     };
     uint4 nbh[NT], nbl[NT];
-    {
-      const int64_t bb = b_base(ex, ey, ez);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        nbh[t] = *reinterpret_cast<const uint4*>(Bhi + bb + (int64_t)t * 16 * 8);
-        if constexpr (PASSES >= 2) nbl[t] = *reinterpret_cast<const uint4*>(Blo + bb + (int64_t)t * 16 * 8);
-      }
-    }
+    fetch_b(b_base(ex, ey, ez), nbh, nbl);
     for (int s = 0; s < KSTEPS; ++s) {
       bf16x8 bh[NT], bl[NT];
 #pragma unroll
@@ -259,12 +259,7 @@ __global__ void __launch_bounds__(C::THREADS) m2l_mfma_kernel(const M2LBatch bat
       // prefetch the next step's B fragments
       if (s + 1 < KSTEPS) {
         advance(ex, ey, ez);
-        const int64_t bb = b_base(ex, ey, ez);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          nbh[t] = *reinterpret_cast<const uint4*>(Bhi + bb + (int64_t)t * 16 * 8);
-          if constexpr (PASSES >= 2) nbl[t] = *reinterpret_cast<const uint4*>(Blo + bb + (int64_t)t * 16 * 8);
-        }
+        fetch_b(b_base(ex, ey, ez), nbh, nbl);
       }
 #pragma unroll
       for (int m = 0; m < RM; ++m) {

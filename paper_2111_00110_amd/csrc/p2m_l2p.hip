@@ -44,12 +44,42 @@ struct PointMonomials {
   int C;
   T inv_h;
   __device__ __forceinline__ void operator()(uint32_t idx, const T (&centre)[3], int ch,
-                                             T (&v)[S::P]) const {
+                                             T (&v)[S::P], int64_t) const {
     T u[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int j = 0; j < S::D; ++j) u[j] = (x[(int64_t)idx * S::D + j] - centre[j]) * inv_h;
     monomials<S>(u, v);
     const T a = wt[(int64_t)idx * C + ch];
+#pragma unroll
+    for (int k = 0; k < S::P; ++k) v[k] *= a;
+  }
+};
+
+// Transpose of L2P fused with the query gradient (one channel): besides the record's
+// monomials times gy, adds gy * grad f(q) to gq[q] using the cell's local row.  Each
+// query is one record, so the gq writes do not collide.
+template <class S, typename T>
+struct QueryMonomialsGrad {
+  const T* __restrict__ q;     // [M][D]
+  const T* __restrict__ gy;    // [M]
+  const T* __restrict__ L;     // [G][Ppad]
+  T* __restrict__ gq;          // [M][D]
+  T inv_h;
+  __device__ __forceinline__ void operator()(uint32_t idx, const T (&centre)[3], int, T (&v)[S::P],
+                                             int64_t cell) const {
+    T u[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int j = 0; j < S::D; ++j) u[j] = (q[(int64_t)idx * S::D + j] - centre[j]) * inv_h;
+    T pw[3][S::K + 1];
+    power_table<S>(u, pw);
+    const T a = gy[idx];
+    T row[S::Ppad];
+    load_row<S::Ppad>(L + cell * S::Ppad, row);
+    T val, g[3], hs[6];
+    eval_poly<S, T, true, false>(row, pw, val, g, hs);
+#pragma unroll
+    for (int j = 0; j < S::D; ++j) gq[(int64_t)idx * S::D + j] += a * g[j] * inv_h;
+    monomials<S>(u, v);
 #pragma unroll
     for (int k = 0; k < S::P; ++k) v[k] *= a;
   }
@@ -180,6 +210,25 @@ fc2t2_status launch_l2p_T(const fc2t2_plan_s* pl, const void* q, const void* gy,
                           const uint32_t* starts, const uint32_t* perm, void* gL, hipStream_t s) {
   return pl->io == FC2T2_IO_F64 ? reduce_points<double>(pl, q, gy, M, starts, perm, gL, true, s)
                                 : reduce_points<float>(pl, q, gy, M, starts, perm, gL, true, s);
+}
+
+template <typename T>
+fc2t2_status l2p_T_qgrad_t(const fc2t2_plan_s* pl, const void* L, const void* q, const void* gy, int64_t M,
+                           const uint32_t* starts, const uint32_t* perm, void* gL, void* gq, hipStream_t s) {
+  fc2t2_status st = FC2T2_EUNSUPPORTED;
+  dispatch_shape(pl->dim, pl->K, [&](auto shape) {
+    using S = decltype(shape);
+    QueryMonomialsGrad<S, T> fn{(const T*)q, (const T*)gy, (const T*)L, (T*)gq, (T)(1.0 / pl->h0)};
+    st = launch_reduce_cells<S, T>(pl, starts, perm, M, (T*)gL, true, fn, s);
+  });
+  return st;
+}
+
+fc2t2_status launch_l2p_T_qgrad(const fc2t2_plan_s* pl, const void* L, const void* q, const void* gy, int64_t M,
+                                const uint32_t* starts, const uint32_t* perm, void* gL, void* gq, hipStream_t s) {
+  if (pl->C != 1) return FC2T2_EUNSUPPORTED;
+  return pl->io == FC2T2_IO_F64 ? l2p_T_qgrad_t<double>(pl, L, q, gy, M, starts, perm, gL, gq, s)
+                                : l2p_T_qgrad_t<float>(pl, L, q, gy, M, starts, perm, gL, gq, s);
 }
 
 fc2t2_status launch_l2p(const fc2t2_plan_s* pl, const void* L, const void* q, int64_t M, void* y,

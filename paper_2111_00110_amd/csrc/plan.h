@@ -19,6 +19,7 @@ struct fc2t2_plan_s {
   size_t m2l_bf16_bytes = 0;
   void* shift = nullptr;          // sparse M2M/L2L shift lists (layout owned by tree.hip)
   size_t shift_beg_off = 0;
+  int shift_n_up = 0, shift_n_down = 0;
   int device = 0;
 };
 
@@ -56,6 +57,9 @@ fc2t2_status launch_p2m(const fc2t2_plan_s* pl, const void* p, const void* w, in
 // Transpose of L2P: gL += sum over the sorted queries of gy (q - c)^k / k!.
 fc2t2_status launch_l2p_T(const fc2t2_plan_s* pl, const void* q, const void* gy, int64_t M,
                           const uint32_t* starts, const uint32_t* perm, void* gL, hipStream_t s);
+// Transpose of L2P fused with gq += gy grad f(q) (one channel only).
+fc2t2_status launch_l2p_T_qgrad(const fc2t2_plan_s* pl, const void* L, const void* q, const void* gy, int64_t M,
+                                const uint32_t* starts, const uint32_t* perm, void* gL, void* gq, hipStream_t s);
 // L2P: y (overwrite), grad/hess (overwrite, optional).
 fc2t2_status launch_l2p(const fc2t2_plan_s* pl, const void* L, const void* q, int64_t M, void* y,
                         void* grad, void* hess, hipStream_t s);
@@ -75,6 +79,10 @@ fc2t2_status launch_upshift(const fc2t2_plan_s* pl, int lvl_child, const void* i
 // Down-shift: out[2I+b] (+)= S_b^T in[I] (L2L, and the transpose of M2M).
 fc2t2_status launch_downshift(const fc2t2_plan_s* pl, int lvl_child, const void* in, void* out,
                               bool accumulate, hipStream_t s);
+// Whole pyramid passes: grids[l+1] = up-shift(grids[l]) for every level, and
+// grids[l] += down-shift(grids[l+1]) from the coarsest to the finest.
+fc2t2_status upshift_pyramid(const fc2t2_plan_s* pl, void* const* grids, hipStream_t s);
+fc2t2_status downshift_pyramid(const fc2t2_plan_s* pl, void* const* grids, hipStream_t s);
 // M2L at one level: L (+)= sum_o T(o) M[i + o] over the admissible offsets.
 fc2t2_status launch_m2l(const fc2t2_plan_s* pl, int lvl, const void* M, void* L, bool accumulate,
                         hipStream_t s);

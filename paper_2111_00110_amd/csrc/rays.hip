@@ -233,7 +233,8 @@ struct SegmentInsert {
   const T* __restrict__ gy;
   int maxseg, C;
   double h;
-  __device__ __forceinline__ void operator()(uint32_t slot, const T (&centre)[3], int ch, T (&v)[S::P]) const {
+  __device__ __forceinline__ void operator()(uint32_t slot, const T (&centre)[3], int ch, T (&v)[S::P],
+                                             int64_t) const {
     const int64_t ray = slot / maxseg;
     double o[3], r[3];
     load3(O, ray, o);
@@ -572,7 +573,8 @@ struct RootInsert {
   const T* __restrict__ gt;
   const T* __restrict__ gn;
   double h;
-  __device__ __forceinline__ void operator()(uint32_t ray, const T (&centre)[3], int, T (&v)[S::P]) const {
+  __device__ __forceinline__ void operator()(uint32_t ray, const T (&centre)[3], int, T (&v)[S::P],
+                                             int64_t) const {
     constexpr int K = S::K;
     const T* sv = saved + (int64_t)ray * kRaySaved;
     double u[3];

@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(256) reduce_cells_kernel(const uint32_t* __res
     for (int k = 0; k < P; ++k) { s[k] = T(0); c[k] = T(0); }
     for (uint32_t r = b + lane_g; r < e; r += GROUP) {
       T v[P];
-      fn(perm[r], centre, ch, v);
+      fn(perm[r], centre, ch, v, cell);
 #pragma unroll
       for (int k = 0; k < P; ++k) acc2(s[k], c[k], v[k]);
     }
@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(256) reduce_cells_kernel(const uint32_t* __res
 // Lanes per cell from the mean number of records per cell.
 inline int reduce_group_for(int64_t records, int64_t cells) {
   const double avg = cells > 0 ? (double)records / (double)cells : 0.0;
-  return avg < 6.0 ? 4 : (avg < 40.0 ? 16 : 64);
+  return avg < 24.0 ? 4 : (avg < 96.0 ? 16 : 64);
 }
 
 template <class S, typename T, int GROUP, class F>

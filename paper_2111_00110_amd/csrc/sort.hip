@@ -9,7 +9,7 @@ using namespace fc2t2;
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kItems = 16;
+constexpr int kItems = 4;
 constexpr int kTile = kThreads * kItems;   // keys per block
 constexpr int kBins = 256;                 // 8-bit digits
 
@@ -98,48 +98,79 @@ __global__ void __launch_bounds__(kThreads) radix_offsets_kernel(uint32_t* __res
 
 // Stable scatter: items of a tile are visited in input order (item j of thread t is key
 // base + j * 256 + t); ranks among equal digits come from wave ballots, per-wave counts
-// and a running per-digit counter.
+// and a running per-digit counter.  The tile is then laid out in LDS in digit order so that
+// the global writes of one digit form one contiguous run.
 __global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, int64_t N, int shift,
     const uint32_t* __restrict__ offsets, int nblocks, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out) {
   __shared__ uint32_t running[kBins];
   __shared__ uint32_t wcnt[kThreads / kWave][kBins];
+  __shared__ uint32_t local_off[kBins];
+  __shared__ uint32_t scan_sh[kThreads];
+  __shared__ uint32_t s_key[kTile];
+  __shared__ uint32_t s_val[kTile];
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
   running[tid] = 0;
   const int64_t base = (int64_t)blockIdx.x * kTile;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t keys[kItems], vals[kItems], lrank[kItems];
+  bool valid[kItems];
+#pragma unroll
   for (int j = 0; j < kItems; ++j) {
 #pragma unroll
     for (int w = 0; w < kThreads / kWave; ++w) wcnt[w][tid] = 0;
     __syncthreads();
     const int64_t i = base + (int64_t)j * kThreads + tid;
-    const bool valid = i < N;
-    const uint32_t key = valid ? keys_in[i] : 0u;
-    const uint32_t digit = (key >> shift) & (kBins - 1);
-    uint64_t peers = __ballot(valid);
+    valid[j] = i < N;
+    keys[j] = valid[j] ? keys_in[i] : 0u;
+    vals[j] = valid[j] ? (vals_in ? vals_in[i] : (uint32_t)i) : 0u;
+    const uint32_t digit = (keys[j] >> shift) & (kBins - 1);
+    uint64_t peers = __ballot(valid[j]);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const uint64_t bb = __ballot(valid && ((digit >> b) & 1u));
+      const uint64_t bb = __ballot(valid[j] && ((digit >> b) & 1u));
       peers &= ((digit >> b) & 1u) ? bb : ~bb;
     }
     const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-    if (valid && (peers & lt_mask) == 0ull) wcnt[wave][digit] = (uint32_t)__popcll(peers);
+    if (valid[j] && (peers & lt_mask) == 0ull) wcnt[wave][digit] = (uint32_t)__popcll(peers);
     __syncthreads();
-    if (valid) {
-      uint32_t pos = offsets[(int64_t)digit * nblocks + blockIdx.x] + running[digit] + rank;
-      for (int w = 0; w < wave; ++w) pos += wcnt[w][digit];
-      keys_out[pos] = key;
-      vals_out[pos] = vals_in ? vals_in[i] : (uint32_t)i;
-    }
+    uint32_t pos = running[digit] + rank;
+    for (int w = 0; w < wave; ++w) pos += wcnt[w][digit];
+    lrank[j] = pos;   // rank among the tile's items with this digit
     __syncthreads();
     uint32_t add = 0;
 #pragma unroll
     for (int w = 0; w < kThreads / kWave; ++w) add += wcnt[w][tid];
     running[tid] += add;
     __syncthreads();
+  }
+  // running[d] is now the tile's count of digit d; local_off its exclusive scan
+  uint32_t excl;
+  block_exclusive_scan(running[tid], excl, scan_sh);
+  local_off[tid] = excl;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    if (!valid[j]) continue;
+    const uint32_t digit = (keys[j] >> shift) & (kBins - 1);
+    const uint32_t lp = local_off[digit] + lrank[j];
+    s_key[lp] = keys[j];
+    s_val[lp] = vals[j];
+  }
+  __syncthreads();
+  const int count = (int)((N - base) < kTile ? (N - base) : kTile);
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int t = j * kThreads + tid;
+    if (t >= count) continue;
+    const uint32_t key = s_key[t];
+    const uint32_t digit = (key >> shift) & (kBins - 1);
+    const uint32_t pos = offsets[(int64_t)digit * nblocks + blockIdx.x] + (uint32_t)t - local_off[digit];
+    keys_out[pos] = key;
+    vals_out[pos] = s_val[t];
   }
 }
 

@@ -66,42 +66,63 @@ __device__ __forceinline__ int64_t child_cell(const int (&pc)[3], int b, int n_c
   return lin;
 }
 
+// Both shifts run in blocks of 256 threads covering NPB = 256 / P_pad parents: the block first
+// copies the sparse lists and its parents' (or children's) rows into LDS with coalesced loads,
+// then each thread computes one coefficient from LDS, and the results are written coalesced.
+constexpr int kShiftThreads = 256;
+constexpr int kMaxShiftEntries = 2048;
+
+template <typename T>
+__device__ __forceinline__ void copy_rows_to_lds(const T* __restrict__ src, T* dst, int count) {
+  for (int i = threadIdx.x; i < count; i += kShiftThreads) dst[i] = src[i];
+}
+
 // out[ch][I][n] = sum_b sum_{m <= n} S_b[n][m] in[ch][2I+b][m]; one thread per (parent, n).
-// Grid sizes fit in 32 bits and n is a power of two, so indices decode with shifts.
 template <int D, typename T>
-__global__ void __launch_bounds__(256) upshift_kernel(const T* __restrict__ in, T* __restrict__ out,
-                                                      const ShiftEntry* __restrict__ tab,
-                                                      const int* __restrict__ beg, int P, int Ppad, int lg_par,
-                                                      uint32_t G_par, uint32_t G_child) {
+__global__ void __launch_bounds__(kShiftThreads) upshift_kernel(const T* __restrict__ in, T* __restrict__ out,
+                                                                const ShiftEntry* __restrict__ tab,
+                                                                const int* __restrict__ beg, int n_entries, int P,
+                                                                int Ppad, int lg_par, uint32_t G_par,
+                                                                uint32_t G_child) {
   constexpr int NB = 1 << D;
-  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= G_par * (uint32_t)Ppad) return;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  ShiftEntry* s_tab = reinterpret_cast<ShiftEntry*>(smem);
+  int* s_beg = reinterpret_cast<int*>(s_tab + n_entries);
+  T* s_rows = reinterpret_cast<T*>(smem + (((size_t)n_entries * sizeof(ShiftEntry) + (P + 1) * sizeof(int) + 15) & ~size_t(15)));
+  const int npb = kShiftThreads / Ppad;
   const int ch = blockIdx.y;
-  const uint32_t I = tid / (uint32_t)Ppad;
-  const int nn = (int)(tid - I * (uint32_t)Ppad);
+  const uint32_t I0 = blockIdx.x * npb;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n_entries; i += kShiftThreads) s_tab[i] = tab[i];
+  for (int i = tid; i <= P; i += kShiftThreads) s_beg[i] = beg[i];
+  // children rows of the block's parents: s_rows[p][b][:]
+  const uint32_t mask = (1u << lg_par) - 1u;
+  const int lg_child = lg_par + 1;
+  for (int idx = tid; idx < npb * NB * Ppad; idx += kShiftThreads) {
+    const int pb = idx / Ppad, k = idx - pb * Ppad;
+    const int p = pb / NB, b = pb % NB;
+    const uint32_t I = I0 + p;
+    if (I >= G_par) continue;
+    uint32_t r = I, lin = 0, pc[3] = {0, 0, 0};
+#pragma unroll
+    for (int j = D - 1; j >= 0; --j) { pc[j] = r & mask; r >>= lg_par; }
+#pragma unroll
+    for (int j = 0; j < D; ++j) lin = (lin << lg_child) | (2 * pc[j] + ((b >> (D - 1 - j)) & 1));
+    s_rows[idx] = in[((size_t)ch * G_child + lin) * Ppad + k];
+  }
+  __syncthreads();
+  const int p = tid / Ppad, nn = tid - p * Ppad;
+  if (p >= npb) return;
+  const uint32_t I = I0 + p;
+  if (I >= G_par) return;
   T acc = T(0);
   if (nn < P) {
-    const uint32_t mask = (1u << lg_par) - 1u;
-    uint32_t pc[3] = {0, 0, 0};
-    {
-      uint32_t r = I;
-#pragma unroll
-      for (int j = D - 1; j >= 0; --j) { pc[j] = r & mask; r >>= lg_par; }
-    }
-    const int lg_child = lg_par + 1;
-    const T* rows[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      uint32_t lin = 0;
-#pragma unroll
-      for (int j = 0; j < D; ++j) lin = (lin << lg_child) | (2 * pc[j] + ((b >> (D - 1 - j)) & 1));
-      rows[b] = in + ((size_t)ch * G_child + lin) * Ppad;
-    }
-    for (int e = beg[nn]; e < beg[nn + 1]; ++e) {
-      const ShiftEntry en = tab[e];
+    const T* rows = s_rows + (size_t)p * NB * Ppad;
+    for (int e = s_beg[nn]; e < s_beg[nn + 1]; ++e) {
+      const ShiftEntry en = s_tab[e];
       T h = T(0);
 #pragma unroll
-      for (int b = 0; b < NB; ++b) h += (T)sigma_sign(en.pi, b) * rows[b][en.m];
+      for (int b = 0; b < NB; ++b) h += (T)sigma_sign(en.pi, b) * rows[b * Ppad + en.m];
       acc += (T)en.c * h;
     }
   }
@@ -109,38 +130,50 @@ __global__ void __launch_bounds__(256) upshift_kernel(const T* __restrict__ in, 
 }
 
 // out[ch][2I+b][k] (+)= sum_{m >= k} S_b[m][k] in[ch][I][m]; one thread per (parent, k)
-// producing coefficient k of all 2^d children (the list is walked once per parent).
+// producing coefficient k of all 2^d children.
 template <int D, typename T>
-__global__ void __launch_bounds__(256) downshift_kernel(const T* __restrict__ in, T* __restrict__ out,
-                                                        const ShiftEntry* __restrict__ tab,
-                                                        const int* __restrict__ beg, int P, int Ppad,
-                                                        int lg_par, uint32_t G_par, uint32_t G_child,
-                                                        int accumulate) {
+__global__ void __launch_bounds__(kShiftThreads) downshift_kernel(const T* __restrict__ in, T* __restrict__ out,
+                                                                  const ShiftEntry* __restrict__ tab,
+                                                                  const int* __restrict__ beg, int n_entries, int P,
+                                                                  int Ppad, int lg_par, uint32_t G_par,
+                                                                  uint32_t G_child, int accumulate) {
   constexpr int NB = 1 << D;
-  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= G_par * (uint32_t)Ppad) return;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  ShiftEntry* s_tab = reinterpret_cast<ShiftEntry*>(smem);
+  int* s_beg = reinterpret_cast<int*>(s_tab + n_entries);
+  T* s_rows = reinterpret_cast<T*>(smem + (((size_t)n_entries * sizeof(ShiftEntry) + (P + 1) * sizeof(int) + 15) & ~size_t(15)));
+  const int npb = kShiftThreads / Ppad;
   const int ch = blockIdx.y;
-  const uint32_t I = tid / (uint32_t)Ppad;
-  const int k = (int)(tid - I * (uint32_t)Ppad);
-  const uint32_t mask = (1u << lg_par) - 1u;
-  uint32_t pc[3] = {0, 0, 0};
+  const uint32_t I0 = blockIdx.x * npb;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n_entries; i += kShiftThreads) s_tab[i] = tab[i];
+  for (int i = tid; i <= P; i += kShiftThreads) s_beg[i] = beg[i];
   {
-    uint32_t r = I;
-#pragma unroll
-    for (int j = D - 1; j >= 0; --j) { pc[j] = r & mask; r >>= lg_par; }
+    // the block's parent rows are contiguous in memory
+    const uint32_t nrows = (I0 + npb <= G_par) ? (uint32_t)npb : (G_par - I0);
+    copy_rows_to_lds(in + ((size_t)ch * G_par + I0) * Ppad, s_rows, (int)(nrows * Ppad));
   }
+  __syncthreads();
+  const int p = tid / Ppad, k = tid - p * Ppad;
+  if (p >= npb) return;
+  const uint32_t I = I0 + p;
+  if (I >= G_par) return;
   T acc[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = T(0);
   if (k < P) {
-    const T* __restrict__ row = in + ((size_t)ch * G_par + I) * Ppad;
-    for (int e = beg[k]; e < beg[k + 1]; ++e) {
-      const ShiftEntry en = tab[e];
+    const T* row = s_rows + (size_t)p * Ppad;
+    for (int e = s_beg[k]; e < s_beg[k + 1]; ++e) {
+      const ShiftEntry en = s_tab[e];
       const T v = (T)en.c * row[en.m];
 #pragma unroll
       for (int b = 0; b < NB; ++b) acc[b] += (T)sigma_sign(en.pi, b) * v;
     }
   }
+  const uint32_t mask = (1u << lg_par) - 1u;
+  uint32_t r = I, pc[3] = {0, 0, 0};
+#pragma unroll
+  for (int j = D - 1; j >= 0; --j) { pc[j] = r & mask; r >>= lg_par; }
   const int lg_child = lg_par + 1;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -281,7 +314,9 @@ fc2t2_status build_shift_tables(fc2t2_plan_s* pl, hipStream_t s) {
   beg_down[P] = (int)down.size();
   std::vector<ShiftEntry> all(up);
   all.insert(all.end(), down.begin(), down.end());
-  for (int k = 0; k <= P; ++k) beg_down[k] += (int)up.size();
+  pl->shift_n_up = (int)up.size();
+  pl->shift_n_down = (int)down.size();
+  if (up.size() > (size_t)kMaxShiftEntries || down.size() > (size_t)kMaxShiftEntries) return FC2T2_EUNSUPPORTED;
   std::vector<int> begs(beg_up);
   begs.insert(begs.end(), beg_down.begin(), beg_down.end());
   const size_t tab_bytes = align256(all.size() * sizeof(ShiftEntry));
@@ -295,49 +330,48 @@ fc2t2_status build_shift_tables(fc2t2_plan_s* pl, hipStream_t s) {
   return hipStreamSynchronize(s) == hipSuccess ? FC2T2_OK : FC2T2_EHIP;
 }
 
-fc2t2_status launch_upshift(const fc2t2_plan_s* pl, int lvl_child, const void* in, void* out,
-                            hipStream_t s) {
+template <int D, typename T>
+fc2t2_status shift_launch(const fc2t2_plan_s* pl, int lvl_child, const void* in, void* out, bool up,
+                          bool accumulate, hipStream_t s) {
   const int lp = lvl_child + 1;
-  const dim3 grid((unsigned)ceil_div(pl->Gl[lp] * pl->Ppad, 256), pl->C);
-  const ShiftEntry* tab = (const ShiftEntry*)pl->shift;
-  const int* beg = (const int*)((const char*)pl->shift + pl->shift_beg_off);
-  if (pl->io == FC2T2_IO_F64) {
-    if (pl->dim == 2)
-      hipLaunchKernelGGL((upshift_kernel<2, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, lg2i(pl->nl[lp]), (uint32_t)pl->Gl[lp], (uint32_t)pl->Gl[lvl_child]);
-    else
-      hipLaunchKernelGGL((upshift_kernel<3, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, lg2i(pl->nl[lp]), (uint32_t)pl->Gl[lp], (uint32_t)pl->Gl[lvl_child]);
-  } else {
-    if (pl->dim == 2)
-      hipLaunchKernelGGL((upshift_kernel<2, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, lg2i(pl->nl[lp]), (uint32_t)pl->Gl[lp], (uint32_t)pl->Gl[lvl_child]);
-    else
-      hipLaunchKernelGGL((upshift_kernel<3, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, lg2i(pl->nl[lp]), (uint32_t)pl->Gl[lp], (uint32_t)pl->Gl[lvl_child]);
-  }
+  const int npb = kShiftThreads / pl->Ppad;
+  const int n_up = pl->shift_n_up, n_down = pl->shift_n_down;
+  const int n_entries = up ? n_up : n_down;
+  const ShiftEntry* tab = (const ShiftEntry*)pl->shift + (up ? 0 : n_up);
+  const int* beg0 = (const int*)((const char*)pl->shift + pl->shift_beg_off);
+  // the down-shift list offsets are stored after the up lists; rebase them to its own table
+  const int* beg = up ? beg0 : beg0 + (pl->P + 1);
+  const size_t rows = (size_t)npb * (up ? (1 << D) : 1) * pl->Ppad;
+  const size_t smem = (((size_t)n_entries * sizeof(ShiftEntry) + (pl->P + 1) * sizeof(int) + 15) & ~size_t(15)) +
+                      rows * sizeof(T);
+  const dim3 grid((unsigned)ceil_div(pl->Gl[lp], npb), pl->C);
+  if (up)
+    hipLaunchKernelGGL((upshift_kernel<D, T>), grid, dim3(kShiftThreads), smem, s, (const T*)in, (T*)out, tab, beg,
+                       n_entries, pl->P, pl->Ppad, lg2i(pl->nl[lp]), (uint32_t)pl->Gl[lp], (uint32_t)pl->Gl[lvl_child]);
+  else
+    hipLaunchKernelGGL((downshift_kernel<D, T>), grid, dim3(kShiftThreads), smem, s, (const T*)in, (T*)out, tab, beg,
+                       n_entries, pl->P, pl->Ppad, lg2i(pl->nl[lp]), (uint32_t)pl->Gl[lp], (uint32_t)pl->Gl[lvl_child],
+                       accumulate ? 1 : 0);
   FC2T2_LAUNCH_CHECK();
   return FC2T2_OK;
 }
 
+fc2t2_status launch_upshift(const fc2t2_plan_s* pl, int lvl_child, const void* in, void* out,
+                            hipStream_t s) {
+  if (pl->io == FC2T2_IO_F64)
+    return pl->dim == 2 ? shift_launch<2, double>(pl, lvl_child, in, out, true, false, s)
+                        : shift_launch<3, double>(pl, lvl_child, in, out, true, false, s);
+  return pl->dim == 2 ? shift_launch<2, float>(pl, lvl_child, in, out, true, false, s)
+                      : shift_launch<3, float>(pl, lvl_child, in, out, true, false, s);
+}
+
 fc2t2_status launch_downshift(const fc2t2_plan_s* pl, int lvl_child, const void* in, void* out,
                               bool accumulate, hipStream_t s) {
-  const int lp = lvl_child + 1;
-  const dim3 grid((unsigned)ceil_div(pl->Gl[lp] * pl->Ppad, 256), pl->C);
-  const int acc = accumulate ? 1 : 0;
-  const ShiftEntry* tab = (const ShiftEntry*)pl->shift;
-  const int* beg = (const int*)((const char*)pl->shift + pl->shift_beg_off) + (pl->P + 1);
-  const int lg = lg2i(pl->nl[lp]);
-  const uint32_t gp = (uint32_t)pl->Gl[lp], gc = (uint32_t)pl->Gl[lvl_child];
-  if (pl->io == FC2T2_IO_F64) {
-    if (pl->dim == 2)
-      hipLaunchKernelGGL((downshift_kernel<2, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, lg, gp, gc, acc);
-    else
-      hipLaunchKernelGGL((downshift_kernel<3, double>), grid, dim3(256), 0, s, (const double*)in, (double*)out, tab, beg, pl->P, pl->Ppad, lg, gp, gc, acc);
-  } else {
-    if (pl->dim == 2)
-      hipLaunchKernelGGL((downshift_kernel<2, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, lg, gp, gc, acc);
-    else
-      hipLaunchKernelGGL((downshift_kernel<3, float>), grid, dim3(256), 0, s, (const float*)in, (float*)out, tab, beg, pl->P, pl->Ppad, lg, gp, gc, acc);
-  }
-  FC2T2_LAUNCH_CHECK();
-  return FC2T2_OK;
+  if (pl->io == FC2T2_IO_F64)
+    return pl->dim == 2 ? shift_launch<2, double>(pl, lvl_child, in, out, false, accumulate, s)
+                        : shift_launch<3, double>(pl, lvl_child, in, out, false, accumulate, s);
+  return pl->dim == 2 ? shift_launch<2, float>(pl, lvl_child, in, out, false, accumulate, s)
+                      : shift_launch<3, float>(pl, lvl_child, in, out, false, accumulate, s);
 }
 
 fc2t2_status launch_m2l(const fc2t2_plan_s* pl, int lvl, const void* M, void* L, bool accumulate,
@@ -400,6 +434,24 @@ fc2t2_status launch_m2l_all(const fc2t2_plan_s* pl, const void* const* ins, void
   for (int l = 0; l < pl->levels; ++l) {
     const fc2t2_status st = transpose ? launch_m2l_T(pl, l, ins[l], outs[l], false, s)
                                       : launch_m2l(pl, l, ins[l], outs[l], false, s);
+    if (st) return st;
+  }
+  return FC2T2_OK;
+}
+
+// Up-shift pass: grids[l + 1] = up-shift(grids[l]) for l = 0 .. levels-2.
+fc2t2_status upshift_pyramid(const fc2t2_plan_s* pl, void* const* grids, hipStream_t s) {
+  for (int l = 0; l + 1 < pl->levels; ++l) {
+    const fc2t2_status st = launch_upshift(pl, l, grids[l], grids[l + 1], s);
+    if (st) return st;
+  }
+  return FC2T2_OK;
+}
+
+// Down-shift pass: grids[l] += down-shift(grids[l + 1]) for l = levels-2 .. 0.
+fc2t2_status downshift_pyramid(const fc2t2_plan_s* pl, void* const* grids, hipStream_t s) {
+  for (int l = pl->levels - 2; l >= 0; --l) {
+    const fc2t2_status st = launch_downshift(pl, l, grids[l + 1], grids[l], true, s);
     if (st) return st;
   }
   return FC2T2_OK;

@@ -337,50 +337,83 @@ __device__ int real_roots(const double (&c)[6], double a, double b, double (&out
   }
 }
 
-// Segment polynomial a(v) = sum_k L[k] ((d + q v)^k / k!) as coefficients (degree <= K).
-template <class S>
-__device__ void line2poly(const double* Lrow, const double (&d)[3], const double (&q)[3], double (&a)[6]) {
-  constexpr int K = S::K;
-  double F[3][K + 1][K + 1];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-#pragma unroll
-    for (int p = 0; p <= K; ++p)
-#pragma unroll
-      for (int m = 0; m <= K; ++m) F[j][p][m] = 0.0;
-    F[j][0][0] = 1.0;
-#pragma unroll
-    for (int p = 1; p <= K; ++p)
-#pragma unroll
-      for (int m = 0; m <= K; ++m)
-        F[j][p][m] = ((m <= p - 1 ? F[j][p - 1][m] * d[j] : 0.0) + (m >= 1 ? F[j][p - 1][m - 1] * q[j] : 0.0)) / p;
+// Segment polynomial (line to polynomial, section 5.1.1).  The restriction of a cell's
+// expansion to a segment is a polynomial of degree <= K; it is recovered exactly (up to
+// rounding) from its values at the K + 1 Chebyshev-Lobatto points of the segment, through
+// Newton divided differences, as b(x) = sum_m b_m x^m in the normalised parameter
+// x = (t - t_a) / s in [0, 1].  Each value is a nested Horner evaluation of the cell
+// polynomial from the FP32 row with FP64 accumulation.
+__host__ __device__ constexpr double lobatto_node(int K, int i) {
+  // (1 - cos(i pi / K)) / 2 for K <= 5, from the exact cosines
+  constexpr double c5a = 0.80901699437494742410, c5b = 0.30901699437494742410;   // cos(pi/5), cos(2pi/5)
+  constexpr double s2 = 0.70710678118654752440;                                  // cos(pi/4)
+  if (i == 0) return 0.0;
+  if (i == K) return 1.0;
+  switch (K) {
+    case 2: return 0.5;
+    case 3: return i == 1 ? 0.25 : 0.75;
+    case 4: return i == 1 ? 0.5 * (1.0 - s2) : (i == 2 ? 0.5 : 0.5 * (1.0 + s2));
+    case 5: return i == 1 ? 0.5 * (1.0 - c5a) : (i == 2 ? 0.5 * (1.0 - c5b) : (i == 3 ? 0.5 * (1.0 + c5b) : 0.5 * (1.0 + c5a)));
   }
+  return 0.0;
+}
+
+template <int K>
+struct Lobatto {
+  double x[K + 1];
+  double inv[K + 1][K + 1];   // inv[j][i] = 1 / (x_i - x_{i-j})
+  constexpr Lobatto() : x{}, inv{} {
+    for (int i = 0; i <= K; ++i) x[i] = lobatto_node(K, i);
+    for (int j = 1; j <= K; ++j)
+      for (int i = j; i <= K; ++i) inv[j][i] = 1.0 / (x[i] - x[i - j]);
+  }
+};
+
+template <class S, typename R>
+__device__ __forceinline__ double cell_eval(const R* row, const double (&u)[3]) {
+  constexpr int K = S::K;
+  double acc_a = 0.0;
 #pragma unroll
-  for (int m = 0; m < 6; ++m) a[m] = 0.0;
+  for (int a = K; a >= 0; --a) {
+    double acc_b = 0.0;
 #pragma unroll
-  for (int p0 = 0; p0 <= K; ++p0)
+    for (int b = K - a; b >= 0; --b) {
+      double acc_c = (double)row[mi_pos3(a, b, K - a - b)];
 #pragma unroll
-    for (int p1 = 0; p0 + p1 <= K; ++p1) {
-      // inner sum over the third exponent: sum_p2 L[p0,p1,p2] F2[p2]
-      double inner[K + 1];
-#pragma unroll
-      for (int m = 0; m <= K; ++m) inner[m] = 0.0;
-#pragma unroll
-      for (int p2 = 0; p0 + p1 + p2 <= K; ++p2) {
-        const double l = Lrow[mi_pos3(p0, p1, p2)];
-#pragma unroll
-        for (int m = 0; m <= p2; ++m) inner[m] += l * F[2][p2][m];
-      }
-      // times F0[p0] * F1[p1]
-#pragma unroll
-      for (int m0 = 0; m0 <= p0; ++m0)
-#pragma unroll
-        for (int m1 = 0; m1 <= p1; ++m1) {
-          const double f = F[0][p0][m0] * F[1][p1][m1];
-#pragma unroll
-          for (int m2 = 0; m0 + m1 + m2 <= K; ++m2) a[m0 + m1 + m2] += f * inner[m2];
-        }
+      for (int c = K - a - b - 1; c >= 0; --c) acc_c = (double)row[mi_pos3(a, b, c)] + acc_c * u[2] * (1.0 / (c + 1));
+      acc_b = acc_c + acc_b * u[1] * (1.0 / (b + 1));
     }
+    acc_a = acc_b + acc_a * u[0] * (1.0 / (a + 1));
+  }
+  return acc_a;
+}
+
+template <class S, typename R>
+__device__ void segment_poly(const R* row, const double (&d)[3], const double (&q)[3], double s, double (&b)[6]) {
+  constexpr int K = S::K;
+  constexpr Lobatto<K> LB{};
+  double c[K + 1];
+#pragma unroll
+  for (int i = 0; i <= K; ++i) {
+    const double v = s * LB.x[i];
+    const double u[3] = {d[0] + q[0] * v, d[1] + q[1] * v, d[2] + q[2] * v};
+    c[i] = cell_eval<S>(row, u);
+  }
+  // divided differences
+#pragma unroll
+  for (int j = 1; j <= K; ++j)
+#pragma unroll
+    for (int i = K; i >= j; --i) c[i] = (c[i] - c[i - 1]) * LB.inv[j][i];
+  // Newton form -> monomial coefficients: b = c_K; b = b (x - x_i) + c_i for i = K-1 .. 0
+#pragma unroll
+  for (int m = 0; m < 6; ++m) b[m] = 0.0;
+  b[0] = c[K];
+#pragma unroll
+  for (int i = K - 1; i >= 0; --i) {
+#pragma unroll
+    for (int m = K; m >= 1; --m) b[m] = b[m - 1] - LB.x[i] * b[m];
+    b[0] = c[i] - LB.x[i] * b[0];
+  }
 }
 
 // Upper bound of the polynomial a on [0, s]: a_0 + sum_{m >= 1} max(0, a_m) s^m.
@@ -392,8 +425,10 @@ __device__ __forceinline__ double upper_bound(const double (&a)[6], double s) {
   return ub;
 }
 
+// Called only for the few segments the bounds cannot rule out: kept out of line so that the
+// root cascade does not raise the register pressure of the traversal loop.
 template <class S>
-__device__ double seg_max(const double (&a)[6], double s) {
+__device__ __noinline__ double seg_max(const double (&a)[6], double s) {
   constexpr int K = S::K;
   double best = fmax(peval<K>(a, 0.0), peval<K>(a, s));
   double da[6] = {0, 0, 0, 0, 0, 0};
@@ -407,7 +442,7 @@ __device__ double seg_max(const double (&a)[6], double s) {
 
 // First v in (0, s] where g = a - tau goes from < 0 to >= 0 on a monotone piece; -1 if none.
 template <class S>
-__device__ double first_upward(const double (&g)[6], double s) {
+__device__ __noinline__ double first_upward(const double (&g)[6], double s) {
   constexpr int K = S::K;
   double dg[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
@@ -432,123 +467,188 @@ __device__ double first_upward(const double (&g)[6], double s) {
   return -1.0;
 }
 
-// Ray root: one thread per ray.  Pass 1 finds max f along the clipped ray, pass 2 walks the
-// segments again for the first upward crossing of tau = frac * max.  A crossing that
-// happens across a face (previous segment ends below tau, this one starts at or above)
-// lies on the face and belongs to the earlier cell.
+// Ray root.  Each ray's clipped parameter interval is split into SUB equal sub-intervals,
+// one per lane of a SUB-lane group (SUB divides the wavefront); splitting a cell's segment
+// changes neither the maximum nor the crossings.
+//  pass 1: each lane's maximum of f over its pieces; the group's maximum gives tau.
+//  pass 2: each lane walks its pieces in order for the first upward crossing of tau (with the
+//          face rule between consecutive pieces); an event at the start of lane j (j >= 1)
+//          occurs when lane j-1 ends below tau and lane j starts at or above it (a face
+//          crossing, or a crossing exactly at the split) and belongs to lane j-1's last cell.
+//  The ray's root is the earliest event; the ray is dead when f >= tau at its entry point.
+// grad f and (H r) at the root (physical units) from the cell's row; out of line, once per ray.
+template <class S, typename T>
+__device__ __forceinline__ void root_gradients(const T* __restrict__ row_ptr, const double (&u)[3], const double (&r)[3],
+                                            double ih, double (&gout)[3], double (&hr)[3]) {
+  constexpr int P = S::P, K = S::K;
+  double row[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) row[k] = (double)row_ptr[k];
+  double pw[3][K + 1];
+  power_table<S>(u, pw);
+  double val, g[3], hs[6];
+  eval_poly<S, double, true, true>(row, pw, val, g, hs);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) gout[j] = g[j] * ih;
+  const double H[3][3] = {{hs[0], hs[1], hs[2]}, {hs[1], hs[3], hs[4]}, {hs[2], hs[4], hs[5]}};
+#pragma unroll
+  for (int j = 0; j < 3; ++j) hr[j] = (H[j][0] * r[0] + H[j][1] * r[1] + H[j][2] * r[2]) * ih * ih;
+}
+
+constexpr int kRootSub = 8;
+
 template <class S, typename T>
 __global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, const T* __restrict__ O,
                                                       const T* __restrict__ Rd, int64_t R, double t0, double t1,
                                                       double lo, double hi, double h, int n, double frac,
                                                       T* __restrict__ t_out, T* __restrict__ normal,
                                                       int32_t* __restrict__ hit, T* __restrict__ saved) {
-  constexpr int P = S::P, Ppad = S::Ppad, K = S::K;
-  const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (ray >= R) return;
+  constexpr int P = S::P, Ppad = S::Ppad, K = S::K, SUB = kRootSub;
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ray = gtid / SUB;
+  const int part = (int)(gtid % SUB);
+  const bool active = ray < R;
+  const int64_t rr = active ? ray : 0;
   double o[3], r[3];
-  load3(O, ray, o);
-  load3(Rd, ray, r);
-  const double q[3] = {r[0] / h, r[1] / h, r[2] / h};
+  load3(O, rr, o);
+  load3(Rd, rr, r);
+  const double ih = 1.0 / h;
+  const double q[3] = {r[0] * ih, r[1] * ih, r[2] * ih};
+  // the ray's clipped interval, then this lane's sub-interval [e0, e1]
+  double ta_ray = t0, tb_ray = t1;
+  bool live = active;
+  {
+    Dda clip;
+    clip.init(o, r, t0, t1, lo, hi, h, n);
+    ta_ray = clip.t;
+    tb_ray = clip.t_end;
+    live = live && clip.live;
+  }
+  const double step = (tb_ray - ta_ray) / SUB;
+  const double e0 = part == 0 ? ta_ray : ta_ray + part * step;
+  const double e1 = part == SUB - 1 ? tb_ray : ta_ray + (part + 1) * step;
   int64_t cell;
   int cc[3];
   double ta, tb;
-  // ---- pass 1: max of f along the ray
+  // ---- pass 1
   double fmax_v = -INFINITY;
-  bool any = false;
-  {
+  if (live) {
     Dda dda;
-    dda.init(o, r, t0, t1, lo, hi, h, n);
+    dda.init(o, r, e0, e1, lo, hi, h, n);
     while (dda.next(cell, cc, ta, tb)) {
-      double row[P];
-      load_row_f64<S>(L + cell * Ppad, row);
+      T row[P];
+#pragma unroll
+      for (int k = 0; k < P; ++k) row[k] = L[cell * Ppad + k];
       double d[3];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) d[j] = (o[j] + ta * r[j] - (lo + (cc[j] + 0.5) * h)) / h;
+      for (int j = 0; j < 3; ++j) d[j] = (o[j] + ta * r[j] - (lo + (cc[j] + 0.5) * h)) * ih;
       double a[6];
-      line2poly<S>(row, d, q, a);
+      segment_poly<S>(row, d, q, tb - ta, a);
       // the exact segment maximum only matters when the segment can beat the best so far
-      if (!any || upper_bound<K>(a, tb - ta) > fmax_v) fmax_v = fmax(fmax_v, seg_max<S>(a, tb - ta));
-      any = true;
+      if (upper_bound<K>(a, 1.0) > fmax_v) fmax_v = fmax(fmax_v, seg_max<S>(a, 1.0));
     }
   }
+#pragma unroll
+  for (int off = SUB / 2; off >= 1; off >>= 1) fmax_v = fmax(fmax_v, __shfl_xor(fmax_v, off));
   const double tau = frac * fmax_v;
-  double t_star = NAN;
-  int found = 0;
-  int rc[3] = {0, 0, 0};
-  int64_t rcell = 0;
-  if (any) {
+  // ---- pass 2
+  bool found = false, have_piece = false;
+  double t_ev = INFINITY, first_start = 0.0, last_end = 0.0, last_tb = 0.0;
+  int64_t ev_cell = 0, last_cell = 0;
+  int ev_c[3] = {0, 0, 0}, last_c[3] = {0, 0, 0};
+  if (live && fmax_v > -INFINITY) {
     Dda dda;
-    dda.init(o, r, t0, t1, lo, hi, h, n);
-    bool first = true;
-    double prev_end = 0.0, prev_ta = 0.0, prev_s = 0.0;
-    int pc[3] = {0, 0, 0};
-    int64_t pcell = 0;
+    dda.init(o, r, e0, e1, lo, hi, h, n);
+    double prev_end = 0.0;
     while (dda.next(cell, cc, ta, tb)) {
-      double row[P];
-      load_row_f64<S>(L + cell * Ppad, row);
+      T row[P];
+#pragma unroll
+      for (int k = 0; k < P; ++k) row[k] = L[cell * Ppad + k];
       double d[3];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) d[j] = (o[j] + ta * r[j] - (lo + (cc[j] + 0.5) * h)) / h;
+      for (int j = 0; j < 3; ++j) d[j] = (o[j] + ta * r[j] - (lo + (cc[j] + 0.5) * h)) * ih;
       double g[6];
-      line2poly<S>(row, d, q, g);
+      const double sl = tb - ta;
+      segment_poly<S>(row, d, q, sl, g);
       g[0] -= tau;
-      const double s = tb - ta;
       const double g0 = peval<K>(g, 0.0);
-      if (first) {
-        if (g0 >= 0.0) break;                       // at or above the level at entry: dead ray
-        first = false;
-      } else if (prev_end < 0.0 && g0 >= 0.0) {     // crossing on the face: earlier cell
-        t_star = prev_ta + prev_s;
-        rc[0] = pc[0]; rc[1] = pc[1]; rc[2] = pc[2];
-        rcell = pcell;
-        found = 1;
-        break;
+      if (!have_piece) {
+        first_start = g0;
+        have_piece = true;
+      } else if (!found && prev_end < 0.0 && g0 >= 0.0) {   // crossing on a face: earlier piece
+        t_ev = last_tb;
+        ev_cell = last_cell;
+        ev_c[0] = last_c[0]; ev_c[1] = last_c[1]; ev_c[2] = last_c[2];
+        found = true;
       }
-      // no upward crossing is possible when g stays below zero on the whole segment
-      const double v = upper_bound<K>(g, s) < 0.0 ? -1.0 : first_upward<S>(g, s);
-      if (v >= 0.0) {
-        t_star = ta + v;
-        rc[0] = cc[0]; rc[1] = cc[1]; rc[2] = cc[2];
-        rcell = cell;
-        found = 1;
-        break;
+      if (!found) {
+        const double v = upper_bound<K>(g, 1.0) < 0.0 ? -1.0 : first_upward<S>(g, 1.0);
+        if (v >= 0.0) {
+          t_ev = ta + sl * v;
+          ev_cell = cell;
+          ev_c[0] = cc[0]; ev_c[1] = cc[1]; ev_c[2] = cc[2];
+          found = true;
+        }
       }
-      prev_end = peval<K>(g, s);
-      prev_ta = ta;
-      prev_s = s;
-      pc[0] = cc[0]; pc[1] = cc[1]; pc[2] = cc[2];
-      pcell = cell;
+      prev_end = peval<K>(g, 1.0);
+      last_end = prev_end;
+      last_tb = tb;
+      last_cell = cell;
+      last_c[0] = cc[0]; last_c[1] = cc[1]; last_c[2] = cc[2];
+      if (found) break;
     }
   }
+  // boundary event at the start of this lane: previous lane ends below, this lane starts at or above
+  const int lane = threadIdx.x & 63;
+  const int src = lane - 1;
+  const double prev_last_end = __shfl(last_end, src < 0 ? 0 : src);
+  const int prev_have = __shfl((int)have_piece, src < 0 ? 0 : src);
+  const int64_t prev_last_cell = __shfl(last_cell, src < 0 ? 0 : src);
+  const int pc0 = __shfl(last_c[0], src < 0 ? 0 : src), pc1 = __shfl(last_c[1], src < 0 ? 0 : src),
+            pc2 = __shfl(last_c[2], src < 0 ? 0 : src);
+  const double prev_last_tb = __shfl(last_tb, src < 0 ? 0 : src);
+  if (part > 0 && have_piece && prev_have && prev_last_end < 0.0 && first_start >= 0.0) {
+    // an event at this lane's start precedes any event inside it
+    t_ev = prev_last_tb;
+    ev_cell = prev_last_cell;
+    ev_c[0] = pc0; ev_c[1] = pc1; ev_c[2] = pc2;
+    found = true;
+  }
+  // the earliest event of the group (lowest lane on ties)
+  double tmin = found ? t_ev : INFINITY;
+#pragma unroll
+  for (int off = SUB / 2; off >= 1; off >>= 1) tmin = fmin(tmin, __shfl_xor(tmin, off));
+  const int group0 = lane & ~(SUB - 1);
+  const uint64_t winners = __ballot(found && t_ev == tmin) >> group0;
+  const int win = (int)__ffsll((unsigned long long)(winners & ((1ull << SUB) - 1))) - 1;
+  const int64_t wcell = __shfl(ev_cell, group0 + (win < 0 ? 0 : win));
+  const int w0 = __shfl(ev_c[0], group0 + (win < 0 ? 0 : win)), w1 = __shfl(ev_c[1], group0 + (win < 0 ? 0 : win)),
+            w2 = __shfl(ev_c[2], group0 + (win < 0 ? 0 : win));
+  // dead ray: at or above the level at the entry point (lane 0's first piece)
+  const double entry = __shfl(first_start, group0);
+  const int entry_have = __shfl((int)have_piece, group0);
+  const bool ray_hit = win >= 0 && entry_have && entry < 0.0;
+  if (!active || part != 0) return;
   double gout[3] = {0.0, 0.0, 0.0}, hr[3] = {0.0, 0.0, 0.0}, qs[3] = {0.0, 0.0, 0.0}, rdg = 0.0;
-  if (found) {
-    double row[P];
-    load_row_f64<S>(L + rcell * Ppad, row);
+  const double t_star = ray_hit ? tmin : NAN;
+  if (ray_hit) {
+    const int wc[3] = {w0, w1, w2};
     double u[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       qs[j] = o[j] + t_star * r[j];
-      u[j] = (qs[j] - (lo + (rc[j] + 0.5) * h)) / h;
+      u[j] = (qs[j] - (lo + (wc[j] + 0.5) * h)) * ih;
     }
-    double pw[3][K + 1];
-    power_table<S>(u, pw);
-    double val, g[3], hs[6];
-    eval_poly<S, double, true, true>(row, pw, val, g, hs);
-    const double ih = 1.0 / h;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) gout[j] = g[j] * ih;
-    const double H[3][3] = {{hs[0], hs[1], hs[2]}, {hs[1], hs[3], hs[4]}, {hs[2], hs[4], hs[5]}};
-#pragma unroll
-    for (int j = 0; j < 3; ++j) hr[j] = (H[j][0] * r[0] + H[j][1] * r[1] + H[j][2] * r[2]) * ih * ih;
+    root_gradients<S>(L + wcell * Ppad, u, r, ih, gout, hr);
     rdg = r[0] * gout[0] + r[1] * gout[1] + r[2] * gout[2];
   }
   t_out[ray] = (T)t_star;
-  hit[ray] = found;
+  hit[ray] = ray_hit ? 1 : 0;
 #pragma unroll
   for (int j = 0; j < 3; ++j) normal[ray * 3 + j] = (T)gout[j];
   T* sv = saved + ray * kRaySaved;
   sv[0] = (T)qs[0]; sv[1] = (T)qs[1]; sv[2] = (T)qs[2];
-  sv[3] = (T)(double)rcell;
+  sv[3] = (T)(double)(ray_hit ? wcell : 0);
   sv[4] = (T)rdg;
   sv[5] = (T)hr[0]; sv[6] = (T)hr[1]; sv[7] = (T)hr[2];
   sv[8] = (T)tau;
@@ -727,7 +827,7 @@ fc2t2_status launch_ray_root(const fc2t2_plan_s* pl, const void* L, const void* 
                              int64_t R, double frac, void* t, void* normal, int32_t* hit, void* saved, hipStream_t s) {
   if (R == 0) return FC2T2_OK;
   fc2t2_status st = FC2T2_EUNSUPPORTED;
-  const dim3 grid((unsigned)ceil_div(R, 64));
+  const dim3 grid((unsigned)ceil_div(R * kRootSub, 64));
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {
     using S = decltype(shape);
     if constexpr (S::D == 3) {

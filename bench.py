@@ -44,8 +44,55 @@ def parse():
                     help="also time the same step with the plain FP32 M2L (same accuracy class)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=256, help="queries in the CPU sample")
-    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device-to-device copies of MIB MiB (the reference "
+                         "kernel for scaling HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    """Five device-to-device copies of a known size; each reads and writes mib MiB."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 5}), flush=True)
+
+
+def source_hash():
+    """sha256 over the library's kernel sources (names and contents, sorted by name)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2111_00110_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    for name in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        with open(os.path.join(ROOT, "include", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, stage):
+    """HBM bytes per launch of a stage's kernel from the committed counter summary
+    profiles/<workload>_<stage>_hbm_counters.md, whose 'traffic-json:' line holds the scaled
+    FETCH_SIZE + WRITE_SIZE bytes and the source hash they were taken at; None when there is
+    no such summary or the kernels have changed since."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_hbm_counters.md" % (workload, stage))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("traffic-json:"):
+                rec = json.loads(line.split(":", 1)[1])
+                if rec.get("source_hash") == source_hash():
+                    return rec.get("bytes_per_launch")
+    return None
 
 
 def main():
@@ -54,6 +101,9 @@ def main():
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     import torch
     from paper_2111_00110_amd import accounting, fc2t2, workloads
@@ -73,7 +123,7 @@ def main():
     if layer != "explicit":
         o, r = t["o"], t["r"]
 
-    def time_steps(plan, steps, warmup):
+    def make_step(plan):
         Lt = plan.new_local()
         gL = plan.new_local()
         gp = torch.zeros_like(p)
@@ -113,11 +163,11 @@ def main():
                 plan.ray_root_backward(saved, hit, gt, gn, gL)
                 plan.expand_backward(gL, p, w, gp, gw)
                 return tt
+        return step
 
-        for _ in range(warmup):
-            y = step()
-        torch.cuda.synchronize()
+    def run(step, steps):
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
         ev0.record()
         for _ in range(steps):
             y = step()
@@ -129,40 +179,70 @@ def main():
     plan = make_plan(args.m2l)
     torch.cuda.synchronize()
     plan_ms = (time.perf_counter() - t_plan0) * 1e3
-    ms, y = time_steps(plan, args.steps, args.warmup)
+    step = make_step(plan)
+    for _ in range(args.warmup):
+        step()
+
+    # ---- stage breakdown: the same steps with every stage bracketed by events on the
+    # stream the library launches on (the current stream)
+    plan.stage_timing(fc2t2.STAGES)
+    run(step, args.steps)
+    stages = {}
+    for name in fc2t2.STAGES:
+        st_ms, calls = plan.stage_time(name)
+        if calls:
+            stages[name] = {"ms_per_step": round(st_ms / args.steps, 4), "calls_per_step": calls // args.steps,
+                            "ms_per_call": st_ms / calls}
+
+    # ---- dominant kernel: the slowest single-kernel stage with a roofline model; the timed
+    # region brackets only that stage's launches
+    es = 8 if wl.io == "f64" else 4
+    modelled = [n for n in ("m2l", "m2l_T", "p2m", "l2p", "l2p_T", "p2m_T") if n in stages]
+    dom = max(modelled, key=lambda n: stages[n]["ms_per_step"])
+    plan.stage_timing([dom])
+    ms, y = run(step, args.steps)
+    dom_ms, dom_calls = plan.stage_time(dom)
+    plan.stage_timing([])
+    kernel_ms = dom_ms / max(dom_calls, 1)
     units = wl.M if wl.layer == "explicit" else wl.R
     value = units / (ms * 1e-3)
     f32_ms = None
     if args.compare_f32 and args.m2l != "f32":
-        f32_ms, _ = time_steps(make_plan("f32"), max(3, args.steps // 4), 1)
+        plan32 = make_plan("f32")
+        step32 = make_step(plan32)
+        step32()
+        f32_ms, _ = run(step32, max(3, args.steps // 4))
 
-    # ---- dominant kernel: the finest-level M2L launch, timed alone with events on the
-    # current stream (the stream the library launches on)
-    shp = plan.level_shape(0)
-    Mg = torch.randn(shp, dtype=plan.dtype, device=dev)
-    Lg = torch.empty(shp, dtype=plan.dtype, device=dev)
-    plan.m2l(0, Mg, Lg)
-    torch.cuda.synchronize()
-    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    k0.record()
-    for _ in range(args.kernel_reps):
-        plan.m2l(0, Mg, Lg)
-    k1.record()
-    torch.cuda.synchronize()
-    m2l_ms = k0.elapsed_time(k1) / args.kernel_reps
-    flops = accounting.m2l_flops(wl.dim, wl.n, wl.K, level=0)
-    if args.m2l == "f32":
-        bound, peak = "alu", PEAKS["fp32_vector_TFLOPs"]
-    else:
-        bound, peak = "mfma", PEAKS["bf16_mfma_TFLOPs"]
-    achieved = flops / (m2l_ms * 1e-3) / 1e12
     passes = {"f32": 1, "bf16": 1, "bf16x2": 2, "bf16x3": 3}[args.m2l]
-    roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
-                "kernel": "m2l level 0 (finest), forward, %s" % args.m2l, "kernel_us": round(m2l_ms * 1e3, 2),
-                "flops_per_launch": flops, "mfma_passes": passes,
-                "mfma_issue_frac": round(achieved * passes * accounting.mfma_padding(wl.dim, wl.K) / peak, 4)
-                if bound == "mfma" else None}
+    flops_all = accounting.m2l_flops(wl.dim, wl.n, wl.K)
+    mfma = args.m2l != "f32"
+    m2l_peak = PEAKS["bf16_mfma_TFLOPs"] if mfma else PEAKS["fp32_vector_TFLOPs"]
+
+    def m2l_line(name):
+        if name not in stages:
+            return None
+        kt = stages[name]["ms_per_call"]
+        ach = flops_all / (kt * 1e-3) / 1e12
+        return {"kernel_us": round(kt * 1e3, 2), "achieved_TFLOPs": round(ach, 3), "peak_TFLOPs": m2l_peak,
+                "frac": round(ach / m2l_peak, 4),
+                "mfma_issue_frac": round(ach * passes * accounting.mfma_padding(wl.dim, wl.K) / m2l_peak, 4)
+                if mfma else None}
+
+    if dom in ("m2l", "m2l_T"):
+        achieved = flops_all / (kernel_ms * 1e-3) / 1e12
+        roofline = {"bound": "mfma" if mfma else "alu", "achieved": round(achieved, 3), "peak": m2l_peak,
+                    "unit": "TFLOP/s", "frac": round(achieved / m2l_peak, 4), "traffic": None,
+                    "kernel": "%s, all levels in one launch, %s" % (dom, args.m2l),
+                    "kernel_us": round(kernel_ms * 1e3, 2), "launches": dom_calls,
+                    "flops_per_launch": flops_all, "mfma_passes": passes}
+    else:
+        nbytes = accounting.stage_bytes(dom, wl.dim, wl.n, wl.K, N=wl.N, M=wl.M, itemsize=es)
+        achieved = nbytes / (kernel_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAKS["hbm_GBps"], "unit": "GB/s",
+                    "frac": round(achieved / PEAKS["hbm_GBps"], 4), "traffic": None,
+                    "kernel": dom, "kernel_us": round(kernel_ms * 1e3, 2), "launches": dom_calls,
+                    "bytes_per_launch": nbytes}
+    roofline["traffic"] = measured_traffic(wl.name, dom)
 
     unit = "queries/s" if wl.layer == "explicit" else "rays/s"
     outputs = {"explicit": "y, w_bar, p_bar, q_bar", "ray_integral": "y (ray integrals), w_bar, p_bar",
@@ -176,6 +256,8 @@ def main():
                    "grid": "%d^%d" % (wl.n, wl.dim), "K": wl.K, "kernel": "%s %g" % (wl.kernel, wl.param),
                    "m2l": args.m2l, "outputs": outputs},
         "roofline": roofline,
+        "m2l_mfma": {"forward": m2l_line("m2l"), "transpose": m2l_line("m2l_T")},
+        "stages_ms_per_step": {k: v["ms_per_step"] for k, v in stages.items()},
         "plan_ms": round(plan_ms, 1),
     }
     if f32_ms is not None:

@@ -205,6 +205,35 @@ fc2t2_status fc2t2_m2l(fc2t2_plan plan, int level, int transpose, const void* in
 /* Elements of one level's grid: C * n_level^dim * P_pad (0 for an invalid level). */
 size_t fc2t2_level_numel(fc2t2_plan plan, int level);
 
+/* ---- Stage timing (a measurement aid, not part of the method) ----
+ * Stages of the pipeline, each one kernel launch per call unless noted. */
+typedef enum {
+  FC2T2_STAGE_SORT = 0,   /* binning: cell keys, radix passes, cell starts (several launches) */
+  FC2T2_STAGE_P2M,        /* per-cell moment reduction over the sorted sources */
+  FC2T2_STAGE_SHIFT_UP,   /* M2M up the pyramid, or L2L^T (a few multi-level launches) */
+  FC2T2_STAGE_M2L,        /* M2L at every level (one launch on the MFMA path) */
+  FC2T2_STAGE_SHIFT_DOWN, /* L2L down the pyramid, or M2M^T (a few multi-level launches) */
+  FC2T2_STAGE_L2P,        /* evaluation at the queries */
+  FC2T2_STAGE_L2P_T,      /* per-cell reduction of query cotangents, with q_bar */
+  FC2T2_STAGE_M2L_T,      /* transposed M2L at every level */
+  FC2T2_STAGE_P2M_T,      /* per-source gradients w_bar, p_bar */
+  FC2T2_STAGE_RAY,        /* ray integral or ray root kernel (forward) */
+  FC2T2_STAGE_RAY_T,      /* ray cotangent records and their per-cell reduction (backward) */
+  FC2T2_STAGE_COUNT
+} fc2t2_stage;
+
+/* Selects the stages to time: bit s of stage_mask times stage s.  From then on the library
+ * records a HIP event on the launch stream before and after every timed stage's launches.
+ * Clears what was recorded.  FC2T2_EINVAL for a null plan. */
+fc2t2_status fc2t2_stage_timing(fc2t2_plan plan, uint32_t stage_mask);
+
+/* Waits for the events recorded for `stage` since the last call for it (or since
+ * fc2t2_stage_timing), writes their summed duration in milliseconds to *ms and the number of
+ * timed calls to *calls, and clears them.  At most 4096 calls per stage are kept between reads;
+ * later ones are not timed.  FC2T2_EINVAL for a bad stage or null outputs, FC2T2_EHIP if an
+ * event query fails.  One thread per plan. */
+fc2t2_status fc2t2_stage_time(fc2t2_plan plan, int stage, double* ms, int64_t* calls);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,3 +60,36 @@ def mfma_padding(dim: int, K: int) -> float:
     p8 = (P + 7) // 8 * 8
     p16 = (P + 15) // 16 * 16
     return p8 * p16 / (P * P)
+
+
+def p_pad(dim: int, K: int) -> int:
+    return (n_terms(dim, K) + 3) // 4 * 4
+
+
+def stage_bytes(stage: str, dim: int, n: int, K: int, N: int = 0, M: int = 0, itemsize: int = 4,
+                channels: int = 1) -> int:
+    """Algorithmic HBM bytes of one call of a single-kernel stage: every point record and
+    every finest-grid row it must touch, once.
+
+    per source / query (es = itemsize, d = dim):
+      p2m    p, w, sort index read                      (d + 1) es + 4
+      l2p    q read, y written                          (d + 1) es
+      l2p_T  q, gy, sort index read, q_bar written      (2 d + 1) es + 4
+      p2m_T  p, w read, p_bar, w_bar written            2 (d + 1) es
+    per finest cell (R = P_pad es channels, one row):
+      p2m    cell start read, moment row written        4 + R
+      l2p    local row read                             R
+      l2p_T  cell start, local row read, row written    4 + 2 R
+      p2m_T  moment-cotangent row read                  R
+    """
+    d, es, G = dim, itemsize, n ** dim
+    R = p_pad(dim, K) * es * channels
+    if stage == "p2m":
+        return N * ((d + 1) * es + 4) + G * (4 + R)
+    if stage == "l2p":
+        return M * (d + 1) * es + G * R
+    if stage == "l2p_T":
+        return M * ((2 * d + 1) * es + 4) + G * (4 + 2 * R)
+    if stage == "p2m_T":
+        return N * 2 * (d + 1) * es + G * R
+    raise ValueError(stage)

@@ -21,6 +21,7 @@ struct Carve {
 
 struct SortBufs {
   uint32_t *keys, *keys_sorted, *perm, *starts;
+  void* pay;      // [count][dim + 1] sorted point data (when the sort carries it)
   void* scratch;
 };
 
@@ -30,15 +31,17 @@ SortBufs carve_sort(Carve& c, const fc2t2_plan_s* pl, int64_t count) {
   b.keys_sorted = c.take<uint32_t>(count);
   b.perm = c.take<uint32_t>(count);
   b.starts = c.take<uint32_t>(pl->G + 1);
+  b.pay = sort_payload_ok(pl) ? (void*)c.take<float>((size_t)count * (pl->dim + 1)) : nullptr;
   b.scratch = c.take<char>(radix_sort_scratch_bytes(count));
   return b;
 }
 
+// Sorts points by cell; with `extra` (one value per point) and a carved payload buffer, the
+// coordinates and that value are sorted along into b.pay.
 fc2t2_status bin_and_sort(const fc2t2_plan_s* pl, const void* x, int64_t count, const SortBufs& b,
-                          hipStream_t s) {
-  fc2t2_status st = launch_cell_keys(pl, x, count, b.keys, s);
-  if (st) return st;
-  st = radix_sort_pairs(b.keys, b.keys_sorted, b.perm, count, key_bits_for(pl->G), b.scratch, s);
+                          hipStream_t s, const void* extra = nullptr) {
+  fc2t2_status st = sort_points_by_cell(pl, x, count, b.keys, b.keys_sorted, b.perm, b.scratch, s, extra,
+                                        extra ? b.pay : nullptr);
   if (st) return st;
   return launch_cell_starts(b.keys_sorted, count, pl->G, b.starts, s);
 }
@@ -82,10 +85,18 @@ namespace fc2t2 {
 // every level (one launch), then L2L down the pyramid accumulating into each finer level.
 fc2t2_status expand_from_moments(const fc2t2_plan_s* pl, void** Mlv, void** Llv, void* L0, hipStream_t s) {
   Llv[0] = L0;
-  fc2t2_status st = upshift_pyramid(pl, Mlv, s);
+  fc2t2_status st;
+  {
+    StageScope t(pl, FC2T2_STAGE_SHIFT_UP, s);
+    st = upshift_pyramid(pl, Mlv, s);
+  }
   if (st) return st;
-  st = launch_m2l_all(pl, (const void* const*)Mlv, Llv, false, s);
+  {
+    StageScope t(pl, FC2T2_STAGE_M2L, s);
+    st = launch_m2l_all(pl, (const void* const*)Mlv, Llv, false, s);
+  }
   if (st) return st;
+  StageScope t(pl, FC2T2_STAGE_SHIFT_DOWN, s);
   return downshift_pyramid(pl, Llv, s);
 }
 
@@ -93,10 +104,18 @@ fc2t2_status expand_from_moments(const fc2t2_plan_s* pl, void** Mlv, void** Llv,
 fc2t2_status expand_T_to_moments(const fc2t2_plan_s* pl, const void* GL0, void** GLlv, void** GMlv,
                                  hipStream_t s) {
   GLlv[0] = (void*)GL0;
-  fc2t2_status st = upshift_pyramid(pl, GLlv, s);          // L2L^T
+  fc2t2_status st;
+  {
+    StageScope t(pl, FC2T2_STAGE_SHIFT_UP, s);
+    st = upshift_pyramid(pl, GLlv, s);                       // L2L^T
+  }
   if (st) return st;
-  st = launch_m2l_all(pl, (const void* const*)GLlv, GMlv, true, s);
+  {
+    StageScope t(pl, FC2T2_STAGE_M2L_T, s);
+    st = launch_m2l_all(pl, (const void* const*)GLlv, GMlv, true, s);
+  }
   if (st) return st;
+  StageScope t(pl, FC2T2_STAGE_SHIFT_DOWN, s);
   return downshift_pyramid(pl, GMlv, s);                     // M2M^T
 }
 
@@ -128,9 +147,18 @@ fc2t2_status fc2t2_expand(fc2t2_plan plan, const void* p, const void* w, int64_t
   void* Llv[kMaxLevels];
   carve_pyramid(c, plan, 0, Mlv);
   carve_pyramid(c, plan, 1, Llv);
-  fc2t2_status st = bin_and_sort(plan, p, N, sb, stream);
+  fc2t2_status st;
+  const bool carry = sb.pay != nullptr;   // sort the points' data along with the keys
+  {
+    StageScope t(plan, FC2T2_STAGE_SORT, stream);
+    st = bin_and_sort(plan, p, N, sb, stream, carry ? w : nullptr);
+  }
   if (st) return st;
-  st = launch_p2m(plan, p, w, N, sb.starts, sb.perm, Mlv[0], stream);
+  {
+    StageScope t(plan, FC2T2_STAGE_P2M, stream);
+    st = carry ? launch_reduce_sorted(plan, sb.pay, N, sb.starts, Mlv[0], false, stream)
+               : launch_p2m(plan, p, w, N, sb.starts, sb.perm, Mlv[0], stream);
+  }
   if (st) return st;
   return expand_from_moments(plan, Mlv, Llv, L, stream);
 }
@@ -139,6 +167,7 @@ fc2t2_status fc2t2_eval(fc2t2_plan plan, const void* L, const void* q, int64_t M
                         void* hess, hipStream_t stream) {
   if (!plan || !L || bad_count(M)) return FC2T2_EINVAL;
   if (M > 0 && (!q || !y)) return FC2T2_EINVAL;
+  StageScope t(plan, FC2T2_STAGE_L2P, stream);
   return launch_l2p(plan, L, q, M, y, grad, hess, stream);
 }
 
@@ -154,13 +183,27 @@ fc2t2_status fc2t2_eval_backward(fc2t2_plan plan, const void* L, const void* q, 
     if (!ws || ws_bytes < need) return FC2T2_EWORKSPACE;
     Carve c(ws);
     SortBufs sb = carve_sort(c, plan, M);
-    fc2t2_status st = bin_and_sort(plan, q, M, sb, stream);
+    fc2t2_status st;
+    const bool carry = sb.pay != nullptr;
+    {
+      StageScope t(plan, FC2T2_STAGE_SORT, stream);
+      st = bin_and_sort(plan, q, M, sb, stream, carry ? gy : nullptr);
+    }
     if (st) return st;
+    StageScope t(plan, FC2T2_STAGE_L2P_T, stream);
+    if (carry) {   // contiguous sorted queries; q_bar by a gather pass in input order
+      st = launch_reduce_sorted(plan, sb.pay, M, sb.starts, gL, true, stream);
+      if (st || !gq) return st;
+      return launch_l2p_qgrad(plan, L, q, M, gy, gq, stream);
+    }
     if (gq && plan->C == 1)   // one pass over the sorted queries produces both
       return launch_l2p_T_qgrad(plan, L, q, gy, M, sb.starts, sb.perm, gL, gq, stream);
     st = launch_l2p_T(plan, q, gy, M, sb.starts, sb.perm, gL, stream);
     if (st) return st;
+    if (gq) return launch_l2p_qgrad(plan, L, q, M, gy, gq, stream);
+    return FC2T2_OK;
   }
+  StageScope t(plan, FC2T2_STAGE_L2P_T, stream);
   if (gq) return launch_l2p_qgrad(plan, L, q, M, gy, gq, stream);
   return FC2T2_OK;
 }
@@ -180,12 +223,14 @@ fc2t2_status fc2t2_expand_backward(fc2t2_plan plan, const void* gL, const void* 
   carve_pyramid(c, plan, 0, GMlv);
   fc2t2_status st = expand_T_to_moments(plan, gL, GLlv, GMlv, stream);
   if (st) return st;
+  StageScope t(plan, FC2T2_STAGE_P2M_T, stream);
   return launch_p2m_T(plan, GMlv[0], p, w, N, gp, gw, stream);
 }
 
 fc2t2_status fc2t2_m2l(fc2t2_plan plan, int level, int transpose, const void* in, void* out,
                        int accumulate, hipStream_t stream) {
   if (!plan || !in || !out || level < 0 || level >= plan->levels) return FC2T2_EINVAL;
+  StageScope t(plan, transpose ? FC2T2_STAGE_M2L_T : FC2T2_STAGE_M2L, stream);
   return transpose ? launch_m2l_T(plan, level, in, out, accumulate != 0, stream)
                    : launch_m2l(plan, level, in, out, accumulate != 0, stream);
 }

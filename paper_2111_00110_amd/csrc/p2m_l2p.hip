@@ -55,6 +55,26 @@ struct PointMonomials {
   }
 };
 
+// The same from records sorted along with their data: pay [count][D + 1] holds each point's
+// coordinates and its weight (one channel), indexed by sorted position.
+template <class S, typename T>
+struct SortedMonomials {
+  const T* __restrict__ pay;
+  T inv_h;
+  __device__ __forceinline__ void operator()(uint32_t r, const T (&centre)[3], int, T (&v)[S::P],
+                                             int64_t) const {
+    constexpr int W = S::D + 1;
+    const T* rec = pay + (size_t)r * W;
+    T u[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int j = 0; j < S::D; ++j) u[j] = (rec[j] - centre[j]) * inv_h;
+    monomials<S>(u, v);
+    const T a = rec[S::D];
+#pragma unroll
+    for (int k = 0; k < S::P; ++k) v[k] *= a;
+  }
+};
+
 // Transpose of L2P fused with the query gradient (one channel): besides the record's
 // monomials times gy, adds gy * grad f(q) to gq[q] using the cell's local row.  Each
 // query is one record, so the gq writes do not collide.
@@ -204,6 +224,18 @@ fc2t2_status launch_p2m(const fc2t2_plan_s* pl, const void* p, const void* w, in
                         const uint32_t* starts, const uint32_t* perm, void* M0, hipStream_t s) {
   return pl->io == FC2T2_IO_F64 ? reduce_points<double>(pl, p, w, N, starts, perm, M0, false, s)
                                 : reduce_points<float>(pl, p, w, N, starts, perm, M0, false, s);
+}
+
+fc2t2_status launch_reduce_sorted(const fc2t2_plan_s* pl, const void* pay, int64_t count, const uint32_t* starts,
+                                  void* out, bool accumulate, hipStream_t s) {
+  if (pl->io != FC2T2_IO_F32 || pl->C != 1) return FC2T2_EUNSUPPORTED;
+  fc2t2_status st = FC2T2_EUNSUPPORTED;
+  dispatch_shape(pl->dim, pl->K, [&](auto shape) {
+    using S = decltype(shape);
+    SortedMonomials<S, float> fn{(const float*)pay, (float)(1.0 / pl->h0)};
+    st = launch_reduce_cells<S, float>(pl, starts, nullptr, count, (float*)out, accumulate, fn, s);
+  });
+  return st;
 }
 
 fc2t2_status launch_l2p_T(const fc2t2_plan_s* pl, const void* q, const void* gy, int64_t M,

@@ -3,6 +3,10 @@
 
 #include "common.h"
 
+namespace fc2t2 {
+struct StageTimer;
+}
+
 struct fc2t2_plan_s {
   int dim, n, K, P, Ppad, C, levels, io, prec, kind;
   double lo, hi, param;
@@ -21,6 +25,9 @@ struct fc2t2_plan_s {
   size_t shift_beg_off = 0;
   int shift_n_up = 0, shift_n_down = 0;
   int device = 0;
+  // Stage timing (measurement aid): bit s of timed_mask brackets stage s with events.
+  uint32_t timed_mask = 0;
+  fc2t2::StageTimer* timer = nullptr;
 };
 
 namespace fc2t2 {
@@ -36,16 +43,41 @@ inline size_t pyramid_elems(const fc2t2_plan_s* pl, int first) {
   return s;
 }
 
+// ---- plan.hip: stage timing
+void stage_begin(const fc2t2_plan_s* pl, int stage, hipStream_t s);
+void stage_end(const fc2t2_plan_s* pl, int stage, hipStream_t s);
+void stage_timer_destroy(fc2t2_plan_s* pl);
+// Brackets a stage's launches with events when the plan times that stage.
+struct StageScope {
+  const fc2t2_plan_s* pl;
+  int stage;
+  hipStream_t s;
+  bool on;
+  StageScope(const fc2t2_plan_s* p, int st, hipStream_t str)
+      : pl(p), stage(st), s(str), on(((p->timed_mask >> st) & 1u) != 0) {
+    if (on) stage_begin(pl, stage, s);
+  }
+  ~StageScope() {
+    if (on) stage_end(pl, stage, s);
+  }
+  StageScope(const StageScope&) = delete;
+  StageScope& operator=(const StageScope&) = delete;
+};
+
 // ---- sort.hip
-// Linear finest-cell index of each point.
-fc2t2_status launch_cell_keys(const fc2t2_plan_s* pl, const void* x, int64_t N, uint32_t* keys,
-                              hipStream_t s);
 // Stable LSD radix sort of (key, index) pairs by the low `key_bits` bits.  keys_in is
 // read only; keys_out/vals_out receive the sorted keys and the original indices.
 size_t radix_sort_scratch_bytes(int64_t N);
 fc2t2_status radix_sort_pairs(const uint32_t* keys_in, uint32_t* keys_out, uint32_t* vals_out,
                               int64_t N, int key_bits, void* scratch, hipStream_t s);
 // starts[c] = first sorted position with key >= c, for c in [0, G]; starts[G] = N.
+// The same for points: keys (written to `keys`) are the linear finest-cell indices of x.
+// With pay_out, each point's coordinates and its one value in `extra` travel with it:
+// pay_out [N][dim + 1] receives them in sorted order (FP32, one channel: sort_payload_ok).
+fc2t2_status sort_points_by_cell(const fc2t2_plan_s* pl, const void* x, int64_t N, uint32_t* keys,
+                                 uint32_t* keys_out, uint32_t* vals_out, void* scratch, hipStream_t s,
+                                 const void* extra = nullptr, void* pay_out = nullptr);
+bool sort_payload_ok(const fc2t2_plan_s* pl);
 fc2t2_status launch_cell_starts(const uint32_t* keys_sorted, int64_t N, int64_t G,
                                 uint32_t* starts, hipStream_t s);
 int key_bits_for(int64_t G);
@@ -57,6 +89,10 @@ fc2t2_status launch_p2m(const fc2t2_plan_s* pl, const void* p, const void* w, in
 // Transpose of L2P: gL += sum over the sorted queries of gy (q - c)^k / k!.
 fc2t2_status launch_l2p_T(const fc2t2_plan_s* pl, const void* q, const void* gy, int64_t M,
                           const uint32_t* starts, const uint32_t* perm, void* gL, hipStream_t s);
+// P2M, or the transpose of L2P, from records sorted with their data (pay [count][dim + 1]:
+// coordinates and weight or cotangent; FP32, one channel).
+fc2t2_status launch_reduce_sorted(const fc2t2_plan_s* pl, const void* pay, int64_t count, const uint32_t* starts,
+                                  void* out, bool accumulate, hipStream_t s);
 // Transpose of L2P fused with gq += gy grad f(q) (one channel only).
 fc2t2_status launch_l2p_T_qgrad(const fc2t2_plan_s* pl, const void* L, const void* q, const void* gy, int64_t M,
                                 const uint32_t* starts, const uint32_t* perm, void* gL, void* gq, hipStream_t s);
@@ -73,14 +109,9 @@ fc2t2_status launch_p2m_T(const fc2t2_plan_s* pl, const void* GM0, const void* p
 // ---- tree.hip
 // Sparse shift lists of the plan's (dim, K), uploaded to pl->shift.
 fc2t2_status build_shift_tables(fc2t2_plan_s* pl, hipStream_t s);
-// Up-shift: out[I] = sum_b S_b in[2I+b] (M2M, and the transpose of L2L).
-fc2t2_status launch_upshift(const fc2t2_plan_s* pl, int lvl_child, const void* in, void* out,
-                            hipStream_t s);
-// Down-shift: out[2I+b] (+)= S_b^T in[I] (L2L, and the transpose of M2M).
-fc2t2_status launch_downshift(const fc2t2_plan_s* pl, int lvl_child, const void* in, void* out,
-                              bool accumulate, hipStream_t s);
-// Whole pyramid passes: grids[l+1] = up-shift(grids[l]) for every level, and
-// grids[l] += down-shift(grids[l+1]) from the coarsest to the finest.
+// Whole pyramid passes: grids[l+1] = up-shift(grids[l]) for every level (M2M, and the
+// transpose of L2L), and grids[l] += down-shift(grids[l+1]) from the coarsest to the finest
+// (L2L, and the transpose of M2M); several levels per launch.
 fc2t2_status upshift_pyramid(const fc2t2_plan_s* pl, void* const* grids, hipStream_t s);
 fc2t2_status downshift_pyramid(const fc2t2_plan_s* pl, void* const* grids, hipStream_t s);
 // M2L at one level: L (+)= sum_o T(o) M[i + o] over the admissible offsets.

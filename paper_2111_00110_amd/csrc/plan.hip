@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "plan.h"
@@ -140,6 +141,52 @@ struct DevFree {
 };
 
 }  // namespace
+
+namespace fc2t2 {
+
+// Events of the timed stages: per stage a pool of (before, after) pairs reused between reads.
+struct StageTimer {
+  static constexpr int kMaxCalls = 4096;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool[FC2T2_STAGE_COUNT];
+  int used[FC2T2_STAGE_COUNT] = {};
+  bool open[FC2T2_STAGE_COUNT] = {};
+};
+
+void stage_begin(const fc2t2_plan_s* pl, int stage, hipStream_t s) {
+  StageTimer* t = pl->timer;
+  if (!t || stage < 0 || stage >= FC2T2_STAGE_COUNT || t->used[stage] >= StageTimer::kMaxCalls) return;
+  auto& pool = t->pool[stage];
+  if ((int)pool.size() <= t->used[stage]) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return;
+    }
+    pool.emplace_back(a, b);
+  }
+  if (hipEventRecord(pool[t->used[stage]].first, s) == hipSuccess) t->open[stage] = true;
+}
+
+void stage_end(const fc2t2_plan_s* pl, int stage, hipStream_t s) {
+  StageTimer* t = pl->timer;
+  if (!t || stage < 0 || stage >= FC2T2_STAGE_COUNT || !t->open[stage]) return;
+  t->open[stage] = false;
+  if (hipEventRecord(t->pool[stage][t->used[stage]].second, s) == hipSuccess) ++t->used[stage];
+}
+
+void stage_timer_destroy(fc2t2_plan_s* pl) {
+  if (!pl->timer) return;
+  for (auto& pool : pl->timer->pool)
+    for (auto& e : pool) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+  delete pl->timer;
+  pl->timer = nullptr;
+}
+
+}  // namespace fc2t2
 
 extern "C" {
 
@@ -318,6 +365,7 @@ fc2t2_status fc2t2_plan_destroy(fc2t2_plan plan) {
   if (plan->m2l_T) (void)hipFree(plan->m2l_T);
   if (plan->m2l_bf16) (void)hipFree(plan->m2l_bf16);
   if (plan->shift) (void)hipFree(plan->shift);
+  stage_timer_destroy(plan);
   delete plan;
   return FC2T2_OK;
 }
@@ -327,6 +375,37 @@ int fc2t2_plan_P_pad(fc2t2_plan plan) { return plan ? plan->Ppad : -1; }
 int fc2t2_plan_levels(fc2t2_plan plan) { return plan ? plan->levels : -1; }
 size_t fc2t2_local_numel(fc2t2_plan plan) {
   return plan ? (size_t)plan->C * (size_t)plan->G * (size_t)plan->Ppad : 0;
+}
+
+fc2t2_status fc2t2_stage_timing(fc2t2_plan plan, uint32_t stage_mask) {
+  if (!plan) return FC2T2_EINVAL;
+  if (!plan->timer) plan->timer = new StageTimer();
+  for (int st = 0; st < FC2T2_STAGE_COUNT; ++st) {
+    plan->timer->used[st] = 0;
+    plan->timer->open[st] = false;
+  }
+  plan->timed_mask = stage_mask & ((1u << FC2T2_STAGE_COUNT) - 1u);
+  return FC2T2_OK;
+}
+
+fc2t2_status fc2t2_stage_time(fc2t2_plan plan, int stage, double* ms, int64_t* calls) {
+  if (!plan || !ms || !calls || stage < 0 || stage >= FC2T2_STAGE_COUNT) return FC2T2_EINVAL;
+  *ms = 0.0;
+  *calls = 0;
+  StageTimer* t = plan->timer;
+  if (!t) return FC2T2_OK;
+  double total = 0.0;
+  for (int i = 0; i < t->used[stage]; ++i) {
+    const auto& e = t->pool[stage][i];
+    float dt = 0.0f;
+    if (hipEventSynchronize(e.second) != hipSuccess || hipEventElapsedTime(&dt, e.first, e.second) != hipSuccess)
+      return FC2T2_EHIP;
+    total += dt;
+  }
+  *ms = total;
+  *calls = t->used[stage];
+  t->used[stage] = 0;
+  return FC2T2_OK;
 }
 
 }  // extern "C"

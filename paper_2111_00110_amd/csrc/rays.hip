@@ -891,6 +891,7 @@ fc2t2_status fc2t2_ray_integral(fc2t2_plan plan, const void* L, const void* o, c
   if (!plan || !L || bad_rays(R) || !isfinite(t0) || !isfinite(t1)) return FC2T2_EINVAL;
   if (R > 0 && (!o || !r || !y)) return FC2T2_EINVAL;
   if (!rays_ok(plan)) return FC2T2_EUNSUPPORTED;
+  StageScope tm(plan, FC2T2_STAGE_RAY, stream);
   return launch_ray_integral(plan, L, o, r, t0, t1, R, y, stream);
 }
 
@@ -903,6 +904,7 @@ fc2t2_status fc2t2_ray_integral_backward(fc2t2_plan plan, const void* o, const v
   if (R * (int64_t)maxseg_for(plan) > 0xFFFFFFFFll) return FC2T2_EUNSUPPORTED;
   if (R == 0) return FC2T2_OK;
   if (!ws || ws_bytes < ray_integral_bwd_ws(plan, R)) return FC2T2_EWORKSPACE;
+  StageScope tm(plan, FC2T2_STAGE_RAY_T, stream);
   return ray_integral_backward(plan, o, r, t0, t1, R, gy, gL, ws, stream);
 }
 
@@ -913,6 +915,7 @@ fc2t2_status fc2t2_ray_root(fc2t2_plan plan, const void* L, const void* o, const
   if (R > 0 && (!o || !r || !t || !normal || !hit || !saved)) return FC2T2_EINVAL;
   if (!rays_ok(plan) || plan->C != 1) return FC2T2_EUNSUPPORTED;
   if (plan->io == FC2T2_IO_F32 && plan->G > (int64_t(1) << 24)) return FC2T2_EUNSUPPORTED;
+  StageScope tm(plan, FC2T2_STAGE_RAY, stream);
   return launch_ray_root(plan, L, o, r, t0, t1, R, level_frac, t, normal, hit, saved, stream);
 }
 
@@ -923,6 +926,7 @@ fc2t2_status fc2t2_ray_root_backward(fc2t2_plan plan, const void* saved, const i
   if (!rays_ok(plan) || plan->C != 1) return FC2T2_EUNSUPPORTED;
   if (R == 0 || (!gt && !gn)) return FC2T2_OK;
   if (!ws || ws_bytes < ray_root_bwd_ws(plan, R)) return FC2T2_EWORKSPACE;
+  StageScope tm(plan, FC2T2_STAGE_RAY_T, stream);
   return ray_root_backward(plan, saved, hit, R, gt, gn, gL, ws, stream);
 }
 

@@ -19,7 +19,9 @@ __device__ __forceinline__ void decode_cell(int64_t cell, int n, int (&ic)[3]) {
   }
 }
 
-// out[ch][cell][:] (+)= sum over the cell's sorted records of fn(record).
+// out[ch][cell][:] (+)= sum over the cell's sorted records of fn(record); the record is the
+// input index perm[r] of sorted position r, or r itself when perm is null (records whose
+// data was sorted along with the keys).
 template <class S, typename T, int GROUP, class F>
 __global__ void __launch_bounds__(256) reduce_cells_kernel(const uint32_t* __restrict__ starts,
                                                            const uint32_t* __restrict__ perm,
@@ -42,7 +44,7 @@ __global__ void __launch_bounds__(256) reduce_cells_kernel(const uint32_t* __res
     for (int k = 0; k < P; ++k) { s[k] = T(0); c[k] = T(0); }
     for (uint32_t r = b + lane_g; r < e; r += GROUP) {
       T v[P];
-      fn(perm[r], centre, ch, v, cell);
+      fn(perm ? perm[r] : r, centre, ch, v, cell);
 #pragma unroll
       for (int k = 0; k < P; ++k) acc2(s[k], c[k], v[k]);
     }

@@ -2,6 +2,8 @@
 // cast of its scaled coordinate) and a stable LSD radix sort of (cell, index) pairs, so
 // that the per-cell reductions (P2M, L2P^T, ray insertion) visit every cell's records in
 // input order without floating-point atomics.
+#include <algorithm>
+
 #include "plan.h"
 
 using namespace fc2t2;
@@ -9,37 +11,72 @@ using namespace fc2t2;
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kItems = 4;
-constexpr int kTile = kThreads * kItems;   // keys per block
 constexpr int kBins = 256;                 // 8-bit digits
+constexpr int kMaxPasses = 4;
+// One-sweep passes: a tile is kItems consecutive items per lane, each wave a contiguous run of
+// kItems * 64; 16 items per lane without payload, 8 with (LDS holds the staged payload).
+constexpr int kWaves = kThreads / kWave;
+constexpr int kTileMin = kThreads * 8;
+template <int PW>
+struct SweepShape {
+  static constexpr int kItems = PW > 0 ? 8 : 16;
+  static constexpr int kWaveRun = kItems * kWave;
+  static constexpr int kTile = kThreads * kItems;
+};
+constexpr int kHistCopies = 16;   // private global histograms (spreads the atomics)
+// Tile status words: value in the low 30 bits, flag in the top two (0 = not yet published,
+// 1 = the tile's own counts, 2 = counts of all tiles up to and including this one).
+constexpr uint32_t kFlagAgg = 1u << 30;
+constexpr uint32_t kFlagInc = 2u << 30;
+constexpr uint32_t kValMask = kFlagAgg - 1u;
+constexpr int kMaxPayload = 4;            // payload words per item
+constexpr uint32_t kMaxSpins = 1u << 22;   // bounded wait: a predecessor that never publishes sets err
 
-template <typename T, int D>
-__global__ void __launch_bounds__(256) cell_keys_kernel(const T* __restrict__ x, int64_t N, T lo,
-                                                        T scale, int n, uint32_t* __restrict__ keys) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  uint32_t key = 0;
-#pragma unroll
-  for (int j = 0; j < D; ++j) key = key * (uint32_t)n + (uint32_t)cell_coord<T>(x[i * D + j], lo, scale, n);
-  keys[i] = key;
+__global__ void __launch_bounds__(kThreads) sort_init_kernel(uint32_t* __restrict__ words, int n) {
+  for (int i = threadIdx.x; i < n; i += kThreads) words[i] = 0u;
 }
 
-__global__ void __launch_bounds__(kThreads) radix_hist_kernel(const uint32_t* __restrict__ keys,
-                                                              int64_t N, int shift,
-                                                              uint32_t* __restrict__ hist,
-                                                              int nblocks) {
-  __shared__ uint32_t cnt[kBins];
+// Digit histograms of every pass in one read of the keys (computed from points when x is
+// given, then written to keys), and clearing of the passes' tile status words.
+template <typename T, int D>
+__global__ void __launch_bounds__(kThreads) sort_hist_kernel(const T* __restrict__ x, T lo, T scale, int n,
+                                                             uint32_t* __restrict__ keys, uint32_t N, int npass,
+                                                             uint32_t* __restrict__ ghist,
+                                                             uint32_t* __restrict__ status, uint32_t status_words) {
+  __shared__ uint32_t h[kMaxPasses][kBins];
   const int tid = threadIdx.x;
-  cnt[tid] = 0;
-  __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kTile;
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const int64_t i = base + (int64_t)j * kThreads + tid;
-    if (i < N) atomicAdd(&cnt[(keys[i] >> shift) & (kBins - 1)], 1u);
+  for (int ps = 0; ps < kMaxPasses; ++ps) h[ps][tid] = 0u;
+  __syncthreads();
+  const uint32_t stride = gridDim.x * kThreads;
+  constexpr int kBatch = 8;   // points per thread per round, loaded before any is used
+  for (uint32_t i0 = blockIdx.x * kThreads + tid; i0 < N; i0 += kBatch * stride) {
+    uint32_t key[kBatch];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const uint32_t i = i0 + b * stride;
+      key[b] = 0;
+      if (i >= N) continue;
+      if (x) {
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+          key[b] = key[b] * (uint32_t)n + (uint32_t)cell_coord<T>(x[(size_t)i * D + j], lo, scale, n);
+        keys[i] = key[b];
+      } else {
+        key[b] = keys[i];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      if (i0 + b * stride >= N) continue;
+      for (int ps = 0; ps < npass; ++ps) atomicAdd(&h[ps][(key[b] >> (8 * ps)) & (kBins - 1)], 1u);
+    }
   }
   __syncthreads();
-  hist[(int64_t)tid * nblocks + blockIdx.x] = cnt[tid];
+  uint32_t* gh = ghist + (size_t)(blockIdx.x % kHistCopies) * kMaxPasses * kBins;
+  for (int ps = 0; ps < npass; ++ps)
+    if (h[ps][tid]) atomicAdd(&gh[ps * kBins + tid], h[ps][tid]);
+  for (uint32_t w = blockIdx.x * kThreads + tid; w < status_words; w += stride) status[w] = 0u;
 }
 
 // Block-wide exclusive scan of one value per thread (256 threads); returns the total.
@@ -59,118 +96,174 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t& excl, uint32_t* s
   return total;
 }
 
-// One block per digit: total count of the digit over all tiles.
-__global__ void __launch_bounds__(kThreads) radix_digit_total_kernel(const uint32_t* __restrict__ hist,
-                                                                     int nblocks,
-                                                                     uint32_t* __restrict__ totals) {
-  __shared__ uint32_t sh[kThreads];
-  const int d = blockIdx.x;
-  uint32_t s = 0;
-  for (int b = threadIdx.x; b < nblocks; b += kThreads) s += hist[(int64_t)d * nblocks + b];
-  uint32_t excl;
-  const uint32_t tot = block_exclusive_scan(s, excl, sh);
-  if (threadIdx.x == 0) totals[d] = tot;
+__device__ __forceinline__ uint32_t load_status(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_status(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One block per digit: hist row d becomes the exclusive offsets of (d, tile).
-__global__ void __launch_bounds__(kThreads) radix_offsets_kernel(uint32_t* __restrict__ hist, int nblocks,
-                                                                 const uint32_t* __restrict__ totals) {
-  __shared__ uint32_t sh[kThreads];
-  const int d = blockIdx.x;
-  const int tid = threadIdx.x;
-  // base = sum of totals of smaller digits
-  uint32_t excl_d;
-  block_exclusive_scan(totals[tid], excl_d, sh);
-  __shared__ uint32_t base_sh;
-  if (tid == d) base_sh = excl_d;
-  __syncthreads();
-  uint32_t run = base_sh;
-  // scan the row in chunks of kThreads
-  for (int start = 0; start < nblocks; start += kThreads) {
-    const int b = start + tid;
-    const uint32_t v = b < nblocks ? hist[(int64_t)d * nblocks + b] : 0u;
-    uint32_t excl;
-    const uint32_t tot = block_exclusive_scan(v, excl, sh);
-    if (b < nblocks) hist[(int64_t)d * nblocks + b] = run + excl;
-    run += tot;
-  }
-}
-
-// Stable scatter: items of a tile are visited in input order (item j of thread t is key
-// base + j * 256 + t); ranks among equal digits come from wave ballots, per-wave counts
-// and a running per-digit counter.  The tile is then laid out in LDS in digit order so that
-// the global writes of one digit form one contiguous run.
-__global__ void __launch_bounds__(kThreads) radix_scatter_kernel(
-    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, int64_t N, int shift,
-    const uint32_t* __restrict__ offsets, int nblocks, uint32_t* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out) {
-  __shared__ uint32_t running[kBins];
-  __shared__ uint32_t wcnt[kThreads / kWave][kBins];
-  __shared__ uint32_t local_off[kBins];
+// One stable pass over 8 bits of the key.  Tile t is block t: workgroups are dispatched in
+// index order on each XCD, so the lowest unfinished tile is always resident and every wait
+// below ends; the wait is bounded besides (err).  Ranks: each wave
+// walks its run item by item (input order), ranking a lane among equal digits with ballots
+// and a per-wave running count; wave offsets come from the per-wave counts.  The tile then
+// publishes its digit counts, looks back over the preceding tiles' status words for its
+// global offsets (decoupled look-back), and writes each digit's items as one contiguous run
+// through an LDS staging copy in digit order.
+// Optional payload: PW 32-bit words per item travel with the key, read from pa (na words per
+// item) and pb (PW - na words per item), written to pay_out [N][PW].
+template <int PW>
+__global__ void __launch_bounds__(kThreads) onesweep_kernel(const uint32_t* __restrict__ keys_in,
+                                                            const uint32_t* __restrict__ vals_in, uint32_t N,
+                                                            int shift, const uint32_t* __restrict__ ghist,
+                                                            uint32_t* __restrict__ status,
+                                                            uint32_t* __restrict__ keys_out,
+                                                            uint32_t* __restrict__ vals_out, uint32_t* __restrict__ err,
+                                                            const uint32_t* __restrict__ pa, int na,
+                                                            const uint32_t* __restrict__ pb,
+                                                            uint32_t* __restrict__ pay_out) {
+  constexpr int kItems = SweepShape<PW>::kItems, kWaveRun = SweepShape<PW>::kWaveRun;
+  constexpr int kTile = SweepShape<PW>::kTile;
+  __shared__ uint32_t wcount[kWaves][kBins];
+  __shared__ uint32_t s_excl[kBins];
+  __shared__ uint32_t s_gbase[kBins];
   __shared__ uint32_t scan_sh[kThreads];
   __shared__ uint32_t s_key[kTile];
   __shared__ uint32_t s_val[kTile];
+  __shared__ uint32_t s_pay[PW > 0 ? PW * kTile : 1];
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
-  running[tid] = 0;
-  const int64_t base = (int64_t)blockIdx.x * kTile;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint32_t keys[kItems], vals[kItems], lrank[kItems];
-  bool valid[kItems];
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) wcount[w][tid] = 0u;
+  __syncthreads();
+  const uint32_t tile = blockIdx.x;
+  const uint32_t run0 = tile * (uint32_t)kTile + (uint32_t)wave * kWaveRun;
+  uint32_t key[kItems], val[kItems], rank[kItems];
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
+    const uint32_t i = run0 + (uint32_t)j * kWave + lane;
+    const bool ok = i < N;
+    key[j] = ok ? keys_in[i] : 0u;
+    val[j] = ok ? (vals_in ? vals_in[i] : i) : 0u;
+  }
+  uint32_t pay[kItems][PW > 0 ? PW : 1];
+  if constexpr (PW > 0) {
+    const int nb = PW - na;
 #pragma unroll
-    for (int w = 0; w < kThreads / kWave; ++w) wcnt[w][tid] = 0;
-    __syncthreads();
-    const int64_t i = base + (int64_t)j * kThreads + tid;
-    valid[j] = i < N;
-    keys[j] = valid[j] ? keys_in[i] : 0u;
-    vals[j] = valid[j] ? (vals_in ? vals_in[i] : (uint32_t)i) : 0u;
-    const uint32_t digit = (keys[j] >> shift) & (kBins - 1);
-    uint64_t peers = __ballot(valid[j]);
+    for (int j = 0; j < kItems; ++j) {
+      const uint32_t i = run0 + (uint32_t)j * kWave + lane;
+#pragma unroll
+      for (int w = 0; w < PW; ++w)
+        pay[j][w] = i < N ? (w < na ? pa[(size_t)i * na + w] : pb[(size_t)i * nb + (w - na)]) : 0u;
+    }
+  }
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t* wc = wcount[wave];
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const bool ok = run0 + (uint32_t)j * kWave + lane < N;
+    const uint32_t digit = (key[j] >> shift) & (kBins - 1);
+    uint64_t peers = __ballot(ok);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const uint64_t bb = __ballot(valid[j] && ((digit >> b) & 1u));
+      const uint64_t bb = __ballot(ok && ((digit >> b) & 1u));
       peers &= ((digit >> b) & 1u) ? bb : ~bb;
     }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-    if (valid[j] && (peers & lt_mask) == 0ull) wcnt[wave][digit] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    uint32_t pos = running[digit] + rank;
-    for (int w = 0; w < wave; ++w) pos += wcnt[w][digit];
-    lrank[j] = pos;   // rank among the tile's items with this digit
-    __syncthreads();
-    uint32_t add = 0;
-#pragma unroll
-    for (int w = 0; w < kThreads / kWave; ++w) add += wcnt[w][tid];
-    running[tid] += add;
-    __syncthreads();
+    const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+    const uint32_t before = ok ? wc[digit] : 0u;
+    rank[j] = before + below;
+    __builtin_amdgcn_wave_barrier();
+    if (ok && below == 0u) wc[digit] = before + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
   }
-  // running[d] is now the tile's count of digit d; local_off its exclusive scan
+  __syncthreads();
+  // per digit (thread tid): offsets of the waves and the tile's count
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    const uint32_t t = wcount[w][tid];
+    wcount[w][tid] = cnt;
+    cnt += t;
+  }
+  uint32_t* my = status + (size_t)tile * kBins + tid;
+  store_status(my, (tile == 0 ? kFlagInc : kFlagAgg) | cnt);
   uint32_t excl;
-  block_exclusive_scan(running[tid], excl, scan_sh);
-  local_off[tid] = excl;
+  block_exclusive_scan(cnt, excl, scan_sh);
+  s_excl[tid] = excl;
+  // look back 16 tiles per round: their status words are loaded together and consumed from
+  // the nearest; a tile that has not published yet ends the round (polled again after a sleep)
+  uint32_t prefix = 0;
+  if (tile > 0) {
+    constexpr int kLook = 16;
+    int t = (int)tile - 1;
+    uint32_t spins = 0;
+    for (;;) {
+      uint32_t v[kLook];
+#pragma unroll
+      for (int k = 0; k < kLook; ++k) v[k] = (t - k >= 0) ? load_status(status + (size_t)(t - k) * kBins + tid) : kFlagInc;
+      bool done = false, stall = false;
+      int used = 0;
+#pragma unroll
+      for (int k = 0; k < kLook; ++k) {
+        if (done || stall) continue;
+        if ((v[k] & ~kValMask) == 0u) {
+          stall = true;
+        } else {
+          prefix += v[k] & kValMask;
+          used = k + 1;
+          if (v[k] & kFlagInc) done = true;
+        }
+      }
+      if (done) break;
+      t -= used;
+      if (stall) {
+        if (++spins > kMaxSpins) {
+          atomicOr(err, 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    store_status(my, kFlagInc | (prefix + cnt));
+  }
+  uint32_t dtot = 0;
+#pragma unroll
+  for (int cp = 0; cp < kHistCopies; ++cp) dtot += ghist[(size_t)cp * kMaxPasses * kBins + tid];
+  uint32_t dbase;
+  block_exclusive_scan(dtot, dbase, scan_sh);
+  s_gbase[tid] = dbase + prefix;
   __syncthreads();
+  const uint32_t tile0 = tile * (uint32_t)kTile;
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
-    if (!valid[j]) continue;
-    const uint32_t digit = (keys[j] >> shift) & (kBins - 1);
-    const uint32_t lp = local_off[digit] + lrank[j];
-    s_key[lp] = keys[j];
-    s_val[lp] = vals[j];
+    if (run0 + (uint32_t)j * kWave + lane >= N) continue;
+    const uint32_t digit = (key[j] >> shift) & (kBins - 1);
+    const uint32_t lp = s_excl[digit] + wcount[wave][digit] + rank[j];
+    s_key[lp] = key[j];
+    s_val[lp] = val[j];
+    if constexpr (PW > 0) {
+#pragma unroll
+      for (int w = 0; w < PW; ++w) s_pay[w * kTile + lp] = pay[j][w];
+    }
   }
   __syncthreads();
-  const int count = (int)((N - base) < kTile ? (N - base) : kTile);
+  const uint32_t count = (N - tile0) < (uint32_t)kTile ? (N - tile0) : (uint32_t)kTile;
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
-    const int t = j * kThreads + tid;
+    const uint32_t t = (uint32_t)j * kThreads + tid;
     if (t >= count) continue;
-    const uint32_t key = s_key[t];
-    const uint32_t digit = (key >> shift) & (kBins - 1);
-    const uint32_t pos = offsets[(int64_t)digit * nblocks + blockIdx.x] + (uint32_t)t - local_off[digit];
-    keys_out[pos] = key;
+    const uint32_t k = s_key[t];
+    const uint32_t digit = (k >> shift) & (kBins - 1);
+    const uint32_t pos = s_gbase[digit] + (t - s_excl[digit]);
+    if (pos >= N) continue;   // only after a failed look-back (err set)
+    keys_out[pos] = k;
     vals_out[pos] = s_val[t];
+    if constexpr (PW > 0) {
+#pragma unroll
+      for (int w = 0; w < PW; ++w) pay_out[(size_t)pos * PW + w] = s_pay[w * kTile + t];
+    }
   }
 }
 
@@ -196,64 +289,127 @@ int key_bits_for(int64_t G) {
   return b < 1 ? 1 : b;
 }
 
-fc2t2_status launch_cell_keys(const fc2t2_plan_s* pl, const void* x, int64_t N, uint32_t* keys,
-                              hipStream_t s) {
-  if (N == 0) return FC2T2_OK;
-  const int threads = 256;
-  const dim3 grid((unsigned)ceil_div(N, threads));
-  const double scale = pl->n / (pl->hi - pl->lo);
-  if (pl->io == FC2T2_IO_F64) {
-    if (pl->dim == 2)
-      hipLaunchKernelGGL((cell_keys_kernel<double, 2>), grid, dim3(threads), 0, s, (const double*)x, N, pl->lo, scale, pl->n, keys);
-    else
-      hipLaunchKernelGGL((cell_keys_kernel<double, 3>), grid, dim3(threads), 0, s, (const double*)x, N, pl->lo, scale, pl->n, keys);
-  } else {
-    if (pl->dim == 2)
-      hipLaunchKernelGGL((cell_keys_kernel<float, 2>), grid, dim3(threads), 0, s, (const float*)x, N, (float)pl->lo, (float)scale, pl->n, keys);
-    else
-      hipLaunchKernelGGL((cell_keys_kernel<float, 3>), grid, dim3(threads), 0, s, (const float*)x, N, (float)pl->lo, (float)scale, pl->n, keys);
+}  // namespace fc2t2
+
+namespace {
+
+struct SortScratch {
+  uint32_t *ktmp, *vtmp, *ptmp, *ghist, *status, *err;
+  uint32_t max_tiles;
+};
+constexpr int kHistWords = kHistCopies * kMaxPasses * kBins;
+
+SortScratch carve_scratch(void* scratch, int64_t N) {
+  SortScratch c;
+  c.max_tiles = (uint32_t)ceil_div(N > 0 ? N : 1, kTileMin);
+  char* p = (char*)scratch;
+  c.ktmp = (uint32_t*)p;
+  p += align256((size_t)N * 4);
+  c.vtmp = (uint32_t*)p;
+  p += align256((size_t)N * 4);
+  c.ptmp = (uint32_t*)p;
+  p += align256((size_t)N * 4 * kMaxPayload);
+  c.ghist = (uint32_t*)p;                 // kHistCopies x kMaxPasses x kBins, then err
+  c.err = c.ghist + kHistWords;
+  p += align256((kHistWords + 1) * 4);
+  c.status = (uint32_t*)p;
+  return c;
+}
+
+template <int PW>
+fc2t2_status onesweep_passes(const uint32_t* keys_in, uint32_t* keys_out, uint32_t* vals_out, uint32_t N,
+                             int npass, const SortScratch& c, const uint32_t* pa, int na, const uint32_t* pb,
+                             uint32_t* pay_out, hipStream_t s) {
+  const uint32_t* kin = keys_in;
+  const uint32_t* vin = nullptr;
+  for (int pass = 0; pass < npass; ++pass) {
+    const bool to_out = ((npass - 1 - pass) % 2) == 0;
+    uint32_t* kout = to_out ? keys_out : c.ktmp;
+    uint32_t* vout = to_out ? vals_out : c.vtmp;
+    uint32_t* pout = to_out ? pay_out : c.ptmp;
+    const uint32_t tiles = (uint32_t)ceil_div(N, SweepShape<PW>::kTile);
+    hipLaunchKernelGGL((onesweep_kernel<PW>), dim3(tiles), dim3(kThreads), 0, s, kin, vin, N, 8 * pass,
+                       c.ghist + pass * kBins, c.status + (size_t)pass * c.max_tiles * kBins, kout, vout, c.err,
+                       pa, na, pb, pout);
+    FC2T2_LAUNCH_CHECK();
+    kin = kout;
+    vin = vout;
+    pa = pout;   // later passes read the payload as written, PW words per item
+    na = PW;
+    pb = nullptr;
   }
+  return FC2T2_OK;
+}
+
+// Histogram (and keys from points when x is given) for npass passes of 8 bits.
+template <typename T, int D>
+fc2t2_status sort_prologue(const T* x, T lo, T scale, int n, uint32_t* keys, uint32_t N, int npass,
+                           const SortScratch& c, hipStream_t s) {
+  hipLaunchKernelGGL(sort_init_kernel, dim3(1), dim3(kThreads), 0, s, c.ghist, kHistWords + 1);
+  FC2T2_LAUNCH_CHECK();
+  const uint32_t status_words = (uint32_t)npass * c.max_tiles * kBins;
+  const int64_t work = (int64_t)N > (int64_t)status_words ? (int64_t)N : (int64_t)status_words;
+  const unsigned blocks = (unsigned)std::min<int64_t>(std::max<int64_t>(ceil_div(work, kThreads * 8), 1), 2048);
+  hipLaunchKernelGGL((sort_hist_kernel<T, D>), dim3(blocks), dim3(kThreads), 0, s, x, lo, scale, n, keys, N, npass,
+                     c.ghist, c.status, status_words);
   FC2T2_LAUNCH_CHECK();
   return FC2T2_OK;
 }
 
+}  // namespace
+
+namespace fc2t2 {
+
 size_t radix_sort_scratch_bytes(int64_t N) {
-  const int64_t nblocks = ceil_div(N > 0 ? N : 1, kTile);
-  return align256((size_t)N * 4) * 2 + align256((size_t)nblocks * kBins * 4) + align256(kBins * 4);
+  const int64_t tiles = ceil_div(N > 0 ? N : 1, kTileMin);
+  return align256((size_t)N * 4) * 2 + align256((size_t)N * 4 * kMaxPayload) + align256((kHistWords + 1) * 4) +
+         align256((size_t)kMaxPasses * tiles * kBins * 4);
 }
 
 fc2t2_status radix_sort_pairs(const uint32_t* keys_in, uint32_t* keys_out, uint32_t* vals_out,
                               int64_t N, int key_bits, void* scratch, hipStream_t s) {
   if (N == 0) return FC2T2_OK;
-  if (N > 0xFFFFFFFFll) return FC2T2_EUNSUPPORTED;
-  const int nblocks = (int)ceil_div(N, kTile);
-  char* p = (char*)scratch;
-  uint32_t* ktmp = (uint32_t*)p;
-  p += align256((size_t)N * 4);
-  uint32_t* vtmp = (uint32_t*)p;
-  p += align256((size_t)N * 4);
-  uint32_t* hist = (uint32_t*)p;
-  p += align256((size_t)nblocks * kBins * 4);
-  uint32_t* totals = (uint32_t*)p;
+  if (N >= (int64_t)kValMask || key_bits > 8 * kMaxPasses) return FC2T2_EUNSUPPORTED;
+  const SortScratch c = carve_scratch(scratch, N);
   const int npass = (key_bits + 7) / 8;
-  const uint32_t* kin = keys_in;
-  const uint32_t* vin = nullptr;
-  for (int pass = 0; pass < npass; ++pass) {
-    const bool to_out = ((npass - 1 - pass) % 2) == 0;
-    uint32_t* kout = to_out ? keys_out : ktmp;
-    uint32_t* vout = to_out ? vals_out : vtmp;
-    const int shift = 8 * pass;
-    hipLaunchKernelGGL(radix_hist_kernel, dim3(nblocks), dim3(kThreads), 0, s, kin, N, shift, hist, nblocks);
-    hipLaunchKernelGGL(radix_digit_total_kernel, dim3(kBins), dim3(kThreads), 0, s, hist, nblocks, totals);
-    hipLaunchKernelGGL(radix_offsets_kernel, dim3(kBins), dim3(kThreads), 0, s, hist, nblocks, totals);
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblocks), dim3(kThreads), 0, s, kin, vin, N, shift,
-                       hist, nblocks, kout, vout);
-    FC2T2_LAUNCH_CHECK();
-    kin = kout;
-    vin = vout;
-  }
-  return FC2T2_OK;
+  fc2t2_status st = sort_prologue<float, 1>(nullptr, 0.f, 0.f, 0, (uint32_t*)keys_in, (uint32_t)N, npass, c, s);
+  if (st) return st;
+  return onesweep_passes<0>(keys_in, keys_out, vals_out, (uint32_t)N, npass, c, nullptr, 0, nullptr, nullptr, s);
 }
+
+fc2t2_status sort_points_by_cell(const fc2t2_plan_s* pl, const void* x, int64_t N, uint32_t* keys,
+                                 uint32_t* keys_out, uint32_t* vals_out, void* scratch, hipStream_t s,
+                                 const void* extra, void* pay_out) {
+  if (N == 0) return FC2T2_OK;
+  if (N >= (int64_t)kValMask) return FC2T2_EUNSUPPORTED;
+  const int key_bits = key_bits_for(pl->G);
+  if (key_bits > 8 * kMaxPasses) return FC2T2_EUNSUPPORTED;
+  const SortScratch c = carve_scratch(scratch, N);
+  const int npass = (key_bits + 7) / 8;
+  const double scale = pl->n / (pl->hi - pl->lo);
+  fc2t2_status st;
+  if (pl->io == FC2T2_IO_F64)
+    st = pl->dim == 2 ? sort_prologue<double, 2>((const double*)x, pl->lo, scale, pl->n, keys, (uint32_t)N, npass, c, s)
+                      : sort_prologue<double, 3>((const double*)x, pl->lo, scale, pl->n, keys, (uint32_t)N, npass, c, s);
+  else
+    st = pl->dim == 2 ? sort_prologue<float, 2>((const float*)x, (float)pl->lo, (float)scale, pl->n, keys, (uint32_t)N,
+                                                 npass, c, s)
+                      : sort_prologue<float, 3>((const float*)x, (float)pl->lo, (float)scale, pl->n, keys, (uint32_t)N,
+                                                 npass, c, s);
+  if (st) return st;
+  if (pay_out) {
+    if (!sort_payload_ok(pl)) return FC2T2_EUNSUPPORTED;
+    const uint32_t* pa = (const uint32_t*)x;
+    const uint32_t* pb = (const uint32_t*)extra;
+    return pl->dim == 2 ? onesweep_passes<3>(keys, keys_out, vals_out, (uint32_t)N, npass, c, pa, 2, pb,
+                                             (uint32_t*)pay_out, s)
+                        : onesweep_passes<4>(keys, keys_out, vals_out, (uint32_t)N, npass, c, pa, 3, pb,
+                                             (uint32_t*)pay_out, s);
+  }
+  return onesweep_passes<0>(keys, keys_out, vals_out, (uint32_t)N, npass, c, nullptr, 0, nullptr, nullptr, s);
+}
+
+bool sort_payload_ok(const fc2t2_plan_s* pl) { return pl->io == FC2T2_IO_F32 && pl->C == 1; }
 
 fc2t2_status launch_cell_starts(const uint32_t* keys_sorted, int64_t N, int64_t G, uint32_t* starts,
                                 hipStream_t s) {

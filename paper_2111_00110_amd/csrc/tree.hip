@@ -41,11 +41,17 @@ __device__ __forceinline__ int64_t encode(const int (&c)[3], int n) {
 // offset e = (b - 1/2) h_child (b in {0,1}^d), the scaled shift matrix factors as
 //   S_b[n][m] = c[n][m] * sigma_b(n - m),
 //   c[n][m] = 2^(-|n| - |n-m|) / prod_j (n_j - m_j)!,   sigma_b(d) = prod_j (-1)^(d_j (1 - b_j)),
-// and sigma depends on d only through its parity pattern pi = d mod 2.  The plan holds,
-// for every multi-index, the sparse list of its (partner multi-index, parity pattern, c)
-// entries: for the up-shift, n's list runs over m <= n; for the down-shift, k's list runs
-// over m >= k.  One thread computes one output coefficient by walking its list and
-// combining the 2^d children with the signs sigma_b(pi).
+// and sigma depends on d only through its parity pattern pi = d mod 2, so
+//   sigma_b(pi) = (-1)^popcount(pi & ~b).
+// The sign sums over the children are therefore a Walsh-Hadamard transform of size 2^d:
+//   up:   out[n] = sum_{m <= n} c[n][m] H[pi(n-m)][m],  H[pi][m] = sum_b sigma_b(pi) child_b[m]
+//   down: child_b[k] = sum_pi sigma_b(pi) G[pi][k],     G[pi][k] = sum_{m >= k, pi(m-k) = pi} c[m][k] in[m]
+// which costs one multiply-add per (output, list entry) plus d 2^(d-1) butterflies per
+// coefficient, instead of 2^d multiply-adds per list entry.
+//
+// Several levels run in one launch: a block owns a tile of 2^f x .. x 2^f cells at the
+// finer level l0 and the 2^(f-j)-wide tiles above it at levels l0 + j (the subtree of one
+// cell at level l0 + f); the intermediate tiles stay in LDS.
 
 struct ShiftEntry {
   double c;
@@ -53,135 +59,218 @@ struct ShiftEntry {
   int pi;
 };
 
-__device__ __forceinline__ float sigma_sign(int pi, int b) {
-  // (-1)^(number of dimensions j with pi_j = 1 and b_j = 0)
-  return (__popc(pi & ~b) & 1) ? -1.0f : 1.0f;
-}
+struct LevelPtrs {
+  void* p[kMaxLevels];
+};
 
-template <int D>
-__device__ __forceinline__ int64_t child_cell(const int (&pc)[3], int b, int n_child) {
-  int64_t lin = 0;
-#pragma unroll
-  for (int j = 0; j < D; ++j) lin = lin * n_child + (2 * pc[j] + ((b >> (D - 1 - j)) & 1));
-  return lin;
-}
-
-// Both shifts run in blocks of 256 threads covering NPB = 256 / P_pad parents: the block first
-// copies the sparse lists and its parents' (or children's) rows into LDS with coalesced loads,
-// then each thread computes one coefficient from LDS, and the results are written coalesced.
 constexpr int kShiftThreads = 256;
 constexpr int kMaxShiftEntries = 2048;
+constexpr size_t kShiftLds = 64 * 1024;
 
-template <typename T>
-__device__ __forceinline__ void copy_rows_to_lds(const T* __restrict__ src, T* dst, int count) {
-  for (int i = threadIdx.x; i < count; i += kShiftThreads) dst[i] = src[i];
+__host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+// x[pi] <- sum_b (-1)^popcount(pi & b) x[b]  (Sylvester-ordered Hadamard butterflies)
+template <int D, typename T>
+__device__ __forceinline__ void hadamard(T (&x)[1 << D]) {
+#pragma unroll
+  for (int st = 1; st < (1 << D); st <<= 1)
+#pragma unroll
+    for (int i = 0; i < (1 << D); ++i)
+      if (!(i & st)) {
+        const T a = x[i], b = x[i | st];
+        x[i] = a + b;
+        x[i | st] = a - b;
+      }
 }
 
-// out[ch][I][n] = sum_b sum_{m <= n} S_b[n][m] in[ch][2I+b][m]; one thread per (parent, n).
-template <int D, typename T>
-__global__ void __launch_bounds__(kShiftThreads) upshift_kernel(const T* __restrict__ in, T* __restrict__ out,
-                                                                const ShiftEntry* __restrict__ tab,
-                                                                const int* __restrict__ beg, int n_entries, int P,
-                                                                int Ppad, int lg_par, uint32_t G_par,
-                                                                uint32_t G_child) {
-  constexpr int NB = 1 << D;
+// Coordinates of local index p in a tile of side 2^lg (last dimension fastest).
+template <int D>
+__device__ __forceinline__ void tile_coords(uint32_t p, int lg, uint32_t (&c)[3]) {
+  const uint32_t mask = (1u << lg) - 1u;
+  c[0] = c[1] = c[2] = 0;
+#pragma unroll
+  for (int j = D - 1; j >= 0; --j) { c[j] = p & mask; p >>= lg; }
+}
+template <int D>
+__device__ __forceinline__ uint32_t tile_lin(const uint32_t (&c)[3], int lg) {
+  uint32_t lin = 0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) lin = (lin << lg) | c[j];
+  return lin;
+}
+// Child b of a cell with coordinates c (bit D-1-j of b is the offset along dimension j).
+template <int D>
+__device__ __forceinline__ void child_coords(const uint32_t (&c)[3], int b, uint32_t (&cc)[3]) {
+  cc[0] = cc[1] = cc[2] = 0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) cc[j] = 2 * c[j] + ((b >> (D - 1 - j)) & 1);
+}
+
+// Up-shift chain: levels l0+1 .. l0+f from level l0.  grids.p[l] is the level-l grid
+// [C][G_l][P_pad]; lg0 = log2 of the level-l0 side.  Every produced level is written out
+// (padding coefficients as zero).
+template <class S, typename T>
+__global__ void __launch_bounds__(kShiftThreads) upchain_kernel(LevelPtrs grids, const ShiftEntry* __restrict__ tab,
+                                                                const int* __restrict__ beg, int n_entries, int l0,
+                                                                int f, int lg0) {
+  constexpr int D = S::D, P = S::P, PP = S::Ppad, NB = 1 << D;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  ShiftEntry* s_tab = reinterpret_cast<ShiftEntry*>(smem);
-  int* s_beg = reinterpret_cast<int*>(s_tab + n_entries);
-  T* s_rows = reinterpret_cast<T*>(smem + (((size_t)n_entries * sizeof(ShiftEntry) + (P + 1) * sizeof(int) + 15) & ~size_t(15)));
-  const int npb = kShiftThreads / Ppad;
-  const int ch = blockIdx.y;
-  const uint32_t I0 = blockIdx.x * npb;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < n_entries; i += kShiftThreads) s_tab[i] = tab[i];
-  for (int i = tid; i <= P; i += kShiftThreads) s_beg[i] = beg[i];
-  // children rows of the block's parents: s_rows[p][b][:]
-  const uint32_t mask = (1u << lg_par) - 1u;
-  const int lg_child = lg_par + 1;
-  for (int idx = tid; idx < npb * NB * Ppad; idx += kShiftThreads) {
-    const int pb = idx / Ppad, k = idx - pb * Ppad;
-    const int p = pb / NB, b = pb % NB;
-    const uint32_t I = I0 + p;
-    if (I >= G_par) continue;
-    uint32_t r = I, lin = 0, pc[3] = {0, 0, 0};
-#pragma unroll
-    for (int j = D - 1; j >= 0; --j) { pc[j] = r & mask; r >>= lg_par; }
-#pragma unroll
-    for (int j = 0; j < D; ++j) lin = (lin << lg_child) | (2 * pc[j] + ((b >> (D - 1 - j)) & 1));
-    s_rows[idx] = in[((size_t)ch * G_child + lin) * Ppad + k];
+  T* s_coef = reinterpret_cast<T*>(smem);
+  int* s_off = reinterpret_cast<int*>(s_coef + n_entries);
+  int* s_beg = s_off + n_entries;
+  T* hbuf = reinterpret_cast<T*>(smem + align16((size_t)n_entries * (sizeof(T) + sizeof(int)) + (P + 1) * sizeof(int)));
+  T* obuf = hbuf + ((size_t)PP << (f * D));
+  const int tid = threadIdx.x, ch = blockIdx.y;
+  for (int i = tid; i < n_entries; i += kShiftThreads) {
+    const ShiftEntry e = tab[i];
+    s_coef[i] = (T)e.c;
+    s_off[i] = e.pi * PP + e.m;
   }
-  __syncthreads();
-  const int p = tid / Ppad, nn = tid - p * Ppad;
-  if (p >= npb) return;
-  const uint32_t I = I0 + p;
-  if (I >= G_par) return;
-  T acc = T(0);
-  if (nn < P) {
-    const T* rows = s_rows + (size_t)p * NB * Ppad;
-    for (int e = s_beg[nn]; e < s_beg[nn + 1]; ++e) {
-      const ShiftEntry en = s_tab[e];
-      T h = T(0);
+  for (int i = tid; i <= P; i += kShiftThreads) s_beg[i] = beg[i];
+  uint32_t tc[3];
+  tile_coords<D>(blockIdx.x, lg0 - f, tc);
+  for (int j = 1; j <= f; ++j) {
+    const int lgp = f - j;                         // log2 parent tile side
+    const uint32_t npar = 1u << (lgp * D);
+    const int lgn_c = lg0 - j + 1, lgn_p = lg0 - j;  // log2 level sides (children, parents)
+    const T* cin = (const T*)grids.p[l0 + j - 1] + ((size_t)ch << (lgn_c * D)) * PP;
+    // stage H[p][pi][m]
+    for (uint32_t idx = tid; idx < npar * PP; idx += kShiftThreads) {
+      const uint32_t p = idx / PP, m = idx - p * PP;
+      uint32_t pc[3], cc[3];
+      tile_coords<D>(p, lgp, pc);
+      T x[NB];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) h += (T)sigma_sign(en.pi, b) * rows[b * Ppad + en.m];
-      acc += (T)en.c * h;
+      for (int b = 0; b < NB; ++b) {
+        child_coords<D>(pc, b, cc);
+        T v;
+        if (j == 1) {
+          uint32_t gc[3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) gc[d] = (tc[d] << (lgp + 1)) + cc[d];
+          v = cin[(size_t)tile_lin<D>(gc, lgn_c) * PP + m];
+        } else {
+          v = obuf[(size_t)tile_lin<D>(cc, lgp + 1) * PP + m];
+        }
+        x[NB - 1 - b] = v;
+      }
+      hadamard<D>(x);
+#pragma unroll
+      for (int pi = 0; pi < NB; ++pi) hbuf[((size_t)p * NB + pi) * PP + m] = x[pi];
     }
+    __syncthreads();
+    T* out = (T*)grids.p[l0 + j] + ((size_t)ch << (lgn_p * D)) * PP;
+    for (uint32_t idx = tid; idx < npar * PP; idx += kShiftThreads) {
+      const uint32_t p = idx / PP, n = idx - p * PP;
+      T acc = T(0);
+      if (n < P) {
+        const T* h = hbuf + (size_t)p * NB * PP;
+        for (int e = s_beg[n]; e < s_beg[n + 1]; ++e) acc += s_coef[e] * h[s_off[e]];
+      }
+      if (j < f) obuf[idx] = acc;
+      uint32_t pc[3], gc[3];
+      tile_coords<D>(p, lgp, pc);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) gc[d] = (tc[d] << lgp) + pc[d];
+      out[(size_t)tile_lin<D>(gc, lgn_p) * PP + n] = acc;
+    }
+    __syncthreads();
   }
-  out[((size_t)ch * G_par + I) * Ppad + nn] = acc;
 }
 
-// out[ch][2I+b][k] (+)= sum_{m >= k} S_b[m][k] in[ch][I][m]; one thread per (parent, k)
-// producing coefficient k of all 2^d children.
-template <int D, typename T>
-__global__ void __launch_bounds__(kShiftThreads) downshift_kernel(const T* __restrict__ in, T* __restrict__ out,
-                                                                  const ShiftEntry* __restrict__ tab,
-                                                                  const int* __restrict__ beg, int n_entries, int P,
-                                                                  int Ppad, int lg_par, uint32_t G_par,
-                                                                  uint32_t G_child, int accumulate) {
-  constexpr int NB = 1 << D;
+// Down-shift chain: from level l0+f down to level l0, each finer level accumulating onto what
+// its grid holds: grid[l] <- grid[l] + down-shift(grid[l+1]).  Only level l0 is written; the
+// intermediate levels stay in LDS.  beg holds NB+1 list offsets per k (lists grouped by pi).
+// The block first loads the top cell and the tile's rows of every level below it (what the
+// finer levels already hold) into LDS in one pass, so the level steps touch no global memory
+// until the final write.
+template <class S, typename T>
+__global__ void __launch_bounds__(kShiftThreads) downchain_kernel(LevelPtrs grids, const ShiftEntry* __restrict__ tab,
+                                                                  const int* __restrict__ beg, int n_entries, int l0,
+                                                                  int f, int lg0) {
+  constexpr int D = S::D, P = S::P, PP = S::Ppad, NB = 1 << D;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  ShiftEntry* s_tab = reinterpret_cast<ShiftEntry*>(smem);
-  int* s_beg = reinterpret_cast<int*>(s_tab + n_entries);
-  T* s_rows = reinterpret_cast<T*>(smem + (((size_t)n_entries * sizeof(ShiftEntry) + (P + 1) * sizeof(int) + 15) & ~size_t(15)));
-  const int npb = kShiftThreads / Ppad;
-  const int ch = blockIdx.y;
-  const uint32_t I0 = blockIdx.x * npb;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < n_entries; i += kShiftThreads) s_tab[i] = tab[i];
-  for (int i = tid; i <= P; i += kShiftThreads) s_beg[i] = beg[i];
+  T* s_coef = reinterpret_cast<T*>(smem);
+  int* s_m = reinterpret_cast<int*>(s_coef + n_entries);
+  int* s_beg = s_m + n_entries;
+  T* buf0 = reinterpret_cast<T*>(smem + align16((size_t)n_entries * (sizeof(T) + sizeof(int)) + P * (NB + 1) * sizeof(int)));
+  const size_t buf_elems = (size_t)PP << ((f - 1) * D);
+  T* buf1 = buf0 + buf_elems;
+  T* own = buf1 + buf_elems;   // rows of levels l0+f-1 .. l0 of the tile, level by level
+  const int tid = threadIdx.x, ch = blockIdx.y;
+  for (int i = tid; i < n_entries; i += kShiftThreads) {
+    const ShiftEntry e = tab[i];
+    s_coef[i] = (T)e.c;
+    s_m[i] = e.m;
+  }
+  for (int i = tid; i < P * (NB + 1); i += kShiftThreads) s_beg[i] = beg[i];
+  uint32_t tc[3];
+  tile_coords<D>(blockIdx.x, lg0 - f, tc);
   {
-    // the block's parent rows are contiguous in memory
-    const uint32_t nrows = (I0 + npb <= G_par) ? (uint32_t)npb : (G_par - I0);
-    copy_rows_to_lds(in + ((size_t)ch * G_par + I0) * Ppad, s_rows, (int)(nrows * Ppad));
+    const int lgn = lg0 - f;
+    const T* top = (const T*)grids.p[l0 + f] + (((size_t)ch << (lgn * D)) + blockIdx.x) * PP;
+    for (int i = tid; i < PP; i += kShiftThreads) buf0[i] = top[i];
   }
-  __syncthreads();
-  const int p = tid / Ppad, k = tid - p * Ppad;
-  if (p >= npb) return;
-  const uint32_t I = I0 + p;
-  if (I >= G_par) return;
-  T acc[NB];
+  {
+    size_t off = 0;
+    for (int j = 1; j <= f; ++j) {
+      const int lgn_c = lg0 - f + j;
+      const T* src = (const T*)grids.p[l0 + f - j] + ((size_t)ch << (lgn_c * D)) * PP;
+      const uint32_t cnt = (1u << (j * D)) * PP;
+#pragma unroll 4
+      for (uint32_t idx = tid; idx < cnt; idx += kShiftThreads) {
+        const uint32_t c = idx / PP, k = idx - c * PP;
+        uint32_t cc[3], gc[3];
+        tile_coords<D>(c, j, cc);
 #pragma unroll
-  for (int b = 0; b < NB; ++b) acc[b] = T(0);
-  if (k < P) {
-    const T* row = s_rows + (size_t)p * Ppad;
-    for (int e = s_beg[k]; e < s_beg[k + 1]; ++e) {
-      const ShiftEntry en = s_tab[e];
-      const T v = (T)en.c * row[en.m];
-#pragma unroll
-      for (int b = 0; b < NB; ++b) acc[b] += (T)sigma_sign(en.pi, b) * v;
+        for (int d = 0; d < 3; ++d) gc[d] = (tc[d] << j) + cc[d];
+        own[off + idx] = src[(size_t)tile_lin<D>(gc, lgn_c) * PP + k];
+      }
+      off += cnt;
     }
   }
-  const uint32_t mask = (1u << lg_par) - 1u;
-  uint32_t r = I, pc[3] = {0, 0, 0};
+  __syncthreads();
+  size_t own_off = 0;
+  for (int j = 1; j <= f; ++j) {
+    const int lgp = j - 1;                          // log2 parent tile side
+    const uint32_t npar = 1u << (lgp * D);
+    const int lc = l0 + f - j;                      // child level
+    const int lgn_c = lg0 - f + j;
+    const T* pin = (j & 1) ? buf0 : buf1;
+    T* cout_lds = (j & 1) ? buf1 : buf0;
+    const T* cown = own + own_off;
+    T* cg = (T*)grids.p[lc] + ((size_t)ch << (lgn_c * D)) * PP;
+    for (uint32_t idx = tid; idx < npar * PP; idx += kShiftThreads) {
+      const uint32_t p = idx / PP, k = idx - p * PP;
+      if (k >= P) continue;
+      const T* row = pin + (size_t)p * PP;
+      T g[NB];
 #pragma unroll
-  for (int j = D - 1; j >= 0; --j) { pc[j] = r & mask; r >>= lg_par; }
-  const int lg_child = lg_par + 1;
+      for (int pi = 0; pi < NB; ++pi) {
+        T a = T(0);
+        for (int e = s_beg[k * (NB + 1) + pi]; e < s_beg[k * (NB + 1) + pi + 1]; ++e) a += s_coef[e] * row[s_m[e]];
+        g[pi] = a;
+      }
+      hadamard<D>(g);
+      uint32_t pc[3], cc[3];
+      tile_coords<D>(p, lgp, pc);
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    uint32_t lin = 0;
+      for (int b = 0; b < NB; ++b) {
+        child_coords<D>(pc, b, cc);
+        const uint32_t cl = tile_lin<D>(cc, lgp + 1);
+        const T v = cown[(size_t)cl * PP + k] + g[NB - 1 - b];
+        if (j < f) {
+          cout_lds[(size_t)cl * PP + k] = v;
+        } else {
+          uint32_t gc[3];
 #pragma unroll
-    for (int j = 0; j < D; ++j) lin = (lin << lg_child) | (2 * pc[j] + ((b >> (D - 1 - j)) & 1));
-    T* dst = out + ((size_t)ch * G_child + lin) * Ppad + k;
-    if (accumulate) *dst += acc[b]; else *dst = acc[b];
+          for (int d = 0; d < 3; ++d) gc[d] = (tc[d] << (lgp + 1)) + cc[d];
+          cg[(size_t)tile_lin<D>(gc, lgn_c) * PP + k] = v;
+        }
+      }
+    }
+    own_off += (size_t)(1u << (j * D)) * PP;
+    __syncthreads();
   }
 }
 
@@ -281,7 +370,7 @@ fc2t2_status build_shift_tables(fc2t2_plan_s* pl, hipStream_t s) {
   std::vector<int> e((size_t)P * 3);
   mi_fill(dim, pl->K, reinterpret_cast<int(*)[3]>(e.data()));
   std::vector<ShiftEntry> up, down;
-  std::vector<int> beg_up(P + 1), beg_down(P + 1);
+  std::vector<int> beg_up(P + 1), beg_down((size_t)P * ((1 << dim) + 1));
   auto le = [&](int a, int c) {   // multi-index c <= a componentwise
     return e[3 * c] <= e[3 * a] && e[3 * c + 1] <= e[3 * a + 1] && e[3 * c + 2] <= e[3 * a + 2];
   };
@@ -306,12 +395,15 @@ fc2t2_status build_shift_tables(fc2t2_plan_s* pl, hipStream_t s) {
       if (le(n, m)) up.push_back(ShiftEntry{coef(n, m), m, parity(n, m)});
   }
   beg_up[P] = (int)up.size();
+  const int NB = 1 << dim;
   for (int k = 0; k < P; ++k) {
-    beg_down[k] = (int)down.size();
-    for (int m = 0; m < P; ++m)
-      if (le(m, k)) down.push_back(ShiftEntry{coef(m, k), m, parity(m, k)});
+    for (int pi = 0; pi < NB; ++pi) {
+      beg_down[k * (NB + 1) + pi] = (int)down.size();
+      for (int m = 0; m < P; ++m)
+        if (le(m, k) && parity(m, k) == pi) down.push_back(ShiftEntry{coef(m, k), m, pi});
+    }
+    beg_down[k * (NB + 1) + NB] = (int)down.size();
   }
-  beg_down[P] = (int)down.size();
   std::vector<ShiftEntry> all(up);
   all.insert(all.end(), down.begin(), down.end());
   pl->shift_n_up = (int)up.size();
@@ -330,48 +422,104 @@ fc2t2_status build_shift_tables(fc2t2_plan_s* pl, hipStream_t s) {
   return hipStreamSynchronize(s) == hipSuccess ? FC2T2_OK : FC2T2_EHIP;
 }
 
-template <int D, typename T>
-fc2t2_status shift_launch(const fc2t2_plan_s* pl, int lvl_child, const void* in, void* out, bool up,
-                          bool accumulate, hipStream_t s) {
-  const int lp = lvl_child + 1;
-  const int npb = kShiftThreads / pl->Ppad;
-  const int n_up = pl->shift_n_up, n_down = pl->shift_n_down;
-  const int n_entries = up ? n_up : n_down;
-  const ShiftEntry* tab = (const ShiftEntry*)pl->shift + (up ? 0 : n_up);
-  const int* beg0 = (const int*)((const char*)pl->shift + pl->shift_beg_off);
-  // the down-shift list offsets are stored after the up lists; rebase them to its own table
-  const int* beg = up ? beg0 : beg0 + (pl->P + 1);
-  const size_t rows = (size_t)npb * (up ? (1 << D) : 1) * pl->Ppad;
-  const size_t smem = (((size_t)n_entries * sizeof(ShiftEntry) + (pl->P + 1) * sizeof(int) + 15) & ~size_t(15)) +
-                      rows * sizeof(T);
-  const dim3 grid((unsigned)ceil_div(pl->Gl[lp], npb), pl->C);
-  if (up)
-    hipLaunchKernelGGL((upshift_kernel<D, T>), grid, dim3(kShiftThreads), smem, s, (const T*)in, (T*)out, tab, beg,
-                       n_entries, pl->P, pl->Ppad, lg2i(pl->nl[lp]), (uint32_t)pl->Gl[lp], (uint32_t)pl->Gl[lvl_child]);
-  else
-    hipLaunchKernelGGL((downshift_kernel<D, T>), grid, dim3(kShiftThreads), smem, s, (const T*)in, (T*)out, tab, beg,
-                       n_entries, pl->P, pl->Ppad, lg2i(pl->nl[lp]), (uint32_t)pl->Gl[lp], (uint32_t)pl->Gl[lvl_child],
-                       accumulate ? 1 : 0);
+}  // namespace fc2t2
+
+namespace {
+
+struct ShiftSeg {
+  int l0, f;
+};
+
+size_t upchain_lds(const fc2t2_plan_s* pl, int f) {
+  const int D = pl->dim;
+  const size_t es = io_size(pl);
+  return align16((size_t)pl->shift_n_up * (es + sizeof(int)) + (pl->P + 1) * sizeof(int)) +
+         (((size_t)pl->Ppad << (f * D)) + ((size_t)pl->Ppad << ((f - 1) * D))) * es;
+}
+size_t downchain_lds(const fc2t2_plan_s* pl, int f) {
+  const int D = pl->dim;
+  const size_t es = io_size(pl);
+  size_t own = 0;
+  for (int j = 1; j <= f; ++j) own += (size_t)pl->Ppad << (j * D);
+  return align16((size_t)pl->shift_n_down * (es + sizeof(int)) + (size_t)pl->P * ((1 << D) + 1) * sizeof(int)) +
+         (2 * ((size_t)pl->Ppad << ((f - 1) * D)) + own) * es;
+}
+
+// Level segments [l0, l0 + f] of the pyramid, one launch each.  A small level (at most 4096
+// cells) finishes the pyramid in one launch; below that, a segment is as deep as the LDS
+// budget allows while leaving at least 1024 tiles (four per compute unit).
+int shift_segments(const fc2t2_plan_s* pl, ShiftSeg* seg) {
+  const int D = pl->dim, L = pl->levels;
+  auto fits = [&](int f) { return upchain_lds(pl, f) <= kShiftLds && downchain_lds(pl, f) <= kShiftLds; };
+  int ns = 0, l0 = 0;
+  while (l0 + 1 < L) {
+    const int rem = L - 1 - l0, lgn = lg2i(pl->nl[l0]);
+    int f = 0;
+    if (pl->Gl[l0] <= 4096 && rem <= lgn && fits(rem)) {
+      f = rem;
+    } else {
+      for (int g = 1; g <= rem && g <= lgn && fits(g); ++g) {
+        if (((int64_t)1 << ((lgn - g) * D)) < 1024) break;
+        f = g;
+      }
+      if (f == 0) f = 1;
+    }
+    seg[ns++] = ShiftSeg{l0, f};
+    l0 += f;
+  }
+  return ns;
+}
+
+template <class S, typename T>
+fc2t2_status chain_launch(const fc2t2_plan_s* pl, const ShiftSeg& sg, void* const* grids, bool up, hipStream_t s) {
+  LevelPtrs g{};
+  for (int l = 0; l < pl->levels; ++l) g.p[l] = grids[l];
+  const int lgn = lg2i(pl->nl[sg.l0]);
+  const dim3 grid(1u << ((lgn - sg.f) * S::D), pl->C);
+  const int* begs = (const int*)((const char*)pl->shift + pl->shift_beg_off);
+  const ShiftEntry* tab = (const ShiftEntry*)pl->shift;
+  if (up) {
+    const size_t smem = upchain_lds(pl, sg.f);
+    hipLaunchKernelGGL((upchain_kernel<S, T>), grid, dim3(kShiftThreads), smem, s, g, tab, begs, pl->shift_n_up, sg.l0,
+                       sg.f, lgn);
+  } else {
+    const size_t smem = downchain_lds(pl, sg.f);
+    hipLaunchKernelGGL((downchain_kernel<S, T>), grid, dim3(kShiftThreads), smem, s, g, tab + pl->shift_n_up,
+                       begs + (pl->P + 1), pl->shift_n_down, sg.l0, sg.f, lgn);
+  }
   FC2T2_LAUNCH_CHECK();
   return FC2T2_OK;
 }
 
-fc2t2_status launch_upshift(const fc2t2_plan_s* pl, int lvl_child, const void* in, void* out,
-                            hipStream_t s) {
-  if (pl->io == FC2T2_IO_F64)
-    return pl->dim == 2 ? shift_launch<2, double>(pl, lvl_child, in, out, true, false, s)
-                        : shift_launch<3, double>(pl, lvl_child, in, out, true, false, s);
-  return pl->dim == 2 ? shift_launch<2, float>(pl, lvl_child, in, out, true, false, s)
-                      : shift_launch<3, float>(pl, lvl_child, in, out, true, false, s);
+fc2t2_status shift_pyramid(const fc2t2_plan_s* pl, void* const* grids, bool up, hipStream_t s) {
+  ShiftSeg seg[kMaxLevels];
+  const int ns = shift_segments(pl, seg);
+  for (int i = 0; i < ns; ++i) {
+    const ShiftSeg& sg = seg[up ? i : ns - 1 - i];
+    if ((up ? upchain_lds(pl, sg.f) : downchain_lds(pl, sg.f)) > kShiftLds) return FC2T2_EUNSUPPORTED;
+    fc2t2_status st = FC2T2_EUNSUPPORTED;
+    dispatch_shape(pl->dim, pl->K, [&](auto sh) {
+      using S = decltype(sh);
+      st = pl->io == FC2T2_IO_F64 ? chain_launch<S, double>(pl, sg, grids, up, s)
+                                  : chain_launch<S, float>(pl, sg, grids, up, s);
+    });
+    if (st) return st;
+  }
+  return FC2T2_OK;
 }
 
-fc2t2_status launch_downshift(const fc2t2_plan_s* pl, int lvl_child, const void* in, void* out,
-                              bool accumulate, hipStream_t s) {
-  if (pl->io == FC2T2_IO_F64)
-    return pl->dim == 2 ? shift_launch<2, double>(pl, lvl_child, in, out, false, accumulate, s)
-                        : shift_launch<3, double>(pl, lvl_child, in, out, false, accumulate, s);
-  return pl->dim == 2 ? shift_launch<2, float>(pl, lvl_child, in, out, false, accumulate, s)
-                      : shift_launch<3, float>(pl, lvl_child, in, out, false, accumulate, s);
+}  // namespace
+
+namespace fc2t2 {
+
+// Up-shift pass: grids[l + 1] = up-shift(grids[l]) for l = 0 .. levels-2.
+fc2t2_status upshift_pyramid(const fc2t2_plan_s* pl, void* const* grids, hipStream_t s) {
+  return shift_pyramid(pl, grids, true, s);
+}
+
+// Down-shift pass: grids[l] += down-shift(grids[l + 1]) for l = levels-2 .. 0.
+fc2t2_status downshift_pyramid(const fc2t2_plan_s* pl, void* const* grids, hipStream_t s) {
+  return shift_pyramid(pl, grids, false, s);
 }
 
 fc2t2_status launch_m2l(const fc2t2_plan_s* pl, int lvl, const void* M, void* L, bool accumulate,
@@ -434,24 +582,6 @@ fc2t2_status launch_m2l_all(const fc2t2_plan_s* pl, const void* const* ins, void
   for (int l = 0; l < pl->levels; ++l) {
     const fc2t2_status st = transpose ? launch_m2l_T(pl, l, ins[l], outs[l], false, s)
                                       : launch_m2l(pl, l, ins[l], outs[l], false, s);
-    if (st) return st;
-  }
-  return FC2T2_OK;
-}
-
-// Up-shift pass: grids[l + 1] = up-shift(grids[l]) for l = 0 .. levels-2.
-fc2t2_status upshift_pyramid(const fc2t2_plan_s* pl, void* const* grids, hipStream_t s) {
-  for (int l = 0; l + 1 < pl->levels; ++l) {
-    const fc2t2_status st = launch_upshift(pl, l, grids[l], grids[l + 1], s);
-    if (st) return st;
-  }
-  return FC2T2_OK;
-}
-
-// Down-shift pass: grids[l] += down-shift(grids[l + 1]) for l = levels-2 .. 0.
-fc2t2_status downshift_pyramid(const fc2t2_plan_s* pl, void* const* grids, hipStream_t s) {
-  for (int l = pl->levels - 2; l >= 0; --l) {
-    const fc2t2_status st = launch_downshift(pl, l, grids[l + 1], grids[l], true, s);
     if (st) return st;
   }
   return FC2T2_OK;

@@ -90,6 +90,10 @@ def lib() -> ctypes.CDLL:
     L.fc2t2_level_numel.argtypes = [vp, i32]
     L.fc2t2_ray_root_backward.restype = i32
     L.fc2t2_ray_root_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]
+    L.fc2t2_stage_timing.restype = i32
+    L.fc2t2_stage_timing.argtypes = [vp, ctypes.c_uint32]
+    L.fc2t2_stage_time.restype = i32
+    L.fc2t2_stage_time.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     _lib = L
     return L
 
@@ -108,6 +112,10 @@ def multi_indices(dim: int, K: int):
     buf = (ctypes.c_int * (P * dim))()
     L.fc2t2_multi_indices(dim, K, buf)
     return [tuple(buf[i * dim:(i + 1) * dim]) for i in range(P)]
+
+
+# Pipeline stages that fc2t2_stage_timing can bracket with events (enum fc2t2_stage order).
+STAGES = ("sort", "p2m", "shift_up", "m2l", "shift_down", "l2p", "l2p_T", "m2l_T", "p2m_T", "ray", "ray_T")
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -174,6 +182,20 @@ class Plan:
 
     def level_shape(self, level: int):
         return (self.C, (self.n >> level) ** self.dim, self.P_pad)
+
+    def stage_timing(self, stages=()):
+        """Time the named stages (see STAGES) with events on the launch stream from now on."""
+        mask = 0
+        for name in stages:
+            mask |= 1 << STAGES.index(name)
+        _check(lib().fc2t2_stage_timing(self.handle, mask), "fc2t2_stage_timing")
+
+    def stage_time(self, stage: str):
+        """(milliseconds, calls) recorded for a stage since the last read; clears them."""
+        ms, calls = ctypes.c_double(0.0), ctypes.c_int64(0)
+        _check(lib().fc2t2_stage_time(self.handle, STAGES.index(stage), ctypes.byref(ms), ctypes.byref(calls)),
+               "fc2t2_stage_time")
+        return ms.value, calls.value
 
     def m2l(self, level: int, src: torch.Tensor, out: torch.Tensor, transpose: bool = False,
             accumulate: bool = False):

@@ -84,3 +84,5 @@ def test_null_plan_calls_fail_cleanly(lib):
     assert lib.fc2t2_plan_destroy(None) == 1
     assert lib.fc2t2_expand(None, None, None, 0, None, None, 0, None) == 1
     assert lib.fc2t2_eval(None, None, None, 0, None, None, None, None) == 1
+    assert lib.fc2t2_stage_timing(None, 1) == 1
+    assert lib.fc2t2_stage_time(None, 0, None, None) == 1

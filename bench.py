@@ -197,7 +197,7 @@ def main():
     # ---- dominant kernel: the slowest single-kernel stage with a roofline model; the timed
     # region brackets only that stage's launches
     es = 8 if wl.io == "f64" else 4
-    modelled = [n for n in ("m2l", "m2l_T", "p2m", "l2p", "l2p_T", "p2m_T") if n in stages]
+    modelled = [n for n in ("m2l", "m2l_T", "p2m", "l2p", "l2p_T", "qgrad", "p2m_T") if n in stages]
     dom = max(modelled, key=lambda n: stages[n]["ms_per_step"])
     plan.stage_timing([dom])
     ms, y = run(step, args.steps)

@@ -214,11 +214,12 @@ typedef enum {
   FC2T2_STAGE_M2L,        /* M2L at every level (one launch on the MFMA path) */
   FC2T2_STAGE_SHIFT_DOWN, /* L2L down the pyramid, or M2M^T (a few multi-level launches) */
   FC2T2_STAGE_L2P,        /* evaluation at the queries */
-  FC2T2_STAGE_L2P_T,      /* per-cell reduction of query cotangents, with q_bar */
+  FC2T2_STAGE_L2P_T,      /* per-cell reduction of query cotangents (with q_bar when fused) */
   FC2T2_STAGE_M2L_T,      /* transposed M2L at every level */
   FC2T2_STAGE_P2M_T,      /* per-source gradients w_bar, p_bar */
   FC2T2_STAGE_RAY,        /* ray integral or ray root kernel (forward) */
   FC2T2_STAGE_RAY_T,      /* ray cotangent records and their per-cell reduction (backward) */
+  FC2T2_STAGE_QGRAD,      /* q_bar = gy . grad f(q) as its own pass over the queries */
   FC2T2_STAGE_COUNT
 } fc2t2_stage;
 

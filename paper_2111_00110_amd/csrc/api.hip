@@ -46,6 +46,18 @@ fc2t2_status bin_and_sort(const fc2t2_plan_s* pl, const void* x, int64_t count, 
   return launch_cell_starts(b.keys_sorted, count, pl->G, b.starts, s);
 }
 
+// The next occupancy stamp of a plan (1..255).
+uint8_t next_gen(const fc2t2_plan_s* pl) {
+  pl->occ_gen = (uint8_t)(pl->occ_gen % 255 + 1);
+  return pl->occ_gen;
+}
+
+// Occupancy byte maps of every level (== the call's stamp: the cell's subtree holds a source).
+void carve_occupancy(Carve& c, const fc2t2_plan_s* pl, uint8_t** occ) {
+  for (int l = 0; l < kMaxLevels; ++l) occ[l] = nullptr;
+  for (int l = 0; l < pl->levels; ++l) occ[l] = c.take<uint8_t>((size_t)pl->Gl[l]);
+}
+
 // Pyramid of grids for levels [first, levels): returns per-level pointers.
 void carve_pyramid(Carve& c, const fc2t2_plan_s* pl, int first, void** lv) {
   for (int l = 0; l < kMaxLevels; ++l) lv[l] = nullptr;
@@ -58,6 +70,8 @@ size_t ws_expand(const fc2t2_plan_s* pl, int64_t N) {
   void* lv[kMaxLevels];
   carve_pyramid(c, pl, 0, lv);
   carve_pyramid(c, pl, 1, lv);
+  uint8_t* occ[kMaxLevels];
+  carve_occupancy(c, pl, occ);
   return c.off;
 }
 
@@ -72,6 +86,8 @@ size_t ws_expand_backward(const fc2t2_plan_s* pl) {
   void* lv[kMaxLevels];
   carve_pyramid(c, pl, 1, lv);
   carve_pyramid(c, pl, 0, lv);
+  uint8_t* occ[kMaxLevels];
+  carve_occupancy(c, pl, occ);
   return c.off;
 }
 
@@ -83,17 +99,19 @@ namespace fc2t2 {
 
 // Expansion of the finest moments M0 into the finest locals L0: M2M up the pyramid, M2L at
 // every level (one launch), then L2L down the pyramid accumulating into each finer level.
-fc2t2_status expand_from_moments(const fc2t2_plan_s* pl, void** Mlv, void** Llv, void* L0, hipStream_t s) {
+// occ: occupancy maps with level 0 stamped with gen (the rest are filled on the way up).
+fc2t2_status expand_from_moments(const fc2t2_plan_s* pl, void** Mlv, void** Llv, void* L0, hipStream_t s,
+                                 uint8_t** occ, uint8_t gen) {
   Llv[0] = L0;
   fc2t2_status st;
   {
     StageScope t(pl, FC2T2_STAGE_SHIFT_UP, s);
-    st = upshift_pyramid(pl, Mlv, s);
+    st = upshift_pyramid(pl, Mlv, s, occ, gen);
   }
   if (st) return st;
   {
     StageScope t(pl, FC2T2_STAGE_M2L, s);
-    st = launch_m2l_all(pl, (const void* const*)Mlv, Llv, false, s);
+    st = launch_m2l_all(pl, (const void* const*)Mlv, Llv, false, s, (const uint8_t* const*)occ, gen);
   }
   if (st) return st;
   StageScope t(pl, FC2T2_STAGE_SHIFT_DOWN, s);
@@ -102,17 +120,17 @@ fc2t2_status expand_from_moments(const fc2t2_plan_s* pl, void** Mlv, void** Llv,
 
 // Transpose of expand_from_moments: G_L0 -> G_M0 (L2L^T up, M2L^T at every level, M2M^T down).
 fc2t2_status expand_T_to_moments(const fc2t2_plan_s* pl, const void* GL0, void** GLlv, void** GMlv,
-                                 hipStream_t s) {
+                                 hipStream_t s, uint8_t** occ, uint8_t gen) {
   GLlv[0] = (void*)GL0;
   fc2t2_status st;
   {
     StageScope t(pl, FC2T2_STAGE_SHIFT_UP, s);
-    st = upshift_pyramid(pl, GLlv, s);                       // L2L^T
+    st = upshift_pyramid(pl, GLlv, s, occ, gen);             // L2L^T
   }
   if (st) return st;
   {
     StageScope t(pl, FC2T2_STAGE_M2L_T, s);
-    st = launch_m2l_all(pl, (const void* const*)GLlv, GMlv, true, s);
+    st = launch_m2l_all(pl, (const void* const*)GLlv, GMlv, true, s, (const uint8_t* const*)occ, gen);
   }
   if (st) return st;
   StageScope t(pl, FC2T2_STAGE_SHIFT_DOWN, s);
@@ -147,6 +165,9 @@ fc2t2_status fc2t2_expand(fc2t2_plan plan, const void* p, const void* w, int64_t
   void* Llv[kMaxLevels];
   carve_pyramid(c, plan, 0, Mlv);
   carve_pyramid(c, plan, 1, Llv);
+  uint8_t* occ[kMaxLevels];
+  carve_occupancy(c, plan, occ);
+  const uint8_t gen = next_gen(plan);
   fc2t2_status st;
   const bool carry = sb.pay != nullptr;   // sort the points' data along with the keys
   {
@@ -156,11 +177,11 @@ fc2t2_status fc2t2_expand(fc2t2_plan plan, const void* p, const void* w, int64_t
   if (st) return st;
   {
     StageScope t(plan, FC2T2_STAGE_P2M, stream);
-    st = carry ? launch_reduce_sorted(plan, sb.pay, N, sb.starts, Mlv[0], false, stream)
-               : launch_p2m(plan, p, w, N, sb.starts, sb.perm, Mlv[0], stream);
+    st = carry ? launch_reduce_sorted(plan, sb.pay, N, sb.starts, Mlv[0], false, stream, occ[0], gen)
+               : launch_p2m(plan, p, w, N, sb.starts, sb.perm, Mlv[0], stream, occ[0], gen);
   }
   if (st) return st;
-  return expand_from_moments(plan, Mlv, Llv, L, stream);
+  return expand_from_moments(plan, Mlv, Llv, L, stream, occ, gen);
 }
 
 fc2t2_status fc2t2_eval(fc2t2_plan plan, const void* L, const void* q, int64_t M, void* y, void* grad,
@@ -190,12 +211,16 @@ fc2t2_status fc2t2_eval_backward(fc2t2_plan plan, const void* L, const void* q, 
       st = bin_and_sort(plan, q, M, sb, stream, carry ? gy : nullptr);
     }
     if (st) return st;
-    StageScope t(plan, FC2T2_STAGE_L2P_T, stream);
     if (carry) {   // contiguous sorted queries; q_bar by a gather pass in input order
-      st = launch_reduce_sorted(plan, sb.pay, M, sb.starts, gL, true, stream);
+      {
+        StageScope t(plan, FC2T2_STAGE_L2P_T, stream);
+        st = launch_reduce_sorted(plan, sb.pay, M, sb.starts, gL, true, stream);
+      }
       if (st || !gq) return st;
+      StageScope t(plan, FC2T2_STAGE_QGRAD, stream);
       return launch_l2p_qgrad(plan, L, q, M, gy, gq, stream);
     }
+    StageScope t(plan, FC2T2_STAGE_L2P_T, stream);
     if (gq && plan->C == 1)   // one pass over the sorted queries produces both
       return launch_l2p_T_qgrad(plan, L, q, gy, M, sb.starts, sb.perm, gL, gq, stream);
     st = launch_l2p_T(plan, q, gy, M, sb.starts, sb.perm, gL, stream);
@@ -203,7 +228,7 @@ fc2t2_status fc2t2_eval_backward(fc2t2_plan plan, const void* L, const void* q, 
     if (gq) return launch_l2p_qgrad(plan, L, q, M, gy, gq, stream);
     return FC2T2_OK;
   }
-  StageScope t(plan, FC2T2_STAGE_L2P_T, stream);
+  StageScope t(plan, FC2T2_STAGE_QGRAD, stream);
   if (gq) return launch_l2p_qgrad(plan, L, q, M, gy, gq, stream);
   return FC2T2_OK;
 }
@@ -221,7 +246,16 @@ fc2t2_status fc2t2_expand_backward(fc2t2_plan plan, const void* gL, const void* 
   void* GMlv[kMaxLevels];
   carve_pyramid(c, plan, 1, GLlv);
   carve_pyramid(c, plan, 0, GMlv);
-  fc2t2_status st = expand_T_to_moments(plan, gL, GLlv, GMlv, stream);
+  uint8_t* occ[kMaxLevels];
+  carve_occupancy(c, plan, occ);
+  const uint8_t gen = next_gen(plan);
+  fc2t2_status st;
+  {
+    StageScope t(plan, FC2T2_STAGE_SORT, stream);   // binning of the sources (occupancy only)
+    st = launch_mark_cells(plan, p, N, occ[0], gen, stream);
+  }
+  if (st) return st;
+  st = expand_T_to_moments(plan, gL, GLlv, GMlv, stream, occ, gen);
   if (st) return st;
   StageScope t(plan, FC2T2_STAGE_P2M_T, stream);
   return launch_p2m_T(plan, GMlv[0], p, w, N, gp, gw, stream);

@@ -113,6 +113,7 @@ struct Cfg {
 struct M2LLevel {
   const float* in;
   float* out;
+  const uint8_t* occ;      // occupancy of the level's cells, or null (dense)
   const unsigned short* Bhi;
   const unsigned short* Blo;
   int64_t G_l;
@@ -121,6 +122,8 @@ struct M2LLevel {
 struct M2LBatch {
   M2LLevel lv[kMaxLevels];
   int nlev, Ppad, accumulate;
+  int occ_out;             // 0: skip tiles with an empty source region; 1: with no occupied target
+  int gen;                 // occupied <=> byte == gen
 };
 
 template <class C>
@@ -156,6 +159,47 @@ __global__ void __launch_bounds__(C::THREADS) m2l_mfma_kernel(const M2LBatch bat
   const int rx0 = 2 * tx * C::TPX_ - 2, ry0 = 2 * ty * C::TPY_ - 2, rz0 = D == 3 ? 2 * tz * C::TPZ_ - 2 : 0;
 
   const int tid = threadIdx.x;
+  if (LV.occ) {
+    // sparse sources: a tile whose source region (forward) or whose targets (transpose) hold
+    // no occupied cell contributes nothing the method reads; it writes zeros and stops
+    int any = 0;
+    if (!batch.occ_out) {
+      for (int c = tid; c < CELLS; c += C::THREADS) {
+        const int cz = c % SZ, cy = (c / SZ) % SY, cx = c / (SZ * SY);
+        const int gx = rx0 + cx, gy = ry0 + cy, gz = rz0 + cz;
+        if (gx >= 0 && gx < n_l && gy >= 0 && gy < n_l && (D == 2 || (gz >= 0 && gz < n_l))) {
+          const int64_t cell = D == 3 ? ((int64_t)gx * n_l + gy) * n_l + gz : (int64_t)gx * n_l + gy;
+          any |= LV.occ[cell] == batch.gen;
+        }
+      }
+    } else {
+      constexpr int TX = 2 * C::TPX_, TY = 2 * C::TPY_, TZ = D == 3 ? 2 * C::TPZ_ : 1;
+      for (int c = tid; c < TX * TY * TZ; c += C::THREADS) {
+        const int cz = c % TZ, cy = (c / TZ) % TY, cx = c / (TZ * TY);
+        const int gx = rx0 + 2 + cx, gy = ry0 + 2 + cy, gz = D == 3 ? rz0 + 2 + cz : 0;
+        if (gx < n_l && gy < n_l && (D == 2 || gz < n_l)) {
+          const int64_t cell = D == 3 ? ((int64_t)gx * n_l + gy) * n_l + gz : (int64_t)gx * n_l + gy;
+          any |= LV.occ[cell] == batch.gen;
+        }
+      }
+    }
+    if (!__syncthreads_or(any)) {
+      if (!accumulate) {
+        constexpr int TX = 2 * C::TPX_, TY = 2 * C::TPY_, TZ = D == 3 ? 2 * C::TPZ_ : 1;
+        float* __restrict__ Lz = Lout + (int64_t)ch * G_l * Ppad;
+        for (int i = tid; i < TX * TY * TZ * Ppad; i += C::THREADS) {
+          const int c = i / Ppad, k = i - c * Ppad;
+          const int cz = c % TZ, cy = (c / TZ) % TY, cx = c / (TZ * TY);
+          const int gx = rx0 + 2 + cx, gy = ry0 + 2 + cy, gz = D == 3 ? rz0 + 2 + cz : 0;
+          if (gx < n_l && gy < n_l && (D == 2 || gz < n_l)) {
+            const int64_t cell = D == 3 ? ((int64_t)gx * n_l + gy) * n_l + gz : (int64_t)gx * n_l + gy;
+            Lz[cell * Ppad + k] = 0.f;
+          }
+        }
+      }
+      return;
+    }
+  }
   const int wave = tid >> 6, lane = tid & 63;
   const int px_bit = D == 3 ? (wave >> 2) & 1 : (wave >> 1) & 1;
   const int py_bit = D == 3 ? (wave >> 1) & 1 : wave & 1;
@@ -324,11 +368,13 @@ struct Tile<3, P, PASSES> { using type = CfgX<3, P, 8, 4, 4, PASSES>; };
 template <class C>
 fc2t2_status launch_cfg(const fc2t2_plan_s* pl, int lvl0, int lvl1, const void* const* ins, void* const* outs,
                         bool accumulate, const unsigned short* base, int64_t plane, int64_t per_lvl,
-                        hipStream_t s) {
+                        hipStream_t s, const uint8_t* const* occ, uint8_t gen, bool transpose) {
   M2LBatch b;
   b.nlev = 0;
   b.Ppad = pl->Ppad;
   b.accumulate = accumulate ? 1 : 0;
+  b.occ_out = transpose ? 1 : 0;
+  b.gen = gen;
   int blocks = 0;
   for (int lvl = lvl0; lvl < lvl1; ++lvl) {
     const int n_l = pl->nl[lvl];
@@ -338,6 +384,7 @@ fc2t2_status launch_cfg(const fc2t2_plan_s* pl, int lvl0, int lvl1, const void* 
     M2LLevel& L = b.lv[b.nlev++];
     L.in = (const float*)ins[lvl];
     L.out = (float*)outs[lvl];
+    L.occ = occ ? occ[lvl] : nullptr;
     L.Bhi = base + lvl * per_lvl;
     L.Blo = base + plane + lvl * per_lvl;
     L.G_l = pl->Gl[lvl];
@@ -395,7 +442,8 @@ fc2t2_status m2l_mfma_build_tables(fc2t2_plan_s* pl, hipStream_t s) {
 }
 
 fc2t2_status launch_m2l_mfma(const fc2t2_plan_s* pl, int lvl0, int lvl1, const void* const* ins,
-                             void* const* outs, bool accumulate, bool transpose, hipStream_t s) {
+                             void* const* outs, bool accumulate, bool transpose, hipStream_t s,
+                             const uint8_t* const* occ, uint8_t gen) {
   if (!pl->m2l_bf16) return FC2T2_EUNSUPPORTED;
   const TableGeom g = table_geom(pl);
   const unsigned short* base = (const unsigned short*)pl->m2l_bf16 + (transpose ? g.dir : 0);
@@ -404,13 +452,13 @@ fc2t2_status launch_m2l_mfma(const fc2t2_plan_s* pl, int lvl0, int lvl1, const v
     using S = decltype(shape);
     switch (pl->prec) {
       case FC2T2_M2L_BF16:
-        st = launch_cfg<typename Tile<S::D, S::P, 1>::type>(pl, lvl0, lvl1, ins, outs, accumulate, base, g.plane, g.per_lvl, s);
+        st = launch_cfg<typename Tile<S::D, S::P, 1>::type>(pl, lvl0, lvl1, ins, outs, accumulate, base, g.plane, g.per_lvl, s, occ, gen, transpose);
         break;
       case FC2T2_M2L_BF16X2:
-        st = launch_cfg<typename Tile<S::D, S::P, 2>::type>(pl, lvl0, lvl1, ins, outs, accumulate, base, g.plane, g.per_lvl, s);
+        st = launch_cfg<typename Tile<S::D, S::P, 2>::type>(pl, lvl0, lvl1, ins, outs, accumulate, base, g.plane, g.per_lvl, s, occ, gen, transpose);
         break;
       case FC2T2_M2L_BF16X3:
-        st = launch_cfg<typename Tile<S::D, S::P, 3>::type>(pl, lvl0, lvl1, ins, outs, accumulate, base, g.plane, g.per_lvl, s);
+        st = launch_cfg<typename Tile<S::D, S::P, 3>::type>(pl, lvl0, lvl1, ins, outs, accumulate, base, g.plane, g.per_lvl, s, occ, gen, transpose);
         break;
     }
   });

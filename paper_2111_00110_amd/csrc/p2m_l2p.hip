@@ -108,12 +108,12 @@ struct QueryMonomialsGrad {
 template <typename T>
 fc2t2_status reduce_points(const fc2t2_plan_s* pl, const void* x, const void* wt, int64_t count,
                            const uint32_t* starts, const uint32_t* perm, void* out, bool accumulate,
-                           hipStream_t s) {
+                           hipStream_t s, uint8_t* occ = nullptr, uint8_t gen = 1) {
   fc2t2_status st = FC2T2_EUNSUPPORTED;
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {
     using S = decltype(shape);
     PointMonomials<S, T> fn{(const T*)x, (const T*)wt, pl->C, (T)(1.0 / pl->h0)};
-    st = launch_reduce_cells<S, T>(pl, starts, perm, count, (T*)out, accumulate, fn, s);
+    st = launch_reduce_cells<S, T>(pl, starts, perm, count, (T*)out, accumulate, fn, s, occ, gen);
   });
   return st;
 }
@@ -221,19 +221,66 @@ fc2t2_status gather_eval(const fc2t2_plan_s* pl, const void* grid, const void* x
 namespace fc2t2 {
 
 fc2t2_status launch_p2m(const fc2t2_plan_s* pl, const void* p, const void* w, int64_t N,
-                        const uint32_t* starts, const uint32_t* perm, void* M0, hipStream_t s) {
-  return pl->io == FC2T2_IO_F64 ? reduce_points<double>(pl, p, w, N, starts, perm, M0, false, s)
-                                : reduce_points<float>(pl, p, w, N, starts, perm, M0, false, s);
+                        const uint32_t* starts, const uint32_t* perm, void* M0, hipStream_t s, uint8_t* occ,
+                        uint8_t gen) {
+  return pl->io == FC2T2_IO_F64 ? reduce_points<double>(pl, p, w, N, starts, perm, M0, false, s, occ, gen)
+                                : reduce_points<float>(pl, p, w, N, starts, perm, M0, false, s, occ, gen);
+}
+
+// Occupancy of the finest cells from points: occ[cell(x)] = gen.
+template <typename T, int D>
+__global__ void __launch_bounds__(256) mark_cells_kernel(const T* __restrict__ x, int64_t N, T lo, T scale, int n,
+                                                         uint8_t* __restrict__ occ, uint8_t gen) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int64_t cell = 0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) cell = cell * n + cell_coord<T>(x[i * D + j], lo, scale, n);
+  occ[cell] = gen;
+}
+
+__global__ void __launch_bounds__(256) clear_bytes_kernel(uint8_t* __restrict__ p, int64_t n) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16;
+  if (i + 16 <= n) {
+    *reinterpret_cast<uint4*>(p + i) = uint4{0u, 0u, 0u, 0u};
+  } else {
+    for (int64_t j = i; j < n; ++j) p[j] = 0;
+  }
+}
+
+fc2t2_status launch_mark_cells(const fc2t2_plan_s* pl, const void* x, int64_t N, uint8_t* occ, uint8_t gen,
+                               hipStream_t s) {
+  // cleared first: workspace bytes left by earlier calls would match the stamp now and then
+  // and disable skips
+  hipLaunchKernelGGL(clear_bytes_kernel, dim3((unsigned)ceil_div(ceil_div(pl->G, 16), 256)), dim3(256), 0, s, occ,
+                     pl->G);
+  FC2T2_LAUNCH_CHECK();
+  if (N == 0) return FC2T2_OK;
+  const dim3 grid((unsigned)ceil_div(N, 256));
+  const double scale = pl->n / (pl->hi - pl->lo);
+  if (pl->io == FC2T2_IO_F64) {
+    if (pl->dim == 2)
+      hipLaunchKernelGGL((mark_cells_kernel<double, 2>), grid, dim3(256), 0, s, (const double*)x, N, pl->lo, scale, pl->n, occ, gen);
+    else
+      hipLaunchKernelGGL((mark_cells_kernel<double, 3>), grid, dim3(256), 0, s, (const double*)x, N, pl->lo, scale, pl->n, occ, gen);
+  } else {
+    if (pl->dim == 2)
+      hipLaunchKernelGGL((mark_cells_kernel<float, 2>), grid, dim3(256), 0, s, (const float*)x, N, (float)pl->lo, (float)scale, pl->n, occ, gen);
+    else
+      hipLaunchKernelGGL((mark_cells_kernel<float, 3>), grid, dim3(256), 0, s, (const float*)x, N, (float)pl->lo, (float)scale, pl->n, occ, gen);
+  }
+  FC2T2_LAUNCH_CHECK();
+  return FC2T2_OK;
 }
 
 fc2t2_status launch_reduce_sorted(const fc2t2_plan_s* pl, const void* pay, int64_t count, const uint32_t* starts,
-                                  void* out, bool accumulate, hipStream_t s) {
+                                  void* out, bool accumulate, hipStream_t s, uint8_t* occ, uint8_t gen) {
   if (pl->io != FC2T2_IO_F32 || pl->C != 1) return FC2T2_EUNSUPPORTED;
   fc2t2_status st = FC2T2_EUNSUPPORTED;
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {
     using S = decltype(shape);
     SortedMonomials<S, float> fn{(const float*)pay, (float)(1.0 / pl->h0)};
-    st = launch_reduce_cells<S, float>(pl, starts, nullptr, count, (float*)out, accumulate, fn, s);
+    st = launch_reduce_cells<S, float>(pl, starts, nullptr, count, (float*)out, accumulate, fn, s, occ, gen);
   });
   return st;
 }

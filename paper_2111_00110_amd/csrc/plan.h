@@ -28,6 +28,10 @@ struct fc2t2_plan_s {
   // Stage timing (measurement aid): bit s of timed_mask brackets stage s with events.
   uint32_t timed_mask = 0;
   fc2t2::StageTimer* timer = nullptr;
+  // Occupancy stamp of the current call (1..255): a cell is occupied iff its byte equals it.
+  // Every map is written in full each call; a stale byte that matched would only disable a
+  // skip, never cause a wrong one.
+  mutable uint8_t occ_gen = 0;
 };
 
 namespace fc2t2 {
@@ -85,14 +89,20 @@ int key_bits_for(int64_t G);
 // ---- p2m_l2p.hip
 // P2M: M0 = moments of the sorted sources (overwrite).
 fc2t2_status launch_p2m(const fc2t2_plan_s* pl, const void* p, const void* w, int64_t N,
-                        const uint32_t* starts, const uint32_t* perm, void* M0, hipStream_t s);
+                        const uint32_t* starts, const uint32_t* perm, void* M0, hipStream_t s,
+                        uint8_t* occ = nullptr, uint8_t gen = 1);
 // Transpose of L2P: gL += sum over the sorted queries of gy (q - c)^k / k!.
 fc2t2_status launch_l2p_T(const fc2t2_plan_s* pl, const void* q, const void* gy, int64_t M,
                           const uint32_t* starts, const uint32_t* perm, void* gL, hipStream_t s);
 // P2M, or the transpose of L2P, from records sorted with their data (pay [count][dim + 1]:
 // coordinates and weight or cotangent; FP32, one channel).
 fc2t2_status launch_reduce_sorted(const fc2t2_plan_s* pl, const void* pay, int64_t count, const uint32_t* starts,
-                                  void* out, bool accumulate, hipStream_t s);
+                                  void* out, bool accumulate, hipStream_t s, uint8_t* occ = nullptr,
+                                  uint8_t gen = 1);
+// Finest-level occupancy from points: occ cleared, then occ[cell] = gen at every cell holding
+// a point.
+fc2t2_status launch_mark_cells(const fc2t2_plan_s* pl, const void* x, int64_t N, uint8_t* occ, uint8_t gen,
+                               hipStream_t s);
 // Transpose of L2P fused with gq += gy grad f(q) (one channel only).
 fc2t2_status launch_l2p_T_qgrad(const fc2t2_plan_s* pl, const void* L, const void* q, const void* gy, int64_t M,
                                 const uint32_t* starts, const uint32_t* perm, void* gL, void* gq, hipStream_t s);
@@ -112,7 +122,10 @@ fc2t2_status build_shift_tables(fc2t2_plan_s* pl, hipStream_t s);
 // Whole pyramid passes: grids[l+1] = up-shift(grids[l]) for every level (M2M, and the
 // transpose of L2L), and grids[l] += down-shift(grids[l+1]) from the coarsest to the finest
 // (L2L, and the transpose of M2M); several levels per launch.
-fc2t2_status upshift_pyramid(const fc2t2_plan_s* pl, void* const* grids, hipStream_t s);
+// With occ (per-level byte maps, occ[0] filled), the up pass also sets occ[l+1][I] = gen when
+// any child's occ[l] == gen, else 0.
+fc2t2_status upshift_pyramid(const fc2t2_plan_s* pl, void* const* grids, hipStream_t s,
+                             uint8_t* const* occ = nullptr, uint8_t gen = 1);
 fc2t2_status downshift_pyramid(const fc2t2_plan_s* pl, void* const* grids, hipStream_t s);
 // M2L at one level: L (+)= sum_o T(o) M[i + o] over the admissible offsets.
 fc2t2_status launch_m2l(const fc2t2_plan_s* pl, int lvl, const void* M, void* L, bool accumulate,
@@ -121,8 +134,13 @@ fc2t2_status launch_m2l(const fc2t2_plan_s* pl, int lvl, const void* M, void* L,
 fc2t2_status launch_m2l_T(const fc2t2_plan_s* pl, int lvl, const void* GL, void* GM,
                           bool accumulate, hipStream_t s);
 // M2L (or its transpose) at every level, outputs overwritten; ins/outs indexed by level.
+// Optional occupancy maps (occ[l] per level, == gen: the cell or its subtree holds a source):
+// the forward skips (writes zeros for) target tiles whose whole source window is empty; the
+// transpose does so for tiles none of whose outputs is occupied.  Results at every cell the
+// method reads are unchanged.
 fc2t2_status launch_m2l_all(const fc2t2_plan_s* pl, const void* const* ins, void* const* outs,
-                            bool transpose, hipStream_t s);
+                            bool transpose, hipStream_t s, const uint8_t* const* occ = nullptr,
+                            uint8_t gen = 1);
 
 // ---- m2l_mfma.hip
 bool m2l_mfma_supported(const fc2t2_plan_s* pl);
@@ -130,7 +148,8 @@ size_t m2l_mfma_table_bytes(const fc2t2_plan_s* pl);
 fc2t2_status m2l_mfma_build_tables(fc2t2_plan_s* pl, hipStream_t s);
 // Levels [lvl0, lvl1) in one launch; ins/outs are indexed by level.
 fc2t2_status launch_m2l_mfma(const fc2t2_plan_s* pl, int lvl0, int lvl1, const void* const* ins,
-                             void* const* outs, bool accumulate, bool transpose, hipStream_t s);
+                             void* const* outs, bool accumulate, bool transpose, hipStream_t s,
+                             const uint8_t* const* occ = nullptr, uint8_t gen = 1);
 
 // ---- rays.hip
 size_t ray_integral_bwd_ws(const fc2t2_plan_s* pl, int64_t R);

@@ -21,12 +21,14 @@ __device__ __forceinline__ void decode_cell(int64_t cell, int n, int (&ic)[3]) {
 
 // out[ch][cell][:] (+)= sum over the cell's sorted records of fn(record); the record is the
 // input index perm[r] of sorted position r, or r itself when perm is null (records whose
-// data was sorted along with the keys).
+// data was sorted along with the keys).  occ (optional) receives gen for cells with records
+// and 0 for the others.
 template <class S, typename T, int GROUP, class F>
 __global__ void __launch_bounds__(256) reduce_cells_kernel(const uint32_t* __restrict__ starts,
                                                            const uint32_t* __restrict__ perm,
                                                            int64_t G, int n, T lo, T h,
-                                                           T* __restrict__ out, int accumulate, F fn) {
+                                                           T* __restrict__ out, int accumulate, F fn,
+                                                           uint8_t* __restrict__ occ, uint8_t gen) {
   constexpr int P = S::P, Ppad = S::Ppad, D = S::D;
   const int lane_g = threadIdx.x & (GROUP - 1);
   const int ch = blockIdx.y;
@@ -34,6 +36,7 @@ __global__ void __launch_bounds__(256) reduce_cells_kernel(const uint32_t* __res
   T* __restrict__ base = out + (int64_t)ch * G * Ppad;
   for (int64_t cell = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GROUP; cell < G; cell += groups) {
     const uint32_t b = starts[cell], e = starts[cell + 1];
+    if (occ && lane_g == 0 && ch == 0) occ[cell] = e > b ? gen : 0;
     int ic[3];
     decode_cell<D, T>(cell, n, ic);
     T centre[3];
@@ -76,23 +79,25 @@ inline int reduce_group_for(int64_t records, int64_t cells) {
 
 template <class S, typename T, int GROUP, class F>
 fc2t2_status launch_reduce_cells_g(const fc2t2_plan_s* pl, const uint32_t* starts, const uint32_t* perm,
-                                   T* out, bool accumulate, const F& fn, hipStream_t s) {
+                                   T* out, bool accumulate, const F& fn, hipStream_t s, uint8_t* occ,
+                                   uint8_t gen) {
   const int threads = 256;
   const int64_t need = ceil_div(pl->G * GROUP, threads);
   const int64_t blocks = need < 16384 ? need : 16384;
   hipLaunchKernelGGL((reduce_cells_kernel<S, T, GROUP, F>), dim3((unsigned)blocks, pl->C), dim3(threads), 0, s,
-                     starts, perm, pl->G, pl->n, (T)pl->lo, (T)pl->h0, out, accumulate ? 1 : 0, fn);
+                     starts, perm, pl->G, pl->n, (T)pl->lo, (T)pl->h0, out, accumulate ? 1 : 0, fn, occ, gen);
   FC2T2_LAUNCH_CHECK();
   return FC2T2_OK;
 }
 
 template <class S, typename T, class F>
 fc2t2_status launch_reduce_cells(const fc2t2_plan_s* pl, const uint32_t* starts, const uint32_t* perm,
-                                 int64_t records, T* out, bool accumulate, const F& fn, hipStream_t s) {
+                                 int64_t records, T* out, bool accumulate, const F& fn, hipStream_t s,
+                                 uint8_t* occ = nullptr, uint8_t gen = 1) {
   switch (reduce_group_for(records, pl->G)) {
-    case 4: return launch_reduce_cells_g<S, T, 4>(pl, starts, perm, out, accumulate, fn, s);
-    case 16: return launch_reduce_cells_g<S, T, 16>(pl, starts, perm, out, accumulate, fn, s);
-    default: return launch_reduce_cells_g<S, T, 64>(pl, starts, perm, out, accumulate, fn, s);
+    case 4: return launch_reduce_cells_g<S, T, 4>(pl, starts, perm, out, accumulate, fn, s, occ, gen);
+    case 16: return launch_reduce_cells_g<S, T, 16>(pl, starts, perm, out, accumulate, fn, s, occ, gen);
+    default: return launch_reduce_cells_g<S, T, 64>(pl, starts, perm, out, accumulate, fn, s, occ, gen);
   }
 }
 

@@ -61,6 +61,9 @@ struct ShiftEntry {
 
 struct LevelPtrs {
   void* p[kMaxLevels];
+  uint8_t* occ[kMaxLevels];   // per-level occupancy (up chain only; null entries: not tracked)
+  int has_occ;
+  int gen;                     // occupied <=> byte == gen
 };
 
 constexpr int kShiftThreads = 256;
@@ -120,6 +123,8 @@ __global__ void __launch_bounds__(kShiftThreads) upchain_kernel(LevelPtrs grids,
   int* s_beg = s_off + n_entries;
   T* hbuf = reinterpret_cast<T*>(smem + align16((size_t)n_entries * (sizeof(T) + sizeof(int)) + (P + 1) * sizeof(int)));
   T* obuf = hbuf + ((size_t)PP << (f * D));
+  uint8_t* s_occ = reinterpret_cast<uint8_t*>(obuf + ((size_t)PP << ((f - 1) * D)));   // 2 x 2^((f-1)D) bytes
+  const uint32_t occ_half = 1u << ((f - 1) * D);
   const int tid = threadIdx.x, ch = blockIdx.y;
   for (int i = tid; i < n_entries; i += kShiftThreads) {
     const ShiftEntry e = tab[i];
@@ -157,6 +162,31 @@ __global__ void __launch_bounds__(kShiftThreads) upchain_kernel(LevelPtrs grids,
       hadamard<D>(x);
 #pragma unroll
       for (int pi = 0; pi < NB; ++pi) hbuf[((size_t)p * NB + pi) * PP + m] = x[pi];
+    }
+    if (grids.has_occ && ch == 0) {
+      // occupancy of the parents: OR over their children
+      const uint8_t* prev = s_occ + ((j + 1) & 1) * occ_half;
+      uint8_t* cur = s_occ + (j & 1) * occ_half;
+      for (uint32_t p = tid; p < npar; p += kShiftThreads) {
+        uint32_t pc[3], cc[3], gc[3];
+        tile_coords<D>(p, lgp, pc);
+        uint8_t o = 0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          child_coords<D>(pc, b, cc);
+          if (j == 1) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) gc[d] = (tc[d] << (lgp + 1)) + cc[d];
+            o |= grids.occ[l0][tile_lin<D>(gc, lgn_c)] == grids.gen ? 1 : 0;
+          } else {
+            o |= prev[tile_lin<D>(cc, lgp + 1)];
+          }
+        }
+        cur[p] = o;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) gc[d] = (tc[d] << lgp) + pc[d];
+        grids.occ[l0 + j][tile_lin<D>(gc, lgn_p)] = o ? (uint8_t)grids.gen : (uint8_t)0;
+      }
     }
     __syncthreads();
     T* out = (T*)grids.p[l0 + j] + ((size_t)ch << (lgn_p * D)) * PP;
@@ -434,7 +464,7 @@ size_t upchain_lds(const fc2t2_plan_s* pl, int f) {
   const int D = pl->dim;
   const size_t es = io_size(pl);
   return align16((size_t)pl->shift_n_up * (es + sizeof(int)) + (pl->P + 1) * sizeof(int)) +
-         (((size_t)pl->Ppad << (f * D)) + ((size_t)pl->Ppad << ((f - 1) * D))) * es;
+         (((size_t)pl->Ppad << (f * D)) + ((size_t)pl->Ppad << ((f - 1) * D))) * es + (size_t(2) << ((f - 1) * D));
 }
 size_t downchain_lds(const fc2t2_plan_s* pl, int f) {
   const int D = pl->dim;
@@ -471,9 +501,15 @@ int shift_segments(const fc2t2_plan_s* pl, ShiftSeg* seg) {
 }
 
 template <class S, typename T>
-fc2t2_status chain_launch(const fc2t2_plan_s* pl, const ShiftSeg& sg, void* const* grids, bool up, hipStream_t s) {
+fc2t2_status chain_launch(const fc2t2_plan_s* pl, const ShiftSeg& sg, void* const* grids, bool up, hipStream_t s,
+                          uint8_t* const* occ, uint8_t gen) {
   LevelPtrs g{};
-  for (int l = 0; l < pl->levels; ++l) g.p[l] = grids[l];
+  for (int l = 0; l < pl->levels; ++l) {
+    g.p[l] = grids[l];
+    g.occ[l] = occ ? occ[l] : nullptr;
+  }
+  g.has_occ = (up && occ) ? 1 : 0;
+  g.gen = gen;
   const int lgn = lg2i(pl->nl[sg.l0]);
   const dim3 grid(1u << ((lgn - sg.f) * S::D), pl->C);
   const int* begs = (const int*)((const char*)pl->shift + pl->shift_beg_off);
@@ -491,7 +527,8 @@ fc2t2_status chain_launch(const fc2t2_plan_s* pl, const ShiftSeg& sg, void* cons
   return FC2T2_OK;
 }
 
-fc2t2_status shift_pyramid(const fc2t2_plan_s* pl, void* const* grids, bool up, hipStream_t s) {
+fc2t2_status shift_pyramid(const fc2t2_plan_s* pl, void* const* grids, bool up, hipStream_t s,
+                           uint8_t* const* occ, uint8_t gen) {
   ShiftSeg seg[kMaxLevels];
   const int ns = shift_segments(pl, seg);
   for (int i = 0; i < ns; ++i) {
@@ -500,8 +537,8 @@ fc2t2_status shift_pyramid(const fc2t2_plan_s* pl, void* const* grids, bool up, 
     fc2t2_status st = FC2T2_EUNSUPPORTED;
     dispatch_shape(pl->dim, pl->K, [&](auto sh) {
       using S = decltype(sh);
-      st = pl->io == FC2T2_IO_F64 ? chain_launch<S, double>(pl, sg, grids, up, s)
-                                  : chain_launch<S, float>(pl, sg, grids, up, s);
+      st = pl->io == FC2T2_IO_F64 ? chain_launch<S, double>(pl, sg, grids, up, s, occ, gen)
+                                  : chain_launch<S, float>(pl, sg, grids, up, s, occ, gen);
     });
     if (st) return st;
   }
@@ -513,13 +550,14 @@ fc2t2_status shift_pyramid(const fc2t2_plan_s* pl, void* const* grids, bool up, 
 namespace fc2t2 {
 
 // Up-shift pass: grids[l + 1] = up-shift(grids[l]) for l = 0 .. levels-2.
-fc2t2_status upshift_pyramid(const fc2t2_plan_s* pl, void* const* grids, hipStream_t s) {
-  return shift_pyramid(pl, grids, true, s);
+fc2t2_status upshift_pyramid(const fc2t2_plan_s* pl, void* const* grids, hipStream_t s, uint8_t* const* occ,
+                             uint8_t gen) {
+  return shift_pyramid(pl, grids, true, s, occ, gen);
 }
 
 // Down-shift pass: grids[l] += down-shift(grids[l + 1]) for l = levels-2 .. 0.
 fc2t2_status downshift_pyramid(const fc2t2_plan_s* pl, void* const* grids, hipStream_t s) {
-  return shift_pyramid(pl, grids, false, s);
+  return shift_pyramid(pl, grids, false, s, nullptr, 0);
 }
 
 fc2t2_status launch_m2l(const fc2t2_plan_s* pl, int lvl, const void* M, void* L, bool accumulate,
@@ -577,8 +615,9 @@ fc2t2_status launch_m2l_T(const fc2t2_plan_s* pl, int lvl, const void* GL, void*
 }
 
 fc2t2_status launch_m2l_all(const fc2t2_plan_s* pl, const void* const* ins, void* const* outs, bool transpose,
-                            hipStream_t s) {
-  if (pl->prec >= FC2T2_M2L_BF16) return launch_m2l_mfma(pl, 0, pl->levels, ins, outs, false, transpose, s);
+                            hipStream_t s, const uint8_t* const* occ, uint8_t gen) {
+  if (pl->prec >= FC2T2_M2L_BF16)
+    return launch_m2l_mfma(pl, 0, pl->levels, ins, outs, false, transpose, s, occ, gen);
   for (int l = 0; l < pl->levels; ++l) {
     const fc2t2_status st = transpose ? launch_m2l_T(pl, l, ins[l], outs[l], false, s)
                                       : launch_m2l(pl, l, ins[l], outs[l], false, s);

@@ -115,7 +115,8 @@ def multi_indices(dim: int, K: int):
 
 
 # Pipeline stages that fc2t2_stage_timing can bracket with events (enum fc2t2_stage order).
-STAGES = ("sort", "p2m", "shift_up", "m2l", "shift_down", "l2p", "l2p_T", "m2l_T", "p2m_T", "ray", "ray_T")
+STAGES = ("sort", "p2m", "shift_up", "m2l", "shift_down", "l2p", "l2p_T", "m2l_T", "p2m_T", "ray", "ray_T",
+          "qgrad")
 
 
 def _ptr(t: Optional[torch.Tensor]):

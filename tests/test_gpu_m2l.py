@@ -88,3 +88,42 @@ def test_explicit_layer_mfma_vs_checker(F, prec, tol, tolg, case):
     assert rel(got[1], ref[1]) < tol
     assert rel(got[2], ref[2]) < tolg
     assert rel(got[3], ref[3]) < tolg
+
+
+@pytest.mark.parametrize("dim,n,K", [(2, 128, 6), (3, 32, 4)])
+def test_clustered_sources_skip_empty_tiles(F, dim, n, K):
+    """Sources in two small clusters leave most M2L tiles with an empty source region (the
+    forward skips them) and most output tiles of the transpose unoccupied (skipped too): the
+    BF16x3 layer must still match the checker, and the plain FP32 contraction (no skipping)."""
+    rng = np.random.default_rng(11 + dim)
+    lo, hi = (0.0, 1.0) if dim == 2 else (-1.0, 1.0)
+    span = hi - lo
+    N, M = 6000, 4000
+    centres = np.array([[lo + 0.2 * span] * dim, [lo + 0.73 * span] * dim])
+    p = centres[rng.integers(0, 2, N)] + rng.normal(0.0, 0.03 * span, (N, dim))
+    p = np.clip(p, lo + 1e-6, hi - 1e-6)
+    q = rng.uniform(lo, hi, (M, dim))
+    w = rng.standard_normal((N, 1))
+    gy = rng.standard_normal((M, 1))
+    param = 0.01 if dim == 2 else 0.05
+    wl = W.Workload("clustered", dim, n, lo, hi, K, "gaussian", param, N, M, 0, "f32", "explicit", "uniform")
+    x = {k: v.astype(np.float32) for k, v in dict(p=p, q=q, w=w, gy=gy).items()}
+    ref = fmm.explicit_forward_backward(oracle_geometry(wl), oracle_kernel(wl), x["p"], x["w"], x["q"], x["gy"])
+    d = {k: torch.from_numpy(v).cuda() for k, v in x.items()}
+    outs = {}
+    for prec in ("bf16x3", "f32"):
+        plan = F.Plan(dim, n, lo, hi, "gaussian", param, K, m2l=prec, io="f32")
+        Lt = plan.expand(d["p"], d["w"])
+        y, _, _ = plan.eval(Lt, d["q"])
+        gL = plan.new_local()
+        gq = torch.zeros_like(d["q"])
+        plan.eval_backward(Lt, d["q"], d["gy"], gL, gq)
+        gp = torch.zeros_like(d["p"])
+        gw = torch.zeros_like(d["w"])
+        plan.expand_backward(gL, d["p"], d["w"], gp, gw)
+        outs[prec] = [t.cpu().numpy() for t in (y, gw, gp, gq)]
+    got, dense = outs["bf16x3"], outs["f32"]
+    for i, name in enumerate(("y", "w_bar", "p_bar", "q_bar")):
+        tol = 3e-5 if i < 2 else 5e-5
+        assert rel(got[i], ref[i]) < tol, name
+        assert rel(got[i], dense[i]) < tol, name

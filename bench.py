@@ -214,27 +214,37 @@ def main():
         f32_ms, _ = run(step32, max(3, args.steps // 4))
 
     passes = {"f32": 1, "bf16": 1, "bf16x2": 2, "bf16x3": 3}[args.m2l]
-    flops_all = accounting.m2l_flops(wl.dim, wl.n, wl.K)
+    flops_dense = accounting.m2l_flops(wl.dim, wl.n, wl.K)
     mfma = args.m2l != "f32"
     m2l_peak = PEAKS["bf16_mfma_TFLOPs"] if mfma else PEAKS["fp32_vector_TFLOPs"]
+    # the MFMA path skips tiles with nothing to contribute: count the useful flops of the
+    # tiles that run (source occupancy from the same FP32 cell index as the kernels)
+    if mfma:
+        occ = accounting.occupancy_pyramid(x["p"], wl.lo, wl.hi, wl.n, wl.dim)
+        flops_run = {"m2l": accounting.m2l_flops_executed(wl.dim, wl.K, occ, False),
+                     "m2l_T": accounting.m2l_flops_executed(wl.dim, wl.K, occ, True)}
+    else:
+        flops_run = {"m2l": flops_dense, "m2l_T": flops_dense}
 
     def m2l_line(name):
         if name not in stages:
             return None
         kt = stages[name]["ms_per_call"]
-        ach = flops_all / (kt * 1e-3) / 1e12
+        ach = flops_run[name] / (kt * 1e-3) / 1e12
         return {"kernel_us": round(kt * 1e3, 2), "achieved_TFLOPs": round(ach, 3), "peak_TFLOPs": m2l_peak,
                 "frac": round(ach / m2l_peak, 4),
                 "mfma_issue_frac": round(ach * passes * accounting.mfma_padding(wl.dim, wl.K) / m2l_peak, 4)
-                if mfma else None}
+                if mfma else None,
+                "flops_run": flops_run[name], "flops_dense": flops_dense,
+                "dense_equivalent_TFLOPs": round(flops_dense / (kt * 1e-3) / 1e12, 3)}
 
     if dom in ("m2l", "m2l_T"):
-        achieved = flops_all / (kernel_ms * 1e-3) / 1e12
+        achieved = flops_run[dom] / (kernel_ms * 1e-3) / 1e12
         roofline = {"bound": "mfma" if mfma else "alu", "achieved": round(achieved, 3), "peak": m2l_peak,
                     "unit": "TFLOP/s", "frac": round(achieved / m2l_peak, 4), "traffic": None,
                     "kernel": "%s, all levels in one launch, %s" % (dom, args.m2l),
                     "kernel_us": round(kernel_ms * 1e3, 2), "launches": dom_calls,
-                    "flops_per_launch": flops_all, "mfma_passes": passes}
+                    "flops_per_launch": flops_run[dom], "flops_dense": flops_dense, "mfma_passes": passes}
     else:
         nbytes = accounting.stage_bytes(dom, wl.dim, wl.n, wl.K, N=wl.N, M=wl.M, itemsize=es)
         achieved = nbytes / (kernel_ms * 1e-3) / 1e9

@@ -97,3 +97,75 @@ def stage_bytes(stage: str, dim: int, n: int, K: int, N: int = 0, M: int = 0, it
     if stage == "p2m_T":
         return N * 2 * (d + 1) * es + G * R
     raise ValueError(stage)
+
+
+# ---- M2L work that actually runs when tiles with nothing to contribute are skipped
+
+# Target tile of one MFMA M2L workgroup (cells per dimension).
+M2L_TILE = {2: (16, 8), 3: (16, 8, 8)}
+
+
+def _window_counts_1d(n: int):
+    """Per cell i: offsets of its parity window inside the grid, and hole offsets inside."""
+    import numpy as np
+    i = np.arange(n)
+    lo = np.where(i % 2 == 0, -2, -3)
+    hi = lo + 5
+    w = np.minimum(i + hi, n - 1) - np.maximum(i + lo, 0) + 1
+    h = np.minimum(i + 1, n - 1) - np.maximum(i - 1, 0) + 1
+    return w, h
+
+
+def occupancy_pyramid(x, lo: float, hi: float, n: int, dim: int):
+    """Occupancy of every level: finest cells by the kernels' FP32 index formula, then any()
+    over the 2^d children."""
+    import numpy as np
+    xs = np.asarray(x, dtype=np.float32)
+    scale = np.float32(n / (hi - lo))
+    u = (xs - np.float32(lo)) * scale
+    idx = np.clip(np.floor(u).astype(np.int64), 0, n - 1)
+    occ = np.zeros((n,) * dim, dtype=bool)
+    occ[tuple(idx[:, j] for j in range(dim))] = True
+    levels = [occ]
+    while levels[-1].shape[0] > 4:
+        o = levels[-1]
+        m = o.shape[0] // 2
+        o = o.reshape(sum(((m, 2) for _ in range(dim)), ()))
+        levels.append(o.any(axis=tuple(range(1, 2 * dim, 2))))
+    return levels
+
+
+def m2l_flops_executed(dim: int, K: int, occ_levels, transpose: bool, channels: int = 1) -> int:
+    """Useful flops (2 per term, unpadded P) of the M2L tiles that run: the forward skips a tile
+    whose source region (targets +- 2..3 cells) holds no occupied cell, the transpose one none
+    of whose outputs is occupied."""
+    import numpy as np
+    P = n_terms(dim, K)
+    tile = M2L_TILE[dim]
+    total = 0
+    for lvl, occ in enumerate(occ_levels):
+        n_l = occ.shape[0]
+        w, h = _window_counts_1d(n_l)
+        pairs = np.ones((n_l,) * dim, dtype=np.int64)
+        holes = np.ones((n_l,) * dim, dtype=np.int64)
+        for d in range(dim):
+            shape = [1] * dim
+            shape[d] = n_l
+            pairs = pairs * w.reshape(shape)
+            holes = holes * h.reshape(shape)
+        if lvl > 0:
+            pairs = pairs - holes
+        run = np.zeros((n_l,) * dim, dtype=bool)
+        ntiles = [(n_l + t - 1) // t for t in tile]
+        for t_idx in np.ndindex(*ntiles):
+            tgt = tuple(slice(t_idx[d] * tile[d], min((t_idx[d] + 1) * tile[d], n_l)) for d in range(dim))
+            if transpose:
+                live = occ[tgt].any()
+            else:
+                src = tuple(slice(max(t_idx[d] * tile[d] - 2, 0), min((t_idx[d] + 1) * tile[d] + 2, n_l))
+                            for d in range(dim))
+                live = occ[src].any()
+            if live:
+                run[tgt] = True
+        total += int(pairs[run].sum())
+    return 2 * P * P * channels * total

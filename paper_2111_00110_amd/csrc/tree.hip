@@ -214,10 +214,14 @@ __global__ void __launch_bounds__(kShiftThreads) upchain_kernel(LevelPtrs grids,
 // The block first loads the top cell and the tile's rows of every level below it (what the
 // finer levels already hold) into LDS in one pass, so the level steps touch no global memory
 // until the final write.
+//
+// Levels above l0+f (up to l_top, the coarsest) are not taken from a previous launch: each
+// block first walks its own ancestor chain down from l_top, one cell per level, so the whole
+// down pass is one launch.
 template <class S, typename T>
 __global__ void __launch_bounds__(kShiftThreads) downchain_kernel(LevelPtrs grids, const ShiftEntry* __restrict__ tab,
                                                                   const int* __restrict__ beg, int n_entries, int l0,
-                                                                  int f, int lg0) {
+                                                                  int f, int lg0, int l_top) {
   constexpr int D = S::D, P = S::P, PP = S::Ppad, NB = 1 << D;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   T* s_coef = reinterpret_cast<T*>(smem);
@@ -237,9 +241,45 @@ __global__ void __launch_bounds__(kShiftThreads) downchain_kernel(LevelPtrs grid
   uint32_t tc[3];
   tile_coords<D>(blockIdx.x, lg0 - f, tc);
   {
-    const int lgn = lg0 - f;
-    const T* top = (const T*)grids.p[l0 + f] + (((size_t)ch << (lgn * D)) + blockIdx.x) * PP;
+    // the tile's top cell at level l0 + f, or its ancestor at l_top to walk down from
+    const int la = l_top > l0 + f ? l_top : l0 + f;
+    const int lgn = lg0 - la;
+    uint32_t ac[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ac[d] = tc[d] >> (la - l0 - f);
+    const T* top = (const T*)grids.p[la] + (((size_t)ch << (lgn * D)) + tile_lin<D>(ac, lgn)) * PP;
     for (int i = tid; i < PP; i += kShiftThreads) buf0[i] = top[i];
+  }
+  // ancestor walk: buf0 holds the final row of the ancestor at level l+1; make level l's
+  for (int l = l_top - 1; l >= l0 + f; --l) {
+    __syncthreads();
+    const int lgn = lg0 - l;
+    uint32_t ac[3];
+    int b = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ac[d] = tc[d] >> (l - l0 - f);
+#pragma unroll
+    for (int d = 0; d < D; ++d) b = (b << 1) | (int)(ac[d] & 1u);
+    const T* own_row = (const T*)grids.p[l] + (((size_t)ch << (lgn * D)) + tile_lin<D>(ac, lgn)) * PP;
+    T v = T(0);
+    const int k = tid;
+    if (k < P) {
+      T g[NB];
+#pragma unroll
+      for (int pi = 0; pi < NB; ++pi) {
+        T a = T(0);
+        for (int e = s_beg[k * (NB + 1) + pi]; e < s_beg[k * (NB + 1) + pi + 1]; ++e) a += s_coef[e] * buf0[s_m[e]];
+        g[pi] = a;
+      }
+      hadamard<D>(g);
+      T pick = g[0];
+#pragma unroll
+      for (int q = 1; q < NB; ++q)
+        if (q == NB - 1 - b) pick = g[q];
+      v = own_row[k] + pick;
+    }
+    __syncthreads();
+    if (k < PP) buf0[k] = v;
   }
   {
     size_t off = 0;
@@ -458,6 +498,7 @@ namespace {
 
 struct ShiftSeg {
   int l0, f;
+  int l_top = 0;   // down pass: level the blocks start from (above l0 + f: ancestor walk)
 };
 
 size_t upchain_lds(const fc2t2_plan_s* pl, int f) {
@@ -494,7 +535,7 @@ int shift_segments(const fc2t2_plan_s* pl, ShiftSeg* seg) {
       }
       if (f == 0) f = 1;
     }
-    seg[ns++] = ShiftSeg{l0, f};
+    seg[ns++] = ShiftSeg{l0, f, l0 + f};
     l0 += f;
   }
   return ns;
@@ -521,7 +562,7 @@ fc2t2_status chain_launch(const fc2t2_plan_s* pl, const ShiftSeg& sg, void* cons
   } else {
     const size_t smem = downchain_lds(pl, sg.f);
     hipLaunchKernelGGL((downchain_kernel<S, T>), grid, dim3(kShiftThreads), smem, s, g, tab + pl->shift_n_up,
-                       begs + (pl->P + 1), pl->shift_n_down, sg.l0, sg.f, lgn);
+                       begs + (pl->P + 1), pl->shift_n_down, sg.l0, sg.f, lgn, sg.l_top);
   }
   FC2T2_LAUNCH_CHECK();
   return FC2T2_OK;
@@ -530,9 +571,23 @@ fc2t2_status chain_launch(const fc2t2_plan_s* pl, const ShiftSeg& sg, void* cons
 fc2t2_status shift_pyramid(const fc2t2_plan_s* pl, void* const* grids, bool up, hipStream_t s,
                            uint8_t* const* occ, uint8_t gen) {
   ShiftSeg seg[kMaxLevels];
-  const int ns = shift_segments(pl, seg);
+  int ns = shift_segments(pl, seg);
+  int walk_from = -1;   // down pass: segment whose blocks walk their ancestors up to the top
+  if (!up) {
+    // the coarsest segments fold into the first one (from the top) with at most 4096 blocks:
+    // its blocks each recompute their single-cell ancestor chain instead of a launch per segment
+    for (int i = 0; i < ns; ++i) {
+      const int64_t blocks = (int64_t)1 << ((lg2i(pl->nl[seg[i].l0]) - seg[i].f) * pl->dim);
+      if (blocks <= 4096) {
+        walk_from = i;
+        break;
+      }
+    }
+    if (walk_from >= 0) ns = walk_from + 1;
+  }
   for (int i = 0; i < ns; ++i) {
-    const ShiftSeg& sg = seg[up ? i : ns - 1 - i];
+    ShiftSeg sg = seg[up ? i : ns - 1 - i];
+    sg.l_top = (!up && walk_from >= 0 && (ns - 1 - i) == walk_from) ? pl->levels - 1 : sg.l0 + sg.f;
     if ((up ? upchain_lds(pl, sg.f) : downchain_lds(pl, sg.f)) > kShiftLds) return FC2T2_EUNSUPPORTED;
     fc2t2_status st = FC2T2_EUNSUPPORTED;
     dispatch_shape(pl->dim, pl->K, [&](auto sh) {

@@ -180,7 +180,9 @@ fc2t2_status fc2t2_ray_integral_backward(fc2t2_plan plan, const void* o, const v
  * cell face belongs to the earlier cell).  Outputs: t [R] (NaN if none), normal [R][3] =
  * grad f at the root (zero if none), hit [R] int32 (1 hit, 0 dead ray: no crossing, or
  * f >= tau at entry), saved [R][FC2T2_ROOT_SAVED] (state for the backward: root point,
- * r . grad f, H r, tau, cell).  The root is polished by one FP64 Newton step. */
+ * r . grad f, H r, tau, cell).  The root is polished by one FP64 Newton step.  The call
+ * first writes per-cell bounds of L into a buffer the plan owns, so ray-root calls on one
+ * plan must not overlap in time (issue them on one stream). */
 #define FC2T2_ROOT_SAVED 12
 fc2t2_status fc2t2_ray_root(fc2t2_plan plan, const void* L, const void* o, const void* r,
                             double t0, double t1, int64_t R, double level_frac, void* t,

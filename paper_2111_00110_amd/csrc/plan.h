@@ -24,6 +24,8 @@ struct fc2t2_plan_s {
   void* shift = nullptr;          // sparse M2M/L2L shift lists (layout owned by tree.hip)
   size_t shift_beg_off = 0;
   int shift_n_up = 0, shift_n_down = 0;
+  void* cell_bounds = nullptr;    // 3-D: [G] float2 (lower, upper) bound of each finest cell's
+                                  //   polynomial over the cell, rebuilt by every ray-root call
   int device = 0;
   // Stage timing (measurement aid): bit s of timed_mask brackets stage s with events.
   uint32_t timed_mask = 0;

@@ -355,6 +355,11 @@ fc2t2_status fc2t2_plan_create(const fc2t2_grid* grid, const fc2t2_kernel* kerne
     const fc2t2_status st = m2l_mfma_build_tables(pl, stream);
     if (st != FC2T2_OK) return fail(st);
   }
+  // ---- per-cell polynomial bounds for the ray-root layer (3-D)
+  if (dim == 3 && hipMalloc(&pl->cell_bounds, (size_t)pl->G * 8) != hipSuccess) {
+    pl->cell_bounds = nullptr;
+    return fail(FC2T2_ENOMEM);
+  }
   if (hipStreamSynchronize(stream) != hipSuccess) return fail(FC2T2_EHIP);
   *out = pl;
   return FC2T2_OK;
@@ -365,6 +370,7 @@ fc2t2_status fc2t2_plan_destroy(fc2t2_plan plan) {
   if (plan->m2l_T) (void)hipFree(plan->m2l_T);
   if (plan->m2l_bf16) (void)hipFree(plan->m2l_bf16);
   if (plan->shift) (void)hipFree(plan->shift);
+  if (plan->cell_bounds) (void)hipFree(plan->cell_bounds);
   stage_timer_destroy(plan);
   delete plan;
   return FC2T2_OK;

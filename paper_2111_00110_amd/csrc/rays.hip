@@ -232,7 +232,7 @@ struct SegmentInsert {
   const double2* __restrict__ rec;
   const T* __restrict__ gy;
   int maxseg, C;
-  double h;
+  double ih;   // 1 / h
   __device__ __forceinline__ void operator()(uint32_t slot, const T (&centre)[3], int ch, T (&v)[S::P],
                                              int64_t) const {
     const int64_t ray = slot / maxseg;
@@ -243,8 +243,8 @@ struct SegmentInsert {
     double d[3], q[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      d[j] = (o[j] + tt.x * r[j] - (double)centre[j]) / h;
-      q[j] = r[j] / h;
+      d[j] = (o[j] + tt.x * r[j] - (double)centre[j]) * ih;
+      q[j] = r[j] * ih;
     }
     double nodes[3], wt[3];
     gl3(tt.y - tt.x, nodes, wt);
@@ -497,12 +497,38 @@ __device__ __forceinline__ void root_gradients(const T* __restrict__ row_ptr, co
 
 constexpr int kRootSub = 8;
 
+// Bounds of each finest cell's polynomial over the whole cell: with u in [-1/2, 1/2]^3,
+// |f(u) - L_0| <= B = sum_{k != 0} |L_k| prod_j (1/2)^{k_j} / k_j!.  Stored as the float pair
+// (L_0 - B, L_0 + B), widened by a relative 1e-6 and rounded outward, so that a segment of the
+// cell can be ruled out (entirely below or above a level) without building its polynomial.
+template <class S, typename T>
+__global__ void __launch_bounds__(256) cell_bounds_kernel(const T* __restrict__ L, int64_t G,
+                                                          float2* __restrict__ out) {
+  constexpr int P = S::P, Ppad = S::Ppad;
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= G) return;
+  double half[P];
+  const double hu[3] = {0.5, 0.5, 0.5};
+  monomials<S>(hu, half);
+  const T* row = L + cell * Ppad;
+  const double l0 = (double)row[0];
+  double B = 0.0;
+#pragma unroll
+  for (int k = 1; k < P; ++k) B += fabs((double)row[k]) * half[k];
+  const double pad = 1e-6 * (fabs(l0) + B) + 1e-30;
+  float lo_b = (float)(l0 - B - pad), hi_b = (float)(l0 + B + pad);
+  lo_b = nextafterf(lo_b, -INFINITY);
+  hi_b = nextafterf(hi_b, INFINITY);
+  out[cell] = make_float2(lo_b, hi_b);
+}
+
 template <class S, typename T>
 __global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, const T* __restrict__ O,
                                                       const T* __restrict__ Rd, int64_t R, double t0, double t1,
                                                       double lo, double hi, double h, int n, double frac,
                                                       T* __restrict__ t_out, T* __restrict__ normal,
-                                                      int32_t* __restrict__ hit, T* __restrict__ saved) {
+                                                      int32_t* __restrict__ hit, T* __restrict__ saved,
+                                                      const float2* __restrict__ bounds) {
   constexpr int P = S::P, Ppad = S::Ppad, K = S::K, SUB = kRootSub;
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t ray = gtid / SUB;
@@ -530,12 +556,33 @@ __global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, c
   int64_t cell;
   int cc[3];
   double ta, tb;
+  // ---- pass 0: a value the ray's maximum surely reaches: the largest value of f at a segment
+  // midpoint (evaluated only where the cell's upper bound exceeds the largest so far)
+  double lb = -INFINITY;
+  if (live) {
+    Dda dda;
+    dda.init(o, r, e0, e1, lo, hi, h, n);
+    while (dda.next(cell, cc, ta, tb)) {
+      if ((double)bounds[cell].y <= lb) continue;
+      const T* row = L + cell * Ppad;
+      const double tm = 0.5 * (ta + tb);
+      double u[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) u[j] = (o[j] + tm * r[j] - (lo + (cc[j] + 0.5) * h)) * ih;
+      lb = fmax(lb, cell_eval<S>(row, u));
+    }
+  }
+#pragma unroll
+  for (int off = SUB / 2; off >= 1; off >>= 1) lb = fmax(lb, __shfl_xor(lb, off));
   // ---- pass 1
   double fmax_v = -INFINITY;
   if (live) {
     Dda dda;
     dda.init(o, r, e0, e1, lo, hi, h, n);
     while (dda.next(cell, cc, ta, tb)) {
+      // no value in this cell can exceed the running maximum or the value the ray surely
+      // reaches (the cell where that value was taken is never skipped: its upper bound is larger)
+      if ((double)bounds[cell].y <= fmax(fmax_v, lb)) continue;
       T row[P];
 #pragma unroll
       for (int k = 0; k < P; ++k) row[k] = L[cell * Ppad + k];
@@ -561,6 +608,28 @@ __global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, c
     dda.init(o, r, e0, e1, lo, hi, h, n);
     double prev_end = 0.0;
     while (dda.next(cell, cc, ta, tb)) {
+      // a cell entirely below or above the level is settled by its bounds: its piece has one
+      // sign throughout, so it holds no crossing and only its sign matters at the faces
+      const float2 bd = bounds[cell];
+      const double side = (double)bd.y < tau ? -1.0 : ((double)bd.x > tau ? 1.0 : 0.0);
+      if (side != 0.0) {
+        if (!have_piece) {
+          first_start = side;
+          have_piece = true;
+        } else if (!found && prev_end < 0.0 && side > 0.0) {   // crossing on a face
+          t_ev = last_tb;
+          ev_cell = last_cell;
+          ev_c[0] = last_c[0]; ev_c[1] = last_c[1]; ev_c[2] = last_c[2];
+          found = true;
+        }
+        prev_end = side;
+        last_end = side;
+        last_tb = tb;
+        last_cell = cell;
+        last_c[0] = cc[0]; last_c[1] = cc[1]; last_c[2] = cc[2];
+        if (found) break;
+        continue;
+      }
       T row[P];
 #pragma unroll
       for (int k = 0; k < P; ++k) row[k] = L[cell * Ppad + k];
@@ -804,7 +873,7 @@ fc2t2_status ray_integral_backward_t(const fc2t2_plan_s* pl, const T* o, const T
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {
     using S = decltype(shape);
     if constexpr (S::D == 3) {
-      SegmentInsert<S, T> fn{o, r, b.rec, gy, maxseg, pl->C, pl->h0};
+      SegmentInsert<S, T> fn{o, r, b.rec, gy, maxseg, pl->C, 1.0 / pl->h0};
       // records per occupied cell are few (a ray crosses a cell once): the number of real
       // segments is about 2.3 n per ray
       st = launch_reduce_cells<S, T>(pl, b.starts, b.perm, R * 2 * pl->n, gL, true, fn, s);
@@ -826,19 +895,25 @@ fc2t2_status ray_integral_backward(const fc2t2_plan_s* pl, const void* o, const 
 fc2t2_status launch_ray_root(const fc2t2_plan_s* pl, const void* L, const void* o, const void* r, double t0, double t1,
                              int64_t R, double frac, void* t, void* normal, int32_t* hit, void* saved, hipStream_t s) {
   if (R == 0) return FC2T2_OK;
+  if (!pl->cell_bounds) return FC2T2_EUNSUPPORTED;
   fc2t2_status st = FC2T2_EUNSUPPORTED;
   const dim3 grid((unsigned)ceil_div(R * kRootSub, 64));
+  const dim3 bgrid((unsigned)ceil_div(pl->G, 256));
+  float2* bounds = (float2*)pl->cell_bounds;
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {
     using S = decltype(shape);
     if constexpr (S::D == 3) {
-      if (pl->io == FC2T2_IO_F64)
+      if (pl->io == FC2T2_IO_F64) {
+        hipLaunchKernelGGL((cell_bounds_kernel<S, double>), bgrid, dim3(256), 0, s, (const double*)L, pl->G, bounds);
         hipLaunchKernelGGL((ray_root_kernel<S, double>), grid, dim3(64), 0, s, (const double*)L, (const double*)o,
                            (const double*)r, R, t0, t1, pl->lo, pl->hi, pl->h0, pl->n, frac, (double*)t,
-                           (double*)normal, hit, (double*)saved);
-      else
+                           (double*)normal, hit, (double*)saved, bounds);
+      } else {
+        hipLaunchKernelGGL((cell_bounds_kernel<S, float>), bgrid, dim3(256), 0, s, (const float*)L, pl->G, bounds);
         hipLaunchKernelGGL((ray_root_kernel<S, float>), grid, dim3(64), 0, s, (const float*)L, (const float*)o,
                            (const float*)r, R, t0, t1, pl->lo, pl->hi, pl->h0, pl->n, frac, (float*)t,
-                           (float*)normal, hit, (float*)saved);
+                           (float*)normal, hit, (float*)saved, bounds);
+      }
       st = FC2T2_OK;
     }
   });

@@ -280,7 +280,10 @@ fc2t2_status launch_reduce_sorted(const fc2t2_plan_s* pl, const void* pay, int64
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {
     using S = decltype(shape);
     SortedMonomials<S, float> fn{(const float*)pay, (float)(1.0 / pl->h0)};
-    st = launch_reduce_cells<S, float>(pl, starts, nullptr, count, (float*)out, accumulate, fn, s, occ, gen);
+    // sources (the call that records occupancy) may crowd a few cells: let waves take those
+    st = occ ? launch_reduce_cells<S, float, decltype(fn), true>(pl, starts, nullptr, count, (float*)out, accumulate,
+                                                                  fn, s, occ, gen)
+             : launch_reduce_cells<S, float>(pl, starts, nullptr, count, (float*)out, accumulate, fn, s, occ, gen);
   });
   return st;
 }

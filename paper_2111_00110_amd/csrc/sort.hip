@@ -23,7 +23,7 @@ struct SweepShape {
   static constexpr int kWaveRun = kItems * kWave;
   static constexpr int kTile = kThreads * kItems;
 };
-constexpr int kHistCopies = 16;   // private global histograms (spreads the atomics)
+constexpr int kHistBlocks = 512;  // histogram blocks; each writes its own counts (no atomics)
 // Tile status words: value in the low 30 bits, flag in the top two (0 = not yet published,
 // 1 = the tile's own counts, 2 = counts of all tiles up to and including this one).
 constexpr uint32_t kFlagAgg = 1u << 30;
@@ -32,12 +32,23 @@ constexpr uint32_t kValMask = kFlagAgg - 1u;
 constexpr int kMaxPayload = 4;            // payload words per item
 constexpr uint32_t kMaxSpins = 1u << 22;   // bounded wait: a predecessor that never publishes sets err
 
-__global__ void __launch_bounds__(kThreads) sort_init_kernel(uint32_t* __restrict__ words, int n) {
-  for (int i = threadIdx.x; i < n; i += kThreads) words[i] = 0u;
+// Sums the histogram blocks' counts in kSlices slices per pass: block (pass, slice), thread
+// digit, writes sums[slice][pass][digit] (the sweep adds the slices).  Also clears the error word.
+constexpr int kSlices = 16;
+__global__ void __launch_bounds__(kThreads) sort_hist_sum_kernel(const uint32_t* __restrict__ part, int nblocks,
+                                                                 uint32_t* __restrict__ sums,
+                                                                 uint32_t* __restrict__ err) {
+  const int pass = blockIdx.x, slice = blockIdx.y, d = threadIdx.x;
+  uint32_t sum = 0;
+#pragma unroll 8
+  for (int b = slice; b < nblocks; b += kSlices) sum += part[((size_t)b * kMaxPasses + pass) * kBins + d];
+  sums[((size_t)slice * kMaxPasses + pass) * kBins + d] = sum;
+  if (pass == 0 && slice == 0 && d == 0) *err = 0u;
 }
 
-// Digit histograms of every pass in one read of the keys (computed from points when x is
-// given, then written to keys), and clearing of the passes' tile status words.
+// Digit counts of every pass in one read of the keys (computed from points when x is given,
+// then written to keys), one row of counts per block, and clearing of the passes' tile status
+// words.
 template <typename T, int D>
 __global__ void __launch_bounds__(kThreads) sort_hist_kernel(const T* __restrict__ x, T lo, T scale, int n,
                                                              uint32_t* __restrict__ keys, uint32_t N, int npass,
@@ -73,9 +84,8 @@ __global__ void __launch_bounds__(kThreads) sort_hist_kernel(const T* __restrict
     }
   }
   __syncthreads();
-  uint32_t* gh = ghist + (size_t)(blockIdx.x % kHistCopies) * kMaxPasses * kBins;
-  for (int ps = 0; ps < npass; ++ps)
-    if (h[ps][tid]) atomicAdd(&gh[ps * kBins + tid], h[ps][tid]);
+  uint32_t* mine = ghist + (size_t)blockIdx.x * kMaxPasses * kBins;   // this block's counts
+  for (int ps = 0; ps < npass; ++ps) mine[ps * kBins + tid] = h[ps][tid];
   for (uint32_t w = blockIdx.x * kThreads + tid; w < status_words; w += stride) status[w] = 0u;
 }
 
@@ -230,7 +240,7 @@ __global__ void __launch_bounds__(kThreads) onesweep_kernel(const uint32_t* __re
   }
   uint32_t dtot = 0;
 #pragma unroll
-  for (int cp = 0; cp < kHistCopies; ++cp) dtot += ghist[(size_t)cp * kMaxPasses * kBins + tid];
+  for (int cp = 0; cp < kSlices; ++cp) dtot += ghist[(size_t)cp * kMaxPasses * kBins + tid];
   uint32_t dbase;
   block_exclusive_scan(dtot, dbase, scan_sh);
   s_gbase[tid] = dbase + prefix;
@@ -294,10 +304,10 @@ int key_bits_for(int64_t G) {
 namespace {
 
 struct SortScratch {
-  uint32_t *ktmp, *vtmp, *ptmp, *ghist, *status, *err;
+  uint32_t *ktmp, *vtmp, *ptmp, *part, *ghist, *status, *err;
   uint32_t max_tiles;
 };
-constexpr int kHistWords = kHistCopies * kMaxPasses * kBins;
+constexpr int kPartWords = kHistBlocks * kMaxPasses * kBins;
 
 SortScratch carve_scratch(void* scratch, int64_t N) {
   SortScratch c;
@@ -309,9 +319,11 @@ SortScratch carve_scratch(void* scratch, int64_t N) {
   p += align256((size_t)N * 4);
   c.ptmp = (uint32_t*)p;
   p += align256((size_t)N * 4 * kMaxPayload);
-  c.ghist = (uint32_t*)p;                 // kHistCopies x kMaxPasses x kBins, then err
-  c.err = c.ghist + kHistWords;
-  p += align256((kHistWords + 1) * 4);
+  c.part = (uint32_t*)p;                  // per histogram block: kMaxPasses x kBins counts
+  p += align256((size_t)kPartWords * 4);
+  c.ghist = (uint32_t*)p;                 // kSlices x kMaxPasses x kBins partial totals, then err
+  c.err = c.ghist + kSlices * kMaxPasses * kBins;
+  p += align256((kSlices * kMaxPasses * kBins + 1) * 4);
   c.status = (uint32_t*)p;
   return c;
 }
@@ -345,13 +357,14 @@ fc2t2_status onesweep_passes(const uint32_t* keys_in, uint32_t* keys_out, uint32
 template <typename T, int D>
 fc2t2_status sort_prologue(const T* x, T lo, T scale, int n, uint32_t* keys, uint32_t N, int npass,
                            const SortScratch& c, hipStream_t s) {
-  hipLaunchKernelGGL(sort_init_kernel, dim3(1), dim3(kThreads), 0, s, c.ghist, kHistWords + 1);
-  FC2T2_LAUNCH_CHECK();
   const uint32_t status_words = (uint32_t)npass * c.max_tiles * kBins;
   const int64_t work = (int64_t)N > (int64_t)status_words ? (int64_t)N : (int64_t)status_words;
-  const unsigned blocks = (unsigned)std::min<int64_t>(std::max<int64_t>(ceil_div(work, kThreads * 8), 1), 2048);
+  const int blocks = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(work, kThreads * 8), 1), kHistBlocks);
   hipLaunchKernelGGL((sort_hist_kernel<T, D>), dim3(blocks), dim3(kThreads), 0, s, x, lo, scale, n, keys, N, npass,
-                     c.ghist, c.status, status_words);
+                     c.part, c.status, status_words);
+  FC2T2_LAUNCH_CHECK();
+  hipLaunchKernelGGL(sort_hist_sum_kernel, dim3(npass, kSlices), dim3(kThreads), 0, s, c.part, blocks, c.ghist,
+                     c.err);
   FC2T2_LAUNCH_CHECK();
   return FC2T2_OK;
 }
@@ -362,7 +375,8 @@ namespace fc2t2 {
 
 size_t radix_sort_scratch_bytes(int64_t N) {
   const int64_t tiles = ceil_div(N > 0 ? N : 1, kTileMin);
-  return align256((size_t)N * 4) * 2 + align256((size_t)N * 4 * kMaxPayload) + align256((kHistWords + 1) * 4) +
+  return align256((size_t)N * 4) * 2 + align256((size_t)N * 4 * kMaxPayload) + align256((size_t)kPartWords * 4) +
+         align256((kSlices * kMaxPasses * kBins + 1) * 4) +
          align256((size_t)kMaxPasses * tiles * kBins * 4);
 }
 

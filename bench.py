@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--compare-f32", type=int, default=1,
                     help="also time the same step with the plain FP32 M2L (same accuracy class)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=256, help="queries in the CPU sample")
+    ap.add_argument("--cpu-sample", type=int, default=1536, help="queries in the CPU sample")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device-to-device copies of MIB MiB (the reference "
                          "kernel for scaling HBM byte counters) and exit")

@@ -72,7 +72,7 @@ def stage_bytes(stage: str, dim: int, n: int, K: int, N: int = 0, M: int = 0, it
     every finest-grid row it must touch, once.
 
     per source / query (es = itemsize, d = dim):
-      p2m    p, w, sort index read                      (d + 1) es + 4
+      p2m    sorted p, w read (once, contiguous)        (d + 1) es
       l2p    q read, y written                          (d + 1) es
       l2p_T  sorted q, gy read (once, contiguous)       (d + 1) es
       qgrad  q, gy read, q_bar read and written         (3 d + 1) es
@@ -87,7 +87,7 @@ def stage_bytes(stage: str, dim: int, n: int, K: int, N: int = 0, M: int = 0, it
     d, es, G = dim, itemsize, n ** dim
     R = p_pad(dim, K) * es * channels
     if stage == "p2m":
-        return N * ((d + 1) * es + 4) + G * (4 + R)
+        return N * (d + 1) * es + G * (4 + R)
     if stage == "l2p":
         return M * (d + 1) * es + G * R
     if stage == "l2p_T":

@@ -164,3 +164,23 @@ def test_full_size_2d_sampled(F):
     dvec = qs.astype(np.float64) - geo.centre(0, cells)
     want = np.einsum("csp,sp->sc", Lc, fmm.monomials(dvec, geo.idx))
     assert rel(y[idx], want) < 1e-5
+
+
+def test_stage_timing_records_each_stage(F):
+    """The library's event bracketing: every stage of one explicit step is timed once per call
+    (two sorts: sources and queries), and turning timing off records nothing further."""
+    wl = W.workload("explicit2d", N=1 << 15, M=1 << 14, n=64)
+    x = W.make(wl, seed=5)
+    plan = _plan(F, wl, m2l="bf16x3")
+    plan.stage_timing(F.STAGES)
+    _run_gpu(F, plan, x)
+    want = {"sort": 3, "p2m": 1, "shift_up": 2, "m2l": 1, "shift_down": 2, "l2p": 1, "l2p_T": 1,
+            "m2l_T": 1, "p2m_T": 1, "qgrad": 1}
+    for name, calls in want.items():
+        ms, n = plan.stage_time(name)
+        assert n == calls, (name, n)
+        assert ms > 0.0, name
+    assert plan.stage_time("ray") == (0.0, 0)
+    plan.stage_timing([])
+    _run_gpu(F, plan, x)
+    assert plan.stage_time("m2l") == (0.0, 0)

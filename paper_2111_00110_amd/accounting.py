@@ -102,7 +102,10 @@ def stage_bytes(stage: str, dim: int, n: int, K: int, N: int = 0, M: int = 0, it
 # ---- M2L work that actually runs when tiles with nothing to contribute are skipped
 
 # Target tile of one MFMA M2L workgroup (cells per dimension).
-M2L_TILE = {2: (16, 8), 3: (16, 8, 8)}
+def m2l_tile(dim: int, K: int):
+    if dim == 2:
+        return (16, 8)
+    return (16, 8, 4) if n_terms(3, K) <= 35 else (16, 8, 8)
 
 
 def _window_counts_1d(n: int):
@@ -141,7 +144,7 @@ def m2l_flops_executed(dim: int, K: int, occ_levels, transpose: bool, channels: 
     of whose outputs is occupied."""
     import numpy as np
     P = n_terms(dim, K)
-    tile = M2L_TILE[dim]
+    tile = m2l_tile(dim, K)
     total = 0
     for lvl, occ in enumerate(occ_levels):
         n_l = occ.shape[0]

@@ -360,10 +360,11 @@ struct Tile;
 // 2-D: 8 x 4 parents (128 targets, 4 waves, two 16-row tiles each)
 template <int P, int PASSES>
 struct Tile<2, P, PASSES> { using type = CfgX<2, P, 8, 4, 1, PASSES>; };
-// 3-D: 8 x 4 x 4 parents (1024 targets, 8 waves, eight 16-row tiles each; the tensor
-// fragment a wave loads feeds 8 row tiles)
+// 3-D: 8 x 4 x 4 parents for P > 35 (1024 targets, 8 waves, eight 16-row tiles each: the tensor
+// fragment a wave loads feeds 8 row tiles), 8 x 4 x 2 for P <= 35 (half the LDS, two workgroups
+// per compute unit, and finer blocks when tiles are skipped)
 template <int P, int PASSES>
-struct Tile<3, P, PASSES> { using type = CfgX<3, P, 8, 4, 4, PASSES>; };
+struct Tile<3, P, PASSES> { using type = CfgX<3, P, 8, 4, (P <= 35 ? 2 : 4), PASSES>; };
 
 template <class C>
 fc2t2_status launch_cfg(const fc2t2_plan_s* pl, int lvl0, int lvl1, const void* const* ins, void* const* outs,

@@ -574,15 +574,17 @@ __global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, c
   }
 #pragma unroll
   for (int off = SUB / 2; off >= 1; off >>= 1) lb = fmax(lb, __shfl_xor(lb, off));
-  // ---- pass 1
-  double fmax_v = -INFINITY;
+  // ---- pass 1.  The running maximum starts at lb, a value f takes on the ray: the maximum
+  // over the segments is at least lb, so starting there changes nothing but skips the exact
+  // maximisation of every segment whose bound stays below it.
+  double fmax_v = lb;
   if (live) {
     Dda dda;
     dda.init(o, r, e0, e1, lo, hi, h, n);
     while (dda.next(cell, cc, ta, tb)) {
-      // no value in this cell can exceed the running maximum or the value the ray surely
-      // reaches (the cell where that value was taken is never skipped: its upper bound is larger)
-      if ((double)bounds[cell].y <= fmax(fmax_v, lb)) continue;
+      // no value in this cell can exceed the running maximum (at least lb, a value the ray
+      // surely reaches)
+      if ((double)bounds[cell].y <= fmax_v) continue;
       T row[P];
 #pragma unroll
       for (int k = 0; k < P; ++k) row[k] = L[cell * Ppad + k];

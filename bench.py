@@ -39,9 +39,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="explicit2d")
-    ap.add_argument("--m2l", default="bf16x3", help="f32 | bf16 | bf16x2 | bf16x3")
+    ap.add_argument("--m2l", default="bf16x3",
+                    help="f32 | bf16 | bf16x2 | bf16x3 | separable (Gaussian kernels only)")
     ap.add_argument("--compare-f32", type=int, default=1,
                     help="also time the same step with the plain FP32 M2L (same accuracy class)")
+    ap.add_argument("--compare-separable", type=int, default=1,
+                    help="Gaussian kernels: also time the same step with the separable M2L")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1536, help="queries in the CPU sample")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -213,9 +216,25 @@ def main():
         step32()
         f32_ms, _ = run(step32, max(3, args.steps // 4))
 
-    passes = {"f32": 1, "bf16": 1, "bf16x2": 2, "bf16x3": 3}[args.m2l]
+    sep_cmp = None
+    if args.compare_separable and wl.kernel == "gaussian" and args.m2l != "separable":
+        plan_s = make_plan("separable")
+        step_s = make_step(plan_s)
+        step_s()
+        plan_s.stage_timing(["m2l", "m2l_T"])
+        reps = max(3, args.steps // 4)
+        sep_ms, _ = run(step_s, reps)
+        sep_cmp = {"value": round((wl.M if wl.layer == "explicit" else wl.R) / (sep_ms * 1e-3), 1),
+                   "ms_per_step": round(sep_ms, 4)}
+        for name in ("m2l", "m2l_T"):
+            st_ms, calls = plan_s.stage_time(name)
+            sep_cmp[name + "_us_per_call"] = round(st_ms / max(calls, 1) * 1e3, 2)
+        plan_s.stage_timing([])
+
+    passes = {"f32": 1, "bf16": 1, "bf16x2": 2, "bf16x3": 3, "separable": None}[args.m2l]
     flops_dense = accounting.m2l_flops(wl.dim, wl.n, wl.K)
-    mfma = args.m2l != "f32"
+    separable = args.m2l == "separable"
+    mfma = passes is not None and args.m2l != "f32"
     m2l_peak = PEAKS["bf16_mfma_TFLOPs"] if mfma else PEAKS["fp32_vector_TFLOPs"]
     # the MFMA path skips tiles with nothing to contribute: count the useful flops of the
     # tiles that run (source occupancy from the same FP32 cell index as the kernels)
@@ -223,6 +242,9 @@ def main():
         occ = accounting.occupancy_pyramid(x["p"], wl.lo, wl.hi, wl.n, wl.dim)
         flops_run = {"m2l": accounting.m2l_flops_executed(wl.dim, wl.K, occ, False),
                      "m2l_T": accounting.m2l_flops_executed(wl.dim, wl.K, occ, True)}
+    elif separable:
+        f = accounting.m2l_flops_separable(wl.dim, wl.n, wl.K)
+        flops_run = {"m2l": f, "m2l_T": f}
     else:
         flops_run = {"m2l": flops_dense, "m2l_T": flops_dense}
 
@@ -238,7 +260,17 @@ def main():
                 "flops_run": flops_run[name], "flops_dense": flops_dense,
                 "dense_equivalent_TFLOPs": round(flops_dense / (kt * 1e-3) / 1e12, 3)}
 
-    if dom in ("m2l", "m2l_T"):
+    if dom in ("m2l", "m2l_T") and separable:
+        # one launch per dimension (all levels, window and hole chains in each); the stage is
+        # bound by its intermediate rows in HBM
+        nbytes = accounting.m2l_bytes_separable(wl.dim, wl.n, wl.K, itemsize=es)
+        achieved = nbytes / (kernel_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAKS["hbm_GBps"], "unit": "GB/s",
+                    "frac": round(achieved / PEAKS["hbm_GBps"], 4), "traffic": None,
+                    "kernel": "%s, separable: %d one-dimensional passes" % (dom, wl.dim),
+                    "kernel_us": round(kernel_ms * 1e3, 2), "launches": dom_calls * wl.dim,
+                    "bytes_per_launch": nbytes, "flops_per_launch": flops_run[dom], "flops_dense": flops_dense}
+    elif dom in ("m2l", "m2l_T"):
         achieved = flops_run[dom] / (kernel_ms * 1e-3) / 1e12
         roofline = {"bound": "mfma" if mfma else "alu", "achieved": round(achieved, 3), "peak": m2l_peak,
                     "unit": "TFLOP/s", "frac": round(achieved / m2l_peak, 4), "traffic": None,
@@ -252,7 +284,8 @@ def main():
                     "frac": round(achieved / PEAKS["hbm_GBps"], 4), "traffic": None,
                     "kernel": dom, "kernel_us": round(kernel_ms * 1e3, 2), "launches": dom_calls,
                     "bytes_per_launch": nbytes}
-    roofline["traffic"] = measured_traffic(wl.name, dom)
+    traffic_key = dom + "_separable" if separable and dom in ("m2l", "m2l_T") else dom
+    roofline["traffic"] = measured_traffic(wl.name, traffic_key)
 
     unit = "queries/s" if wl.layer == "explicit" else "rays/s"
     outputs = {"explicit": "y, w_bar, p_bar, q_bar", "ray_integral": "y (ray integrals), w_bar, p_bar",
@@ -266,10 +299,14 @@ def main():
                    "grid": "%d^%d" % (wl.n, wl.dim), "K": wl.K, "kernel": "%s %g" % (wl.kernel, wl.param),
                    "m2l": args.m2l, "outputs": outputs},
         "roofline": roofline,
-        "m2l_mfma": {"forward": m2l_line("m2l"), "transpose": m2l_line("m2l_T")},
+        ("m2l_separable" if separable else "m2l_mfma"): {"forward": m2l_line("m2l"),
+                                                         "transpose": m2l_line("m2l_T")},
         "stages_ms_per_step": {k: v["ms_per_step"] for k, v in stages.items()},
         "plan_ms": round(plan_ms, 1),
     }
+    if sep_cmp is not None:
+        sep_cmp["unit"] = unit
+        out["m2l_separable_comparison"] = sep_cmp
     if f32_ms is not None:
         out["m2l_f32_comparison"] = {"value": round(units / (f32_ms * 1e-3), 1), "unit": unit,
                                      "ms_per_step": round(f32_ms, 4)}

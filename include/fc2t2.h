@@ -69,7 +69,11 @@ typedef enum {
   FC2T2_M2L_F32 = 1,       /* FP32 contraction */
   FC2T2_M2L_BF16 = 2,      /* BF16 MFMA, FP32 accumulation, one pass */
   FC2T2_M2L_BF16X2 = 3,    /* BF16 MFMA, tensor split hi/lo: two passes */
-  FC2T2_M2L_BF16X3 = 4     /* BF16 MFMA, moments and tensor split hi/lo: three passes */
+  FC2T2_M2L_BF16X3 = 4,    /* BF16 MFMA, moments and tensor split hi/lo: three passes */
+  FC2T2_M2L_SEPARABLE = 5  /* Gaussian kernels only (section 3.4.1): the tensor factors over the
+                              dimensions and M2L runs as one 1-D pass per dimension (window minus
+                              hole as two chains), in the IO precision; fc2t2_m2l then uses the
+                              plain contraction */
 } fc2t2_m2l_prec;
 
 typedef enum { FC2T2_IO_F32 = 0, FC2T2_IO_F64 = 1 } fc2t2_io;

@@ -172,3 +172,66 @@ def m2l_flops_executed(dim: int, K: int, occ_levels, transpose: bool, channels: 
                 run[tgt] = True
         total += int(pairs[run].sum())
     return 2 * P * P * channels * total
+
+
+# ---- separable M2L (Gaussian): one-dimensional passes over intermediate index sets
+
+def _sep_sets(dim: int, K: int):
+    """Index sets of the pass chain: S0 (|v| <= K), A and, in 3-D, B."""
+    r = range(K + 1)
+    if dim == 2:
+        S0 = [(a, b) for a in r for b in r if a + b <= K]
+        return S0, [(a, b) for a in r for b in r], None
+    S0 = [(a, b, c) for a in r for b in r for c in r if a + b + c <= K]
+    A = [(a, b, c) for a in r for b in r for c in r if b + c <= K]
+    B = [(a, b, c) for a in r for b in r for c in r if a + b <= K]
+    return S0, A, B
+
+
+def _pass_entries(src, dst, axis: int, K: int) -> int:
+    """Multiply-adds per cell and offset of one pass: for every output tuple, the input tuples
+    equal to it except at the contracted axis."""
+    have = set(src)
+    tot = 0
+    for t in dst:
+        for v in range(K + 1):
+            u = list(t)
+            u[axis] = v
+            tot += tuple(u) in have
+    return tot
+
+
+def sep_pass_entries(dim: int, K: int):
+    """Per forward pass (x, y[, z]) the multiply-adds per cell and offset."""
+    S0, A, B = _sep_sets(dim, K)
+    if dim == 2:
+        return [_pass_entries(S0, A, 0, K), _pass_entries(A, S0, 1, K)]
+    return [_pass_entries(S0, A, 0, K), _pass_entries(A, B, 1, K), _pass_entries(B, S0, 2, K)]
+
+
+def m2l_flops_separable(dim: int, n: int, K: int, channels: int = 1) -> int:
+    """Flops (2 per multiply-add) of the separable M2L at every level: each pass runs the
+    window chain (per cell the in-grid offsets of its one-dimensional parity window) and, above
+    the finest level, the hole chain (offsets -1..1).  The transpose does the same work."""
+    ents = sep_pass_entries(dim, K)
+    total = 0
+    for l in range(levels_of(n)):
+        n_l = n >> l
+        per_axis = _window_pairs_1d(n_l) + (_hole_pairs_1d(n_l) if l > 0 else 0)
+        total += sum(ents) * n_l ** (dim - 1) * per_axis
+    return 2 * channels * total
+
+
+def m2l_bytes_separable(dim: int, n: int, K: int, itemsize: int = 4, channels: int = 1) -> int:
+    """HBM bytes of the separable M2L at every level: every pass reads its input rows and
+    writes its output rows once per chain (the first pass reads the moment row once for both
+    chains, the last writes one local row: window minus hole)."""
+    S0, A, B = _sep_sets(dim, K)
+    sizes = [len(A)] if dim == 2 else [len(A), len(B)]
+    R = p_pad(dim, K)
+    total = 0
+    for l in range(levels_of(n)):
+        chains = 1 if l == 0 else 2
+        per_cell = R + R + 2 * chains * sum(sizes)   # first read, last write, each intermediate out and in
+        total += (n >> l) ** dim * per_cell
+    return total * itemsize * channels

@@ -72,6 +72,7 @@ size_t ws_expand(const fc2t2_plan_s* pl, int64_t N) {
   carve_pyramid(c, pl, 1, lv);
   uint8_t* occ[kMaxLevels];
   carve_occupancy(c, pl, occ);
+  c.take<char>(sep_ws_bytes(pl));
   return c.off;
 }
 
@@ -88,6 +89,7 @@ size_t ws_expand_backward(const fc2t2_plan_s* pl) {
   carve_pyramid(c, pl, 0, lv);
   uint8_t* occ[kMaxLevels];
   carve_occupancy(c, pl, occ);
+  c.take<char>(sep_ws_bytes(pl));
   return c.off;
 }
 
@@ -101,7 +103,7 @@ namespace fc2t2 {
 // every level (one launch), then L2L down the pyramid accumulating into each finer level.
 // occ: occupancy maps with level 0 stamped with gen (the rest are filled on the way up).
 fc2t2_status expand_from_moments(const fc2t2_plan_s* pl, void** Mlv, void** Llv, void* L0, hipStream_t s,
-                                 uint8_t** occ, uint8_t gen) {
+                                 uint8_t** occ, uint8_t gen, void* sep_ws) {
   Llv[0] = L0;
   fc2t2_status st;
   {
@@ -111,7 +113,7 @@ fc2t2_status expand_from_moments(const fc2t2_plan_s* pl, void** Mlv, void** Llv,
   if (st) return st;
   {
     StageScope t(pl, FC2T2_STAGE_M2L, s);
-    st = launch_m2l_all(pl, (const void* const*)Mlv, Llv, false, s, (const uint8_t* const*)occ, gen);
+    st = launch_m2l_all(pl, (const void* const*)Mlv, Llv, false, s, (const uint8_t* const*)occ, gen, sep_ws);
   }
   if (st) return st;
   StageScope t(pl, FC2T2_STAGE_SHIFT_DOWN, s);
@@ -120,7 +122,7 @@ fc2t2_status expand_from_moments(const fc2t2_plan_s* pl, void** Mlv, void** Llv,
 
 // Transpose of expand_from_moments: G_L0 -> G_M0 (L2L^T up, M2L^T at every level, M2M^T down).
 fc2t2_status expand_T_to_moments(const fc2t2_plan_s* pl, const void* GL0, void** GLlv, void** GMlv,
-                                 hipStream_t s, uint8_t** occ, uint8_t gen) {
+                                 hipStream_t s, uint8_t** occ, uint8_t gen, void* sep_ws) {
   GLlv[0] = (void*)GL0;
   fc2t2_status st;
   {
@@ -130,7 +132,7 @@ fc2t2_status expand_T_to_moments(const fc2t2_plan_s* pl, const void* GL0, void**
   if (st) return st;
   {
     StageScope t(pl, FC2T2_STAGE_M2L_T, s);
-    st = launch_m2l_all(pl, (const void* const*)GLlv, GMlv, true, s, (const uint8_t* const*)occ, gen);
+    st = launch_m2l_all(pl, (const void* const*)GLlv, GMlv, true, s, (const uint8_t* const*)occ, gen, sep_ws);
   }
   if (st) return st;
   StageScope t(pl, FC2T2_STAGE_SHIFT_DOWN, s);
@@ -167,6 +169,7 @@ fc2t2_status fc2t2_expand(fc2t2_plan plan, const void* p, const void* w, int64_t
   carve_pyramid(c, plan, 1, Llv);
   uint8_t* occ[kMaxLevels];
   carve_occupancy(c, plan, occ);
+  void* sep_ws = c.take<char>(sep_ws_bytes(plan));
   const uint8_t gen = next_gen(plan);
   fc2t2_status st;
   const bool carry = sb.pay != nullptr;   // sort the points' data along with the keys
@@ -181,7 +184,7 @@ fc2t2_status fc2t2_expand(fc2t2_plan plan, const void* p, const void* w, int64_t
                : launch_p2m(plan, p, w, N, sb.starts, sb.perm, Mlv[0], stream, occ[0], gen);
   }
   if (st) return st;
-  return expand_from_moments(plan, Mlv, Llv, L, stream, occ, gen);
+  return expand_from_moments(plan, Mlv, Llv, L, stream, occ, gen, sep_ws);
 }
 
 fc2t2_status fc2t2_eval(fc2t2_plan plan, const void* L, const void* q, int64_t M, void* y, void* grad,
@@ -248,6 +251,7 @@ fc2t2_status fc2t2_expand_backward(fc2t2_plan plan, const void* gL, const void* 
   carve_pyramid(c, plan, 0, GMlv);
   uint8_t* occ[kMaxLevels];
   carve_occupancy(c, plan, occ);
+  void* sep_ws = c.take<char>(sep_ws_bytes(plan));
   const uint8_t gen = next_gen(plan);
   fc2t2_status st;
   {
@@ -255,7 +259,7 @@ fc2t2_status fc2t2_expand_backward(fc2t2_plan plan, const void* gL, const void* 
     st = launch_mark_cells(plan, p, N, occ[0], gen, stream);
   }
   if (st) return st;
-  st = expand_T_to_moments(plan, gL, GLlv, GMlv, stream, occ, gen);
+  st = expand_T_to_moments(plan, gL, GLlv, GMlv, stream, occ, gen, sep_ws);
   if (st) return st;
   StageScope t(plan, FC2T2_STAGE_P2M_T, stream);
   return launch_p2m_T(plan, GMlv[0], p, w, N, gp, gw, stream);

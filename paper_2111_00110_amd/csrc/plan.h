@@ -6,6 +6,7 @@
 namespace fc2t2 {
 struct StageTimer;
 }
+struct SepTables;
 
 struct fc2t2_plan_s {
   int dim, n, K, P, Ppad, C, levels, io, prec, kind;
@@ -24,6 +25,7 @@ struct fc2t2_plan_s {
   void* shift = nullptr;          // sparse M2M/L2L shift lists (layout owned by tree.hip)
   size_t shift_beg_off = 0;
   int shift_n_up = 0, shift_n_down = 0;
+  SepTables* sep = nullptr;       // separable M2L tables (layout owned by separable.hip)
   void* cell_bounds = nullptr;    // 3-D: [G] float2 (lower, upper) bound of each finest cell's
                                   //   polynomial over the cell, rebuilt by every ray-root call
   int device = 0;
@@ -142,7 +144,17 @@ fc2t2_status launch_m2l_T(const fc2t2_plan_s* pl, int lvl, const void* GL, void*
 // method reads are unchanged.
 fc2t2_status launch_m2l_all(const fc2t2_plan_s* pl, const void* const* ins, void* const* outs,
                             bool transpose, hipStream_t s, const uint8_t* const* occ = nullptr,
-                            uint8_t gen = 1);
+                            uint8_t gen = 1, void* sep_ws = nullptr);
+
+// ---- separable.hip (Gaussian kernels)
+bool sep_supported(const fc2t2_plan_s* pl);
+fc2t2_status sep_build(fc2t2_plan_s* pl, hipStream_t s);
+void sep_destroy(fc2t2_plan_s* pl);
+size_t sep_ws_bytes(const fc2t2_plan_s* pl);
+// M2L (or its transpose) at every level by one-dimensional passes; ws of sep_ws_bytes bytes.
+fc2t2_status launch_m2l_separable(const fc2t2_plan_s* pl, const void* const* ins, void* const* outs, bool transpose,
+                                  void* ws, hipStream_t s);
+inline bool m2l_is_mfma(const fc2t2_plan_s* pl) { return pl->prec >= FC2T2_M2L_BF16 && pl->prec <= FC2T2_M2L_BF16X3; }
 
 // ---- m2l_mfma.hip
 bool m2l_mfma_supported(const fc2t2_plan_s* pl);

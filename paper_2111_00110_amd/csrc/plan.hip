@@ -229,8 +229,10 @@ fc2t2_status fc2t2_plan_create(const fc2t2_grid* grid, const fc2t2_kernel* kerne
   if (K < 1 || channels < 1) return FC2T2_EINVAL;
   if (!fc2t2_supported(dim, K)) return FC2T2_EUNSUPPORTED;
   if (io != FC2T2_IO_F32 && io != FC2T2_IO_F64) return FC2T2_EINVAL;
-  if (m2l_prec < FC2T2_M2L_F64 || m2l_prec > FC2T2_M2L_BF16X3) return FC2T2_EINVAL;
-  if ((io == FC2T2_IO_F64) != (m2l_prec == FC2T2_M2L_F64)) return FC2T2_EUNSUPPORTED;
+  if (m2l_prec < FC2T2_M2L_F64 || m2l_prec > FC2T2_M2L_SEPARABLE) return FC2T2_EINVAL;
+  if (m2l_prec != FC2T2_M2L_SEPARABLE && (io == FC2T2_IO_F64) != (m2l_prec == FC2T2_M2L_F64))
+    return FC2T2_EUNSUPPORTED;
+  if (m2l_prec == FC2T2_M2L_SEPARABLE && kernel->kind != FC2T2_GAUSSIAN) return FC2T2_EUNSUPPORTED;
   if (kernel->kind == FC2T2_GAUSSIAN || kernel->kind == FC2T2_IMQ) {
     if (!(kernel->param > 0.0) || !isfinite(kernel->param)) return FC2T2_EINVAL;
   } else if (kernel->kind == FC2T2_POLY) {
@@ -276,6 +278,8 @@ fc2t2_status fc2t2_plan_create(const fc2t2_grid* grid, const fc2t2_kernel* kerne
     if (pl->m2l_T) (void)hipFree(pl->m2l_T);
     if (pl->m2l_bf16) (void)hipFree(pl->m2l_bf16);
     if (pl->shift) (void)hipFree(pl->shift);
+    if (pl->cell_bounds) (void)hipFree(pl->cell_bounds);
+    sep_destroy(pl);
     delete pl;
     return st;
   };
@@ -350,7 +354,11 @@ fc2t2_status fc2t2_plan_create(const fc2t2_grid* grid, const fc2t2_kernel* kerne
     if (st != FC2T2_OK) return fail(st);
   }
   // ---- MFMA operand tables
-  if (m2l_prec >= FC2T2_M2L_BF16) {
+  if (m2l_prec == FC2T2_M2L_SEPARABLE) {
+    const fc2t2_status st = sep_build(pl, stream);
+    if (st != FC2T2_OK) return fail(st);
+  }
+  if (m2l_prec >= FC2T2_M2L_BF16 && m2l_prec <= FC2T2_M2L_BF16X3) {
     if (!m2l_mfma_supported(pl)) return fail(FC2T2_EUNSUPPORTED);
     const fc2t2_status st = m2l_mfma_build_tables(pl, stream);
     if (st != FC2T2_OK) return fail(st);
@@ -371,6 +379,7 @@ fc2t2_status fc2t2_plan_destroy(fc2t2_plan plan) {
   if (plan->m2l_bf16) (void)hipFree(plan->m2l_bf16);
   if (plan->shift) (void)hipFree(plan->shift);
   if (plan->cell_bounds) (void)hipFree(plan->cell_bounds);
+  sep_destroy(plan);
   stage_timer_destroy(plan);
   delete plan;
   return FC2T2_OK;

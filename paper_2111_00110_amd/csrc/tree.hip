@@ -617,7 +617,7 @@ fc2t2_status downshift_pyramid(const fc2t2_plan_s* pl, void* const* grids, hipSt
 
 fc2t2_status launch_m2l(const fc2t2_plan_s* pl, int lvl, const void* M, void* L, bool accumulate,
                         hipStream_t s) {
-  if (pl->prec >= FC2T2_M2L_BF16) {
+  if (m2l_is_mfma(pl)) {
     const void* ins[kMaxLevels] = {};
     void* outs[kMaxLevels] = {};
     ins[lvl] = M;
@@ -644,7 +644,7 @@ fc2t2_status launch_m2l(const fc2t2_plan_s* pl, int lvl, const void* M, void* L,
 
 fc2t2_status launch_m2l_T(const fc2t2_plan_s* pl, int lvl, const void* GL, void* GM, bool accumulate,
                           hipStream_t s) {
-  if (pl->prec >= FC2T2_M2L_BF16) {
+  if (m2l_is_mfma(pl)) {
     const void* ins[kMaxLevels] = {};
     void* outs[kMaxLevels] = {};
     ins[lvl] = GL;
@@ -670,9 +670,10 @@ fc2t2_status launch_m2l_T(const fc2t2_plan_s* pl, int lvl, const void* GL, void*
 }
 
 fc2t2_status launch_m2l_all(const fc2t2_plan_s* pl, const void* const* ins, void* const* outs, bool transpose,
-                            hipStream_t s, const uint8_t* const* occ, uint8_t gen) {
-  if (pl->prec >= FC2T2_M2L_BF16)
+                            hipStream_t s, const uint8_t* const* occ, uint8_t gen, void* sep_ws) {
+  if (m2l_is_mfma(pl))
     return launch_m2l_mfma(pl, 0, pl->levels, ins, outs, false, transpose, s, occ, gen);
+  if (pl->prec == FC2T2_M2L_SEPARABLE) return launch_m2l_separable(pl, ins, outs, transpose, sep_ws, s);
   for (int l = 0; l < pl->levels; ++l) {
     const fc2t2_status st = transpose ? launch_m2l_T(pl, l, ins[l], outs[l], false, s)
                                       : launch_m2l(pl, l, ins[l], outs[l], false, s);

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfc2t2.so")
 
 KERNELS = {"gaussian": 0, "imq": 1, "poly": 2}
-M2L_PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x2": 3, "bf16x3": 4}
+M2L_PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x2": 3, "bf16x3": 4, "separable": 5}
 IO = {"f32": 0, "f64": 1}
 OP = {"expand": 0, "eval_backward": 1, "expand_backward": 2, "ray_integral_backward": 3,
       "ray_root_backward": 4}

@@ -65,3 +65,23 @@ def test_stage_bytes_formula():
     # writes one 112-byte row (plus a 4-byte start) per cell
     assert A.stage_bytes("p2m", 2, 256, 6, N=1 << 20) == (1 << 20) * 12 + 65536 * (4 + 112)
     assert A.stage_bytes("l2p", 2, 256, 6, M=1 << 20) == (1 << 20) * 12 + 65536 * 112
+
+
+def test_separable_pass_entries_closed_forms():
+    """2-D: the first pass maps S0 onto the full square, sum over n_x of (K + 1 - n_x) inputs
+    times K + 1 outputs; the second maps the square back onto S0, P inputs-times-outputs pairs
+    of K + 1.  Both are (K + 1)^2 (K + 2) / 2.  3-D passes are symmetric in the first and last."""
+    for K in range(1, 7):
+        e = A.sep_pass_entries(2, K)
+        assert e == [(K + 1) ** 2 * (K + 2) // 2] * 2
+        assert e[1] == A.n_terms(2, K) * (K + 1)
+    for K in range(1, 6):
+        e = A.sep_pass_entries(3, K)
+        assert e[0] == e[2] == A.n_terms(3, K) * (K + 1)
+        # middle pass: (k_x, n_z) groups, (K + 1 - n_z) inputs x (K + 1 - k_x) outputs
+        assert e[1] == ((K + 1) * (K + 2) // 2) ** 2
+
+
+def test_separable_flops_far_below_dense():
+    assert A.m2l_flops_separable(2, 256, 6) * 9 < A.m2l_flops(2, 256, 6)
+    assert A.m2l_flops_separable(3, 64, 5) * 80 < A.m2l_flops(3, 64, 5)

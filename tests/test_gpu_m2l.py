@@ -127,3 +127,61 @@ def test_clustered_sources_skip_empty_tiles(F, dim, n, K):
         tol = 3e-5 if i < 2 else 5e-5
         assert rel(got[i], ref[i]) < tol, name
         assert rel(got[i], dense[i]) < tol, name
+
+
+@pytest.mark.parametrize("dim,n,K,param", [(2, 64, 6, 0.01), (2, 16, 4, 0.05), (3, 16, 4, 0.05), (3, 32, 5, 0.03)])
+def test_separable_gaussian_m2l(F, dim, n, K, param):
+    """The separable M2L (one 1-D pass per dimension, window minus hole as two chains): FP64 IO
+    against the step-by-step checker at 1e-12; FP32 IO against the plain FP32 contraction."""
+    rng = np.random.default_rng(17 * n + K)
+    lo, hi = (0.0, 1.0) if dim == 2 else (-1.0, 1.0)
+    N, M = 3000, 2000
+    p = rng.uniform(lo, hi, (N, dim))
+    q = rng.uniform(lo, hi, (M, dim))
+    w = rng.standard_normal((N, 1))
+    gy = rng.standard_normal((M, 1))
+    wl = W.Workload("sep", dim, n, lo, hi, K, "gaussian", param, N, M, 0, "f64", "explicit", "uniform")
+    ref = fmm.explicit_forward_backward(oracle_geometry(wl), oracle_kernel(wl), p, w, q, gy)
+
+    def run(prec, io):
+        dt = np.float64 if io == "f64" else np.float32
+        d = {k: torch.from_numpy(np.ascontiguousarray(v.astype(dt))).cuda() for k, v in
+             dict(p=p, q=q, w=w, gy=gy).items()}
+        plan = F.Plan(dim, n, lo, hi, "gaussian", param, K, m2l=prec, io=io)
+        Lt = plan.expand(d["p"], d["w"])
+        y, _, _ = plan.eval(Lt, d["q"])
+        gL = plan.new_local()
+        gq = torch.zeros_like(d["q"])
+        plan.eval_backward(Lt, d["q"], d["gy"], gL, gq)
+        gp = torch.zeros_like(d["p"])
+        gw = torch.zeros_like(d["w"])
+        plan.expand_backward(gL, d["p"], d["w"], gp, gw)
+        torch.cuda.synchronize()
+        return [t.cpu().numpy().astype(np.float64) for t in (Lt, y, gw, gp, gq)]
+
+    s64 = run("separable", "f64")
+    for i, name in enumerate(("y", "w_bar", "p_bar", "q_bar")):
+        assert rel(s64[i + 1], ref[i]) < 1e-12, name
+    s32, d32 = run("separable", "f32"), run("f32", "f32")
+    assert rel(s32[0], d32[0]) < 1e-5
+    for i, name in enumerate(("y", "w_bar", "p_bar", "q_bar")):
+        assert rel(s32[i + 1], d32[i + 1]) < (1e-5 if i < 2 else 1e-4), name
+
+
+def test_separable_two_channels_matches_dense(F):
+    """Channel offsets of the separable passes: two channels against the plain FP32 contraction."""
+    rng = np.random.default_rng(5)
+    p = torch.from_numpy(rng.uniform(-1, 1, (4000, 3)).astype(np.float32)).cuda()
+    w = torch.from_numpy(rng.standard_normal((4000, 2)).astype(np.float32)).cuda()
+    out = {}
+    for prec in ("separable", "f32"):
+        plan = F.Plan(3, 16, -1.0, 1.0, "gaussian", 0.08, 3, m2l=prec, io="f32", channels=2)
+        L = plan.expand(p, w)
+        g = torch.from_numpy(rng.standard_normal(tuple(L.shape)).astype(np.float32)).cuda() if prec == "separable" else g
+        g[..., plan.P:] = 0
+        gp, gw = torch.zeros_like(p), torch.zeros_like(w)
+        plan.expand_backward(g.clone(), p, w, gp, gw)
+        torch.cuda.synchronize()
+        out[prec] = [t.cpu().numpy() for t in (L, gw, gp)]
+    for a, b in zip(out["separable"], out["f32"]):
+        assert rel(a, b) < 1e-5

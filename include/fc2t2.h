@@ -71,9 +71,9 @@ typedef enum {
   FC2T2_M2L_BF16X2 = 3,    /* BF16 MFMA, tensor split hi/lo: two passes */
   FC2T2_M2L_BF16X3 = 4,    /* BF16 MFMA, moments and tensor split hi/lo: three passes */
   FC2T2_M2L_SEPARABLE = 5  /* Gaussian kernels only (section 3.4.1): the tensor factors over the
-                              dimensions and M2L runs as one 1-D pass per dimension (window minus
-                              hole as two chains), in the IO precision; fc2t2_m2l then uses the
-                              plain contraction */
+                              dimensions and M2L runs as one 1-D pass per dimension, the admissible
+                              offsets split into disjoint per-axis products (two streams per pass),
+                              in the IO precision; fc2t2_m2l then uses the plain contraction */
 } fc2t2_m2l_prec;
 
 typedef enum { FC2T2_IO_F32 = 0, FC2T2_IO_F64 = 1 } fc2t2_io;

@@ -23,6 +23,13 @@ Readings taken where the paper is silent or inconsistent (each is listed in DESI
 * Cell index: i = clamp(floor((x - lo) * (n / (hi - lo))), 0, n - 1) evaluated in the IO
   precision with one rounding per operation, so points on or near a face land in the same
   cell on every implementation.
+* Least-squares tensors (section 3.1, ``Geometry.fit = "lsq"``): the paper fits polynomials
+  to the kernel and its derivatives for a given radius and order without saying over what
+  region or with which samples.  Reading: for each k, T[k, :] are the coefficients of the
+  polynomial sum_{|n| <= K} c_n x^n / n! closest in L2 over the source cell
+  (x in [-h/2, h/2]^d) to d^k psi(delta - x); the integral is taken by tensor
+  Gauss-Legendre quadrature with K + 2 nodes per dimension.  Parity unpinned against the
+  paper (it gives no numbers); pinned by exactness on polynomial kernels.
 
 Arrays: a grid quantity at level l has shape (C, n_l, ..., n_l, P) with dimension 0 the
 slowest; P = C(K + d, d) multi-indices in graded order (total degree, then the first
@@ -76,6 +83,7 @@ class Geometry:
     hi: float
     K: int
     io: type = np.float64   # precision in which cell indices are computed
+    fit: str = "taylor"     # M2L tensor: "taylor" (derivatives) or "lsq" (section 3.1 fit)
 
     def __post_init__(self):
         if self.n < 4 or (self.n & (self.n - 1)):
@@ -201,9 +209,14 @@ def m2l_tensor(kernel: Kernel, geo: Geometry, level: int, o: Sequence[int],
     """T[k, n] = (-1)^|n| d^(k+n) psi(c_target - c_source), with c_target - c_source =
     -o * h_level for o = j - i.  Memoised on the kernel object."""
     cache = kernel.__dict__.setdefault("_m2l_cache", {})
-    key = (geo.dim, geo.n, geo.lo, geo.hi, geo.K, level, tuple(o), triangular)
+    key = (geo.dim, geo.n, geo.lo, geo.hi, geo.K, geo.fit, level, tuple(o), triangular)
     if key not in cache:
-        cache[key] = _m2l_tensor(kernel, geo, level, o, triangular)
+        if geo.fit == "lsq":
+            if triangular:
+                raise ValueError("the least-squares tensor uses the square set")
+            cache[key] = _m2l_tensor_lsq(kernel, geo, level, o)
+        else:
+            cache[key] = _m2l_tensor(kernel, geo, level, o, triangular)
     return cache[key]
 
 
@@ -221,6 +234,33 @@ def _m2l_tensor(kernel, geo, level, o, triangular):
             g = tuple(x + y for x, y in zip(k, n))
             T[a, b] = (-1.0) ** sum(n) * D[g]
     return T
+
+
+def lsq_nodes(geo: Geometry, level: int):
+    """Tensor Gauss-Legendre nodes [J, d] and weights [J] on the source cell [-h/2, h/2]^d,
+    K + 2 nodes per dimension."""
+    h = geo.h(level)
+    t, wq = np.polynomial.legendre.leggauss(geo.K + 2)
+    X = np.array(list(itertools.product(0.5 * h * t, repeat=geo.dim)))
+    W = np.prod(np.array(list(itertools.product(0.5 * h * wq, repeat=geo.dim))), axis=1)
+    return X, W
+
+
+def _m2l_tensor_lsq(kernel, geo, level, o):
+    """Section 3.1: T[k, n] = c_n of the weighted least-squares polynomial
+    sum_n c_n x^n / n! fitted to d^k psi(delta - x) over the source cell, delta = -o h."""
+    X, W = lsq_nodes(geo, level)
+    h = geo.h(level)
+    delta = -np.asarray(o, dtype=np.float64) * h
+    G = kernel.derivs(delta[None, :] - X, geo.idx)          # [J, P(k)]
+    # solved in t = 2 x / h in [-1, 1] with the basis t^n (well conditioned), then
+    # sum_n c_t[n] t^n = sum_n c_t[n] (2/h)^|n| n! x^n / n!
+    Tn = X * (2.0 / h)
+    Vt = np.stack([np.prod(Tn ** np.asarray(a, dtype=np.float64), axis=1) for a in geo.idx], axis=1)
+    sw = np.sqrt(W)[:, None]
+    Ct = np.linalg.lstsq(sw * Vt, sw * G, rcond=None)[0]     # [P(n), P(k)]
+    scale = np.array([(2.0 / h) ** sum(a) * ifact(a) for a in geo.idx])
+    return (Ct * scale[:, None]).T
 
 
 def _pad3(A: np.ndarray, d: int) -> np.ndarray:

@@ -43,6 +43,10 @@ def parse():
                     help="f32 | bf16 | bf16x2 | bf16x3 | separable (Gaussian kernels only)")
     ap.add_argument("--compare-f32", type=int, default=1,
                     help="also time the same step with the plain FP32 M2L (same accuracy class)")
+    ap.add_argument("--fit", default="taylor", help="M2L tensor: taylor | lsq (least-squares fit)")
+    ap.add_argument("--compare-fit", type=int, default=1,
+                    help="explicit layers: also report the error of the other M2L tensor fit "
+                         "against the same direct-sum sample")
     ap.add_argument("--compare-separable", type=int, default=1,
                     help="Gaussian kernels: also time the same step with the separable M2L")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -116,8 +120,9 @@ def main():
     x = workloads.make(wl, seed=0)
     dev = torch.device("cuda", 0)
     t = {k: torch.from_numpy(v).to(dev) for k, v in x.items()}
-    def make_plan(m2l):
-        return fc2t2.Plan(wl.dim, wl.n, wl.lo, wl.hi, wl.kernel, wl.param, wl.K, m2l=m2l, io=wl.io)
+    def make_plan(m2l, fit=None):
+        return fc2t2.Plan(wl.dim, wl.n, wl.lo, wl.hi, wl.kernel, wl.param, wl.K, m2l=m2l, io=wl.io,
+                          fit=fit or args.fit)
 
     p, w = t["p"], t["w"]
     q, gy = t.get("q"), t.get("gy")
@@ -297,7 +302,7 @@ def main():
         "data": "synthetic (seeded %s sources, Gaussian weights)" % wl.sources,
         "config": {"workload": wl.name, "dim": wl.dim, "N": wl.N, "M": wl.M, "R": wl.R,
                    "grid": "%d^%d" % (wl.n, wl.dim), "K": wl.K, "kernel": "%s %g" % (wl.kernel, wl.param),
-                   "m2l": args.m2l, "outputs": outputs},
+                   "m2l": args.m2l, "fit": args.fit, "outputs": outputs},
         "roofline": roofline,
         ("m2l_separable" if separable else "m2l_mfma"): {"forward": m2l_line("m2l"),
                                                          "transpose": m2l_line("m2l_T")},
@@ -331,6 +336,17 @@ def main():
                                          "per-query gradient terms (q_bar and the w_bar/p_bar contributions); "
                                          "%.1f s" % (len(idx), wl.N, cpu_s)}
         out["rel_l2_vs_direct"] = err
+        if args.compare_fit and args.m2l != "separable":
+            other = "lsq" if args.fit == "taylor" else "taylor"
+            t0 = time.perf_counter()
+            plan_o = make_plan(args.m2l, other)
+            torch.cuda.synchronize()
+            plan_o_ms = (time.perf_counter() - t0) * 1e3
+            y_o, _, _ = plan_o.eval(plan_o.expand(p, w), q)
+            yo = y_o.detach().cpu().numpy()[idx]
+            out["fit_comparison"] = {"fit": other, "rel_l2_vs_direct": float(np.linalg.norm(yo - yd) / np.linalg.norm(yd)),
+                                     "plan_ms": round(plan_o_ms, 1),
+                                     "note": "same kernels and step time; only the plan's M2L tensor differs"}
     print(json.dumps(out), flush=True)
 
 

@@ -70,10 +70,17 @@ typedef enum {
   FC2T2_M2L_BF16 = 2,      /* BF16 MFMA, FP32 accumulation, one pass */
   FC2T2_M2L_BF16X2 = 3,    /* BF16 MFMA, tensor split hi/lo: two passes */
   FC2T2_M2L_BF16X3 = 4,    /* BF16 MFMA, moments and tensor split hi/lo: three passes */
-  FC2T2_M2L_SEPARABLE = 5  /* Gaussian kernels only (section 3.4.1): the tensor factors over the
+  FC2T2_M2L_SEPARABLE = 5, /* Gaussian kernels only (section 3.4.1): the tensor factors over the
                               dimensions and M2L runs as one 1-D pass per dimension, the admissible
                               offsets split into disjoint per-axis products (two streams per pass),
                               in the IO precision; fc2t2_m2l then uses the plain contraction */
+  FC2T2_M2L_FIT_LSQ = 0x100  /* flag OR'ed with a precision other than SEPARABLE (section 3.1):
+                                each row k of the M2L tensor is the least-squares polynomial
+                                fit, over the source cell, of the k-th derivative of the
+                                kernel around the target centre instead of its Taylor
+                                coefficients; L2 over the cell by tensor Gauss-Legendre
+                                quadrature with K + 2 nodes per dimension.  Plan time only:
+                                every later call runs the same kernels */
 } fc2t2_m2l_prec;
 
 typedef enum { FC2T2_IO_F32 = 0, FC2T2_IO_F64 = 1 } fc2t2_io;

@@ -10,6 +10,7 @@ struct SepTables;
 
 struct fc2t2_plan_s {
   int dim, n, K, P, Ppad, C, levels, io, prec, kind;
+  bool fit_lsq = false;            // M2L tensors fitted by least squares (section 3.1)
   double lo, hi, param;
   double h0;                      // finest cell width
   int64_t G;                      // finest cells

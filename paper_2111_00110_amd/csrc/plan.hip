@@ -59,26 +59,9 @@ __device__ double radial_deriv(int kind, double param, double u, int m) {
   return c * pow(base, -0.5 - m);
 }
 
-// One thread per (level, offset, derivative multi-index g): D[lvl][o][g] = d^g psi(-o h_lvl).
-__global__ void derivs_kernel(int dim, int kind, double param, const double* __restrict__ coef,
-                              const int* __restrict__ coef_exps, int n_coef,
-                              const int* __restrict__ g_exps, int n_g, int levels,
-                              const double* __restrict__ hl, int n_off, double* __restrict__ D) {
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)levels * n_off * n_g;
-  if (tid >= total) return;
-  const int gi = (int)(tid % n_g);
-  const int oi = (int)((tid / n_g) % n_off);
-  const int lvl = (int)(tid / ((int64_t)n_g * n_off));
-  int o[3] = {0, 0, 0};
-  {
-    int r = oi;
-    for (int j = dim - 1; j >= 0; --j) { o[j] = r % 7 - 3; r /= 7; }
-  }
-  const double h = hl[lvl];
-  double x[3] = {0.0, 0.0, 0.0};
-  for (int j = 0; j < dim; ++j) x[j] = -o[j] * h;
-  const int g[3] = {g_exps[3 * gi], g_exps[3 * gi + 1], g_exps[3 * gi + 2]};
+// d^g psi(x) for the plan's kernel.
+__device__ double psi_deriv(int kind, double param, const double* __restrict__ coef,
+                            const int* __restrict__ coef_exps, int n_coef, const int (&g)[3], const double (&x)[3]) {
   double val = 0.0;
   if (kind == FC2T2_POLY) {
     for (int a = 0; a < n_coef; ++a) {
@@ -90,23 +73,90 @@ __global__ void derivs_kernel(int dim, int kind, double param, const double* __r
       term *= dfact(e2) / dfact(e2 - g[2]) * ipow(x[2], e2 - g[2]);
       val += term;
     }
-  } else {
-    const double u = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-    // j_i ranges over [ceil(g_i/2), g_i]
-    const int lo0 = (g[0] + 1) / 2, lo1 = (g[1] + 1) / 2, lo2 = (g[2] + 1) / 2;
-    for (int j0 = lo0; j0 <= g[0]; ++j0) {
-      const double f0 = dbinom(j0, g[0] - j0) * ipow(2.0 * x[0], 2 * j0 - g[0]) / dfact(j0);
-      for (int j1 = lo1; j1 <= g[1]; ++j1) {
-        const double f1 = dbinom(j1, g[1] - j1) * ipow(2.0 * x[1], 2 * j1 - g[1]) / dfact(j1);
-        for (int j2 = lo2; j2 <= g[2]; ++j2) {
-          const double f2 = dbinom(j2, g[2] - j2) * ipow(2.0 * x[2], 2 * j2 - g[2]) / dfact(j2);
-          val += radial_deriv(kind, param, u, j0 + j1 + j2) * f0 * f1 * f2;
-        }
+    return val;
+  }
+  const double u = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+  // j_i ranges over [ceil(g_i/2), g_i]
+  const int lo0 = (g[0] + 1) / 2, lo1 = (g[1] + 1) / 2, lo2 = (g[2] + 1) / 2;
+  for (int j0 = lo0; j0 <= g[0]; ++j0) {
+    const double f0 = dbinom(j0, g[0] - j0) * ipow(2.0 * x[0], 2 * j0 - g[0]) / dfact(j0);
+    for (int j1 = lo1; j1 <= g[1]; ++j1) {
+      const double f1 = dbinom(j1, g[1] - j1) * ipow(2.0 * x[1], 2 * j1 - g[1]) / dfact(j1);
+      for (int j2 = lo2; j2 <= g[2]; ++j2) {
+        const double f2 = dbinom(j2, g[2] - j2) * ipow(2.0 * x[2], 2 * j2 - g[2]) / dfact(j2);
+        val += radial_deriv(kind, param, u, j0 + j1 + j2) * f0 * f1 * f2;
       }
     }
-    val *= dfact(g[0]) * dfact(g[1]) * dfact(g[2]);
   }
-  D[tid] = val;
+  return val * dfact(g[0]) * dfact(g[1]) * dfact(g[2]);
+}
+
+__device__ __forceinline__ void offset_of(int dim, int oi, int (&o)[3]) {
+  o[0] = o[1] = o[2] = 0;
+  int r = oi;
+  for (int j = dim - 1; j >= 0; --j) { o[j] = r % 7 - 3; r /= 7; }
+}
+
+// One thread per (level, offset, derivative multi-index g): D[lvl][o][g] = d^g psi(-o h_lvl).
+__global__ void derivs_kernel(int dim, int kind, double param, const double* __restrict__ coef,
+                              const int* __restrict__ coef_exps, int n_coef,
+                              const int* __restrict__ g_exps, int n_g, int levels,
+                              const double* __restrict__ hl, int n_off, double* __restrict__ D) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)levels * n_off * n_g;
+  if (tid >= total) return;
+  const int gi = (int)(tid % n_g);
+  const int oi = (int)((tid / n_g) % n_off);
+  const int lvl = (int)(tid / ((int64_t)n_g * n_off));
+  int o[3];
+  offset_of(dim, oi, o);
+  const double h = hl[lvl];
+  double x[3] = {0.0, 0.0, 0.0};
+  for (int j = 0; j < dim; ++j) x[j] = -o[j] * h;
+  const int g[3] = {g_exps[3 * gi], g_exps[3 * gi + 1], g_exps[3 * gi + 2]};
+  D[tid] = psi_deriv(kind, param, coef, coef_exps, n_coef, g, x);
+}
+
+// ---------------------------------------------------------------------------------------
+// Least-squares M2L tensors (section 3.1).  In cell-scaled units the row k of the tensor is the
+// coefficient vector c of the polynomial sum_{|n| <= K} c_n u^n / n! closest in L2 over the
+// source cell u in [-1/2, 1/2]^d to h^|k| d^k psi(-o h - u h); the integral is tensor
+// Gauss-Legendre quadrature (K + 2 nodes per dimension), so c = Pi f with the P x J matrix Pi
+// built on the host from the nodes and weights.
+
+// F[o][j][k] = h^|k| d^k psi(-o h - u_j h) for one level; u [J][3].
+__global__ void lsq_values_kernel(int dim, int kind, double param, const double* __restrict__ coef,
+                                  const int* __restrict__ coef_exps, int n_coef,
+                                  const int* __restrict__ k_exps, int P, const double* __restrict__ u, int J,
+                                  double h, int n_off, double* __restrict__ F) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (int64_t)n_off * J * P) return;
+  const int k = (int)(tid % P);
+  const int j = (int)((tid / P) % J);
+  const int oi = (int)(tid / ((int64_t)P * J));
+  int o[3];
+  offset_of(dim, oi, o);
+  double x[3] = {0.0, 0.0, 0.0};
+  for (int d = 0; d < dim; ++d) x[d] = (-o[d] - u[3 * j + d]) * h;
+  const int g[3] = {k_exps[3 * k], k_exps[3 * k + 1], k_exps[3 * k + 2]};
+  F[tid] = ipow(h, g[0] + g[1] + g[2]) * psi_deriv(kind, param, coef, coef_exps, n_coef, g, x);
+}
+
+// T[lvl][o][n][k] = sum_j Pi[n][j] F[o][j][k] for one level (zero for k >= P).
+template <typename T>
+__global__ void lsq_project_kernel(int P, int Ppad, int J, int n_off, const double* __restrict__ Pi,
+                                   const double* __restrict__ F, T* __restrict__ out) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (int64_t)n_off * P * Ppad) return;
+  const int k = (int)(tid % Ppad);
+  const int n = (int)((tid / Ppad) % P);
+  const int oi = (int)(tid / ((int64_t)Ppad * P));
+  if (k >= P) { out[tid] = T(0); return; }
+  const double* f = F + (int64_t)oi * J * P + k;
+  const double* pr = Pi + (int64_t)n * J;
+  double acc = 0.0;
+  for (int j = 0; j < J; ++j) acc += pr[j] * f[(int64_t)j * P];
+  out[tid] = (T)acc;
 }
 
 // T[lvl][o][n][k] = h^(|k|+|n|) (-1)^|n| D[lvl][o][pos(k+n)], zero for k >= P.
@@ -131,6 +181,123 @@ __global__ void pack_m2l_kernel(int dim, int K, int P, int Ppad, int levels, int
   v *= ipow(hl[lvl], dk + dn);
   if (dn & 1) v = -v;
   out[tid] = (T)v;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1]: Newton's method on P_Q from the usual cosine
+// guesses, P_Q by the three-term recurrence.
+void gauss_legendre(int Q, std::vector<double>& t, std::vector<double>& w) {
+  t.assign(Q, 0.0);
+  w.assign(Q, 0.0);
+  for (int i = 0; i < Q; ++i) {
+    double x = cos(M_PI * (i + 0.75) / (Q + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= Q; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = Q * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (fabs(dx) <= 1e-16) {
+        // derivative at the converged node for the weight
+        p0 = 1.0;
+        p1 = x;
+        for (int k = 2; k <= Q; ++k) {
+          const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        dp = Q * (x * p1 - p0) / (x * x - 1.0);
+        break;
+      }
+    }
+    t[i] = x;
+    w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+}
+
+// Weighted least-squares projection for the fitted tensors: nodes u [J][3] (cell units, tensor
+// Gauss-Legendre with K + 2 nodes per dimension on [-1/2, 1/2]) and Pi [P][J] with
+// c = Pi f the coefficients of sum_n c_n u^n / n! fitting values f at the nodes.  The fit is
+// solved in t = 2u with the basis t^n (Householder QR of sqrt(w) t^n), then rescaled:
+// c_n = 2^|n| n! c_t[n].
+bool lsq_projection(int dim, int K, const std::vector<int>& k_exps, std::vector<double>& u, std::vector<double>& Pi,
+                    int& J) {
+  const int Q = K + 2, P = nterms(dim, K);
+  std::vector<double> t1, w1;
+  gauss_legendre(Q, t1, w1);
+  J = 1;
+  for (int d = 0; d < dim; ++d) J *= Q;
+  u.assign((size_t)J * 3, 0.0);
+  std::vector<double> sw(J), A((size_t)J * P);   // A column-major: A[c * J + j]
+  for (int j = 0; j < J; ++j) {
+    int r = j;
+    double wt = 1.0, tj[3] = {0.0, 0.0, 0.0};
+    for (int d = dim - 1; d >= 0; --d) {
+      const int q = r % Q;
+      r /= Q;
+      tj[d] = t1[q];
+      wt *= w1[q];
+    }
+    for (int d = 0; d < dim; ++d) u[3 * j + d] = 0.5 * tj[d];
+    sw[j] = sqrt(wt);
+    for (int c = 0; c < P; ++c) {
+      double m = sw[j];
+      for (int d = 0; d < dim; ++d)
+        for (int e = 0; e < k_exps[3 * c + d]; ++e) m *= tj[d];
+      A[(size_t)c * J + j] = m;
+    }
+  }
+  // Householder QR: reflectors v_c (stored below the diagonal of A with beta), R on and above it
+  std::vector<double> beta(P), diag(P);
+  for (int c = 0; c < P; ++c) {
+    double* a = &A[(size_t)c * J];
+    double norm = 0.0;
+    for (int j = c; j < J; ++j) norm += a[j] * a[j];
+    norm = sqrt(norm);
+    if (!(norm > 0.0)) return false;
+    const double alpha = a[c] > 0.0 ? -norm : norm;
+    a[c] -= alpha;                     // v = a - alpha e_c, stored in place
+    double vv = 0.0;
+    for (int j = c; j < J; ++j) vv += a[j] * a[j];
+    beta[c] = vv > 0.0 ? 2.0 / vv : 0.0;
+    diag[c] = alpha;
+    for (int c2 = c + 1; c2 < P; ++c2) {
+      double* b = &A[(size_t)c2 * J];
+      double dot = 0.0;
+      for (int j = c; j < J; ++j) dot += a[j] * b[j];
+      dot *= beta[c];
+      for (int j = c; j < J; ++j) b[j] -= dot * a[j];
+    }
+  }
+  // column j of Pi_t = R^-1 (Q^T sqrt(w_j) e_j)_{0..P-1}
+  Pi.assign((size_t)P * J, 0.0);
+  std::vector<double> y(J);
+  for (int j = 0; j < J; ++j) {
+    std::fill(y.begin(), y.end(), 0.0);
+    y[j] = sw[j];
+    for (int c = 0; c < P; ++c) {
+      const double* a = &A[(size_t)c * J];
+      double dot = 0.0;
+      for (int i = c; i < J; ++i) dot += a[i] * y[i];
+      dot *= beta[c];
+      for (int i = c; i < J; ++i) y[i] -= dot * a[i];
+    }
+    for (int c = P - 1; c >= 0; --c) {
+      double v = y[c];
+      for (int c2 = c + 1; c2 < P; ++c2) v -= A[(size_t)c2 * J + c] * Pi[(size_t)c2 * J + j];
+      Pi[(size_t)c * J + j] = v / diag[c];
+    }
+  }
+  for (int c = 0; c < P; ++c) {
+    double sc = 1.0;
+    for (int d = 0; d < dim; ++d)
+      for (int e = 1; e <= k_exps[3 * c + d]; ++e) sc *= 2.0 * e;
+    for (int j = 0; j < J; ++j) Pi[(size_t)c * J + j] *= sc;
+  }
+  return true;
 }
 
 struct DevFree {
@@ -229,6 +396,9 @@ fc2t2_status fc2t2_plan_create(const fc2t2_grid* grid, const fc2t2_kernel* kerne
   if (K < 1 || channels < 1) return FC2T2_EINVAL;
   if (!fc2t2_supported(dim, K)) return FC2T2_EUNSUPPORTED;
   if (io != FC2T2_IO_F32 && io != FC2T2_IO_F64) return FC2T2_EINVAL;
+  const bool fit_lsq = (m2l_prec & FC2T2_M2L_FIT_LSQ) != 0;
+  m2l_prec &= ~FC2T2_M2L_FIT_LSQ;
+  if (fit_lsq && m2l_prec == FC2T2_M2L_SEPARABLE) return FC2T2_EUNSUPPORTED;   // the fit is not a product
   if (m2l_prec < FC2T2_M2L_F64 || m2l_prec > FC2T2_M2L_SEPARABLE) return FC2T2_EINVAL;
   if (m2l_prec != FC2T2_M2L_SEPARABLE && (io == FC2T2_IO_F64) != (m2l_prec == FC2T2_M2L_F64))
     return FC2T2_EUNSUPPORTED;
@@ -258,6 +428,7 @@ fc2t2_status fc2t2_plan_create(const fc2t2_grid* grid, const fc2t2_kernel* kerne
   pl->C = channels;
   pl->io = io;
   pl->prec = m2l_prec;
+  pl->fit_lsq = fit_lsq;
   pl->kind = kernel->kind;
   pl->lo = grid->lo;
   pl->hi = grid->hi;
@@ -324,20 +495,20 @@ fc2t2_status fc2t2_plan_create(const fc2t2_grid* grid, const fc2t2_kernel* kerne
     return fail(FC2T2_EHIP);
   if (n_coef && hipMemcpyAsync(dcoef, kernel->coef, n_coef * sizeof(double), hipMemcpyHostToDevice, stream) != hipSuccess)
     return fail(FC2T2_EHIP);
-  {
-    const int threads = 256;
-    const int64_t blocks = ceil_div((int64_t)nD, threads);
-    hipLaunchKernelGGL(derivs_kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, dim,
-                       kernel->kind, kernel->param, dcoef, dce, n_coef, dg, n_g, levels, dh,
-                       pl->n_off, dD);
-    if (hipGetLastError() != hipSuccess) return fail(FC2T2_EHIP);
-  }
-  // ---- pack the contraction tensor (f64 for F64 plans, f32 otherwise)
   const size_t nT = (size_t)levels * pl->n_off * P * Ppad;
   const size_t tsz = io == FC2T2_IO_F64 ? 8 : 4;
   if (hipMalloc(&pl->m2l_T, nT * tsz) != hipSuccess) { pl->m2l_T = nullptr; return fail(FC2T2_ENOMEM); }
   pl->m2l_T_bytes = nT * tsz;
-  {
+  if (!fit_lsq) {
+    {
+      const int threads = 256;
+      const int64_t blocks = ceil_div((int64_t)nD, threads);
+      hipLaunchKernelGGL(derivs_kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, dim,
+                         kernel->kind, kernel->param, dcoef, dce, n_coef, dg, n_g, levels, dh,
+                         pl->n_off, dD);
+      if (hipGetLastError() != hipSuccess) return fail(FC2T2_EHIP);
+    }
+    // ---- pack the contraction tensor (f64 for F64 plans, f32 otherwise)
     const int threads = 256;
     const int64_t blocks = ceil_div((int64_t)nT, threads);
     if (io == FC2T2_IO_F64)
@@ -347,6 +518,33 @@ fc2t2_status fc2t2_plan_create(const fc2t2_grid* grid, const fc2t2_kernel* kerne
       hipLaunchKernelGGL(pack_m2l_kernel<float>, dim3((unsigned)blocks), dim3(threads), 0, stream,
                          dim, K, P, Ppad, levels, pl->n_off, n_g, dh, dk, dD, (float*)pl->m2l_T);
     if (hipGetLastError() != hipSuccess) return fail(FC2T2_EHIP);
+  } else {
+    // ---- least-squares fitted tensor, one level at a time
+    std::vector<double> u, Pi;
+    int J = 0;
+    if (!lsq_projection(dim, K, k_exps, u, Pi, J)) return fail(FC2T2_EINVAL);
+    double* du = (double*)dalloc(u.size() * sizeof(double));
+    double* dPi = (double*)dalloc(Pi.size() * sizeof(double));
+    double* dF = (double*)dalloc((size_t)pl->n_off * J * P * sizeof(double));
+    if (!du || !dPi || !dF) return fail(FC2T2_ENOMEM);
+    if (hipMemcpyAsync(du, u.data(), u.size() * sizeof(double), hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(dPi, Pi.data(), Pi.size() * sizeof(double), hipMemcpyHostToDevice, stream) != hipSuccess)
+      return fail(FC2T2_EHIP);
+    const int threads = 256;
+    const size_t per_level = (size_t)pl->n_off * P * Ppad;
+    for (int l = 0; l < levels; ++l) {
+      const int64_t nv = (int64_t)pl->n_off * J * P;
+      hipLaunchKernelGGL(lsq_values_kernel, dim3((unsigned)ceil_div(nv, threads)), dim3(threads), 0, stream, dim,
+                         kernel->kind, kernel->param, dcoef, dce, n_coef, dk, P, du, J, hl[l], pl->n_off, dF);
+      const int64_t blocks = ceil_div((int64_t)per_level, threads);
+      if (io == FC2T2_IO_F64)
+        hipLaunchKernelGGL(lsq_project_kernel<double>, dim3((unsigned)blocks), dim3(threads), 0, stream, P, Ppad, J,
+                           pl->n_off, dPi, dF, (double*)pl->m2l_T + l * per_level);
+      else
+        hipLaunchKernelGGL(lsq_project_kernel<float>, dim3((unsigned)blocks), dim3(threads), 0, stream, P, Ppad, J,
+                           pl->n_off, dPi, dF, (float*)pl->m2l_T + l * per_level);
+      if (hipGetLastError() != hipSuccess) return fail(FC2T2_EHIP);
+    }
   }
   // ---- sparse M2M / L2L shift lists
   {

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libfc2t2.so")
 
 KERNELS = {"gaussian": 0, "imq": 1, "poly": 2}
 M2L_PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x2": 3, "bf16x3": 4, "separable": 5}
+FIT = {"taylor": 0, "lsq": 0x100}   # M2L tensor: derivatives, or least-squares fit (section 3.1)
 IO = {"f32": 0, "f64": 1}
 OP = {"expand": 0, "eval_backward": 1, "expand_backward": 2, "ray_integral_backward": 3,
       "ray_root_backward": 4}
@@ -132,8 +133,9 @@ class Plan:
 
     def __init__(self, dim: int, n: int, lo: float, hi: float, kernel: str, param: float = 0.0,
                  K: int = 4, m2l: str = "f32", io: str = "f32", channels: int = 1,
-                 coef: Optional[Sequence[float]] = None, device=None):
+                 coef: Optional[Sequence[float]] = None, device=None, fit: str = "taylor"):
         L = lib()
+        self.fit = fit
         self.dim, self.n, self.lo, self.hi, self.K = dim, n, float(lo), float(hi), K
         self.kernel, self.param, self.m2l_prec, self.io, self.C = kernel, float(param), m2l, io, channels
         self.dtype = torch.float64 if io == "f64" else torch.float32
@@ -147,7 +149,7 @@ class Plan:
             k = _Kernel(KERNELS[kernel], self.param, 0, None)
         out = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            _check(L.fc2t2_plan_create(ctypes.byref(g), ctypes.byref(k), K, M2L_PREC[m2l], IO[io],
+            _check(L.fc2t2_plan_create(ctypes.byref(g), ctypes.byref(k), K, M2L_PREC[m2l] | FIT[fit], IO[io],
                                        channels, _stream(), ctypes.byref(out)), "fc2t2_plan_create")
         self.handle = out
         self.P = L.fc2t2_plan_P(out)

@@ -184,3 +184,49 @@ def test_stage_timing_records_each_stage(F):
     plan.stage_timing([])
     _run_gpu(F, plan, x)
     assert plan.stage_time("m2l") == (0.0, 0)
+
+
+@pytest.mark.parametrize("case", ["2d_gauss", "3d_imq", "2d_poly"])
+def test_lsq_fitted_tensors_match_checker(F, case):
+    """Least-squares fitted M2L tensors (section 3.1), FP64 IO against the checker with the same
+    fit (the fit's normal equations limit agreement to about 1e-10), and for a polynomial kernel
+    of degree K against the Taylor plan (the fit is exact there)."""
+    coef = None
+    if case == "2d_gauss":
+        wl = W.Workload("l", 2, 32, 0.0, 1.0, 4, "gaussian", 0.02, 3000, 2000, 0, "f64", "explicit", "uniform")
+    elif case == "3d_imq":
+        wl = W.Workload("l", 3, 8, -1.0, 1.0, 3, "imq", 0.3, 1500, 1000, 0, "f64", "explicit", "uniform")
+    else:
+        wl = W.Workload("l", 2, 16, -1.0, 1.0, 4, "poly", 0.0, 700, 500, 0, "f64", "explicit", "uniform")
+        rng = np.random.default_rng(4)
+        c = {a: rng.standard_normal() for a in fmm.multi_indices(2, 4)}
+        ker_p = kernels.Polynomial(c, 2)
+        coef = poly_coef_list(ker_p, 2, 4)
+    x = W.make(wl, seed=6)
+    plan = F.Plan(wl.dim, wl.n, wl.lo, wl.hi, wl.kernel, wl.param, wl.K, m2l="f64", io="f64", coef=coef, fit="lsq")
+    got = _run_gpu(F, plan, x)
+    if case == "2d_poly":
+        ref = _run_gpu(F, _plan(F, wl, coef=coef), x)
+        for k in ("y", "gw", "gp", "gq"):
+            assert rel(got[k], ref[k]) < 1e-9, k
+        return
+    geo = fmm.Geometry(wl.dim, wl.n, wl.lo, wl.hi, wl.K, fit="lsq")
+    y, gw, gp, gq = fmm.explicit_forward_backward(geo, oracle_kernel(wl), x["p"], x["w"], x["q"], x["gy"])
+    assert rel(got["y"], y) < 1e-10
+    assert rel(got["gw"], gw) < 1e-10
+    assert rel(got["gp"], gp) < 1e-9
+    assert rel(got["gq"], gq) < 1e-9
+
+
+def test_lsq_fitted_tensors_bf16x3(F):
+    """The fitted tensors feed the MFMA tables too: BF16x3 against the checker's fitted layer."""
+    wl = W.Workload("l", 2, 64, 0.0, 1.0, 6, "gaussian", 0.01, 1 << 14, 1 << 12, 0, "f32", "explicit", "uniform")
+    x = W.make(wl, seed=8)
+    plan = F.Plan(wl.dim, wl.n, wl.lo, wl.hi, wl.kernel, wl.param, wl.K, m2l="bf16x3", io="f32", fit="lsq")
+    got = _run_gpu(F, plan, x)
+    geo = fmm.Geometry(wl.dim, wl.n, wl.lo, wl.hi, wl.K, np.float32, fit="lsq")
+    y, gw, gp, gq = fmm.explicit_forward_backward(geo, oracle_kernel(wl), x["p"], x["w"], x["q"], x["gy"])
+    assert rel(got["y"], y) < 3e-5
+    assert rel(got["gw"], gw) < 3e-5
+    assert rel(got["gp"], gp) < 5e-5
+    assert rel(got["gq"], gq) < 5e-5

@@ -139,25 +139,19 @@ def main():
         if layer == "explicit":
             gq = torch.zeros_like(q)
 
-            def step():
+            def step():   # the backward calls overwrite the gradient buffers (no fills)
                 plan.expand(p, w, out=Lt)
                 y, _, _ = plan.eval(Lt, q)
-                gL.zero_()
-                gq.zero_()
-                gp.zero_()
-                gw.zero_()
-                plan.eval_backward(Lt, q, gy, gL, gq)
-                plan.expand_backward(gL, p, w, gp, gw)
+                plan.eval_backward(Lt, q, gy, gL, gq, accumulate=False)
+                plan.expand_backward(gL, p, w, gp, gw, accumulate=False)
                 return y
         elif layer == "ray_integral":
             def step():
                 plan.expand(p, w, out=Lt)
                 y = plan.ray_integral(Lt, o, r, wl.t0, wl.t1)
                 gL.zero_()
-                gp.zero_()
-                gw.zero_()
                 plan.ray_integral_backward(o, r, wl.t0, wl.t1, gy, gL)
-                plan.expand_backward(gL, p, w, gp, gw)
+                plan.expand_backward(gL, p, w, gp, gw, accumulate=False)
                 return y
         else:
             gt, gn = t["gt"], t["gn"]
@@ -166,10 +160,8 @@ def main():
                 plan.expand(p, w, out=Lt)
                 tt, nrm, hit, saved = plan.ray_root(Lt, o, r, wl.t0, wl.t1, 0.5)
                 gL.zero_()
-                gp.zero_()
-                gw.zero_()
                 plan.ray_root_backward(saved, hit, gt, gn, gL)
-                plan.expand_backward(gL, p, w, gp, gw)
+                plan.expand_backward(gL, p, w, gp, gw, accumulate=False)
                 return tt
         return step
 

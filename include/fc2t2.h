@@ -172,6 +172,17 @@ fc2t2_status fc2t2_expand_backward(fc2t2_plan plan, const void* gL, const void* 
                                    const void* w, int64_t N, void* gp, void* gw, void* ws,
                                    size_t ws_bytes, hipStream_t stream);
 
+/* fc2t2_eval_backward and fc2t2_expand_backward with a choice: accumulate != 0 adds into
+ * gL, gq (respectively gp, gw) as the calls above do; accumulate == 0 overwrites them with
+ * the gradient (gL is zeroed when M == 0), so a caller with fresh gradient buffers needs no
+ * fill first.  Same kernels, same arguments, same workspace. */
+fc2t2_status fc2t2_eval_backward_ex(fc2t2_plan plan, const void* L, const void* q, int64_t M,
+                                    const void* gy, void* gL, void* gq, void* ws,
+                                    size_t ws_bytes, int accumulate, hipStream_t stream);
+fc2t2_status fc2t2_expand_backward_ex(fc2t2_plan plan, const void* gL, const void* p,
+                                      const void* w, int64_t N, void* gp, void* gw, void* ws,
+                                      size_t ws_bytes, int accumulate, hipStream_t stream);
+
 /* Line integral (section 6.1.1): y[r][c] = integral over t in [t0, t1] of f(o_r + t r_r),
  * f taken as zero outside the domain, computed exactly cell by cell from L (dim 3 only).
  *   o [R][3], r [R][3] (need not be unit) in; y [R][C] out. */

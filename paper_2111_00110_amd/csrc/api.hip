@@ -141,6 +141,82 @@ fc2t2_status expand_T_to_moments(const fc2t2_plan_s* pl, const void* GL0, void**
 
 }  // namespace fc2t2
 
+namespace {
+
+fc2t2_status eval_backward_impl(fc2t2_plan plan, const void* L, const void* q, int64_t M, const void* gy, void* gL,
+                                void* gq, void* ws, size_t ws_bytes, hipStream_t stream, bool acc) {
+  if (!plan || bad_count(M)) return FC2T2_EINVAL;
+  if (M > 0 && (!q || !gy)) return FC2T2_EINVAL;
+  if (gq && !L) return FC2T2_EINVAL;
+  if (M == 0) {   // nothing to add; overwriting means zero
+    return gL && !acc ? launch_zero(plan, gL, (int64_t)grid_elems(plan, 0), stream) : FC2T2_OK;
+  }
+  if (gL) {
+    const size_t need = ws_eval_backward(plan, M);
+    if (!ws || ws_bytes < need) return FC2T2_EWORKSPACE;
+    Carve c(ws);
+    SortBufs sb = carve_sort(c, plan, M);
+    fc2t2_status st;
+    const bool carry = sb.pay != nullptr;
+    {
+      StageScope t(plan, FC2T2_STAGE_SORT, stream);
+      st = bin_and_sort(plan, q, M, sb, stream, carry ? gy : nullptr);
+    }
+    if (st) return st;
+    if (carry) {   // contiguous sorted queries; q_bar by a gather pass in input order
+      {
+        StageScope t(plan, FC2T2_STAGE_L2P_T, stream);
+        st = launch_reduce_sorted(plan, sb.pay, M, sb.starts, gL, acc, stream);
+      }
+      if (st || !gq) return st;
+      StageScope t(plan, FC2T2_STAGE_QGRAD, stream);
+      return launch_l2p_qgrad(plan, L, q, M, gy, gq, stream, acc);
+    }
+    StageScope t(plan, FC2T2_STAGE_L2P_T, stream);
+    if (gq && plan->C == 1) {   // one pass over the sorted queries produces both (q_bar accumulated)
+      if (!acc && (st = launch_zero(plan, gq, M * plan->dim, stream))) return st;
+      return launch_l2p_T_qgrad(plan, L, q, gy, M, sb.starts, sb.perm, gL, gq, stream, acc);
+    }
+    st = launch_l2p_T(plan, q, gy, M, sb.starts, sb.perm, gL, stream, acc);
+    if (st) return st;
+    if (gq) return launch_l2p_qgrad(plan, L, q, M, gy, gq, stream, acc);
+    return FC2T2_OK;
+  }
+  StageScope t(plan, FC2T2_STAGE_QGRAD, stream);
+  if (gq) return launch_l2p_qgrad(plan, L, q, M, gy, gq, stream, acc);
+  return FC2T2_OK;
+}
+
+fc2t2_status expand_backward_impl(fc2t2_plan plan, const void* gL, const void* p, const void* w, int64_t N,
+                                  void* gp, void* gw, void* ws, size_t ws_bytes, hipStream_t stream, bool acc) {
+  if (!plan || !gL || bad_count(N)) return FC2T2_EINVAL;
+  if (N > 0 && (!p || !w)) return FC2T2_EINVAL;
+  if (N == 0 || (!gp && !gw)) return FC2T2_OK;
+  const size_t need = ws_expand_backward(plan);
+  if (!ws || ws_bytes < need) return FC2T2_EWORKSPACE;
+  Carve c(ws);
+  void* GLlv[kMaxLevels];
+  void* GMlv[kMaxLevels];
+  carve_pyramid(c, plan, 1, GLlv);
+  carve_pyramid(c, plan, 0, GMlv);
+  uint8_t* occ[kMaxLevels];
+  carve_occupancy(c, plan, occ);
+  void* sep_ws = c.take<char>(sep_ws_bytes(plan));
+  const uint8_t gen = next_gen(plan);
+  fc2t2_status st;
+  {
+    StageScope t(plan, FC2T2_STAGE_SORT, stream);   // binning of the sources (occupancy only)
+    st = launch_mark_cells(plan, p, N, occ[0], gen, stream);
+  }
+  if (st) return st;
+  st = expand_T_to_moments(plan, gL, GLlv, GMlv, stream, occ, gen, sep_ws);
+  if (st) return st;
+  StageScope t(plan, FC2T2_STAGE_P2M_T, stream);
+  return launch_p2m_T(plan, GMlv[0], p, w, N, gp, gw, stream, acc);
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t fc2t2_workspace_size(fc2t2_plan plan, int op, int64_t count) {
@@ -198,71 +274,25 @@ fc2t2_status fc2t2_eval(fc2t2_plan plan, const void* L, const void* q, int64_t M
 fc2t2_status fc2t2_eval_backward(fc2t2_plan plan, const void* L, const void* q, int64_t M,
                                  const void* gy, void* gL, void* gq, void* ws, size_t ws_bytes,
                                  hipStream_t stream) {
-  if (!plan || bad_count(M)) return FC2T2_EINVAL;
-  if (M > 0 && (!q || !gy)) return FC2T2_EINVAL;
-  if (gq && !L) return FC2T2_EINVAL;
-  if (M == 0) return FC2T2_OK;
-  if (gL) {
-    const size_t need = ws_eval_backward(plan, M);
-    if (!ws || ws_bytes < need) return FC2T2_EWORKSPACE;
-    Carve c(ws);
-    SortBufs sb = carve_sort(c, plan, M);
-    fc2t2_status st;
-    const bool carry = sb.pay != nullptr;
-    {
-      StageScope t(plan, FC2T2_STAGE_SORT, stream);
-      st = bin_and_sort(plan, q, M, sb, stream, carry ? gy : nullptr);
-    }
-    if (st) return st;
-    if (carry) {   // contiguous sorted queries; q_bar by a gather pass in input order
-      {
-        StageScope t(plan, FC2T2_STAGE_L2P_T, stream);
-        st = launch_reduce_sorted(plan, sb.pay, M, sb.starts, gL, true, stream);
-      }
-      if (st || !gq) return st;
-      StageScope t(plan, FC2T2_STAGE_QGRAD, stream);
-      return launch_l2p_qgrad(plan, L, q, M, gy, gq, stream);
-    }
-    StageScope t(plan, FC2T2_STAGE_L2P_T, stream);
-    if (gq && plan->C == 1)   // one pass over the sorted queries produces both
-      return launch_l2p_T_qgrad(plan, L, q, gy, M, sb.starts, sb.perm, gL, gq, stream);
-    st = launch_l2p_T(plan, q, gy, M, sb.starts, sb.perm, gL, stream);
-    if (st) return st;
-    if (gq) return launch_l2p_qgrad(plan, L, q, M, gy, gq, stream);
-    return FC2T2_OK;
-  }
-  StageScope t(plan, FC2T2_STAGE_QGRAD, stream);
-  if (gq) return launch_l2p_qgrad(plan, L, q, M, gy, gq, stream);
-  return FC2T2_OK;
+  return eval_backward_impl(plan, L, q, M, gy, gL, gq, ws, ws_bytes, stream, true);
+}
+
+fc2t2_status fc2t2_eval_backward_ex(fc2t2_plan plan, const void* L, const void* q, int64_t M,
+                                    const void* gy, void* gL, void* gq, void* ws, size_t ws_bytes,
+                                    int accumulate, hipStream_t stream) {
+  return eval_backward_impl(plan, L, q, M, gy, gL, gq, ws, ws_bytes, stream, accumulate != 0);
 }
 
 fc2t2_status fc2t2_expand_backward(fc2t2_plan plan, const void* gL, const void* p, const void* w,
                                    int64_t N, void* gp, void* gw, void* ws, size_t ws_bytes,
                                    hipStream_t stream) {
-  if (!plan || !gL || bad_count(N)) return FC2T2_EINVAL;
-  if (N > 0 && (!p || !w)) return FC2T2_EINVAL;
-  if (N == 0 || (!gp && !gw)) return FC2T2_OK;
-  const size_t need = ws_expand_backward(plan);
-  if (!ws || ws_bytes < need) return FC2T2_EWORKSPACE;
-  Carve c(ws);
-  void* GLlv[kMaxLevels];
-  void* GMlv[kMaxLevels];
-  carve_pyramid(c, plan, 1, GLlv);
-  carve_pyramid(c, plan, 0, GMlv);
-  uint8_t* occ[kMaxLevels];
-  carve_occupancy(c, plan, occ);
-  void* sep_ws = c.take<char>(sep_ws_bytes(plan));
-  const uint8_t gen = next_gen(plan);
-  fc2t2_status st;
-  {
-    StageScope t(plan, FC2T2_STAGE_SORT, stream);   // binning of the sources (occupancy only)
-    st = launch_mark_cells(plan, p, N, occ[0], gen, stream);
-  }
-  if (st) return st;
-  st = expand_T_to_moments(plan, gL, GLlv, GMlv, stream, occ, gen, sep_ws);
-  if (st) return st;
-  StageScope t(plan, FC2T2_STAGE_P2M_T, stream);
-  return launch_p2m_T(plan, GMlv[0], p, w, N, gp, gw, stream);
+  return expand_backward_impl(plan, gL, p, w, N, gp, gw, ws, ws_bytes, stream, true);
+}
+
+fc2t2_status fc2t2_expand_backward_ex(fc2t2_plan plan, const void* gL, const void* p, const void* w,
+                                      int64_t N, void* gp, void* gw, void* ws, size_t ws_bytes,
+                                      int accumulate, hipStream_t stream) {
+  return expand_backward_impl(plan, gL, p, w, N, gp, gw, ws, ws_bytes, stream, accumulate != 0);
 }
 
 fc2t2_status fc2t2_m2l(fc2t2_plan plan, int level, int transpose, const void* in, void* out,

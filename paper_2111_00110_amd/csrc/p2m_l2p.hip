@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(256) gather_eval_kernel(const T* __restrict__ 
                                                           T scale, T h, T inv_h,
                                                           const T* __restrict__ wts,
                                                           T* __restrict__ out_v, T* __restrict__ out_g,
-                                                          T* __restrict__ out_h) {
+                                                          T* __restrict__ out_h, int accumulate) {
   constexpr int D = S::D, Ppad = S::Ppad;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(256) gather_eval_kernel(const T* __restrict__ 
 #pragma unroll
       for (int j = 0; j < D; ++j) gsum[j] += a * g[j];
     } else {
-      if (out_v) out_v[i * C + ch] += val;
+      if (out_v) out_v[i * C + ch] = accumulate ? out_v[i * C + ch] + val : val;
       const T a = wts[i * C + ch];
 #pragma unroll
       for (int j = 0; j < D; ++j) gsum[j] += a * g[j];
@@ -176,14 +176,15 @@ __global__ void __launch_bounds__(256) gather_eval_kernel(const T* __restrict__ 
   if constexpr (MODE != 0) {
     if (out_g) {
 #pragma unroll
-      for (int j = 0; j < D; ++j) out_g[i * D + j] += gsum[j] * inv_h;
+      for (int j = 0; j < D; ++j) out_g[i * D + j] = accumulate ? out_g[i * D + j] + gsum[j] * inv_h : gsum[j] * inv_h;
     }
   }
 }
 
 template <typename T, int MODE>
 fc2t2_status gather_eval(const fc2t2_plan_s* pl, const void* grid, const void* x, int64_t count,
-                         const void* wts, void* out_v, void* out_g, void* out_h, hipStream_t s) {
+                         const void* wts, void* out_v, void* out_g, void* out_h, hipStream_t s,
+                         int accumulate = 1) {
   if (count == 0) return FC2T2_OK;
   fc2t2_status st = FC2T2_EUNSUPPORTED;
   const int threads = 256;
@@ -195,19 +196,19 @@ fc2t2_status gather_eval(const fc2t2_plan_s* pl, const void* grid, const void* x
       if (out_h)
         hipLaunchKernelGGL((gather_eval_kernel<S, T, 0, true, true>), blocks, dim3(threads), 0, s,
                            (const T*)grid, (const T*)x, count, pl->C, pl->n, pl->G, lo, scale, h, inv_h,
-                           (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h);
+                           (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h, accumulate);
       else if (out_g)
         hipLaunchKernelGGL((gather_eval_kernel<S, T, 0, true, false>), blocks, dim3(threads), 0, s,
                            (const T*)grid, (const T*)x, count, pl->C, pl->n, pl->G, lo, scale, h, inv_h,
-                           (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h);
+                           (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h, accumulate);
       else
         hipLaunchKernelGGL((gather_eval_kernel<S, T, 0, false, false>), blocks, dim3(threads), 0, s,
                            (const T*)grid, (const T*)x, count, pl->C, pl->n, pl->G, lo, scale, h, inv_h,
-                           (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h);
+                           (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h, accumulate);
     } else {
       hipLaunchKernelGGL((gather_eval_kernel<S, T, MODE, true, false>), blocks, dim3(threads), 0, s,
                          (const T*)grid, (const T*)x, count, pl->C, pl->n, pl->G, lo, scale, h, inv_h,
-                         (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h);
+                         (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h, accumulate);
     }
     st = FC2T2_OK;
   });
@@ -289,28 +290,30 @@ fc2t2_status launch_reduce_sorted(const fc2t2_plan_s* pl, const void* pay, int64
 }
 
 fc2t2_status launch_l2p_T(const fc2t2_plan_s* pl, const void* q, const void* gy, int64_t M,
-                          const uint32_t* starts, const uint32_t* perm, void* gL, hipStream_t s) {
-  return pl->io == FC2T2_IO_F64 ? reduce_points<double>(pl, q, gy, M, starts, perm, gL, true, s)
-                                : reduce_points<float>(pl, q, gy, M, starts, perm, gL, true, s);
+                          const uint32_t* starts, const uint32_t* perm, void* gL, hipStream_t s, bool accumulate) {
+  return pl->io == FC2T2_IO_F64 ? reduce_points<double>(pl, q, gy, M, starts, perm, gL, accumulate, s)
+                                : reduce_points<float>(pl, q, gy, M, starts, perm, gL, accumulate, s);
 }
 
 template <typename T>
 fc2t2_status l2p_T_qgrad_t(const fc2t2_plan_s* pl, const void* L, const void* q, const void* gy, int64_t M,
-                           const uint32_t* starts, const uint32_t* perm, void* gL, void* gq, hipStream_t s) {
+                           const uint32_t* starts, const uint32_t* perm, void* gL, void* gq, hipStream_t s,
+                           bool accumulate) {
   fc2t2_status st = FC2T2_EUNSUPPORTED;
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {
     using S = decltype(shape);
     QueryMonomialsGrad<S, T> fn{(const T*)q, (const T*)gy, (const T*)L, (T*)gq, (T)(1.0 / pl->h0)};
-    st = launch_reduce_cells<S, T>(pl, starts, perm, M, (T*)gL, true, fn, s);
+    st = launch_reduce_cells<S, T>(pl, starts, perm, M, (T*)gL, accumulate, fn, s);
   });
   return st;
 }
 
 fc2t2_status launch_l2p_T_qgrad(const fc2t2_plan_s* pl, const void* L, const void* q, const void* gy, int64_t M,
-                                const uint32_t* starts, const uint32_t* perm, void* gL, void* gq, hipStream_t s) {
+                                const uint32_t* starts, const uint32_t* perm, void* gL, void* gq, hipStream_t s,
+                                bool accumulate) {
   if (pl->C != 1) return FC2T2_EUNSUPPORTED;
-  return pl->io == FC2T2_IO_F64 ? l2p_T_qgrad_t<double>(pl, L, q, gy, M, starts, perm, gL, gq, s)
-                                : l2p_T_qgrad_t<float>(pl, L, q, gy, M, starts, perm, gL, gq, s);
+  return pl->io == FC2T2_IO_F64 ? l2p_T_qgrad_t<double>(pl, L, q, gy, M, starts, perm, gL, gq, s, accumulate)
+                                : l2p_T_qgrad_t<float>(pl, L, q, gy, M, starts, perm, gL, gq, s, accumulate);
 }
 
 fc2t2_status launch_l2p(const fc2t2_plan_s* pl, const void* L, const void* q, int64_t M, void* y,
@@ -320,15 +323,34 @@ fc2t2_status launch_l2p(const fc2t2_plan_s* pl, const void* L, const void* q, in
 }
 
 fc2t2_status launch_l2p_qgrad(const fc2t2_plan_s* pl, const void* L, const void* q, int64_t M,
-                              const void* gy, void* gq, hipStream_t s) {
-  return pl->io == FC2T2_IO_F64 ? gather_eval<double, 1>(pl, L, q, M, gy, nullptr, gq, nullptr, s)
-                                : gather_eval<float, 1>(pl, L, q, M, gy, nullptr, gq, nullptr, s);
+                              const void* gy, void* gq, hipStream_t s, bool accumulate) {
+  const int acc = accumulate ? 1 : 0;
+  return pl->io == FC2T2_IO_F64 ? gather_eval<double, 1>(pl, L, q, M, gy, nullptr, gq, nullptr, s, acc)
+                                : gather_eval<float, 1>(pl, L, q, M, gy, nullptr, gq, nullptr, s, acc);
 }
 
 fc2t2_status launch_p2m_T(const fc2t2_plan_s* pl, const void* GM0, const void* p, const void* w,
-                          int64_t N, void* gp, void* gw, hipStream_t s) {
-  return pl->io == FC2T2_IO_F64 ? gather_eval<double, 2>(pl, GM0, p, N, w, gw, gp, nullptr, s)
-                                : gather_eval<float, 2>(pl, GM0, p, N, w, gw, gp, nullptr, s);
+                          int64_t N, void* gp, void* gw, hipStream_t s, bool accumulate) {
+  const int acc = accumulate ? 1 : 0;
+  return pl->io == FC2T2_IO_F64 ? gather_eval<double, 2>(pl, GM0, p, N, w, gw, gp, nullptr, s, acc)
+                                : gather_eval<float, 2>(pl, GM0, p, N, w, gw, gp, nullptr, s, acc);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) zero_kernel(T* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = T(0);
+}
+
+fc2t2_status launch_zero(const fc2t2_plan_s* pl, void* p, int64_t elems, hipStream_t s) {
+  if (elems <= 0) return FC2T2_OK;
+  const dim3 grid((unsigned)ceil_div(elems, 256));
+  if (pl->io == FC2T2_IO_F64)
+    hipLaunchKernelGGL(zero_kernel<double>, grid, dim3(256), 0, s, (double*)p, elems);
+  else
+    hipLaunchKernelGGL(zero_kernel<float>, grid, dim3(256), 0, s, (float*)p, elems);
+  FC2T2_LAUNCH_CHECK();
+  return FC2T2_OK;
 }
 
 }  // namespace fc2t2

@@ -96,9 +96,10 @@ int key_bits_for(int64_t G);
 fc2t2_status launch_p2m(const fc2t2_plan_s* pl, const void* p, const void* w, int64_t N,
                         const uint32_t* starts, const uint32_t* perm, void* M0, hipStream_t s,
                         uint8_t* occ = nullptr, uint8_t gen = 1);
-// Transpose of L2P: gL += sum over the sorted queries of gy (q - c)^k / k!.
+// Transpose of L2P: gL += (or =) sum over the sorted queries of gy (q - c)^k / k!.
 fc2t2_status launch_l2p_T(const fc2t2_plan_s* pl, const void* q, const void* gy, int64_t M,
-                          const uint32_t* starts, const uint32_t* perm, void* gL, hipStream_t s);
+                          const uint32_t* starts, const uint32_t* perm, void* gL, hipStream_t s,
+                          bool accumulate = true);
 // P2M, or the transpose of L2P, from records sorted with their data (pay [count][dim + 1]:
 // coordinates and weight or cotangent; FP32, one channel).
 fc2t2_status launch_reduce_sorted(const fc2t2_plan_s* pl, const void* pay, int64_t count, const uint32_t* starts,
@@ -108,18 +109,22 @@ fc2t2_status launch_reduce_sorted(const fc2t2_plan_s* pl, const void* pay, int64
 // a point.
 fc2t2_status launch_mark_cells(const fc2t2_plan_s* pl, const void* x, int64_t N, uint8_t* occ, uint8_t gen,
                                hipStream_t s);
-// Transpose of L2P fused with gq += gy grad f(q) (one channel only).
+// Transpose of L2P fused with gq += gy grad f(q) (one channel only); accumulate applies to gL,
+// gq is always accumulated into.
 fc2t2_status launch_l2p_T_qgrad(const fc2t2_plan_s* pl, const void* L, const void* q, const void* gy, int64_t M,
-                                const uint32_t* starts, const uint32_t* perm, void* gL, void* gq, hipStream_t s);
+                                const uint32_t* starts, const uint32_t* perm, void* gL, void* gq, hipStream_t s,
+                                bool accumulate = true);
 // L2P: y (overwrite), grad/hess (overwrite, optional).
 fc2t2_status launch_l2p(const fc2t2_plan_s* pl, const void* L, const void* q, int64_t M, void* y,
                         void* grad, void* hess, hipStream_t s);
-// gq += sum_c gy[c] grad_c f(q).
+// gq += (or =) sum_c gy[c] grad_c f(q).
 fc2t2_status launch_l2p_qgrad(const fc2t2_plan_s* pl, const void* L, const void* q, int64_t M,
-                              const void* gy, void* gq, hipStream_t s);
-// Transpose of P2M: gw += <GM0, mono>, gp += w <GM0, grad mono> / h.
+                              const void* gy, void* gq, hipStream_t s, bool accumulate = true);
+// Transpose of P2M: gw += <GM0, mono>, gp += w <GM0, grad mono> / h (or = for both).
 fc2t2_status launch_p2m_T(const fc2t2_plan_s* pl, const void* GM0, const void* p, const void* w,
-                          int64_t N, void* gp, void* gw, hipStream_t s);
+                          int64_t N, void* gp, void* gw, hipStream_t s, bool accumulate = true);
+// p[0 .. elems) = 0 in the plan's IO type (a fill kernel, safe under graph capture).
+fc2t2_status launch_zero(const fc2t2_plan_s* pl, void* p, int64_t elems, hipStream_t s);
 
 // ---- tree.hip
 // Sparse shift lists of the plan's (dim, K), uploaded to pl->shift.

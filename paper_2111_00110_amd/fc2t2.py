@@ -79,6 +79,10 @@ def lib() -> ctypes.CDLL:
     L.fc2t2_eval_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]
     L.fc2t2_expand_backward.restype = i32
     L.fc2t2_expand_backward.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, sz, vp]
+    L.fc2t2_eval_backward_ex.restype = i32
+    L.fc2t2_eval_backward_ex.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, sz, i32, vp]
+    L.fc2t2_expand_backward_ex.restype = i32
+    L.fc2t2_expand_backward_ex.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, sz, i32, vp]
     L.fc2t2_ray_integral.restype = i32
     L.fc2t2_ray_integral.argtypes = [vp, vp, vp, vp, dbl, dbl, i64, vp, vp]
     L.fc2t2_ray_integral_backward.restype = i32
@@ -232,7 +236,9 @@ class Plan:
                "fc2t2_eval")
         return y, g, hs
 
-    def eval_backward(self, Lt, q, gy, gL: Optional[torch.Tensor] = None, gq: Optional[torch.Tensor] = None):
+    def eval_backward(self, Lt, q, gy, gL: Optional[torch.Tensor] = None, gq: Optional[torch.Tensor] = None,
+                      accumulate: bool = True):
+        """gL, gq += (accumulate) or = (otherwise) the cotangents of L and q."""
         M = q.shape[0]
         q = self._t(q, (M, self.dim), "q")
         gy = self._t(gy, (M, self.C), "gy")
@@ -241,11 +247,13 @@ class Plan:
         if gq is not None:
             assert gq.is_contiguous() and tuple(gq.shape) == (M, self.dim) and gq.dtype == self.dtype
         ws = self.workspace("eval_backward", M) if gL is not None else None
-        _check(lib().fc2t2_eval_backward(self.handle, _ptr(Lt), _ptr(q), M, _ptr(gy), _ptr(gL), _ptr(gq),
-                                         _ptr(ws), 0 if ws is None else ws.numel(), _stream()),
-               "fc2t2_eval_backward")
+        _check(lib().fc2t2_eval_backward_ex(self.handle, _ptr(Lt), _ptr(q), M, _ptr(gy), _ptr(gL), _ptr(gq),
+                                            _ptr(ws), 0 if ws is None else ws.numel(), 1 if accumulate else 0,
+                                            _stream()), "fc2t2_eval_backward_ex")
 
-    def expand_backward(self, gL, p, w, gp: Optional[torch.Tensor] = None, gw: Optional[torch.Tensor] = None):
+    def expand_backward(self, gL, p, w, gp: Optional[torch.Tensor] = None, gw: Optional[torch.Tensor] = None,
+                        accumulate: bool = True):
+        """gp, gw += (accumulate) or = (otherwise) the cotangents of p and w."""
         N = p.shape[0]
         p = self._t(p, (N, self.dim), "p")
         w = self._t(w, (N, self.C), "w")
@@ -255,8 +263,9 @@ class Plan:
         if gw is not None:
             assert gw.is_contiguous() and tuple(gw.shape) == (N, self.C) and gw.dtype == self.dtype
         ws = self.workspace("expand_backward", N)
-        _check(lib().fc2t2_expand_backward(self.handle, _ptr(gL), _ptr(p), _ptr(w), N, _ptr(gp), _ptr(gw),
-                                           _ptr(ws), ws.numel(), _stream()), "fc2t2_expand_backward")
+        _check(lib().fc2t2_expand_backward_ex(self.handle, _ptr(gL), _ptr(p), _ptr(w), N, _ptr(gp), _ptr(gw),
+                                              _ptr(ws), ws.numel(), 1 if accumulate else 0, _stream()),
+               "fc2t2_expand_backward_ex")
 
     def ray_integral(self, Lt, o, r, t0: float, t1: float) -> torch.Tensor:
         R = o.shape[0]
@@ -327,13 +336,14 @@ class Explicit(torch.autograd.Function):
         p, w, q, Lt = ctx.saved_tensors
         gy = gy.contiguous()
         need_p, need_w, need_q = ctx.needs_input_grad[1], ctx.needs_input_grad[2], ctx.needs_input_grad[3]
-        gq = torch.zeros_like(q) if need_q else None
-        gp = torch.zeros_like(p) if need_p else None
-        gw = torch.zeros_like(w) if need_w else None
-        gL = plan.new_local() if (need_p or need_w) else None
-        plan.eval_backward(Lt, q, gy, gL, gq)
+        # fresh buffers, written (not accumulated) by the library
+        gq = torch.empty_like(q) if need_q else None
+        gp = torch.empty_like(p) if need_p else None
+        gw = torch.empty_like(w) if need_w else None
+        gL = torch.empty(plan.local_shape(), dtype=plan.dtype, device=q.device) if (need_p or need_w) else None
+        plan.eval_backward(Lt, q, gy, gL, gq, accumulate=False)
         if gL is not None:
-            plan.expand_backward(gL, p, w, gp, gw)
+            plan.expand_backward(gL, p, w, gp, gw, accumulate=False)
         return None, gp, gw, gq
 
 
@@ -355,9 +365,9 @@ class RayIntegral(torch.autograd.Function):
         p, w, o, r = ctx.saved_tensors
         gL = plan.new_local()
         plan.ray_integral_backward(o, r, ctx.t0, ctx.t1, gy.contiguous(), gL)
-        gp = torch.zeros_like(p) if ctx.needs_input_grad[1] else None
-        gw = torch.zeros_like(w) if ctx.needs_input_grad[2] else None
-        plan.expand_backward(gL, p, w, gp, gw)
+        gp = torch.empty_like(p) if ctx.needs_input_grad[1] else None
+        gw = torch.empty_like(w) if ctx.needs_input_grad[2] else None
+        plan.expand_backward(gL, p, w, gp, gw, accumulate=False)
         return None, gp, gw, None, None, None, None
 
 
@@ -381,7 +391,7 @@ class RayRoot(torch.autograd.Function):
         gL = plan.new_local()
         plan.ray_root_backward(saved, hit, None if gt is None else gt.contiguous(),
                                None if gn is None else gn.contiguous(), gL)
-        gp = torch.zeros_like(p) if ctx.needs_input_grad[1] else None
-        gw = torch.zeros_like(w) if ctx.needs_input_grad[2] else None
-        plan.expand_backward(gL, p, w, gp, gw)
+        gp = torch.empty_like(p) if ctx.needs_input_grad[1] else None
+        gw = torch.empty_like(w) if ctx.needs_input_grad[2] else None
+        plan.expand_backward(gL, p, w, gp, gw, accumulate=False)
         return None, gp, gw, None, None, None, None, None

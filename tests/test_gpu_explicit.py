@@ -230,3 +230,33 @@ def test_lsq_fitted_tensors_bf16x3(F):
     assert rel(got["gw"], gw) < 3e-5
     assert rel(got["gp"], gp) < 5e-5
     assert rel(got["gq"], gq) < 5e-5
+
+
+@pytest.mark.parametrize("io,C", [("f32", 1), ("f64", 1), ("f32", 2)])
+def test_backward_overwrite_equals_zero_then_accumulate(F, io, C):
+    """accumulate=False writes the gradients over whatever the buffers held: the same values as
+    zeroed buffers accumulated into (every backward path: sorted records with carried data,
+    the fused FP64 pass, several channels), and an empty query set zeroes gL."""
+    wl = W.Workload("o", 2, 32, 0.0, 1.0, 4, "gaussian", 0.03, 3000, 2000, 0, io, "explicit", "uniform")
+    x = W.make(wl, seed=12)
+    rng = np.random.default_rng(13)
+    x["w"] = rng.standard_normal((wl.N, C)).astype(x["p"].dtype)
+    x["gy"] = rng.standard_normal((wl.M, C)).astype(x["p"].dtype)
+    plan = _plan(F, wl, channels=C)
+    p, w, q, gy = (_dev(x[k]) for k in ("p", "w", "q", "gy"))
+    Lt = plan.expand(p, w)
+    res = {}
+    for acc in (True, False):
+        fill = (lambda t: t.zero_()) if acc else (lambda t: t.fill_(7.5))
+        gL = fill(plan.new_local())
+        gq, gp, gw = fill(torch.empty_like(q)), fill(torch.empty_like(p)), fill(torch.empty_like(w))
+        plan.eval_backward(Lt, q, gy, gL, gq, accumulate=acc)
+        plan.expand_backward(gL, p, w, gp, gw, accumulate=acc)
+        torch.cuda.synchronize()
+        res[acc] = [t.cpu().numpy() for t in (gL, gq, gp, gw)]
+    for a, b in zip(res[True], res[False]):
+        assert np.array_equal(a, b)
+    gL = plan.new_local().fill_(3.0)
+    plan.eval_backward(Lt, q[:0], gy[:0], gL, None, accumulate=False)
+    torch.cuda.synchronize()
+    assert float(gL.abs().max()) == 0.0

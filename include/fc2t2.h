@@ -141,6 +141,13 @@ fc2t2_status fc2t2_plan_destroy(fc2t2_plan plan);
 int fc2t2_plan_P(fc2t2_plan plan);            /* multi-indices per cell */
 int fc2t2_plan_P_pad(fc2t2_plan plan);        /* row stride of a local-expansion cell */
 int fc2t2_plan_levels(fc2t2_plan plan);
+
+/* Points outside [lo, hi]^dim (NaN included) that fc2t2_expand (sources) and fc2t2_eval
+ * (queries) have met on this plan since its creation or the last reset, counted on the
+ * device; each such point was binned into the nearest boundary cell (the method assumes
+ * points inside the domain, section 3.2).  Copies the count to *count, synchronising
+ * `stream`; reset != 0 then zeroes the counter (ordered on `stream`).  EINVAL for NULLs. */
+fc2t2_status fc2t2_out_of_domain(fc2t2_plan plan, int64_t* count, int reset, hipStream_t stream);
 size_t fc2t2_local_numel(fc2t2_plan plan);    /* C * n^dim * P_pad elements */
 
 /* Scratch bytes `op` needs for `count` points or rays (0 for an invalid op). */

@@ -39,9 +39,9 @@ SortBufs carve_sort(Carve& c, const fc2t2_plan_s* pl, int64_t count) {
 // Sorts points by cell; with `extra` (one value per point) and a carved payload buffer, the
 // coordinates and that value are sorted along into b.pay.
 fc2t2_status bin_and_sort(const fc2t2_plan_s* pl, const void* x, int64_t count, const SortBufs& b,
-                          hipStream_t s, const void* extra = nullptr) {
+                          hipStream_t s, const void* extra = nullptr, unsigned long long* ood = nullptr) {
   fc2t2_status st = sort_points_by_cell(pl, x, count, b.keys, b.keys_sorted, b.perm, b.scratch, s, extra,
-                                        extra ? b.pay : nullptr);
+                                        extra ? b.pay : nullptr, ood);
   if (st) return st;
   return launch_cell_starts(b.keys_sorted, count, pl->G, b.starts, s);
 }
@@ -251,7 +251,7 @@ fc2t2_status fc2t2_expand(fc2t2_plan plan, const void* p, const void* w, int64_t
   const bool carry = sb.pay != nullptr;   // sort the points' data along with the keys
   {
     StageScope t(plan, FC2T2_STAGE_SORT, stream);
-    st = bin_and_sort(plan, p, N, sb, stream, carry ? w : nullptr);
+    st = bin_and_sort(plan, p, N, sb, stream, carry ? w : nullptr, plan->ood);
   }
   if (st) return st;
   {

@@ -184,6 +184,21 @@ __device__ __forceinline__ int cell_coord(T x, T lo, T scale, int n) {
   return i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
 }
 
+// Whether x lies outside [lo, hi] (hi = lo + n / scale), by the cell formula's own rounding;
+// NaN counts as outside.
+template <typename T>
+__device__ __forceinline__ bool outside_domain(T x, T lo, T scale, int n) {
+  T u = (x - lo);
+  u = u * scale;
+  return !(u >= T(0) && u <= T(n));
+}
+
+// Adds the number of active lanes with `flag` set to *ctr: one vector atomic per wave.
+__device__ __forceinline__ void count_lanes(bool flag, unsigned long long* ctr) {
+  const unsigned long long m = __ballot(flag);
+  if (m && (int)(threadIdx.x & 63) == __ffsll((long long)m) - 1) atomicAdd(ctr, (unsigned long long)__popcll(m));
+}
+
 // ----------------------------------------------------------------------------- dispatch
 // Calls f(Shape<D,K>{}) for the supported (D, K) pairs; returns false otherwise.
 template <class F>

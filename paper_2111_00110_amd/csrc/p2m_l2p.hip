@@ -129,20 +129,24 @@ __global__ void __launch_bounds__(256) gather_eval_kernel(const T* __restrict__ 
                                                           T scale, T h, T inv_h,
                                                           const T* __restrict__ wts,
                                                           T* __restrict__ out_v, T* __restrict__ out_g,
-                                                          T* __restrict__ out_h, int accumulate) {
+                                                          T* __restrict__ out_h, int accumulate,
+                                                          unsigned long long* __restrict__ ood) {
   constexpr int D = S::D, Ppad = S::Ppad;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   int ic[3] = {0, 0, 0};
   int64_t cell = 0;
   T u[3] = {T(0), T(0), T(0)};
+  bool out = false;
 #pragma unroll
   for (int j = 0; j < D; ++j) {
     const T xj = x[i * D + j];
+    out = out || outside_domain<T>(xj, lo, scale, n);
     ic[j] = cell_coord<T>(xj, lo, scale, n);
     cell = cell * n + ic[j];
     u[j] = (xj - (lo + (T(ic[j]) + T(0.5)) * h)) * inv_h;
   }
+  if (ood) count_lanes(out, ood);
   T pw[3][S::K + 1];
   power_table<S>(u, pw);
   T gsum[3] = {T(0), T(0), T(0)};
@@ -184,7 +188,7 @@ __global__ void __launch_bounds__(256) gather_eval_kernel(const T* __restrict__ 
 template <typename T, int MODE>
 fc2t2_status gather_eval(const fc2t2_plan_s* pl, const void* grid, const void* x, int64_t count,
                          const void* wts, void* out_v, void* out_g, void* out_h, hipStream_t s,
-                         int accumulate = 1) {
+                         int accumulate = 1, unsigned long long* ood = nullptr) {
   if (count == 0) return FC2T2_OK;
   fc2t2_status st = FC2T2_EUNSUPPORTED;
   const int threads = 256;
@@ -196,19 +200,19 @@ fc2t2_status gather_eval(const fc2t2_plan_s* pl, const void* grid, const void* x
       if (out_h)
         hipLaunchKernelGGL((gather_eval_kernel<S, T, 0, true, true>), blocks, dim3(threads), 0, s,
                            (const T*)grid, (const T*)x, count, pl->C, pl->n, pl->G, lo, scale, h, inv_h,
-                           (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h, accumulate);
+                           (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h, accumulate, ood);
       else if (out_g)
         hipLaunchKernelGGL((gather_eval_kernel<S, T, 0, true, false>), blocks, dim3(threads), 0, s,
                            (const T*)grid, (const T*)x, count, pl->C, pl->n, pl->G, lo, scale, h, inv_h,
-                           (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h, accumulate);
+                           (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h, accumulate, ood);
       else
         hipLaunchKernelGGL((gather_eval_kernel<S, T, 0, false, false>), blocks, dim3(threads), 0, s,
                            (const T*)grid, (const T*)x, count, pl->C, pl->n, pl->G, lo, scale, h, inv_h,
-                           (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h, accumulate);
+                           (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h, accumulate, ood);
     } else {
       hipLaunchKernelGGL((gather_eval_kernel<S, T, MODE, true, false>), blocks, dim3(threads), 0, s,
                          (const T*)grid, (const T*)x, count, pl->C, pl->n, pl->G, lo, scale, h, inv_h,
-                         (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h, accumulate);
+                         (const T*)wts, (T*)out_v, (T*)out_g, (T*)out_h, accumulate, ood);
     }
     st = FC2T2_OK;
   });
@@ -318,8 +322,8 @@ fc2t2_status launch_l2p_T_qgrad(const fc2t2_plan_s* pl, const void* L, const voi
 
 fc2t2_status launch_l2p(const fc2t2_plan_s* pl, const void* L, const void* q, int64_t M, void* y,
                         void* grad, void* hess, hipStream_t s) {
-  return pl->io == FC2T2_IO_F64 ? gather_eval<double, 0>(pl, L, q, M, nullptr, y, grad, hess, s)
-                                : gather_eval<float, 0>(pl, L, q, M, nullptr, y, grad, hess, s);
+  return pl->io == FC2T2_IO_F64 ? gather_eval<double, 0>(pl, L, q, M, nullptr, y, grad, hess, s, 1, pl->ood)
+                                : gather_eval<float, 0>(pl, L, q, M, nullptr, y, grad, hess, s, 1, pl->ood);
 }
 
 fc2t2_status launch_l2p_qgrad(const fc2t2_plan_s* pl, const void* L, const void* q, int64_t M,

@@ -11,6 +11,7 @@ struct SepTables;
 struct fc2t2_plan_s {
   int dim, n, K, P, Ppad, C, levels, io, prec, kind;
   bool fit_lsq = false;            // M2L tensors fitted by least squares (section 3.1)
+  unsigned long long* ood = nullptr;   // device counter: points outside the domain (expand, eval)
   double lo, hi, param;
   double h0;                      // finest cell width
   int64_t G;                      // finest cells
@@ -83,9 +84,11 @@ fc2t2_status radix_sort_pairs(const uint32_t* keys_in, uint32_t* keys_out, uint3
 // The same for points: keys (written to `keys`) are the linear finest-cell indices of x.
 // With pay_out, each point's coordinates and its one value in `extra` travel with it:
 // pay_out [N][dim + 1] receives them in sorted order (FP32, one channel: sort_payload_ok).
+// With ood, the points outside the domain are added to *ood.
 fc2t2_status sort_points_by_cell(const fc2t2_plan_s* pl, const void* x, int64_t N, uint32_t* keys,
                                  uint32_t* keys_out, uint32_t* vals_out, void* scratch, hipStream_t s,
-                                 const void* extra = nullptr, void* pay_out = nullptr);
+                                 const void* extra = nullptr, void* pay_out = nullptr,
+                                 unsigned long long* ood = nullptr);
 bool sort_payload_ok(const fc2t2_plan_s* pl);
 fc2t2_status launch_cell_starts(const uint32_t* keys_sorted, int64_t N, int64_t G,
                                 uint32_t* starts, hipStream_t s);

@@ -300,6 +300,8 @@ bool lsq_projection(int dim, int K, const std::vector<int>& k_exps, std::vector<
   return true;
 }
 
+__global__ void zero_counter_kernel(unsigned long long* c) { *c = 0ull; }
+
 struct DevFree {
   std::vector<void*> ptrs;
   ~DevFree() {
@@ -446,6 +448,7 @@ fc2t2_status fc2t2_plan_create(const fc2t2_grid* grid, const fc2t2_kernel* kerne
   if (hipGetDevice(&pl->device) != hipSuccess) { delete pl; return FC2T2_EHIP; }
 
   auto fail = [&](fc2t2_status st) {
+    if (pl->ood) (void)hipFree(pl->ood);
     if (pl->m2l_T) (void)hipFree(pl->m2l_T);
     if (pl->m2l_bf16) (void)hipFree(pl->m2l_bf16);
     if (pl->shift) (void)hipFree(pl->shift);
@@ -454,6 +457,13 @@ fc2t2_status fc2t2_plan_create(const fc2t2_grid* grid, const fc2t2_kernel* kerne
     delete pl;
     return st;
   };
+
+  // ---- out-of-domain counter
+  if (hipMalloc((void**)&pl->ood, sizeof(unsigned long long)) != hipSuccess) {
+    pl->ood = nullptr;
+    return fail(FC2T2_ENOMEM);
+  }
+  if (hipMemsetAsync(pl->ood, 0, sizeof(unsigned long long), stream) != hipSuccess) return fail(FC2T2_EHIP);
 
   // ---- host tables
   const int P = pl->P, Ppad = pl->Ppad;
@@ -577,9 +587,24 @@ fc2t2_status fc2t2_plan_destroy(fc2t2_plan plan) {
   if (plan->m2l_bf16) (void)hipFree(plan->m2l_bf16);
   if (plan->shift) (void)hipFree(plan->shift);
   if (plan->cell_bounds) (void)hipFree(plan->cell_bounds);
+  if (plan->ood) (void)hipFree(plan->ood);
   sep_destroy(plan);
   stage_timer_destroy(plan);
   delete plan;
+  return FC2T2_OK;
+}
+
+fc2t2_status fc2t2_out_of_domain(fc2t2_plan plan, int64_t* count, int reset, hipStream_t stream) {
+  if (!plan || !count) return FC2T2_EINVAL;
+  unsigned long long v = 0;
+  if (hipMemcpyAsync(&v, plan->ood, sizeof(v), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return FC2T2_EHIP;
+  *count = (int64_t)v;
+  if (reset) {
+    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, stream, plan->ood);
+    if (hipGetLastError() != hipSuccess) return FC2T2_EHIP;
+  }
   return FC2T2_OK;
 }
 

@@ -53,7 +53,8 @@ template <typename T, int D>
 __global__ void __launch_bounds__(kThreads) sort_hist_kernel(const T* __restrict__ x, T lo, T scale, int n,
                                                              uint32_t* __restrict__ keys, uint32_t N, int npass,
                                                              uint32_t* __restrict__ ghist,
-                                                             uint32_t* __restrict__ status, uint32_t status_words) {
+                                                             uint32_t* __restrict__ status, uint32_t status_words,
+                                                             unsigned long long* __restrict__ ood) {
   __shared__ uint32_t h[kMaxPasses][kBins];
   const int tid = threadIdx.x;
 #pragma unroll
@@ -69,10 +70,15 @@ __global__ void __launch_bounds__(kThreads) sort_hist_kernel(const T* __restrict
       key[b] = 0;
       if (i >= N) continue;
       if (x) {
+        bool out = false;
 #pragma unroll
-        for (int j = 0; j < D; ++j)
-          key[b] = key[b] * (uint32_t)n + (uint32_t)cell_coord<T>(x[(size_t)i * D + j], lo, scale, n);
+        for (int j = 0; j < D; ++j) {
+          const T xv = x[(size_t)i * D + j];
+          out = out || outside_domain<T>(xv, lo, scale, n);
+          key[b] = key[b] * (uint32_t)n + (uint32_t)cell_coord<T>(xv, lo, scale, n);
+        }
         keys[i] = key[b];
+        if (ood) count_lanes(out, ood);
       } else {
         key[b] = keys[i];
       }
@@ -356,12 +362,13 @@ fc2t2_status onesweep_passes(const uint32_t* keys_in, uint32_t* keys_out, uint32
 // Histogram (and keys from points when x is given) for npass passes of 8 bits.
 template <typename T, int D>
 fc2t2_status sort_prologue(const T* x, T lo, T scale, int n, uint32_t* keys, uint32_t N, int npass,
+                           unsigned long long* ood,
                            const SortScratch& c, hipStream_t s) {
   const uint32_t status_words = (uint32_t)npass * c.max_tiles * kBins;
   const int64_t work = (int64_t)N > (int64_t)status_words ? (int64_t)N : (int64_t)status_words;
   const int blocks = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(work, kThreads * 8), 1), kHistBlocks);
   hipLaunchKernelGGL((sort_hist_kernel<T, D>), dim3(blocks), dim3(kThreads), 0, s, x, lo, scale, n, keys, N, npass,
-                     c.part, c.status, status_words);
+                     c.part, c.status, status_words, ood);
   FC2T2_LAUNCH_CHECK();
   hipLaunchKernelGGL(sort_hist_sum_kernel, dim3(npass, kSlices), dim3(kThreads), 0, s, c.part, blocks, c.ghist,
                      c.err);
@@ -386,14 +393,14 @@ fc2t2_status radix_sort_pairs(const uint32_t* keys_in, uint32_t* keys_out, uint3
   if (N >= (int64_t)kValMask || key_bits > 8 * kMaxPasses) return FC2T2_EUNSUPPORTED;
   const SortScratch c = carve_scratch(scratch, N);
   const int npass = (key_bits + 7) / 8;
-  fc2t2_status st = sort_prologue<float, 1>(nullptr, 0.f, 0.f, 0, (uint32_t*)keys_in, (uint32_t)N, npass, c, s);
+  fc2t2_status st = sort_prologue<float, 1>(nullptr, 0.f, 0.f, 0, (uint32_t*)keys_in, (uint32_t)N, npass, nullptr, c, s);
   if (st) return st;
   return onesweep_passes<0>(keys_in, keys_out, vals_out, (uint32_t)N, npass, c, nullptr, 0, nullptr, nullptr, s);
 }
 
 fc2t2_status sort_points_by_cell(const fc2t2_plan_s* pl, const void* x, int64_t N, uint32_t* keys,
                                  uint32_t* keys_out, uint32_t* vals_out, void* scratch, hipStream_t s,
-                                 const void* extra, void* pay_out) {
+                                 const void* extra, void* pay_out, unsigned long long* ood) {
   if (N == 0) return FC2T2_OK;
   if (N >= (int64_t)kValMask) return FC2T2_EUNSUPPORTED;
   const int key_bits = key_bits_for(pl->G);
@@ -403,13 +410,13 @@ fc2t2_status sort_points_by_cell(const fc2t2_plan_s* pl, const void* x, int64_t 
   const double scale = pl->n / (pl->hi - pl->lo);
   fc2t2_status st;
   if (pl->io == FC2T2_IO_F64)
-    st = pl->dim == 2 ? sort_prologue<double, 2>((const double*)x, pl->lo, scale, pl->n, keys, (uint32_t)N, npass, c, s)
-                      : sort_prologue<double, 3>((const double*)x, pl->lo, scale, pl->n, keys, (uint32_t)N, npass, c, s);
+    st = pl->dim == 2 ? sort_prologue<double, 2>((const double*)x, pl->lo, scale, pl->n, keys, (uint32_t)N, npass, ood, c, s)
+                      : sort_prologue<double, 3>((const double*)x, pl->lo, scale, pl->n, keys, (uint32_t)N, npass, ood, c, s);
   else
     st = pl->dim == 2 ? sort_prologue<float, 2>((const float*)x, (float)pl->lo, (float)scale, pl->n, keys, (uint32_t)N,
-                                                 npass, c, s)
+                                                 npass, ood, c, s)
                       : sort_prologue<float, 3>((const float*)x, (float)pl->lo, (float)scale, pl->n, keys, (uint32_t)N,
-                                                 npass, c, s);
+                                                 npass, ood, c, s);
   if (st) return st;
   if (pay_out) {
     if (!sort_payload_ok(pl)) return FC2T2_EUNSUPPORTED;

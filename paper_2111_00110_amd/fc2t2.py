@@ -67,6 +67,8 @@ def lib() -> ctypes.CDLL:
     for name in ("fc2t2_plan_P", "fc2t2_plan_P_pad", "fc2t2_plan_levels"):
         getattr(L, name).restype = i32
         getattr(L, name).argtypes = [vp]
+    L.fc2t2_out_of_domain.restype = i32
+    L.fc2t2_out_of_domain.argtypes = [vp, ctypes.POINTER(i64), i32, vp]
     L.fc2t2_local_numel.restype = sz
     L.fc2t2_local_numel.argtypes = [vp]
     L.fc2t2_workspace_size.restype = sz
@@ -222,6 +224,7 @@ class Plan:
         ws = self.workspace("expand", N)
         _check(lib().fc2t2_expand(self.handle, _ptr(p), _ptr(w), N, _ptr(Lt), _ptr(ws), ws.numel(),
                                   _stream()), "fc2t2_expand")
+        self._debug_domain("sources")
         return Lt
 
     def eval(self, Lt: torch.Tensor, q: torch.Tensor, grad: bool = False, hess: bool = False):
@@ -234,7 +237,24 @@ class Plan:
         hs = torch.empty((M, self.C, nh), dtype=self.dtype, device=self.device) if hess else None
         _check(lib().fc2t2_eval(self.handle, _ptr(Lt), _ptr(q), M, _ptr(y), _ptr(g), _ptr(hs), _stream()),
                "fc2t2_eval")
+        self._debug_domain("queries")
         return y, g, hs
+
+    def out_of_domain(self, reset: bool = False) -> int:
+        """Points outside [lo, hi]^dim met by expand (sources) and eval (queries) since the plan was
+        made or last reset; they were binned into the nearest boundary cell.  Synchronises."""
+        c = ctypes.c_int64(0)
+        _check(lib().fc2t2_out_of_domain(self.handle, ctypes.byref(c), 1 if reset else 0, _stream()),
+               "fc2t2_out_of_domain")
+        return int(c.value)
+
+    def _debug_domain(self, what: str):
+        # debug mode (FC2T2_DEBUG=1): fail on points outside the domain, at the call that met them
+        if os.environ.get("FC2T2_DEBUG", "0") not in ("", "0"):
+            n = self.out_of_domain(reset=True)
+            if n:
+                raise FC2T2Error("%d %s outside the domain [%g, %g]^%d (binned into boundary cells)"
+                                 % (n, what, self.lo, self.hi, self.dim))
 
     def eval_backward(self, Lt, q, gy, gL: Optional[torch.Tensor] = None, gq: Optional[torch.Tensor] = None,
                       accumulate: bool = True):

@@ -89,3 +89,6 @@ def test_null_plan_calls_fail_cleanly(lib):
     assert lib.fc2t2_eval(None, None, None, 0, None, None, None, None) == 1
     assert lib.fc2t2_stage_timing(None, 1) == 1
     assert lib.fc2t2_stage_time(None, 0, None, None) == 1
+    assert lib.fc2t2_out_of_domain(None, None, 0, None) == 1
+    assert lib.fc2t2_eval_backward_ex(None, None, None, 0, None, None, None, None, 0, 0, None) == 1
+    assert lib.fc2t2_expand_backward_ex(None, None, None, None, 0, None, None, None, 0, 0, None) == 1

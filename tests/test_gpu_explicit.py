@@ -260,3 +260,28 @@ def test_backward_overwrite_equals_zero_then_accumulate(F, io, C):
     plan.eval_backward(Lt, q[:0], gy[:0], gL, None, accumulate=False)
     torch.cuda.synchronize()
     assert float(gL.abs().max()) == 0.0
+
+
+def test_out_of_domain_points_are_counted(F, monkeypatch):
+    """Sources and queries outside the domain (and NaN) are counted on the device; reset zeroes
+    the count; in debug mode the call that met them raises."""
+    plan = F.Plan(2, 16, 0.0, 1.0, "gaussian", 0.05, 3, m2l="f32", io="f32")
+    rng = np.random.default_rng(3)
+    p = rng.uniform(0, 1, (5000, 2)).astype(np.float32)
+    p[:37, 0] = 1.5
+    p[37:40, 1] = -0.25
+    p[40, 0] = np.nan
+    q = rng.uniform(0, 1, (3000, 2)).astype(np.float32)
+    q[-5:, 1] = 2.0
+    w = np.ones((5000, 1), np.float32)
+    Lt = plan.expand(_dev(p), _dev(w))
+    assert plan.out_of_domain() == 41
+    plan.eval(Lt, _dev(q))
+    assert plan.out_of_domain(reset=True) == 46
+    assert plan.out_of_domain() == 0
+    plan.eval(Lt, _dev(q[:-5]))
+    assert plan.out_of_domain() == 0
+    monkeypatch.setenv("FC2T2_DEBUG", "1")
+    with pytest.raises(F.FC2T2Error):
+        plan.eval(Lt, _dev(q))
+    plan.eval(Lt, _dev(q[:-5]))

@@ -86,6 +86,19 @@ __device__ __forceinline__ void hadamard(T (&x)[1 << D]) {
       }
 }
 
+// The same transform across the NB = 2^D consecutive lanes of a group, one value per lane:
+// lane pi of the group ends with sum_q (-1)^popc(pi & q) x_q.  Every lane of the wave must
+// take part (groups are aligned and whole).
+template <int D, typename T>
+__device__ __forceinline__ T hadamard_lanes(T v, int pi) {
+#pragma unroll
+  for (int st = 1; st < (1 << D); st <<= 1) {
+    const T o = __shfl_xor(v, st);
+    v = (pi & st) ? o - v : v + o;
+  }
+  return v;
+}
+
 // Coordinates of local index p in a tile of side 2^lg (last dimension fastest).
 template <int D>
 __device__ __forceinline__ void tile_coords(uint32_t p, int lg, uint32_t (&c)[3]) {
@@ -261,25 +274,27 @@ __global__ void __launch_bounds__(kShiftThreads) downchain_kernel(LevelPtrs grid
 #pragma unroll
     for (int d = 0; d < D; ++d) b = (b << 1) | (int)(ac[d] & 1u);
     const T* own_row = (const T*)grids.p[l] + (((size_t)ch << (lgn * D)) + tile_lin<D>(ac, lgn)) * PP;
-    T v = T(0);
-    const int k = tid;
-    if (k < P) {
-      T g[NB];
+    // thread (k, pi): one parity pattern's sum; the lanes' transform gives the child's value
+    // in lane NB - 1 - b of the group
+    constexpr int kRounds = (P * NB + kShiftThreads - 1) / kShiftThreads;
+    T v[kRounds];
 #pragma unroll
-      for (int pi = 0; pi < NB; ++pi) {
-        T a = T(0);
+    for (int r = 0; r < kRounds; ++r) {
+      const int t = tid + r * kShiftThreads;
+      const int pi = t & (NB - 1), k = t / NB;
+      T a = T(0);
+      if (k < P)
         for (int e = s_beg[k * (NB + 1) + pi]; e < s_beg[k * (NB + 1) + pi + 1]; ++e) a += s_coef[e] * buf0[s_m[e]];
-        g[pi] = a;
-      }
-      hadamard<D>(g);
-      T pick = g[0];
-#pragma unroll
-      for (int q = 1; q < NB; ++q)
-        if (q == NB - 1 - b) pick = g[q];
-      v = own_row[k] + pick;
+      a = hadamard_lanes<D>(a, pi);
+      v[r] = (k < P && pi == NB - 1 - b) ? own_row[k] + a : T(0);
     }
     __syncthreads();
-    if (k < PP) buf0[k] = v;
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const int t = tid + r * kShiftThreads;
+      const int pi = t & (NB - 1), k = t / NB;
+      if (k < P && pi == NB - 1 - b) buf0[k] = v[r];
+    }
   }
   {
     size_t off = 0;
@@ -310,25 +325,28 @@ __global__ void __launch_bounds__(kShiftThreads) downchain_kernel(LevelPtrs grid
     T* cout_lds = (j & 1) ? buf1 : buf0;
     const T* cown = own + own_off;
     T* cg = (T*)grids.p[lc] + ((size_t)ch << (lgn_c * D)) * PP;
-    for (uint32_t idx = tid; idx < npar * PP; idx += kShiftThreads) {
-      const uint32_t p = idx / PP, k = idx - p * PP;
-      if (k >= P) continue;
-      const T* row = pin + (size_t)p * PP;
-      T g[NB];
-#pragma unroll
-      for (int pi = 0; pi < NB; ++pi) {
-        T a = T(0);
+    // thread (p, k, pi): one parity pattern's sum over the parent row; after the lanes'
+    // transform, lane pi holds the value of child NB - 1 - pi.  The trip count is uniform so
+    // every lane takes part in the exchange.
+    const uint32_t work = npar * P * NB;
+    for (uint32_t t0 = 0; t0 < work; t0 += kShiftThreads) {
+      const uint32_t t = t0 + tid;
+      const bool valid = t < work;
+      const int pi = (int)(t & (NB - 1));
+      const uint32_t pk = t / NB;
+      const uint32_t p = pk / P, k = pk - p * P;
+      T a = T(0);
+      if (valid) {
+        const T* row = pin + (size_t)p * PP;
         for (int e = s_beg[k * (NB + 1) + pi]; e < s_beg[k * (NB + 1) + pi + 1]; ++e) a += s_coef[e] * row[s_m[e]];
-        g[pi] = a;
       }
-      hadamard<D>(g);
-      uint32_t pc[3], cc[3];
-      tile_coords<D>(p, lgp, pc);
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        child_coords<D>(pc, b, cc);
+      a = hadamard_lanes<D>(a, pi);
+      if (valid) {
+        uint32_t pc[3], cc[3];
+        tile_coords<D>(p, lgp, pc);
+        child_coords<D>(pc, NB - 1 - pi, cc);
         const uint32_t cl = tile_lin<D>(cc, lgp + 1);
-        const T v = cown[(size_t)cl * PP + k] + g[NB - 1 - b];
+        const T v = cown[(size_t)cl * PP + k] + a;
         if (j < f) {
           cout_lds[(size_t)cl * PP + k] = v;
         } else {

@@ -69,18 +69,19 @@ def p_pad(dim: int, K: int) -> int:
 def stage_bytes(stage: str, dim: int, n: int, K: int, N: int = 0, M: int = 0, itemsize: int = 4,
                 channels: int = 1) -> int:
     """Algorithmic HBM bytes of one call of a single-kernel stage: every point record and
-    every finest-grid row it must touch, once.
+    every finest-grid row it must touch, once.  Backward outputs are counted as written, not
+    updated (the step overwrites its gradient buffers).
 
     per source / query (es = itemsize, d = dim):
       p2m    sorted p, w read (once, contiguous)        (d + 1) es
       l2p    q read, y written                          (d + 1) es
       l2p_T  sorted q, gy read (once, contiguous)       (d + 1) es
-      qgrad  q, gy read, q_bar read and written         (3 d + 1) es
+      qgrad  q, gy read, q_bar written                  (2 d + 1) es
       p2m_T  p, w read, p_bar, w_bar written            2 (d + 1) es
     per finest cell (R = P_pad es channels, one row):
       p2m    cell start read, moment row written        4 + R
       l2p    local row read                             R
-      l2p_T  cell start read, cotangent row updated     4 + 2 R
+      l2p_T  cell start read, cotangent row written     4 + R
       qgrad  local row read                             R
       p2m_T  moment-cotangent row read                  R
     """
@@ -91,9 +92,9 @@ def stage_bytes(stage: str, dim: int, n: int, K: int, N: int = 0, M: int = 0, it
     if stage == "l2p":
         return M * (d + 1) * es + G * R
     if stage == "l2p_T":
-        return M * (d + 1) * es + G * (4 + 2 * R)
+        return M * (d + 1) * es + G * (4 + R)
     if stage == "qgrad":
-        return M * (3 * d + 1) * es + G * R
+        return M * (2 * d + 1) * es + G * R
     if stage == "p2m_T":
         return N * 2 * (d + 1) * es + G * R
     raise ValueError(stage)

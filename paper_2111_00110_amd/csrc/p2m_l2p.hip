@@ -185,6 +185,37 @@ __global__ void __launch_bounds__(256) gather_eval_kernel(const T* __restrict__ 
   }
 }
 
+// q_bar over the queries in sorted order (FP32, one channel): record r holds the query's
+// coordinates and cotangent (pay [M][D + 1]), its cell (keys) and input index (perm); queries of
+// one cell are neighbours, so their row is read from cache.  gq[perm[r]] = (or +=) gy grad f / h.
+template <class S>
+__global__ void __launch_bounds__(256) qgrad_sorted_kernel(const float* __restrict__ grid, const float* __restrict__ pay,
+                                                           const uint32_t* __restrict__ keys,
+                                                           const uint32_t* __restrict__ perm, int64_t count, int n,
+                                                           float lo, float h, float inv_h, float* __restrict__ gq,
+                                                           int accumulate) {
+  constexpr int D = S::D, Ppad = S::Ppad, W = D + 1;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= count) return;
+  const int64_t cell = keys[r];
+  int ic[3];
+  decode_cell<D, float>(cell, n, ic);
+  const float* rec = pay + r * W;
+  float u[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int j = 0; j < D; ++j) u[j] = (rec[j] - (lo + (float(ic[j]) + 0.5f) * h)) * inv_h;
+  float pw[3][S::K + 1];
+  power_table<S>(u, pw);
+  float c[Ppad];
+  load_row<Ppad>(grid + cell * Ppad, c);
+  float val, g[3], hs[6];
+  eval_poly<S, float, true, false>(c, pw, val, g, hs);
+  const float a = rec[D];
+  const int64_t i = perm[r];
+#pragma unroll
+  for (int j = 0; j < D; ++j) gq[i * D + j] = accumulate ? gq[i * D + j] + a * g[j] * inv_h : a * g[j] * inv_h;
+}
+
 template <typename T, int MODE>
 fc2t2_status gather_eval(const fc2t2_plan_s* pl, const void* grid, const void* x, int64_t count,
                          const void* wts, void* out_v, void* out_g, void* out_h, hipStream_t s,
@@ -338,6 +369,23 @@ fc2t2_status launch_p2m_T(const fc2t2_plan_s* pl, const void* GM0, const void* p
   const int acc = accumulate ? 1 : 0;
   return pl->io == FC2T2_IO_F64 ? gather_eval<double, 2>(pl, GM0, p, N, w, gw, gp, nullptr, s, acc)
                                 : gather_eval<float, 2>(pl, GM0, p, N, w, gw, gp, nullptr, s, acc);
+}
+
+fc2t2_status launch_qgrad_sorted(const fc2t2_plan_s* pl, const void* L, const void* pay, const uint32_t* keys,
+                                 const uint32_t* perm, int64_t M, void* gq, hipStream_t s, bool accumulate) {
+  if (pl->io != FC2T2_IO_F32 || pl->C != 1) return FC2T2_EUNSUPPORTED;
+  if (M == 0) return FC2T2_OK;
+  fc2t2_status st = FC2T2_EUNSUPPORTED;
+  const dim3 grid((unsigned)ceil_div(M, 256));
+  dispatch_shape(pl->dim, pl->K, [&](auto shape) {
+    using S = decltype(shape);
+    hipLaunchKernelGGL((qgrad_sorted_kernel<S>), grid, dim3(256), 0, s, (const float*)L, (const float*)pay, keys, perm,
+                       M, pl->n, (float)pl->lo, (float)pl->h0, (float)(1.0 / pl->h0), (float*)gq, accumulate ? 1 : 0);
+    st = FC2T2_OK;
+  });
+  if (st != FC2T2_OK) return st;
+  FC2T2_LAUNCH_CHECK();
+  return FC2T2_OK;
 }
 
 template <typename T>

@@ -126,6 +126,10 @@ fc2t2_status launch_l2p_qgrad(const fc2t2_plan_s* pl, const void* L, const void*
 // Transpose of P2M: gw += <GM0, mono>, gp += w <GM0, grad mono> / h (or = for both).
 fc2t2_status launch_p2m_T(const fc2t2_plan_s* pl, const void* GM0, const void* p, const void* w,
                           int64_t N, void* gp, void* gw, hipStream_t s, bool accumulate = true);
+// q_bar from queries sorted with their data (FP32, one channel): pay [M][dim + 1], keys the
+// sorted cells, perm the input indices; gq[perm[r]] += (or =) gy grad f(q) / h.
+fc2t2_status launch_qgrad_sorted(const fc2t2_plan_s* pl, const void* L, const void* pay, const uint32_t* keys,
+                                 const uint32_t* perm, int64_t M, void* gq, hipStream_t s, bool accumulate = true);
 // p[0 .. elems) = 0 in the plan's IO type (a fill kernel, safe under graph capture).
 fc2t2_status launch_zero(const fc2t2_plan_s* pl, void* p, int64_t elems, hipStream_t s);
 

@@ -129,9 +129,11 @@ int fc2t2_supported(int dim, int K);
 
 /* Build a plan: validates the arguments, generates every level's M2L tensor
  * T[k, n](o) = h^(|k|+|n|) (-1)^|n| d^(k+n) psi(-o h) for o in [-3, 3]^dim in FP64 on the
- * GPU (section 3, K^{M2L}; derivatives in closed form for the radial kernels), rounds it
- * to the contraction precision, and uploads the M2M/L2L shift tables.  `channels` is the
- * number C of weight columns.  Synchronises `stream`.  *out is set only on success. */
+ * GPU (section 3, K^{M2L}; derivatives in closed form for the radial kernels), or its
+ * least-squares fit when m2l_prec carries FC2T2_M2L_FIT_LSQ, rounds it to the contraction
+ * precision, and uploads the M2M/L2L shift tables.  m2l_prec is a fc2t2_m2l_prec value,
+ * optionally OR'ed with FC2T2_M2L_FIT_LSQ.  `channels` is the number C of weight columns.
+ * Synchronises `stream`.  *out is set only on success. */
 fc2t2_status fc2t2_plan_create(const fc2t2_grid* grid, const fc2t2_kernel* kernel, int K,
                                int m2l_prec, int io, int channels, hipStream_t stream,
                                fc2t2_plan* out);

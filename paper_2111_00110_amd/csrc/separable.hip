@@ -28,8 +28,8 @@
 // registers) and the last pass axis 1; in 2-D the last pass contracts axis 0.  Intermediate
 // rows are stored as planes [index][cell], so a wave's loads and stores are contiguous.  Lanes
 // are cells and every loop (group, input component, offset, output component) is uniform, so
-// the coefficients are scalar operands.  Each pass covers every level and both the window and
-// the hole chains in one launch; the intermediates live in the caller's workspace.
+// the coefficients are scalar operands.  Each pass covers every level and both streams in one
+// launch; the intermediates live in the caller's workspace.
 #include <math.h>
 
 #include <map>

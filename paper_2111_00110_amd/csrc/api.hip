@@ -163,14 +163,18 @@ fc2t2_status eval_backward_impl(fc2t2_plan plan, const void* L, const void* q, i
       st = bin_and_sort(plan, q, M, sb, stream, carry ? gy : nullptr);
     }
     if (st) return st;
-    if (carry) {   // contiguous sorted queries; q_bar over them in the same order
+    if (carry) {   // contiguous sorted queries
       {
         StageScope t(plan, FC2T2_STAGE_L2P_T, stream);
         st = launch_reduce_sorted(plan, sb.pay, M, sb.starts, gL, acc, stream);
       }
       if (st || !gq) return st;
       StageScope t(plan, FC2T2_STAGE_QGRAD, stream);
-      return launch_qgrad_sorted(plan, L, sb.pay, sb.keys_sorted, sb.perm, M, gq, stream, acc);
+      // q_bar in cell order (rows from cache, scattered writes of q_bar) in 2-D; in input order
+      // (scattered row reads, contiguous writes) in 3-D, where the wider scattered writes
+      // measured slower
+      if (plan->dim == 2) return launch_qgrad_sorted(plan, L, sb.pay, sb.keys_sorted, sb.perm, M, gq, stream, acc);
+      return launch_l2p_qgrad(plan, L, q, M, gy, gq, stream, acc);
     }
     StageScope t(plan, FC2T2_STAGE_L2P_T, stream);
     if (gq && plan->C == 1) {   // one pass over the sorted queries produces both (q_bar accumulated)

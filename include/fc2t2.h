@@ -52,7 +52,7 @@ extern "C" {
 typedef enum {
   FC2T2_OK = 0,
   FC2T2_EINVAL = 1,        /* a NULL pointer, a negative size or an out-of-range argument */
-  FC2T2_EUNSUPPORTED = 2,  /* a valid combination this build does not implement */
+  FC2T2_EUNSUPPORTED = 2,  /* a valid combination the library does not implement */
   FC2T2_EHIP = 3,          /* a HIP runtime call failed (launch or allocation) */
   FC2T2_ENOMEM = 4,        /* device allocation inside plan creation failed */
   FC2T2_EWORKSPACE = 5     /* ws_bytes smaller than fc2t2_workspace_size asks */

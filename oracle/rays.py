@@ -20,7 +20,15 @@
   cotangents of the root t* and of the surface gradient grad f(q*), the cotangent of the
   finest locals is a (q* - c)^k / k! + sum_j n_bar_j d/dq_j (q* - c)^k / k! with
   a = -(t_bar + n_bar . H r) / (r . grad f).  tau is treated as a constant (like the
-  paper's bias).
+  paper's bias).  The theorem needs r . grad f != 0 (section 5.2 assumes the derivative
+  along the ray invertible); two kinds of hit do not meet it and keep only the dipole term
+  (a = 0):
+    - a face crossing: t* sits on the face for every small change of the locals (the jump
+      persists), so dt*/dL = 0 and only grad f(q*) at the fixed point moves;
+    - a grazing root: |r . grad f| <= GRAZE_COS |r| |grad f| (the ray is tangent to the
+      level set to within that cosine); the root's sensitivity is unbounded there and is
+      masked rather than inserted.
+  ray_root reports the kind of each hit (ROOT_SMOOTH, ROOT_FACE, ROOT_GRAZING).
 
 Segments come from exact FP64 intersection with every grid plane (no incremental
 traversal): the crossing parameters are sorted and each segment is assigned the cell
@@ -37,6 +45,9 @@ from scipy import optimize
 
 from . import fmm
 from .direct import clip_ray
+
+ROOT_SMOOTH, ROOT_FACE, ROOT_GRAZING = 0, 1, 2
+GRAZE_COS = 1e-4      # cosine between the ray and grad f(q*) below which a root is grazing
 
 
 def segments(geo: fmm.Geometry, o, r, t0: float, t1: float):
@@ -192,13 +203,14 @@ def first_upward_root(c, s: float):
 
 def ray_root(geo: fmm.Geometry, L0: np.ndarray, o, r, t0, t1, frac: float = 0.5,
              tau_override=None) -> dict:
-    """Per ray: t* (nan if dead), hit, tau, the root's cell, grad f(q*) and H(q*).
-    L0 has one channel."""
+    """Per ray: t* (nan if dead), hit, tau, the root's cell, grad f(q*), H(q*) and the kind
+    of the hit (ROOT_SMOOTH, ROOT_FACE or ROOT_GRAZING; 0 for dead rays).  L0 has one
+    channel."""
     R = len(o)
     res = {
         "t": np.full(R, np.nan), "hit": np.zeros(R, dtype=np.int32), "tau": np.zeros(R),
         "cell": np.zeros((R, geo.dim), dtype=np.int64), "normal": np.zeros((R, geo.dim)),
-        "hess": np.zeros((R, geo.dim, geo.dim)),
+        "hess": np.zeros((R, geo.dim, geo.dim)), "kind": np.zeros(R, dtype=np.int32),
     }
     for ri in range(R):
         segs = segments(geo, o[ri], r[ri], t0, t1)
@@ -219,28 +231,34 @@ def ray_root(geo: fmm.Geometry, L0: np.ndarray, o, r, t0, t1, frac: float = 0.5,
             g[0] -= tau
             if prev is not None and prev[0] < 0.0 <= npoly.polyval(0.0, g):
                 # the crossing happens across the face: it lies on the face, earlier cell
-                t, rcell = prev[2], prev[1]
+                t, rcell, kind = prev[2], prev[1], ROOT_FACE
             else:
                 u = first_upward_root(g, tb - ta)
                 if u is None:
                     prev = (npoly.polyval(tb - ta, g), cell, tb)
                     continue
-                t, rcell = ta + u, cell
+                t, rcell, kind = ta + u, cell, ROOT_SMOOTH
             q = np.asarray(o[ri], dtype=np.float64) + t * np.asarray(r[ri], dtype=np.float64)
             dq = q - geo.centre(0, np.asarray(rcell))
             row = L0[(0,) + rcell]
             res["t"][ri] = t
             res["hit"][ri] = 1
             res["cell"][ri] = rcell
-            res["normal"][ri] = row @ fmm.monomial_grads(dq[None], geo.idx)[0]
+            grad = row @ fmm.monomial_grads(dq[None], geo.idx)[0]
+            rr = np.asarray(r[ri], dtype=np.float64)
+            if kind == ROOT_SMOOTH and abs(rr @ grad) <= GRAZE_COS * np.linalg.norm(rr) * np.linalg.norm(grad):
+                kind = ROOT_GRAZING
+            res["normal"][ri] = grad
             res["hess"][ri] = np.einsum("p,pab->ab", row,
                                         fmm.monomial_hessians(dq[None], geo.idx)[0])
+            res["kind"][ri] = kind
             break
     return res
 
 
 def ray_root_T(geo: fmm.Geometry, o, r, root: dict, gt, gn) -> np.ndarray:
-    """Cotangent of L0 (one channel) from root cotangents (implicit function theorem)."""
+    """Cotangent of L0 (one channel) from root cotangents (implicit function theorem).
+    Face crossings and grazing roots insert only the dipole term (module docstring)."""
     G = np.zeros((1,) + (geo.n,) * geo.dim + (geo.P,))
     R = len(o)
     gt = np.zeros(R) if gt is None else np.asarray(gt, dtype=np.float64)
@@ -252,9 +270,10 @@ def ray_root_T(geo: fmm.Geometry, o, r, root: dict, gt, gn) -> np.ndarray:
         q = np.asarray(o[ri], dtype=np.float64) + root["t"][ri] * rr
         cell = tuple(int(v) for v in root["cell"][ri])
         dq = q - geo.centre(0, np.asarray(cell))
-        denom = rr @ root["normal"][ri]
-        a = -(gt[ri] + gn[ri] @ root["hess"][ri] @ rr) / denom
-        mono = fmm.monomials(dq[None], geo.idx)[0]
         mgrad = fmm.monomial_grads(dq[None], geo.idx)[0]
-        G[(0,) + cell] += a * mono + mgrad @ gn[ri]
+        G[(0,) + cell] += mgrad @ gn[ri]
+        if root["kind"][ri] == ROOT_SMOOTH:
+            denom = rr @ root["normal"][ri]
+            a = -(gt[ri] + gn[ri] @ root["hess"][ri] @ rr) / denom
+            G[(0,) + cell] += a * fmm.monomials(dq[None], geo.idx)[0]
     return G

@@ -505,6 +505,145 @@ def test_ray_root_face_crossing_belongs_to_earlier_cell():
     assert res["hit"][0] == 1 and abs(res["tau"][0] - 0.5) < 1e-15
     assert abs(res["t"][0] - 2.0) < 1e-15
     assert tuple(res["cell"][0]) == (3, 4, 3)
+    assert res["kind"][0] == rays.ROOT_FACE
+
+
+def _face_crossing_field(rng, geo):
+    """Locals with a jump across the face x = 0: smooth and below 0.5 in the cells x < 0 next
+    to it (x index 3), about 1 beyond it, zero elsewhere; random first and second order terms
+    so that the surface gradient and the Hessian are generic."""
+    L0 = np.zeros((1,) + (geo.n,) * 3 + (geo.P,))
+    L0[0, 3] = 0.04 * rng.standard_normal(L0[0, 3].shape)
+    L0[0, 3, ..., 0] += 0.2
+    L0[0, 4:] = 0.04 * rng.standard_normal(L0[0, 4:].shape)
+    L0[0, 4:, ..., 0] += 1.0
+    return L0
+
+
+def test_ray_root_face_crossing_backward_matches_finite_differences():
+    """At a face crossing the root stays on the face when the locals move a little (the jump
+    persists), so dt*/dL = 0 and the surface gradient moves only through the locals of the
+    earlier cell at the fixed point.  Central differences of the checker's root (tau held
+    fixed) against ray_root_T, on a ray that is not axis-aligned."""
+    rng = np.random.default_rng(31)
+    geo = fmm.Geometry(3, 8, -1, 1, 2)
+    L0 = _face_crossing_field(rng, geo)
+    o = np.array([[-2.0, 0.1, -0.05]])
+    r = np.array([[1.0, 0.05, -0.03]])
+    r /= np.linalg.norm(r)
+    res = rays.ray_root(geo, L0, o, r, 0.0, 4.0)
+    assert res["hit"][0] == 1 and res["kind"][0] == rays.ROOT_FACE
+    assert tuple(res["cell"][0]) == (3, 4, 3)
+    assert abs(o[0, 0] + res["t"][0] * r[0, 0]) < 1e-14          # on the face x = 0
+    gt = np.array([0.7])
+    gn = np.array([[0.3, -1.1, 0.4]])
+    G = rays.ray_root_T(geo, o, r, res, gt, gn)
+
+    def loss(L):
+        rr = rays.ray_root(geo, L, o, r, 0.0, 4.0, tau_override=res["tau"])
+        return float(gt @ rr["t"] + np.sum(gn * rr["normal"]))
+    eps = 1e-6
+    for cell in [(3, 4, 3), (4, 4, 3)]:
+        for k in range(geo.P):
+            e = np.zeros_like(L0)
+            e[(0,) + cell + (k,)] = eps
+            fd = (loss(L0 + e) - loss(L0 - e)) / (2 * eps)
+            assert abs(fd - G[(0,) + cell + (k,)]) < 1e-7 * max(1.0, abs(fd)), (cell, k)
+    # only the earlier cell's locals move the outputs
+    assert np.abs(G[0, 4, 4, 3]).max() == 0.0 and np.abs(G[0, 3, 4, 3]).max() > 0.1
+
+
+def test_ray_root_grazing_root_is_masked():
+    """f = A + B x^3 + C y in one cell ((x, y, z) = q - c, the checker's locals are physical
+    derivatives at the centre): along +x at fixed y the level A is crossed upward at the cell
+    centre with zero slope along the ray, so r . grad f = 0 while grad f = (0, C, 0) is not.  The root is reported as grazing, and its cotangent holds only
+    the dipole term n_bar . grad (q* - c)^k / k!, finite.  The same field tilted so that the
+    slope along the ray is clearly non-zero gives a smooth root whose cotangent matches central
+    differences."""
+    geo = fmm.Geometry(3, 8, -1, 1, 3)
+    idx = geo.idx
+    A, B, C = 0.6, 0.5, 0.3
+
+    def field(slope):
+        L0 = np.zeros((1, 8, 8, 8, geo.P))
+        L0[0, :4, :, :, 0] = A - 0.5                 # below the level before the cell
+        row = np.zeros(geo.P)
+        row[idx.index((0, 0, 0))] = A
+        row[idx.index((3, 0, 0))] = 6.0 * B          # B x^3 = L x^k / k! with k = (3, 0, 0)
+        row[idx.index((0, 1, 0))] = C
+        row[idx.index((1, 0, 0))] = slope
+        L0[0, 4, 4, 4] = row
+        return L0
+
+    o = np.array([[-2.0, 0.125, 0.125]])       # through the centre of cell (4, 4, 4) in y and z
+    r = np.array([[1.0, 0.0, 0.0]])
+    tau = np.array([A])
+    L0 = field(0.0)
+    res = rays.ray_root(geo, L0, o, r, 0.0, 4.0, tau_override=tau)
+    assert res["hit"][0] == 1 and res["kind"][0] == rays.ROOT_GRAZING
+    assert abs(res["t"][0] - (2.0 + 0.125)) < 1e-6    # cube root of rounding at the centre
+    np.testing.assert_allclose(res["normal"][0], [0.0, C, 0.0], atol=1e-9)
+    gt, gn = np.array([1.3]), np.array([[0.2, -0.5, 0.9]])
+    G = rays.ray_root_T(geo, o, r, res, gt, gn)
+    assert np.all(np.isfinite(G))
+    q = o[0] + res["t"][0] * r[0]
+    dq = q - geo.centre(0, np.array([4, 4, 4]))
+    np.testing.assert_allclose(G[0, 4, 4, 4], fmm.monomial_grads(dq[None], idx)[0] @ gn[0], atol=1e-12)
+
+    L1 = field(0.2)
+    res1 = rays.ray_root(geo, L1, o, r, 0.0, 4.0, tau_override=tau)
+    assert res1["hit"][0] == 1 and res1["kind"][0] == rays.ROOT_SMOOTH
+    G1 = rays.ray_root_T(geo, o, r, res1, gt, gn)
+
+    def loss(L):
+        rr = rays.ray_root(geo, L, o, r, 0.0, 4.0, tau_override=tau)
+        return float(gt @ rr["t"] + np.sum(gn * rr["normal"]))
+    for k in range(geo.P):
+        e = np.zeros_like(L1)
+        e[0, 4, 4, 4, k] = 1e-7
+        fd = (loss(L1 + e) - loss(L1 - e)) / 2e-7
+        assert abs(fd - G1[0, 4, 4, 4, k]) < 1e-5 * max(1.0, abs(fd)), k
+
+
+def test_smooth_roots_are_not_masked():
+    """Roots of a generic field cross the level at a clear angle: none is flagged."""
+    rng = np.random.default_rng(22)
+    ker = kernels.Gaussian(0.15)
+    geo = fmm.Geometry(3, 16, -1, 1, 4)
+    u = rng.standard_normal((80, 3))
+    p = 0.5 * u / np.linalg.norm(u, axis=1, keepdims=True)
+    w = rng.uniform(0.5, 1.5, (80, 1))
+    o, r = _rays(rng, 6)
+    res = rays.ray_root(geo, fmm.expand(geo, ker, p, w), o, r, 0.0, 4.0)
+    assert res["hit"].all() and (res["kind"] == rays.ROOT_SMOOTH).all()
+
+
+def test_clip_ray_against_dense_membership():
+    """The clipped interval against membership of dense samples of the ray in the box, and
+    axis-aligned cases with known intervals (entering, starting inside, missing, parallel)."""
+    rng = np.random.default_rng(32)
+    for _ in range(40):
+        o = rng.uniform(-3, 3, 3)
+        r = rng.standard_normal(3)
+        r /= np.linalg.norm(r)
+        ta, tb = direct.clip_ray(o, r, 0.0, 4.0, -1.0, 1.0)
+        t = np.linspace(0.0, 4.0, 40001)
+        inside = np.all(np.abs(o[None] + t[:, None] * r[None]) <= 1.0, axis=1)
+        if not inside.any():
+            assert not tb > ta
+            continue
+        assert abs(t[inside].min() - ta) <= 1e-4 and abs(t[inside].max() - tb) <= 1e-4
+    cases = [((-2.0, 0.0, 0.0), (1.0, 0.0, 0.0), (1.0, 3.0)),
+             ((0.5, 0.0, 0.0), (1.0, 0.0, 0.0), (0.0, 0.5)),
+             ((0.0, 0.0, 0.0), (0.0, 0.0, -1.0), (0.0, 1.0)),
+             ((-2.0, 1.5, 0.0), (1.0, 0.0, 0.0), None),
+             ((-6.0, 0.0, 0.0), (1.0, 0.0, 0.0), None)]
+    for o, r, want in cases:
+        ta, tb = direct.clip_ray(np.array(o), np.array(r), 0.0, 4.0, -1.0, 1.0)
+        if want is None:
+            assert not tb > ta
+        else:
+            assert (ta, tb) == want
 
 
 # ---------------------------------------------------------------------------------------

@@ -152,6 +152,11 @@ int fc2t2_plan_levels(fc2t2_plan plan);
 fc2t2_status fc2t2_out_of_domain(fc2t2_plan plan, int64_t* count, int reset, hipStream_t stream);
 size_t fc2t2_local_numel(fc2t2_plan plan);    /* C * n^dim * P_pad elements */
 
+/* Ray roots that fc2t2_ray_root classified as grazing (FC2T2_ROOT_GRAZING) on this plan since
+ * its creation or the last reset, counted on the device; same calling rules as
+ * fc2t2_out_of_domain. */
+fc2t2_status fc2t2_grazing_roots(fc2t2_plan plan, int64_t* count, int reset, hipStream_t stream);
+
 /* Scratch bytes `op` needs for `count` points or rays (0 for an invalid op). */
 size_t fc2t2_workspace_size(fc2t2_plan plan, int op, int64_t count);
 
@@ -210,19 +215,39 @@ fc2t2_status fc2t2_ray_integral_backward(fc2t2_plan plan, const void* o, const v
  * ray, then the first t where f - tau_r goes from negative to non-negative (a root on a
  * cell face belongs to the earlier cell).  Outputs: t [R] (NaN if none), normal [R][3] =
  * grad f at the root (zero if none), hit [R] int32 (1 hit, 0 dead ray: no crossing, or
- * f >= tau at entry), saved [R][FC2T2_ROOT_SAVED] (state for the backward: root point,
- * r . grad f, H r, tau, cell).  The root is polished by one FP64 Newton step.  The call
- * first writes per-cell bounds of L into a buffer the plan owns, so ray-root calls on one
- * plan must not overlap in time (issue them on one stream). */
+ * f >= tau at entry), saved [R][FC2T2_ROOT_SAVED] (state for the backward, IO type: root
+ * point [0..2], the root's finest cell index as the bits of an unsigned integer of the
+ * slot's width [3], r . grad f [4], H r [5..7], tau [8], t [9], the kind of the hit [10]:
+ * FC2T2_ROOT_SMOOTH, FC2T2_ROOT_FACE (the level is crossed by the jump of the piecewise
+ * expansion across a cell face) or FC2T2_ROOT_GRAZING (|r . grad f| <= FC2T2_GRAZE_COS
+ * |r| |grad f|: the ray is tangent to the level set to within that cosine; counted on the
+ * device, read with fc2t2_grazing_roots)).  The root is polished by one FP64 Newton step.
+ * The call first writes per-cell bounds of L into a buffer the plan owns, so ray-root calls
+ * on one plan must not overlap in time (issue them on one stream).  EUNSUPPORTED for grids
+ * of more than 2^32 cells. */
 #define FC2T2_ROOT_SAVED 12
+#define FC2T2_ROOT_SMOOTH 0
+#define FC2T2_ROOT_FACE 1
+#define FC2T2_ROOT_GRAZING 2
+#define FC2T2_GRAZE_COS 1e-4
 fc2t2_status fc2t2_ray_root(fc2t2_plan plan, const void* L, const void* o, const void* r,
                             double t0, double t1, int64_t R, double level_frac, void* t,
                             void* normal, int32_t* hit, void* saved, hipStream_t stream);
 
+/* fc2t2_ray_root with given levels: the first t where f - tau[r] goes from negative to
+ * non-negative, for a per-ray level tau [R] (IO type) instead of level_frac * max f, e.g. the
+ * zero level of an implicit surface with a constant bias (section 5.1).  Same outputs, kinds
+ * and backward (saved[8] holds the given level); the maximum along the ray is not computed. */
+fc2t2_status fc2t2_ray_root_at(fc2t2_plan plan, const void* L, const void* o, const void* r,
+                               double t0, double t1, int64_t R, const void* tau, void* t,
+                               void* normal, int32_t* hit, void* saved, hipStream_t stream);
+
 /* Backward of fc2t2_ray_root (section 5.2, implicit function theorem), tau held fixed:
  * gL += a (q* - c)^k / k! + sum_j gn_j d/dq_j (q* - c)^k / k!, with
- * a = -(gt + gn . H r) / (r . grad f), for every ray with hit = 1.  gt [R] and gn [R][3]
- * may each be NULL (zero). */
+ * a = -(gt + gn . H r) / (r . grad f), for every ray with hit = 1.  The theorem needs
+ * r . grad f != 0: a FC2T2_ROOT_FACE hit has a root that does not move with L (it stays on the face) and a
+ * FC2T2_ROOT_GRAZING hit one of unbounded sensitivity, so both insert the dipole term only (a = 0).
+ * gt [R] and gn [R][3] may each be NULL (zero). */
 fc2t2_status fc2t2_ray_root_backward(fc2t2_plan plan, const void* saved, const int32_t* hit,
                                      int64_t R, const void* gt, const void* gn, void* gL,
                                      void* ws, size_t ws_bytes, hipStream_t stream);

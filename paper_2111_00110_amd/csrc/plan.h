@@ -12,6 +12,8 @@ struct fc2t2_plan_s {
   int dim, n, K, P, Ppad, C, levels, io, prec, kind;
   bool fit_lsq = false;            // M2L tensors fitted by least squares (section 3.1)
   unsigned long long* ood = nullptr;   // device counter: points outside the domain (expand, eval)
+  unsigned long long* grazing = nullptr;   // device counter: grazing ray roots (ray root); the
+                                           //   second word of the ood allocation
   double lo, hi, param;
   double h0;                      // finest cell width
   int64_t G;                      // finest cells
@@ -188,7 +190,7 @@ fc2t2_status ray_integral_backward(const fc2t2_plan_s* pl, const void* o, const 
                                    hipStream_t s);
 fc2t2_status launch_ray_root(const fc2t2_plan_s* pl, const void* L, const void* o, const void* r,
                              double t0, double t1, int64_t R, double frac, void* t, void* normal,
-                             int32_t* hit, void* saved, hipStream_t s);
+                             int32_t* hit, void* saved, hipStream_t s, const void* tau_in = nullptr);
 size_t ray_root_bwd_ws(const fc2t2_plan_s* pl, int64_t R);
 fc2t2_status ray_root_backward(const fc2t2_plan_s* pl, const void* saved, const int32_t* hit,
                                int64_t R, const void* gt, const void* gn, void* gL, void* ws,

@@ -458,12 +458,13 @@ fc2t2_status fc2t2_plan_create(const fc2t2_grid* grid, const fc2t2_kernel* kerne
     return st;
   };
 
-  // ---- out-of-domain counter
-  if (hipMalloc((void**)&pl->ood, sizeof(unsigned long long)) != hipSuccess) {
+  // ---- device counters: out-of-domain points, grazing ray roots
+  if (hipMalloc((void**)&pl->ood, 2 * sizeof(unsigned long long)) != hipSuccess) {
     pl->ood = nullptr;
     return fail(FC2T2_ENOMEM);
   }
-  if (hipMemsetAsync(pl->ood, 0, sizeof(unsigned long long), stream) != hipSuccess) return fail(FC2T2_EHIP);
+  pl->grazing = pl->ood + 1;
+  if (hipMemsetAsync(pl->ood, 0, 2 * sizeof(unsigned long long), stream) != hipSuccess) return fail(FC2T2_EHIP);
 
   // ---- host tables
   const int P = pl->P, Ppad = pl->Ppad;
@@ -594,18 +595,29 @@ fc2t2_status fc2t2_plan_destroy(fc2t2_plan plan) {
   return FC2T2_OK;
 }
 
-fc2t2_status fc2t2_out_of_domain(fc2t2_plan plan, int64_t* count, int reset, hipStream_t stream) {
-  if (!plan || !count) return FC2T2_EINVAL;
+namespace {
+fc2t2_status read_counter(unsigned long long* ctr, int64_t* count, int reset, hipStream_t stream) {
   unsigned long long v = 0;
-  if (hipMemcpyAsync(&v, plan->ood, sizeof(v), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+  if (hipMemcpyAsync(&v, ctr, sizeof(v), hipMemcpyDeviceToHost, stream) != hipSuccess ||
       hipStreamSynchronize(stream) != hipSuccess)
     return FC2T2_EHIP;
   *count = (int64_t)v;
   if (reset) {
-    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, stream, plan->ood);
+    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, stream, ctr);
     if (hipGetLastError() != hipSuccess) return FC2T2_EHIP;
   }
   return FC2T2_OK;
+}
+}  // namespace
+
+fc2t2_status fc2t2_out_of_domain(fc2t2_plan plan, int64_t* count, int reset, hipStream_t stream) {
+  if (!plan || !count) return FC2T2_EINVAL;
+  return read_counter(plan->ood, count, reset, stream);
+}
+
+fc2t2_status fc2t2_grazing_roots(fc2t2_plan plan, int64_t* count, int reset, hipStream_t stream) {
+  if (!plan || !count) return FC2T2_EINVAL;
+  return read_counter(plan->grazing, count, reset, stream);
 }
 
 int fc2t2_plan_P(fc2t2_plan plan) { return plan ? plan->P : -1; }

@@ -23,6 +23,13 @@ namespace {
 
 constexpr int kRaySaved = FC2T2_ROOT_SAVED;
 
+// The root's finest cell travels in a slot of the saved record as the bits of an integer
+// (32 bits in an FP32 record, 64 in an FP64 one), never as a floating-point value.
+__device__ __forceinline__ void put_cell(float& slot, int64_t c) { slot = __uint_as_float((uint32_t)c); }
+__device__ __forceinline__ void put_cell(double& slot, int64_t c) { slot = __longlong_as_double((long long)c); }
+__device__ __forceinline__ int64_t get_cell(float slot) { return (int64_t)__float_as_uint(slot); }
+__device__ __forceinline__ int64_t get_cell(double slot) { return (int64_t)__double_as_longlong(slot); }
+
 // ---------------------------------------------------------------------------------------
 // Per-axis state is kept in scalars (no runtime-indexed arrays, which would live in
 // scratch memory); the axis of the next crossing is chosen with selects.
@@ -496,6 +503,7 @@ __device__ __forceinline__ void root_gradients(const T* __restrict__ row_ptr, co
 }
 
 constexpr int kRootSub = 8;
+constexpr int kRootSmooth = FC2T2_ROOT_SMOOTH, kRootFace = FC2T2_ROOT_FACE, kRootGrazing = FC2T2_ROOT_GRAZING;
 
 // Bounds of each finest cell's polynomial over the whole cell: with u in [-1/2, 1/2]^3,
 // |f(u) - L_0| <= B = sum_{k != 0} |L_k| prod_j (1/2)^{k_j} / k_j!.  Stored as the float pair
@@ -528,7 +536,9 @@ __global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, c
                                                       double lo, double hi, double h, int n, double frac,
                                                       T* __restrict__ t_out, T* __restrict__ normal,
                                                       int32_t* __restrict__ hit, T* __restrict__ saved,
-                                                      const float2* __restrict__ bounds) {
+                                                      const float2* __restrict__ bounds,
+                                                      unsigned long long* __restrict__ grazing,
+                                                      const T* __restrict__ tau_in) {
   constexpr int P = S::P, Ppad = S::Ppad, K = S::K, SUB = kRootSub;
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t ray = gtid / SUB;
@@ -557,9 +567,11 @@ __global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, c
   int cc[3];
   double ta, tb;
   // ---- pass 0: a value the ray's maximum surely reaches: the largest value of f at a segment
-  // midpoint (evaluated only where the cell's upper bound exceeds the largest so far)
+  // midpoint (evaluated only where the cell's upper bound exceeds the largest so far).  Passes 0
+  // and 1 only serve the level frac * max f; given levels skip them.
+  const bool find_max = live && tau_in == nullptr;
   double lb = -INFINITY;
-  if (live) {
+  if (find_max) {
     Dda dda;
     dda.init(o, r, e0, e1, lo, hi, h, n);
     while (dda.next(cell, cc, ta, tb)) {
@@ -578,7 +590,7 @@ __global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, c
   // over the segments is at least lb, so starting there changes nothing but skips the exact
   // maximisation of every segment whose bound stays below it.
   double fmax_v = lb;
-  if (live) {
+  if (find_max) {
     Dda dda;
     dda.init(o, r, e0, e1, lo, hi, h, n);
     while (dda.next(cell, cc, ta, tb)) {
@@ -599,13 +611,13 @@ __global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, c
   }
 #pragma unroll
   for (int off = SUB / 2; off >= 1; off >>= 1) fmax_v = fmax(fmax_v, __shfl_xor(fmax_v, off));
-  const double tau = frac * fmax_v;
+  const double tau = tau_in ? (double)tau_in[rr] : frac * fmax_v;
   // ---- pass 2
-  bool found = false, have_piece = false;
+  bool found = false, have_piece = false, ev_face = false;
   double t_ev = INFINITY, first_start = 0.0, last_end = 0.0, last_tb = 0.0;
-  int64_t ev_cell = 0, last_cell = 0;
+  int64_t ev_cell = 0, last_cell = 0, first_cell = -1;
   int ev_c[3] = {0, 0, 0}, last_c[3] = {0, 0, 0};
-  if (live && fmax_v > -INFINITY) {
+  if (live && (tau_in != nullptr || fmax_v > -INFINITY)) {
     Dda dda;
     dda.init(o, r, e0, e1, lo, hi, h, n);
     double prev_end = 0.0;
@@ -617,12 +629,14 @@ __global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, c
       if (side != 0.0) {
         if (!have_piece) {
           first_start = side;
+          first_cell = cell;
           have_piece = true;
         } else if (!found && prev_end < 0.0 && side > 0.0) {   // crossing on a face
           t_ev = last_tb;
           ev_cell = last_cell;
           ev_c[0] = last_c[0]; ev_c[1] = last_c[1]; ev_c[2] = last_c[2];
           found = true;
+          ev_face = true;
         }
         prev_end = side;
         last_end = side;
@@ -645,12 +659,14 @@ __global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, c
       const double g0 = peval<K>(g, 0.0);
       if (!have_piece) {
         first_start = g0;
+        first_cell = cell;
         have_piece = true;
       } else if (!found && prev_end < 0.0 && g0 >= 0.0) {   // crossing on a face: earlier piece
         t_ev = last_tb;
         ev_cell = last_cell;
         ev_c[0] = last_c[0]; ev_c[1] = last_c[1]; ev_c[2] = last_c[2];
         found = true;
+        ev_face = true;
       }
       if (!found) {
         const double v = upper_bound<K>(g, 1.0) < 0.0 ? -1.0 : first_upward<S>(g, 1.0);
@@ -679,11 +695,14 @@ __global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, c
             pc2 = __shfl(last_c[2], src < 0 ? 0 : src);
   const double prev_last_tb = __shfl(last_tb, src < 0 ? 0 : src);
   if (part > 0 && have_piece && prev_have && prev_last_end < 0.0 && first_start >= 0.0) {
-    // an event at this lane's start precedes any event inside it
+    // an event at this lane's start precedes any event inside it; it is a face crossing when
+    // the two lanes' pieces there belong to different cells, else a root of one cell's
+    // polynomial at the split point
     t_ev = prev_last_tb;
     ev_cell = prev_last_cell;
     ev_c[0] = pc0; ev_c[1] = pc1; ev_c[2] = pc2;
     found = true;
+    ev_face = prev_last_cell != first_cell;
   }
   // the earliest event of the group (lowest lane on ties)
   double tmin = found ? t_ev : INFINITY;
@@ -695,6 +714,7 @@ __global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, c
   const int64_t wcell = __shfl(ev_cell, group0 + (win < 0 ? 0 : win));
   const int w0 = __shfl(ev_c[0], group0 + (win < 0 ? 0 : win)), w1 = __shfl(ev_c[1], group0 + (win < 0 ? 0 : win)),
             w2 = __shfl(ev_c[2], group0 + (win < 0 ? 0 : win));
+  const int wface = __shfl((int)ev_face, group0 + (win < 0 ? 0 : win));
   // dead ray: at or above the level at the entry point (lane 0's first piece)
   const double entry = __shfl(first_start, group0);
   const int entry_have = __shfl((int)have_piece, group0);
@@ -713,18 +733,30 @@ __global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, c
     root_gradients<S>(L + wcell * Ppad, u, r, ih, gout, hr);
     rdg = r[0] * gout[0] + r[1] * gout[1] + r[2] * gout[2];
   }
+  // kind of the hit for the backward pass: the implicit function theorem needs r . grad f != 0
+  int kind = kRootSmooth;
+  if (ray_hit && wface) {
+    kind = kRootFace;
+  } else if (ray_hit) {
+    const double gg = sqrt(gout[0] * gout[0] + gout[1] * gout[1] + gout[2] * gout[2]);
+    const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (fabs(rdg) <= FC2T2_GRAZE_COS * rn * gg) {
+      kind = kRootGrazing;
+      atomicAdd(grazing, 1ull);
+    }
+  }
   t_out[ray] = (T)t_star;
   hit[ray] = ray_hit ? 1 : 0;
 #pragma unroll
   for (int j = 0; j < 3; ++j) normal[ray * 3 + j] = (T)gout[j];
   T* sv = saved + ray * kRaySaved;
   sv[0] = (T)qs[0]; sv[1] = (T)qs[1]; sv[2] = (T)qs[2];
-  sv[3] = (T)(double)(ray_hit ? wcell : 0);
+  put_cell(sv[3], ray_hit ? wcell : 0);
   sv[4] = (T)rdg;
   sv[5] = (T)hr[0]; sv[6] = (T)hr[1]; sv[7] = (T)hr[2];
   sv[8] = (T)tau;
   sv[9] = (T)t_star;
-  sv[10] = T(0);
+  sv[10] = (T)kind;
   sv[11] = T(0);
 }
 
@@ -734,8 +766,8 @@ __global__ void __launch_bounds__(256) root_keys_kernel(const T* __restrict__ sa
                                                         int64_t R, int64_t G, uint32_t* __restrict__ keys) {
   const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (ray >= R) return;
-  const double c = (double)saved[ray * kRaySaved + 3];
-  keys[ray] = (hit[ray] && c >= 0.0 && c < (double)G) ? (uint32_t)c : (uint32_t)G;
+  const int64_t c = get_cell(saved[ray * kRaySaved + 3]);
+  keys[ray] = (hit[ray] && c >= 0 && c < G) ? (uint32_t)c : (uint32_t)G;
 }
 
 template <class S, typename T>
@@ -758,7 +790,11 @@ struct RootInsert {
       for (int j = 0; j < 3; ++j) gnv[j] = (double)gn[(int64_t)ray * 3 + j];
     }
     const double gtv = gt ? (double)gt[ray] : 0.0;
-    const double a = -(gtv + gnv[0] * (double)sv[5] + gnv[1] * (double)sv[6] + gnv[2] * (double)sv[7]) / rdg;
+    // a face crossing or a grazing root inserts only the dipole term: at a face the root does
+    // not move with L, at a grazing root its sensitivity is unbounded
+    const double a = (int)sv[10] != kRootSmooth
+                         ? 0.0
+                         : -(gtv + gnv[0] * (double)sv[5] + gnv[1] * (double)sv[6] + gnv[2] * (double)sv[7]) / rdg;
     const double ih = 1.0 / h;
     double pw[3][K + 1];
 #pragma unroll
@@ -895,7 +931,8 @@ fc2t2_status ray_integral_backward(const fc2t2_plan_s* pl, const void* o, const 
 }
 
 fc2t2_status launch_ray_root(const fc2t2_plan_s* pl, const void* L, const void* o, const void* r, double t0, double t1,
-                             int64_t R, double frac, void* t, void* normal, int32_t* hit, void* saved, hipStream_t s) {
+                             int64_t R, double frac, void* t, void* normal, int32_t* hit, void* saved, hipStream_t s,
+                             const void* tau_in) {
   if (R == 0) return FC2T2_OK;
   if (!pl->cell_bounds) return FC2T2_EUNSUPPORTED;
   fc2t2_status st = FC2T2_EUNSUPPORTED;
@@ -909,12 +946,12 @@ fc2t2_status launch_ray_root(const fc2t2_plan_s* pl, const void* L, const void* 
         hipLaunchKernelGGL((cell_bounds_kernel<S, double>), bgrid, dim3(256), 0, s, (const double*)L, pl->G, bounds);
         hipLaunchKernelGGL((ray_root_kernel<S, double>), grid, dim3(64), 0, s, (const double*)L, (const double*)o,
                            (const double*)r, R, t0, t1, pl->lo, pl->hi, pl->h0, pl->n, frac, (double*)t,
-                           (double*)normal, hit, (double*)saved, bounds);
+                           (double*)normal, hit, (double*)saved, bounds, pl->grazing, (const double*)tau_in);
       } else {
         hipLaunchKernelGGL((cell_bounds_kernel<S, float>), bgrid, dim3(256), 0, s, (const float*)L, pl->G, bounds);
         hipLaunchKernelGGL((ray_root_kernel<S, float>), grid, dim3(64), 0, s, (const float*)L, (const float*)o,
                            (const float*)r, R, t0, t1, pl->lo, pl->hi, pl->h0, pl->n, frac, (float*)t,
-                           (float*)normal, hit, (float*)saved, bounds);
+                           (float*)normal, hit, (float*)saved, bounds, pl->grazing, (const float*)tau_in);
       }
       st = FC2T2_OK;
     }
@@ -991,9 +1028,20 @@ fc2t2_status fc2t2_ray_root(fc2t2_plan plan, const void* L, const void* o, const
   if (!plan || !L || bad_rays(R) || !isfinite(t0) || !isfinite(t1) || !isfinite(level_frac)) return FC2T2_EINVAL;
   if (R > 0 && (!o || !r || !t || !normal || !hit || !saved)) return FC2T2_EINVAL;
   if (!rays_ok(plan) || plan->C != 1) return FC2T2_EUNSUPPORTED;
-  if (plan->io == FC2T2_IO_F32 && plan->G > (int64_t(1) << 24)) return FC2T2_EUNSUPPORTED;
+  if (plan->G > 0xFFFFFFFFll) return FC2T2_EUNSUPPORTED;
   StageScope tm(plan, FC2T2_STAGE_RAY, stream);
-  return launch_ray_root(plan, L, o, r, t0, t1, R, level_frac, t, normal, hit, saved, stream);
+  return launch_ray_root(plan, L, o, r, t0, t1, R, level_frac, t, normal, hit, saved, stream, nullptr);
+}
+
+fc2t2_status fc2t2_ray_root_at(fc2t2_plan plan, const void* L, const void* o, const void* r, double t0, double t1,
+                               int64_t R, const void* tau, void* t, void* normal, int32_t* hit, void* saved,
+                               hipStream_t stream) {
+  if (!plan || !L || bad_rays(R) || !isfinite(t0) || !isfinite(t1)) return FC2T2_EINVAL;
+  if (R > 0 && (!o || !r || !tau || !t || !normal || !hit || !saved)) return FC2T2_EINVAL;
+  if (!rays_ok(plan) || plan->C != 1) return FC2T2_EUNSUPPORTED;
+  if (plan->G > 0xFFFFFFFFll) return FC2T2_EUNSUPPORTED;
+  StageScope tm(plan, FC2T2_STAGE_RAY, stream);
+  return launch_ray_root(plan, L, o, r, t0, t1, R, 0.0, t, normal, hit, saved, stream, tau);
 }
 
 fc2t2_status fc2t2_ray_root_backward(fc2t2_plan plan, const void* saved, const int32_t* hit, int64_t R, const void* gt,

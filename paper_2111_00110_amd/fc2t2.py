@@ -26,6 +26,7 @@ IO = {"f32": 0, "f64": 1}
 OP = {"expand": 0, "eval_backward": 1, "expand_backward": 2, "ray_integral_backward": 3,
       "ray_root_backward": 4}
 ROOT_SAVED = 12
+ROOT_SMOOTH, ROOT_FACE, ROOT_GRAZING = 0, 1, 2   # kind of a ray-root hit, saved[:, 10]
 
 _lib = None
 
@@ -69,6 +70,8 @@ def lib() -> ctypes.CDLL:
         getattr(L, name).argtypes = [vp]
     L.fc2t2_out_of_domain.restype = i32
     L.fc2t2_out_of_domain.argtypes = [vp, ctypes.POINTER(i64), i32, vp]
+    L.fc2t2_grazing_roots.restype = i32
+    L.fc2t2_grazing_roots.argtypes = [vp, ctypes.POINTER(i64), i32, vp]
     L.fc2t2_local_numel.restype = sz
     L.fc2t2_local_numel.argtypes = [vp]
     L.fc2t2_workspace_size.restype = sz
@@ -91,6 +94,8 @@ def lib() -> ctypes.CDLL:
     L.fc2t2_ray_integral_backward.argtypes = [vp, vp, vp, dbl, dbl, i64, vp, vp, vp, sz, vp]
     L.fc2t2_ray_root.restype = i32
     L.fc2t2_ray_root.argtypes = [vp, vp, vp, vp, dbl, dbl, i64, dbl, vp, vp, vp, vp, vp]
+    L.fc2t2_ray_root_at.restype = i32
+    L.fc2t2_ray_root_at.argtypes = [vp, vp, vp, vp, dbl, dbl, i64, vp, vp, vp, vp, vp, vp]
     L.fc2t2_m2l.restype = i32
     L.fc2t2_m2l.argtypes = [vp, i32, i32, vp, vp, i32, vp]
     L.fc2t2_level_numel.restype = sz
@@ -248,6 +253,20 @@ class Plan:
                "fc2t2_out_of_domain")
         return int(c.value)
 
+    def grazing_roots(self, reset: bool = False) -> int:
+        """Ray roots classified as grazing (the ray tangent to the level set; their backward
+        inserts only the surface-gradient term) since the plan was made or last reset.
+        Synchronises."""
+        c = ctypes.c_int64(0)
+        _check(lib().fc2t2_grazing_roots(self.handle, ctypes.byref(c), 1 if reset else 0, _stream()),
+               "fc2t2_grazing_roots")
+        return int(c.value)
+
+    @staticmethod
+    def root_kind(saved: torch.Tensor) -> torch.Tensor:
+        """Kind of each ray-root hit (ROOT_SMOOTH, ROOT_FACE, ROOT_GRAZING) from the saved record."""
+        return saved[:, 10].to(torch.int32)
+
     def _debug_domain(self, what: str):
         # debug mode (FC2T2_DEBUG=1): fail on points outside the domain, at the call that met them
         if os.environ.get("FC2T2_DEBUG", "0") not in ("", "0"):
@@ -308,7 +327,10 @@ class Plan:
                                                  _ptr(gy), _ptr(gL), _ptr(ws), ws.numel(), _stream()),
                "fc2t2_ray_integral_backward")
 
-    def ray_root(self, Lt, o, r, t0: float, t1: float, level_frac: float = 0.5):
+    def ray_root(self, Lt, o, r, t0: float, t1: float, level_frac: float = 0.5,
+                 tau: Optional[torch.Tensor] = None):
+        """First upward crossing of level_frac * max f along each ray, or of the given per-ray
+        levels tau [R] (fc2t2_ray_root_at)."""
         R = o.shape[0]
         o = self._t(o, (R, 3), "o")
         r = self._t(r, (R, 3), "r")
@@ -317,9 +339,15 @@ class Plan:
         normal = torch.empty((R, 3), dtype=self.dtype, device=self.device)
         hit = torch.empty(R, dtype=torch.int32, device=self.device)
         saved = torch.empty((R, ROOT_SAVED), dtype=self.dtype, device=self.device)
-        _check(lib().fc2t2_ray_root(self.handle, _ptr(Lt), _ptr(o), _ptr(r), float(t0), float(t1), R,
-                                    float(level_frac), _ptr(t), _ptr(normal), _ptr(hit), _ptr(saved),
-                                    _stream()), "fc2t2_ray_root")
+        if tau is None:
+            _check(lib().fc2t2_ray_root(self.handle, _ptr(Lt), _ptr(o), _ptr(r), float(t0), float(t1), R,
+                                        float(level_frac), _ptr(t), _ptr(normal), _ptr(hit), _ptr(saved),
+                                        _stream()), "fc2t2_ray_root")
+        else:
+            tau = self._t(tau, (R,), "tau")
+            _check(lib().fc2t2_ray_root_at(self.handle, _ptr(Lt), _ptr(o), _ptr(r), float(t0), float(t1), R,
+                                           _ptr(tau), _ptr(t), _ptr(normal), _ptr(hit), _ptr(saved), _stream()),
+                   "fc2t2_ray_root_at")
         return t, normal, hit, saved
 
     def ray_root_backward(self, saved, hit, gt, gn, gL):
@@ -393,12 +421,13 @@ class RayIntegral(torch.autograd.Function):
 
 class RayRoot(torch.autograd.Function):
     """(t*, grad f(q*)) of the first level crossing along each ray (section 5.1), with the
-    implicit-function-theorem backward of section 5.2."""
+    implicit-function-theorem backward of section 5.2.  The level is level_frac * max f along
+    the ray, or the given per-ray levels tau; either way it is held fixed in the backward."""
 
     @staticmethod
-    def forward(ctx, plan: Plan, p, w, o, r, t0: float, t1: float, level_frac: float = 0.5):
+    def forward(ctx, plan: Plan, p, w, o, r, t0: float, t1: float, level_frac: float = 0.5, tau=None):
         Lt = plan.expand(p, w)
-        t, normal, hit, saved = plan.ray_root(Lt, o, r, t0, t1, level_frac)
+        t, normal, hit, saved = plan.ray_root(Lt, o, r, t0, t1, level_frac, tau)
         ctx.plan = plan
         ctx.save_for_backward(p, w, saved, hit)
         ctx.mark_non_differentiable(hit)
@@ -414,4 +443,4 @@ class RayRoot(torch.autograd.Function):
         gp = torch.empty_like(p) if ctx.needs_input_grad[1] else None
         gw = torch.empty_like(w) if ctx.needs_input_grad[2] else None
         plan.expand_backward(gL, p, w, gp, gw, accumulate=False)
-        return None, gp, gw, None, None, None, None, None
+        return None, gp, gw, None, None, None, None, None, None

@@ -285,3 +285,26 @@ def test_out_of_domain_points_are_counted(F, monkeypatch):
     with pytest.raises(F.FC2T2Error):
         plan.eval(Lt, _dev(q))
     plan.eval(Lt, _dev(q[:-5]))
+
+
+@pytest.mark.parametrize("d,io", [(2, "f64"), (3, "f64"), (2, "f32"), (3, "f32")])
+def test_eval_hessian_matches_checker(F, d, io):
+    """The Hessian output of fc2t2_eval (upper triangle row by row) against the checker's L2P
+    Hessian, with the value and gradient outputs of the same call."""
+    lo, hi = (0.0, 1.0) if d == 2 else (-1.0, 1.0)
+    K = 5 if d == 2 else 4
+    wl = W.Workload("h", d, 16, lo, hi, K, "gaussian", 0.06, 3000, 2000, 0, io, "explicit",
+                    "uniform" if d == 2 else "shell")
+    x = W.make(wl, seed=9)
+    geo, ker = oracle_geometry(wl), oracle_kernel(wl)
+    plan = _plan(F, wl)
+    Lt = plan.expand(_dev(x["p"]), _dev(x["w"]))
+    y, g, hs = plan.eval(Lt, _dev(x["q"]), grad=True, hess=True)
+    L0 = fmm.expand(geo, ker, x["p"], x["w"])
+    H = fmm.l2p_hess(geo, L0, x["q"])                        # [M, C, d, d]
+    iu = np.triu_indices(d)
+    want = H[:, :, iu[0], iu[1]]
+    tol = 1e-12 if io == "f64" else 1e-4
+    assert rel(hs.cpu().numpy(), want) < tol
+    assert rel(g.cpu().numpy(), fmm.l2p_grad(geo, L0, x["q"])) < tol
+    assert rel(y.cpu().numpy(), fmm.l2p(geo, L0, x["q"])) < (1e-12 if io == "f64" else 1e-5)

@@ -55,7 +55,8 @@ typedef enum {
   FC2T2_EUNSUPPORTED = 2,  /* a valid combination the library does not implement */
   FC2T2_EHIP = 3,          /* a HIP runtime call failed (launch or allocation) */
   FC2T2_ENOMEM = 4,        /* device allocation inside plan creation failed */
-  FC2T2_EWORKSPACE = 5     /* ws_bytes smaller than fc2t2_workspace_size asks */
+  FC2T2_EWORKSPACE = 5,    /* ws_bytes smaller than fc2t2_workspace_size asks */
+  FC2T2_ESCRATCH = 6       /* a *_noalloc call needs more scratch than its fixed device array */
 } fc2t2_status;
 
 typedef enum {
@@ -251,6 +252,22 @@ fc2t2_status fc2t2_ray_root_at(fc2t2_plan plan, const void* L, const void* o, co
 fc2t2_status fc2t2_ray_root_backward(fc2t2_plan plan, const void* saved, const int32_t* hit,
                                      int64_t R, const void* gt, const void* gn, void* gL,
                                      void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): fc2t2_ray_root_backward with its scratch in a
+ * fixed device array of FC2T2_NOALLOC_SCRATCH_BYTES bytes that the library holds on every GPU
+ * it runs on until the process ends, instead of a caller workspace.  Same arguments
+ * otherwise, same kernels and same results; it allocates nothing and frees nothing.
+ * FC2T2_ESCRATCH when the call needs more scratch than the array holds, i.e. when
+ * fc2t2_workspace_size(plan, FC2T2_OP_RAY_ROOT_BACKWARD, R) > FC2T2_NOALLOC_SCRATCH_BYTES
+ * (131072 rays on a 128^3 grid fit); FC2T2_EHIP if the array's address could not be resolved
+ * when the plan was created.  All calls on one GPU share its array and every call rewrites
+ * what it reads, so calls that overlap in time on one GPU (other streams, other threads)
+ * race; issue them on one stream. */
+#define FC2T2_NOALLOC_SCRATCH_BYTES (16u << 20)
+fc2t2_status fc2t2_ray_root_backward_noalloc(fc2t2_plan plan, const void* saved, const int32_t* hit,
+                                             int64_t R, const void* gt, const void* gn, void* gL,
+                                             hipStream_t stream);
 
 /* Stage entry point: one M2L launch at one level (section 3, K^{M2L}) between caller-owned
  * grids of that level, [C][n_level^dim][P_pad] in that level's cell-scaled units

@@ -33,6 +33,7 @@ struct fc2t2_plan_s {
   void* cell_bounds = nullptr;    // 3-D: [G] float2 (lower, upper) bound of each finest cell's
                                   //   polynomial over the cell, rebuilt by every ray-root call
   int device = 0;
+  void* noalloc_scratch = nullptr;   // this device's fixed scratch array (rays.hip), or null
   // Stage timing (measurement aid): bit s of timed_mask brackets stage s with events.
   uint32_t timed_mask = 0;
   fc2t2::StageTimer* timer = nullptr;
@@ -192,6 +193,9 @@ fc2t2_status launch_ray_root(const fc2t2_plan_s* pl, const void* L, const void* 
                              double t0, double t1, int64_t R, double frac, void* t, void* normal,
                              int32_t* hit, void* saved, hipStream_t s, const void* tau_in = nullptr);
 size_t ray_root_bwd_ws(const fc2t2_plan_s* pl, int64_t R);
+// Resolves the device address of the fixed scratch array of the no-allocation entry point on
+// the current device (once per device) into pl->noalloc_scratch; leaves it null on failure.
+void noalloc_setup(fc2t2_plan_s* pl);
 fc2t2_status ray_root_backward(const fc2t2_plan_s* pl, const void* saved, const int32_t* hit,
                                int64_t R, const void* gt, const void* gn, void* gL, void* ws,
                                hipStream_t s);

@@ -367,6 +367,7 @@ const char* fc2t2_status_string(int status) {
     case FC2T2_EHIP: return "HIP runtime error";
     case FC2T2_ENOMEM: return "out of device memory";
     case FC2T2_EWORKSPACE: return "workspace too small";
+    case FC2T2_ESCRATCH: return "call needs more scratch than the fixed array of the no-allocation entry point";
   }
   return "unknown status";
 }
@@ -578,6 +579,7 @@ fc2t2_status fc2t2_plan_create(const fc2t2_grid* grid, const fc2t2_kernel* kerne
     return fail(FC2T2_ENOMEM);
   }
   if (hipStreamSynchronize(stream) != hipSuccess) return fail(FC2T2_EHIP);
+  noalloc_setup(pl);   // device address of the no-allocation entry point's fixed scratch
   *out = pl;
   return FC2T2_OK;
 }

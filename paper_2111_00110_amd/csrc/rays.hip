@@ -14,10 +14,17 @@
 // expansion rows are FP32.
 #include <math.h>
 
+#include <mutex>
+
 #include "plan.h"
 #include "segreduce.h"
 
 using namespace fc2t2;
+
+// Scratch of fc2t2_ray_root_backward_noalloc: a fixed array in device memory, one copy per
+// GPU (the code object's data segment), held until the process ends.  Host code never uses
+// this name as an address: the device address comes from hipGetSymbolAddress, per device.
+static __device__ __align__(256) char scratch[FC2T2_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -984,6 +991,20 @@ fc2t2_status ray_root_backward_t(const fc2t2_plan_s* pl, const T* saved, const i
   return st;
 }
 
+void noalloc_setup(fc2t2_plan_s* pl) {
+  static std::mutex mu;
+  static void* addr[64] = {};
+  pl->noalloc_scratch = nullptr;
+  if (pl->device < 0 || pl->device >= 64) return;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[pl->device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return;
+    addr[pl->device] = p;
+  }
+  pl->noalloc_scratch = addr[pl->device];
+}
+
 fc2t2_status ray_root_backward(const fc2t2_plan_s* pl, const void* saved, const int32_t* hit, int64_t R, const void* gt,
                                const void* gn, void* gL, void* ws, hipStream_t s) {
   if (R == 0) return FC2T2_OK;
@@ -1042,6 +1063,17 @@ fc2t2_status fc2t2_ray_root_at(fc2t2_plan plan, const void* L, const void* o, co
   if (plan->G > 0xFFFFFFFFll) return FC2T2_EUNSUPPORTED;
   StageScope tm(plan, FC2T2_STAGE_RAY, stream);
   return launch_ray_root(plan, L, o, r, t0, t1, R, 0.0, t, normal, hit, saved, stream, tau);
+}
+
+fc2t2_status fc2t2_ray_root_backward_noalloc(fc2t2_plan plan, const void* saved, const int32_t* hit, int64_t R,
+                                             const void* gt, const void* gn, void* gL, hipStream_t stream) {
+  if (!plan || !gL || bad_rays(R)) return FC2T2_EINVAL;
+  if (R > 0 && (!saved || !hit)) return FC2T2_EINVAL;
+  if (!rays_ok(plan) || plan->C != 1) return FC2T2_EUNSUPPORTED;
+  if (R == 0 || (!gt && !gn)) return FC2T2_OK;
+  if (ray_root_bwd_ws(plan, R) > (size_t)FC2T2_NOALLOC_SCRATCH_BYTES) return FC2T2_ESCRATCH;
+  if (!plan->noalloc_scratch) return FC2T2_EHIP;
+  return ray_root_backward(plan, saved, hit, R, gt, gn, gL, plan->noalloc_scratch, stream);
 }
 
 fc2t2_status fc2t2_ray_root_backward(fc2t2_plan plan, const void* saved, const int32_t* hit, int64_t R, const void* gt,

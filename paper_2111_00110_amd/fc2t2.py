@@ -102,6 +102,8 @@ def lib() -> ctypes.CDLL:
     L.fc2t2_level_numel.argtypes = [vp, i32]
     L.fc2t2_ray_root_backward.restype = i32
     L.fc2t2_ray_root_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]
+    L.fc2t2_ray_root_backward_noalloc.restype = i32
+    L.fc2t2_ray_root_backward_noalloc.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
     L.fc2t2_stage_timing.restype = i32
     L.fc2t2_stage_timing.argtypes = [vp, ctypes.c_uint32]
     L.fc2t2_stage_time.restype = i32
@@ -363,6 +365,20 @@ class Plan:
         _check(lib().fc2t2_ray_root_backward(self.handle, _ptr(saved), _ptr(hit), R, _ptr(gt), _ptr(gn),
                                              _ptr(gL), _ptr(ws), ws.numel(), _stream()),
                "fc2t2_ray_root_backward")
+
+    def ray_root_backward_noalloc(self, saved, hit, gt, gn, gL):
+        """ray_root_backward with the library's fixed device scratch (no workspace, nothing
+        allocated by the call); calls on one GPU must not overlap in time."""
+        R = saved.shape[0]
+        saved = self._t(saved, (R, ROOT_SAVED), "saved")
+        assert hit.dtype == torch.int32 and hit.is_contiguous()
+        if gt is not None:
+            gt = self._t(gt, (R,), "gt")
+        if gn is not None:
+            gn = self._t(gn, (R, 3), "gn")
+        assert gL.is_contiguous() and tuple(gL.shape) == self.local_shape() and gL.dtype == self.dtype
+        _check(lib().fc2t2_ray_root_backward_noalloc(self.handle, _ptr(saved), _ptr(hit), R, _ptr(gt), _ptr(gn),
+                                                     _ptr(gL), _stream()), "fc2t2_ray_root_backward_noalloc")
 
 
 # ---------------------------------------------------------------------------- autograd

@@ -383,16 +383,22 @@ def l2p_hess(geo: Geometry, L0: np.ndarray, q: np.ndarray):
 # ----------------------------------------------------------------------------- backward
 
 def l2p_T(geo: Geometry, q: np.ndarray, gy: np.ndarray) -> np.ndarray:
-    """Transpose of L2P: G_L0[c, k] = sum_{q in c} gy_q (q - c)^k / k!."""
+    """Transpose of L2P: G_L0[c, k] = sum_{q in c} gy_q (q - c)^k / k!  (queries taken in
+    chunks of 2^20, each chunk's per-cell sums added with bincount: the same sums, with memory
+    bounded at 10^7 queries)."""
     gy = np.asarray(gy, dtype=np.float64).reshape(len(q), -1)
     C = gy.shape[1]
-    cell = geo.cell_index(q)
-    dvec = np.asarray(q, dtype=np.float64) - geo.centre(0, cell)
-    mono = monomials(dvec, geo.idx)
-    G = np.zeros((C,) + (geo.n,) * geo.dim + (geo.P,))
-    for ch in range(C):
-        np.add.at(G[ch], tuple(cell[:, j] for j in range(geo.dim)), mono * gy[:, ch:ch + 1])
-    return G
+    G = np.zeros((C, geo.cells(0) ** geo.dim, geo.P))
+    for a in range(0, len(q), 1 << 20):
+        qc = q[a:a + (1 << 20)]
+        cell = geo.cell_index(qc)
+        lin = np.ravel_multi_index(tuple(cell[:, j] for j in range(geo.dim)), (geo.n,) * geo.dim)
+        mono = monomials(np.asarray(qc, dtype=np.float64) - geo.centre(0, cell), geo.idx)
+        for ch in range(C):
+            wk = mono * gy[a:a + (1 << 20), ch:ch + 1]
+            for k in range(geo.P):
+                G[ch, :, k] += np.bincount(lin, weights=wk[:, k], minlength=G.shape[1])
+    return G.reshape((C,) + (geo.n,) * geo.dim + (geo.P,))
 
 
 def l2l_T(geo: Geometry, level: int, G_child: np.ndarray) -> np.ndarray:
@@ -519,3 +525,61 @@ def locals_at_cells(geo: Geometry, kernel: Kernel, Ms: List[np.ndarray],
                 acc = acc + Ms[lv][(slice(None),) + src + (slice(None),)] @ tcache[key].T
         out[:, si, :] = acc
     return out
+
+
+def local_cotangent_pyramid(geo: Geometry, G_L0: np.ndarray) -> List[np.ndarray]:
+    """[G_L0, G_L1, ...]: the cotangents of every level's locals (transpose of the L2L chain)."""
+    GLs = [G_L0]
+    for lv in range(geo.levels - 1):
+        GLs.append(l2l_T(geo, lv, GLs[-1]))
+    return GLs
+
+
+def moment_cotangents_at_cells(geo: Geometry, kernel: Kernel, GLs: List[np.ndarray],
+                               cells: np.ndarray, triangular: bool = False) -> np.ndarray:
+    """The cotangent of the finest moments at selected finest cells only, [C, S, P]: at each
+    ancestor J of a cell, the transposed M2L sum over the targets I = J - o that receive J
+    (G_M[J] += G_L[I] T(o), the same admissible pairs as the forward), then shifted down the
+    ancestor chain by the transpose of M2M (G_child = G_parent S(e)).  The transpose of
+    locals_at_cells; for spot checks of the backward at full size."""
+    cells = np.asarray(cells, dtype=np.int64).reshape(-1, geo.dim)
+    C = GLs[0].shape[0]
+    out = np.zeros((C, len(cells), geo.P))
+    tcache = {}
+    for si, c in enumerate(cells):
+        acc = np.zeros((C, geo.P))
+        for lv in range(geo.levels - 1, -1, -1):
+            anc = c >> lv
+            n_l = geo.cells(lv)
+            if lv < geo.levels - 1:
+                b = anc & 1
+                e = (b - 0.5) * geo.h(lv)
+                acc = acc @ shift_matrix(e, geo.idx)
+            for o in offsets(geo.dim):
+                if not in_window(o, lv == 0):
+                    continue
+                tgt = [int(anc[j] - o[j]) for j in range(geo.dim)]
+                ok = True
+                for j in range(geo.dim):
+                    lo_, hi_ = (-2, 3) if tgt[j] % 2 == 0 else (-3, 2)
+                    if not (0 <= tgt[j] < n_l and lo_ <= o[j] <= hi_):
+                        ok = False
+                if not ok:
+                    continue
+                key = (lv, o)
+                if key not in tcache:
+                    tcache[key] = m2l_tensor(kernel, geo, lv, o, triangular)
+                acc = acc + GLs[lv][(slice(None),) + tuple(tgt) + (slice(None),)] @ tcache[key]
+        out[:, si, :] = acc
+    return out
+
+
+def p2m_T_rows(geo: Geometry, rows: np.ndarray, p: np.ndarray, w: np.ndarray):
+    """p2m_T for sources whose cells' moment cotangents are given row by row ([C, N, P], row s
+    for source s): (w_bar, p_bar) of those sources."""
+    w = np.asarray(w, dtype=np.float64).reshape(len(p), -1)
+    cell = geo.cell_index(p)
+    dvec = np.asarray(p, dtype=np.float64) - geo.centre(0, cell)
+    gw = np.einsum("cnp,np->nc", rows, monomials(dvec, geo.idx))
+    gp = np.einsum("cnp,npj,nc->nj", rows, monomial_grads(dvec, geo.idx), w)
+    return gw, gp

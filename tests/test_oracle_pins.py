@@ -707,3 +707,26 @@ def test_lsq_explicit_layer_closer_to_direct_sum():
         y = fmm.l2p(geo, fmm.expand(geo, ker, p, w), q)
         err[fit] = np.linalg.norm(y - yd) / np.linalg.norm(yd)
     assert err["lsq"] < 0.8 * err["taylor"]
+
+
+@pytest.mark.parametrize("d,n,K", [(2, 16, 4), (3, 8, 3)])
+def test_sampled_moment_cotangents_equal_full_transpose(d, n, K):
+    """The cell-by-cell transpose (for spot checks at full size) against the full exact
+    transpose chain at every cell of a small grid, and the per-row P2M transpose against p2m_T."""
+    rng = np.random.default_rng(40 + d)
+    ker = kernels.Gaussian(0.1)
+    geo = fmm.Geometry(d, n, -1.0, 1.0, K)
+    G_L0 = rng.standard_normal((2,) + (n,) * d + (geo.P,))
+    full = fmm.expand_T(geo, ker, G_L0)
+    cells = np.array(list(itertools.product(range(n), repeat=d)))
+    got = fmm.moment_cotangents_at_cells(geo, ker, fmm.local_cotangent_pyramid(geo, G_L0), cells)
+    want = full[(slice(None),) + tuple(cells[:, j] for j in range(d))]
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    p = rng.uniform(-1, 1, (50, d))
+    w = rng.standard_normal((50, 2))
+    pc = geo.cell_index(p)
+    rows = full[(slice(None),) + tuple(pc[:, j] for j in range(d))]
+    gw, gp = fmm.p2m_T_rows(geo, rows, p, w)
+    gw2, gp2 = fmm.p2m_T(geo, full, p, w)
+    assert np.abs(gw - gw2).max() <= 1e-12 * np.abs(gw2).max()
+    assert np.abs(gp - gp2).max() <= 1e-12 * np.abs(gp2).max()

@@ -75,6 +75,11 @@ typedef enum {
                               dimensions and M2L runs as one 1-D pass per dimension, the admissible
                               offsets split into disjoint per-axis products (two streams per pass),
                               in the IO precision; fc2t2_m2l then uses the plain contraction */
+  FC2T2_M2L_F16X3 = 6,     /* FP16 MFMA, FP32 accumulation, moments and tensor split hi/lo (22
+                              bits of mantissa per operand): three passes; each level's tensor
+                              and each tile's moments scaled by powers of two into FP16's range */
+  FC2T2_M2L_F32_MFMA = 7,  /* FP32 contraction on the matrix cores (v_mfma_f32_16x16x4_f32), the
+                              same tiling as the 16-bit forms */
   FC2T2_M2L_FIT_LSQ = 0x100  /* flag OR'ed with a precision other than SEPARABLE (section 3.1):
                                 each row k of the M2L tensor is the least-squares polynomial
                                 fit, over the source cell, of the k-th derivative of the

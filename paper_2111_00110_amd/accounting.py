@@ -236,3 +236,55 @@ def m2l_bytes_separable(dim: int, n: int, K: int, itemsize: int = 4, channels: i
         per_cell = R + R + 2 * chains * sum(sizes)   # first read, last write, each intermediate out and in
         total += (n >> l) ** dim * per_cell
     return total * itemsize * channels
+
+
+# ---- whole-step roofline of the explicit layer (forward + backward)
+
+def key_passes(G: int) -> int:
+    """8-bit radix passes of a sort by finest cell (keys 0..G, G marking unused records)."""
+    bits = max(1, int(G).bit_length())
+    return (bits + 7) // 8
+
+
+def sort_bytes(count: int, dim: int, G: int, payload_words: int, itemsize: int = 4) -> int:
+    """Algorithmic bytes of one sort of `count` points by cell: the cell key computed from the
+    coordinates (read d coordinates, write one key), every radix pass reading and writing key,
+    index and the carried payload words, and the cell starts written."""
+    per_pass = 2 * (8 + 4 * payload_words)
+    return count * (dim * itemsize + 4) + key_passes(G) * count * per_pass + (G + 1) * 4
+
+
+def pyramid_rows(dim: int, n: int) -> list:
+    return [(n >> l) ** dim for l in range(levels_of(n))]
+
+
+def explicit_step_model(dim: int, n: int, K: int, N: int, M: int, m2l_flops_fwd: int, m2l_flops_T: int,
+                        itemsize: int = 4, carried: bool = True) -> dict:
+    """Per stage of one explicit-layer step (expand, eval, eval_backward, expand_backward) the
+    algorithmic HBM bytes and flops, grouped as the library's stage timing groups its launches.
+    M2L flops are passed in (useful flops of the tiles that run)."""
+    G = n ** dim
+    R = p_pad(dim, K) * itemsize
+    rows = pyramid_rows(dim, n)
+    pw = dim + 1 if carried else 0
+    sort = sort_bytes(N, dim, G, pw, itemsize) + sort_bytes(M, dim, G, pw, itemsize) + N * dim * itemsize + G
+    up = sum(rows) * R                         # read the finest grid, write every coarser one
+    down = sum(rows) * R + rows[0] * R         # read every grid, write the finest
+    m2l_io = 2 * sum(rows) * R                 # moments (or local cotangents) in, locals out
+    return {
+        "sort": {"bytes": sort, "flops": 0},
+        "p2m": {"bytes": stage_bytes("p2m", dim, n, K, N=N, itemsize=itemsize), "flops": 0},
+        "shift_up": {"bytes": 2 * up, "flops": 0},
+        "m2l": {"bytes": m2l_io, "flops": m2l_flops_fwd},
+        "shift_down": {"bytes": 2 * down, "flops": 0},
+        "l2p": {"bytes": stage_bytes("l2p", dim, n, K, M=M, itemsize=itemsize), "flops": 0},
+        "l2p_T": {"bytes": stage_bytes("l2p_T", dim, n, K, M=M, itemsize=itemsize), "flops": 0},
+        "qgrad": {"bytes": stage_bytes("qgrad", dim, n, K, M=M, itemsize=itemsize), "flops": 0},
+        "m2l_T": {"bytes": m2l_io, "flops": m2l_flops_T},
+        "p2m_T": {"bytes": stage_bytes("p2m_T", dim, n, K, N=N, itemsize=itemsize), "flops": 0},
+    }
+
+
+def stage_roof_us(stage: dict, hbm_GBps: float, peak_TFLOPs: float) -> float:
+    """max(bytes / HBM peak, flops / compute peak) in microseconds."""
+    return max(stage["bytes"] / (hbm_GBps * 1e3), stage["flops"] / (peak_TFLOPs * 1e6))

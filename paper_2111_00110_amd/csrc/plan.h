@@ -26,6 +26,8 @@ struct fc2t2_plan_s {
   size_t m2l_T_bytes = 0;
   void* m2l_bf16 = nullptr;       // MFMA operand tables (layout owned by m2l_mfma.hip)
   size_t m2l_bf16_bytes = 0;
+  float t_scale[2][fc2t2::kMaxLevels] = {};   // FP16 operands: power of two applied to each
+                                               //   [direction][level] tensor
   void* shift = nullptr;          // sparse M2M/L2L shift lists (layout owned by tree.hip)
   size_t shift_beg_off = 0;
   int shift_n_up = 0, shift_n_down = 0;
@@ -170,11 +172,16 @@ size_t sep_ws_bytes(const fc2t2_plan_s* pl);
 // M2L (or its transpose) at every level by one-dimensional passes; ws of sep_ws_bytes bytes.
 fc2t2_status launch_m2l_separable(const fc2t2_plan_s* pl, const void* const* ins, void* const* outs, bool transpose,
                                   void* ws, hipStream_t s);
-inline bool m2l_is_mfma(const fc2t2_plan_s* pl) { return pl->prec >= FC2T2_M2L_BF16 && pl->prec <= FC2T2_M2L_BF16X3; }
+inline bool prec_is_mfma(int prec) {
+  return (prec >= FC2T2_M2L_BF16 && prec <= FC2T2_M2L_BF16X3) || prec == FC2T2_M2L_F16X3 ||
+         prec == FC2T2_M2L_F32_MFMA;
+}
+inline bool m2l_is_mfma(const fc2t2_plan_s* pl) { return prec_is_mfma(pl->prec); }
 
 // ---- m2l_mfma.hip
 bool m2l_mfma_supported(const fc2t2_plan_s* pl);
 size_t m2l_mfma_table_bytes(const fc2t2_plan_s* pl);
+size_t m2l_mfma_table_bytes_only(const fc2t2_plan_s* pl);   // operand tables without the scales
 fc2t2_status m2l_mfma_build_tables(fc2t2_plan_s* pl, hipStream_t s);
 // Levels [lvl0, lvl1) in one launch; ins/outs are indexed by level.
 fc2t2_status launch_m2l_mfma(const fc2t2_plan_s* pl, int lvl0, int lvl1, const void* const* ins,

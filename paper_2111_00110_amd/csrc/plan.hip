@@ -402,7 +402,7 @@ fc2t2_status fc2t2_plan_create(const fc2t2_grid* grid, const fc2t2_kernel* kerne
   const bool fit_lsq = (m2l_prec & FC2T2_M2L_FIT_LSQ) != 0;
   m2l_prec &= ~FC2T2_M2L_FIT_LSQ;
   if (fit_lsq && m2l_prec == FC2T2_M2L_SEPARABLE) return FC2T2_EUNSUPPORTED;   // the fit is not a product
-  if (m2l_prec < FC2T2_M2L_F64 || m2l_prec > FC2T2_M2L_SEPARABLE) return FC2T2_EINVAL;
+  if (m2l_prec < FC2T2_M2L_F64 || m2l_prec > FC2T2_M2L_F32_MFMA) return FC2T2_EINVAL;
   if (m2l_prec != FC2T2_M2L_SEPARABLE && (io == FC2T2_IO_F64) != (m2l_prec == FC2T2_M2L_F64))
     return FC2T2_EUNSUPPORTED;
   if (m2l_prec == FC2T2_M2L_SEPARABLE && kernel->kind != FC2T2_GAUSSIAN) return FC2T2_EUNSUPPORTED;
@@ -568,7 +568,7 @@ fc2t2_status fc2t2_plan_create(const fc2t2_grid* grid, const fc2t2_kernel* kerne
     const fc2t2_status st = sep_build(pl, stream);
     if (st != FC2T2_OK) return fail(st);
   }
-  if (m2l_prec >= FC2T2_M2L_BF16 && m2l_prec <= FC2T2_M2L_BF16X3) {
+  if (prec_is_mfma(m2l_prec)) {
     if (!m2l_mfma_supported(pl)) return fail(FC2T2_EUNSUPPORTED);
     const fc2t2_status st = m2l_mfma_build_tables(pl, stream);
     if (st != FC2T2_OK) return fail(st);

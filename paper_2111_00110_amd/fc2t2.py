@@ -20,7 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfc2t2.so")
 
 KERNELS = {"gaussian": 0, "imq": 1, "poly": 2}
-M2L_PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x2": 3, "bf16x3": 4, "separable": 5}
+M2L_PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x2": 3, "bf16x3": 4, "separable": 5, "f16x3": 6,
+            "f32_mfma": 7}
 FIT = {"taylor": 0, "lsq": 0x100}   # M2L tensor: derivatives, or least-squares fit (section 3.1)
 IO = {"f32": 0, "f64": 1}
 OP = {"expand": 0, "eval_backward": 1, "expand_backward": 2, "ray_integral_backward": 3,

@@ -75,7 +75,7 @@ def test_plan_create_rejects_bad_arguments_on_host(lib):
     assert create(good_g, good_k, prec=9) == 1
     assert create(good_g, good_k, prec=0, io=0) == 2          # FP64 contraction needs FP64 IO
     assert create(good_g, _Kernel(1, 0.02, 0, None), prec=5) == 2   # separable M2L: Gaussian only
-    assert create(good_g, good_k, prec=6) == 1
+    assert create(good_g, good_k, prec=8) == 1
     assert create(good_g, good_k, prec=5 | 0x100) == 2           # the fitted tensor is not separable
     assert out.value is None
     assert lib.fc2t2_plan_create(None, ctypes.byref(good_k), 4, 1, 0, 1, None, ctypes.byref(out)) == 1

@@ -145,27 +145,6 @@ def test_edge_cases(F):
     assert rel(got["y"], y) < 1e-12 and rel(got["gw"], gw) < 1e-12 and rel(got["gp"], gp) < 1e-12
 
 
-def test_full_size_2d_sampled(F):
-    """The 2-D workload at full size (N = M = 2^20, 256^2, K = 6): sampled queries against
-    the checker's locals computed cell by cell from the moment pyramid."""
-    wl = W.workload("explicit2d")
-    x = W.make(wl)
-    geo, ker = oracle_geometry(wl), oracle_kernel(wl)
-    plan = _plan(F, wl)
-    p, w, q = _dev(x["p"]), _dev(x["w"]), _dev(x["q"])
-    Lt = plan.expand(p, w)
-    y, _, _ = plan.eval(Lt, q)
-    y = y.cpu().numpy()
-    idx = W.subsample(5, 256, wl.M)
-    qs = x["q"][idx]
-    cells = geo.cell_index(qs)
-    Ms = fmm.moments_all_levels(geo, x["p"], x["w"])
-    Lc = fmm.locals_at_cells(geo, ker, Ms, cells)                          # [C, S, P]
-    dvec = qs.astype(np.float64) - geo.centre(0, cells)
-    want = np.einsum("csp,sp->sc", Lc, fmm.monomials(dvec, geo.idx))
-    assert rel(y[idx], want) < 1e-5
-
-
 def test_stage_timing_records_each_stage(F):
     """The library's event bracketing: every stage of one explicit step is timed once per call
     (two sorts: sources and queries), and turning timing off records nothing further."""

@@ -1,10 +1,14 @@
-"""GPU checks of the M2L stage on its own and of the matrix-core (BF16 MFMA) variants.
+"""GPU checks of the M2L stage on its own and of the matrix-core variants.
 
 * Stage adjoint: <M2L(x), y> = <x, M2L^T(y)> for every supported (dim, K) and level kind.
-* MFMA vs FP32 contraction at one level on random inputs, forward and transpose.
-* Whole explicit layer with each MFMA precision against the FP64 checker: one-pass BF16
-  within 1.5e-2, two-pass within 1e-2, three-pass (hi/lo split) within 3e-5 on values and
-  5e-5 on the gradient outputs (measured: 2.5e-6 to 1.5e-5)."""
+* Matrix-core forms vs the FP32 VALU contraction at one level on random inputs, forward and
+  transpose: BF16x3 within 1e-4, FP16x3 (hi/lo split, power-of-two scaling) and FP32 MFMA
+  within 3e-6.
+* Whole explicit layer with each matrix-core precision against the FP64 checker.  The error
+  contract (1e-5 on values and w_bar, 1e-4 on the differentiated p_bar and q_bar) holds for
+  FP16x3 and FP32 MFMA.  The BF16 forms do not meet it and are held to what they measure:
+  one pass 1.5e-2 (the contract's 1e-3 is not met), two passes 1e-2, three passes 3e-5 and
+  5e-5 (measured 2.5e-6 to 1.5e-5: a BF16 hi/lo pair keeps 16 bits of each operand)."""
 import numpy as np
 import pytest
 
@@ -40,7 +44,7 @@ def test_stage_adjoint_and_mfma_agree(F, dim, K):
     n = 32 if dim == 2 else 16
     for level in (0, 1):
         plans = {pr: F.Plan(dim, n, -1.0, 1.0, "gaussian", 0.15, K, m2l=pr, io="f32", channels=2)
-                 for pr in ("f32", "bf16x3")}
+                 for pr in ("f32", "bf16x3", "f16x3", "f32_mfma")}
         x = _rand_level(plans["f32"], level, 1)
         y = _rand_level(plans["f32"], level, 2)
         outs = {}
@@ -55,14 +59,39 @@ def test_stage_adjoint_and_mfma_agree(F, dim, K):
         lhs = float((fx[..., :P].double() * y[..., :P].double()).sum())
         rhs = float((x[..., :P].double() * ty[..., :P].double()).sum())
         assert abs(lhs - rhs) <= 1e-5 * (abs(lhs) + 1e-30) + 1e-6 * float(fx.abs().sum())
-        for k in (0, 1):
-            a = outs["bf16x3"][k].cpu().numpy()
-            b = outs["f32"][k].cpu().numpy()
-            assert rel(a, b) < 1e-4, (level, k)
-            assert np.all(a[..., P:] == 0.0)
+        for pr, tol in (("bf16x3", 1e-4), ("f16x3", 3e-6), ("f32_mfma", 3e-6)):
+            for k in (0, 1):
+                a = outs[pr][k].cpu().numpy()
+                b = outs["f32"][k].cpu().numpy()
+                assert rel(a, b) < tol, (pr, level, k)
+                assert np.all(a[..., P:] == 0.0)
 
 
-@pytest.mark.parametrize("prec,tol,tolg", [("bf16", 1.5e-2, 1.5e-2), ("bf16x2", 1e-2, 1e-2), ("bf16x3", 3e-5, 5e-5)])
+@pytest.mark.parametrize("dim,n,kernel,param,K", [(3, 32, "imq", 0.02, 4), (3, 64, "imq", 0.02, 4),
+                                                (2, 256, "gaussian", 0.01, 6), (3, 32, "gaussian", 0.015, 5)])
+def test_f16x3_every_level_matches_f32(F, dim, n, kernel, param, K):
+    """The FP16 split with its power-of-two scaling at every level of narrow-kernel pyramids,
+    where a level's tensor spans many decades (and the near-field hole, which coarse levels do
+    not use, holds the largest derivatives): forward and transpose against the FP32 VALU
+    contraction on random inputs."""
+    plans = {pr: F.Plan(dim, n, -1.0, 1.0, kernel, param, K, m2l=pr, io="f32") for pr in ("f32", "f16x3")}
+    for level in range(plans["f32"].levels):
+        x = _rand_level(plans["f32"], level, 10 + level)
+        ref, got = {}, {}
+        for pr, out in (("f32", ref), ("f16x3", got)):
+            for tr in (False, True):
+                o = torch.empty_like(x)
+                plans[pr].m2l(level, x, o, transpose=tr)
+                out[tr] = o.cpu().numpy()
+        for tr in (False, True):
+            if np.linalg.norm(ref[tr]) == 0.0:
+                assert np.linalg.norm(got[tr]) == 0.0
+                continue
+            assert rel(got[tr], ref[tr]) < 3e-6, (level, tr)
+
+
+@pytest.mark.parametrize("prec,tol,tolg", [("bf16", 1.5e-2, 1.5e-2), ("bf16x2", 1e-2, 1e-2), ("bf16x3", 3e-5, 5e-5),
+                                           ("f16x3", 1e-5, 1e-4), ("f32_mfma", 1e-5, 1e-4)])
 @pytest.mark.parametrize("case", ["2d", "3d_gauss", "3d_imq"])
 def test_explicit_layer_mfma_vs_checker(F, prec, tol, tolg, case):
     if case == "2d":
@@ -111,7 +140,7 @@ def test_clustered_sources_skip_empty_tiles(F, dim, n, K):
     ref = fmm.explicit_forward_backward(oracle_geometry(wl), oracle_kernel(wl), x["p"], x["w"], x["q"], x["gy"])
     d = {k: torch.from_numpy(v).cuda() for k, v in x.items()}
     outs = {}
-    for prec in ("bf16x3", "f32"):
+    for prec in ("bf16x3", "f16x3", "f32"):
         plan = F.Plan(dim, n, lo, hi, "gaussian", param, K, m2l=prec, io="f32")
         Lt = plan.expand(d["p"], d["w"])
         y, _, _ = plan.eval(Lt, d["q"])
@@ -122,11 +151,13 @@ def test_clustered_sources_skip_empty_tiles(F, dim, n, K):
         gw = torch.zeros_like(d["w"])
         plan.expand_backward(gL, d["p"], d["w"], gp, gw)
         outs[prec] = [t.cpu().numpy() for t in (y, gw, gp, gq)]
-    got, dense = outs["bf16x3"], outs["f32"]
-    for i, name in enumerate(("y", "w_bar", "p_bar", "q_bar")):
-        tol = 3e-5 if i < 2 else 5e-5
-        assert rel(got[i], ref[i]) < tol, name
-        assert rel(got[i], dense[i]) < tol, name
+    dense = outs["f32"]
+    for prec, tols in (("bf16x3", (3e-5, 5e-5)), ("f16x3", (1e-5, 1e-4))):
+        got = outs[prec]
+        for i, name in enumerate(("y", "w_bar", "p_bar", "q_bar")):
+            tol = tols[0] if i < 2 else tols[1]
+            assert rel(got[i], ref[i]) < tol, (prec, name)
+            assert rel(got[i], dense[i]) < tol, (prec, name)
 
 
 @pytest.mark.parametrize("dim,n,K,param", [(2, 64, 6, 0.01), (2, 16, 4, 0.05), (3, 16, 4, 0.05), (3, 32, 5, 0.03)])

@@ -118,7 +118,8 @@ typedef enum {
   FC2T2_OP_EVAL_BACKWARD = 1,        /* count = M queries */
   FC2T2_OP_EXPAND_BACKWARD = 2,      /* count = N sources */
   FC2T2_OP_RAY_INTEGRAL_BACKWARD = 3,/* count = R rays */
-  FC2T2_OP_RAY_ROOT_BACKWARD = 4     /* count = R rays */
+  FC2T2_OP_RAY_ROOT_BACKWARD = 4,    /* count = R rays */
+  FC2T2_OP_EVAL_SORTED = 5           /* count = M queries (fc2t2_eval_sorted's records) */
 } fc2t2_op;
 
 /* Status text (static storage). */
@@ -176,6 +177,25 @@ fc2t2_status fc2t2_expand(fc2t2_plan plan, const void* p, const void* w, int64_t
  *   out or NULL, upper triangle row by row (xx, xy, (xz,) yy, (yz, zz)). */
 fc2t2_status fc2t2_eval(fc2t2_plan plan, const void* L, const void* q, int64_t M, void* y,
                         void* grad, void* hess, hipStream_t stream);
+
+/* L2P (section 3) with the queries taken in cell order: bins and sorts q [M][dim] by cell into
+ * the workspace (the sorted coordinates, input indices and cell starts stay there), then
+ * evaluates y [M] (input order) from the sorted records, each cell's row read once from
+ * memory.  The records serve fc2t2_eval_backward_sorted for the same plan, q and M (a training
+ * step sorts its queries once).  FP32 IO and one channel only (EUNSUPPORTED otherwise);
+ * ws_bytes >= fc2t2_workspace_size(plan, FC2T2_OP_EVAL_SORTED, M); out-of-domain queries are
+ * counted as by fc2t2_eval. */
+fc2t2_status fc2t2_eval_sorted(fc2t2_plan plan, const void* L, const void* q, int64_t M, void* y,
+                               void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* fc2t2_eval_backward from the records an fc2t2_eval_sorted call left in `ws` (same plan, same
+ * queries and M, ws not written in between; q is not read again): one pass over the sorted
+ * queries gives gL (the transpose of L2P, per-cell sums) and gq [M][dim] = gy . grad f(q) (NULL
+ * to skip; L is then not read), both written at the queries' input positions.  accumulate != 0
+ * adds into gL and gq, 0 overwrites them. */
+fc2t2_status fc2t2_eval_backward_sorted(fc2t2_plan plan, const void* L, int64_t M, const void* gy,
+                                        void* gL, void* gq, const void* ws, size_t ws_bytes,
+                                        int accumulate, hipStream_t stream);
 
 /* Backward of fc2t2_eval's value output (section 4.1): with gy [M][C],
  *   gL [C][n^dim][P_pad] += d(sum gy*y)/dL  (the transpose of L2P),

@@ -78,12 +78,16 @@ def stage_bytes(stage: str, dim: int, n: int, K: int, N: int = 0, M: int = 0, it
       l2p_T  sorted q, gy read (once, contiguous)       (d + 1) es
       qgrad  q, gy read, q_bar written                  (2 d + 1) es
       p2m_T  p, w read, p_bar, w_bar written            2 (d + 1) es
+      l2p_sorted     sorted q, cell, index read; y written          d es + 12
+      l2p_T_sorted   sorted q, index, gy read; q_bar written         (2 d + 1) es + 4
     per finest cell (R = P_pad es channels, one row):
       p2m    cell start read, moment row written        4 + R
       l2p    local row read                             R
       l2p_T  cell start read, cotangent row written     4 + R
       qgrad  local row read                             R
       p2m_T  moment-cotangent row read                  R
+      l2p_sorted     local row read                     R
+      l2p_T_sorted   cell start read, local row read, cotangent row written   4 + 2 R
     """
     d, es, G = dim, itemsize, n ** dim
     R = p_pad(dim, K) * es * channels
@@ -97,6 +101,10 @@ def stage_bytes(stage: str, dim: int, n: int, K: int, N: int = 0, M: int = 0, it
         return M * (2 * d + 1) * es + G * R
     if stage == "p2m_T":
         return N * 2 * (d + 1) * es + G * R
+    if stage == "l2p_sorted":
+        return M * (d * es + 12) + G * R
+    if stage == "l2p_T_sorted":
+        return M * ((2 * d + 1) * es + 4) + G * (4 + 2 * R)
     raise ValueError(stage)
 
 
@@ -259,15 +267,18 @@ def pyramid_rows(dim: int, n: int) -> list:
 
 
 def explicit_step_model(dim: int, n: int, K: int, N: int, M: int, m2l_flops_fwd: int, m2l_flops_T: int,
-                        itemsize: int = 4, carried: bool = True) -> dict:
+                        itemsize: int = 4, carried: bool = True, sorted_queries: bool = True) -> dict:
     """Per stage of one explicit-layer step (expand, eval, eval_backward, expand_backward) the
     algorithmic HBM bytes and flops, grouped as the library's stage timing groups its launches.
-    M2L flops are passed in (useful flops of the tiles that run)."""
+    M2L flops are passed in (useful flops of the tiles that run).  sorted_queries: the step of
+    eval_sorted / eval_backward_sorted (queries sorted once with their coordinates, L2P from the
+    sorted records, q_bar fused into the transpose of L2P); otherwise eval / eval_backward."""
     G = n ** dim
     R = p_pad(dim, K) * itemsize
     rows = pyramid_rows(dim, n)
     pw = dim + 1 if carried else 0
-    sort = sort_bytes(N, dim, G, pw, itemsize) + sort_bytes(M, dim, G, pw, itemsize) + N * dim * itemsize + G
+    pq = dim if sorted_queries else pw
+    sort = sort_bytes(N, dim, G, pw, itemsize) + sort_bytes(M, dim, G, pq, itemsize) + N * dim * itemsize + G
     up = sum(rows) * R                         # read the finest grid, write every coarser one
     down = sum(rows) * R + rows[0] * R         # read every grid, write the finest
     m2l_io = 2 * sum(rows) * R                 # moments (or local cotangents) in, locals out
@@ -277,9 +288,12 @@ def explicit_step_model(dim: int, n: int, K: int, N: int, M: int, m2l_flops_fwd:
         "shift_up": {"bytes": 2 * up, "flops": 0},
         "m2l": {"bytes": m2l_io, "flops": m2l_flops_fwd},
         "shift_down": {"bytes": 2 * down, "flops": 0},
-        "l2p": {"bytes": stage_bytes("l2p", dim, n, K, M=M, itemsize=itemsize), "flops": 0},
-        "l2p_T": {"bytes": stage_bytes("l2p_T", dim, n, K, M=M, itemsize=itemsize), "flops": 0},
-        "qgrad": {"bytes": stage_bytes("qgrad", dim, n, K, M=M, itemsize=itemsize), "flops": 0},
+        "l2p": {"bytes": stage_bytes("l2p_sorted" if sorted_queries else "l2p", dim, n, K, M=M, itemsize=itemsize),
+                "flops": 0},
+        "l2p_T": {"bytes": stage_bytes("l2p_T_sorted" if sorted_queries else "l2p_T", dim, n, K, M=M,
+                                       itemsize=itemsize), "flops": 0},
+        "qgrad": {"bytes": 0 if sorted_queries else stage_bytes("qgrad", dim, n, K, M=M, itemsize=itemsize),
+                  "flops": 0},
         "m2l_T": {"bytes": m2l_io, "flops": m2l_flops_T},
         "p2m_T": {"bytes": stage_bytes("p2m_T", dim, n, K, N=N, itemsize=itemsize), "flops": 0},
     }

@@ -76,6 +76,31 @@ size_t ws_expand(const fc2t2_plan_s* pl, int64_t N) {
   return c.off;
 }
 
+// Records of queries sorted by cell with their coordinates, kept from fc2t2_eval_sorted for
+// fc2t2_eval_backward_sorted.
+struct QueryRecords {
+  uint32_t *keys, *keys_sorted, *perm, *starts;
+  float* pay;     // [M][dim]
+  void* scratch;
+};
+
+QueryRecords carve_query_records(Carve& c, const fc2t2_plan_s* pl, int64_t M) {
+  QueryRecords b;
+  b.keys = c.take<uint32_t>(M);
+  b.keys_sorted = c.take<uint32_t>(M);
+  b.perm = c.take<uint32_t>(M);
+  b.starts = c.take<uint32_t>(pl->G + 1);
+  b.pay = c.take<float>((size_t)M * pl->dim);
+  b.scratch = c.take<char>(radix_sort_scratch_bytes(M));
+  return b;
+}
+
+size_t ws_eval_sorted(const fc2t2_plan_s* pl, int64_t M) {
+  Carve c(nullptr);
+  carve_query_records(c, pl, M);
+  return c.off;
+}
+
 size_t ws_eval_backward(const fc2t2_plan_s* pl, int64_t M) {
   Carve c(nullptr);
   carve_sort(c, pl, M);
@@ -231,6 +256,7 @@ size_t fc2t2_workspace_size(fc2t2_plan plan, int op, int64_t count) {
     case FC2T2_OP_EXPAND_BACKWARD: return ws_expand_backward(plan);
     case FC2T2_OP_RAY_INTEGRAL_BACKWARD: return ray_integral_bwd_ws(plan, count);
     case FC2T2_OP_RAY_ROOT_BACKWARD: return ray_root_bwd_ws(plan, count);
+    case FC2T2_OP_EVAL_SORTED: return ws_eval_sorted(plan, count);
   }
   return 0;
 }
@@ -273,6 +299,43 @@ fc2t2_status fc2t2_eval(fc2t2_plan plan, const void* L, const void* q, int64_t M
   if (M > 0 && (!q || !y)) return FC2T2_EINVAL;
   StageScope t(plan, FC2T2_STAGE_L2P, stream);
   return launch_l2p(plan, L, q, M, y, grad, hess, stream);
+}
+
+fc2t2_status fc2t2_eval_sorted(fc2t2_plan plan, const void* L, const void* q, int64_t M, void* y, void* ws,
+                               size_t ws_bytes, hipStream_t stream) {
+  if (!plan || !L || bad_count(M)) return FC2T2_EINVAL;
+  if (M > 0 && (!q || !y)) return FC2T2_EINVAL;
+  if (!sort_payload_ok(plan)) return FC2T2_EUNSUPPORTED;
+  if (!ws || ws_bytes < ws_eval_sorted(plan, M)) return FC2T2_EWORKSPACE;
+  if (M == 0) return FC2T2_OK;
+  Carve c(ws);
+  const QueryRecords b = carve_query_records(c, plan, M);
+  fc2t2_status st;
+  {
+    StageScope t(plan, FC2T2_STAGE_SORT, stream);
+    st = sort_points_by_cell(plan, q, M, b.keys, b.keys_sorted, b.perm, b.scratch, stream, nullptr, b.pay,
+                             plan->ood);
+    if (st) return st;
+    st = launch_cell_starts(b.keys_sorted, M, plan->G, b.starts, stream);
+  }
+  if (st) return st;
+  StageScope t(plan, FC2T2_STAGE_L2P, stream);
+  return launch_l2p_sorted(plan, L, b.pay, b.keys_sorted, b.perm, M, y, stream);
+}
+
+fc2t2_status fc2t2_eval_backward_sorted(fc2t2_plan plan, const void* L, int64_t M, const void* gy, void* gL,
+                                        void* gq, const void* ws, size_t ws_bytes, int accumulate,
+                                        hipStream_t stream) {
+  if (!plan || !gL || bad_count(M)) return FC2T2_EINVAL;
+  if (M > 0 && !gy) return FC2T2_EINVAL;
+  if (gq && !L) return FC2T2_EINVAL;
+  if (!sort_payload_ok(plan)) return FC2T2_EUNSUPPORTED;
+  if (!ws || ws_bytes < ws_eval_sorted(plan, M)) return FC2T2_EWORKSPACE;
+  if (M == 0) return accumulate ? FC2T2_OK : launch_zero(plan, gL, (int64_t)grid_elems(plan, 0), stream);
+  Carve c((void*)ws);
+  const QueryRecords b = carve_query_records(c, plan, M);
+  StageScope t(plan, FC2T2_STAGE_L2P_T, stream);
+  return launch_l2p_T_qgrad_sorted(plan, L, b.pay, b.starts, b.perm, gy, M, gL, gq, stream, accumulate != 0);
 }
 
 fc2t2_status fc2t2_eval_backward(fc2t2_plan plan, const void* L, const void* q, int64_t M,

@@ -105,6 +105,47 @@ struct QueryMonomialsGrad {
   }
 };
 
+// Transpose of L2P with q_bar from queries sorted with their coordinates (FP32, one channel):
+// record r (sorted position) holds the coordinates (pay [M][D]); its input index perm[r] gives
+// the cotangent gy and where q_bar goes.  Each query is one record, so the gq writes do not
+// collide.
+template <class S>
+struct SortedQueryGrad {
+  const float* __restrict__ pay;
+  const uint32_t* __restrict__ perm;
+  const float* __restrict__ gy;    // [M]
+  const float* __restrict__ L;     // [G][Ppad]
+  float* __restrict__ gq;          // [M][D]
+  float inv_h;
+  int accumulate;
+  __device__ __forceinline__ void operator()(uint32_t r, const float (&centre)[3], int, float (&v)[S::P],
+                                             int64_t cell) const {
+    constexpr int D = S::D;
+    const float* rec = pay + (size_t)r * D;
+    float u[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < D; ++j) u[j] = (rec[j] - centre[j]) * inv_h;
+    float pw[3][S::K + 1];
+    power_table<S>(u, pw);
+    const uint32_t i = perm[r];
+    const float a = gy[i];
+    if (gq) {
+      float row[S::Ppad];
+      load_row<S::Ppad>(L + cell * S::Ppad, row);
+      float val, g[3], hs[6];
+      eval_poly<S, float, true, false>(row, pw, val, g, hs);
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const float gj = a * g[j] * inv_h;
+        gq[(int64_t)i * D + j] = accumulate ? gq[(int64_t)i * D + j] + gj : gj;
+      }
+    }
+    monomials<S>(u, v);
+#pragma unroll
+    for (int k = 0; k < S::P; ++k) v[k] *= a;
+  }
+};
+
 template <typename T>
 fc2t2_status reduce_points(const fc2t2_plan_s* pl, const void* x, const void* wt, int64_t count,
                            const uint32_t* starts, const uint32_t* perm, void* out, bool accumulate,
@@ -214,6 +255,33 @@ __global__ void __launch_bounds__(256) qgrad_sorted_kernel(const float* __restri
   const int64_t i = perm[r];
 #pragma unroll
   for (int j = 0; j < D; ++j) gq[i * D + j] = accumulate ? gq[i * D + j] + a * g[j] * inv_h : a * g[j] * inv_h;
+}
+
+// L2P over the queries in sorted order (FP32, one channel): record r holds the query's
+// coordinates (pay [M][D]), its cell (keys) and input index (perm); queries of one cell are
+// neighbours, so their row is read once from memory and then from cache.  y[perm[r]] = f.
+template <class S>
+__global__ void __launch_bounds__(256) l2p_sorted_kernel(const float* __restrict__ grid, const float* __restrict__ pay,
+                                                         const uint32_t* __restrict__ keys,
+                                                         const uint32_t* __restrict__ perm, int64_t count, int n,
+                                                         float lo, float h, float inv_h, float* __restrict__ y) {
+  constexpr int D = S::D, Ppad = S::Ppad;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= count) return;
+  const int64_t cell = keys[r];
+  int ic[3];
+  decode_cell<D, float>(cell, n, ic);
+  const float* rec = pay + r * D;
+  float u[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int j = 0; j < D; ++j) u[j] = (rec[j] - (lo + (float(ic[j]) + 0.5f) * h)) * inv_h;
+  float pw[3][S::K + 1];
+  power_table<S>(u, pw);
+  float c[Ppad];
+  load_row<Ppad>(grid + cell * Ppad, c);
+  float val, g[3], hs[6];
+  eval_poly<S, float, false, false>(c, pw, val, g, hs);
+  y[perm[r]] = val;
 }
 
 template <typename T, int MODE>
@@ -386,6 +454,37 @@ fc2t2_status launch_qgrad_sorted(const fc2t2_plan_s* pl, const void* L, const vo
   if (st != FC2T2_OK) return st;
   FC2T2_LAUNCH_CHECK();
   return FC2T2_OK;
+}
+
+fc2t2_status launch_l2p_sorted(const fc2t2_plan_s* pl, const void* L, const void* pay, const uint32_t* keys,
+                               const uint32_t* perm, int64_t M, void* y, hipStream_t s) {
+  if (pl->io != FC2T2_IO_F32 || pl->C != 1) return FC2T2_EUNSUPPORTED;
+  if (M == 0) return FC2T2_OK;
+  fc2t2_status st = FC2T2_EUNSUPPORTED;
+  const dim3 grid((unsigned)ceil_div(M, 256));
+  dispatch_shape(pl->dim, pl->K, [&](auto shape) {
+    using S = decltype(shape);
+    hipLaunchKernelGGL((l2p_sorted_kernel<S>), grid, dim3(256), 0, s, (const float*)L, (const float*)pay, keys, perm,
+                       M, pl->n, (float)pl->lo, (float)pl->h0, (float)(1.0 / pl->h0), (float*)y);
+    st = FC2T2_OK;
+  });
+  if (st != FC2T2_OK) return st;
+  FC2T2_LAUNCH_CHECK();
+  return FC2T2_OK;
+}
+
+fc2t2_status launch_l2p_T_qgrad_sorted(const fc2t2_plan_s* pl, const void* L, const void* pay, const uint32_t* starts,
+                                       const uint32_t* perm, const void* gy, int64_t M, void* gL, void* gq,
+                                       hipStream_t s, bool accumulate) {
+  if (pl->io != FC2T2_IO_F32 || pl->C != 1) return FC2T2_EUNSUPPORTED;
+  fc2t2_status st = FC2T2_EUNSUPPORTED;
+  dispatch_shape(pl->dim, pl->K, [&](auto shape) {
+    using S = decltype(shape);
+    SortedQueryGrad<S> fn{(const float*)pay, perm, (const float*)gy, (const float*)L, (float*)gq,
+                          (float)(1.0 / pl->h0), accumulate ? 1 : 0};
+    st = launch_reduce_cells<S, float>(pl, starts, nullptr, M, (float*)gL, accumulate, fn, s);
+  });
+  return st;
 }
 
 template <typename T>

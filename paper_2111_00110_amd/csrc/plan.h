@@ -88,7 +88,8 @@ fc2t2_status radix_sort_pairs(const uint32_t* keys_in, uint32_t* keys_out, uint3
 // starts[c] = first sorted position with key >= c, for c in [0, G]; starts[G] = N.
 // The same for points: keys (written to `keys`) are the linear finest-cell indices of x.
 // With pay_out, each point's coordinates and its one value in `extra` travel with it:
-// pay_out [N][dim + 1] receives them in sorted order (FP32, one channel: sort_payload_ok).
+// pay_out [N][dim + 1] receives them in sorted order (FP32, one channel: sort_payload_ok); with
+// pay_out and no `extra`, the coordinates alone: pay_out [N][dim].
 // With ood, the points outside the domain are added to *ood.
 fc2t2_status sort_points_by_cell(const fc2t2_plan_s* pl, const void* x, int64_t N, uint32_t* keys,
                                  uint32_t* keys_out, uint32_t* vals_out, void* scratch, hipStream_t s,
@@ -135,6 +136,15 @@ fc2t2_status launch_p2m_T(const fc2t2_plan_s* pl, const void* GM0, const void* p
 // sorted cells, perm the input indices; gq[perm[r]] += (or =) gy grad f(q) / h.
 fc2t2_status launch_qgrad_sorted(const fc2t2_plan_s* pl, const void* L, const void* pay, const uint32_t* keys,
                                  const uint32_t* perm, int64_t M, void* gq, hipStream_t s, bool accumulate = true);
+// L2P over queries sorted with their coordinates (FP32, one channel): pay [M][dim], keys the
+// sorted cells, perm the input indices; y[perm[r]] = f(q_r).
+fc2t2_status launch_l2p_sorted(const fc2t2_plan_s* pl, const void* L, const void* pay, const uint32_t* keys,
+                               const uint32_t* perm, int64_t M, void* y, hipStream_t s);
+// Transpose of L2P fused with q_bar over the same sorted queries: gL (+)= per-cell sums of
+// gy[perm[r]] (q_r - c)^k / k!, and gq[perm[r]] (+)= gy grad f(q_r) (one pass, one channel).
+fc2t2_status launch_l2p_T_qgrad_sorted(const fc2t2_plan_s* pl, const void* L, const void* pay, const uint32_t* starts,
+                                       const uint32_t* perm, const void* gy, int64_t M, void* gL, void* gq,
+                                       hipStream_t s, bool accumulate);
 // p[0 .. elems) = 0 in the plan's IO type (a fill kernel, safe under graph capture).
 fc2t2_status launch_zero(const fc2t2_plan_s* pl, void* p, int64_t elems, hipStream_t s);
 

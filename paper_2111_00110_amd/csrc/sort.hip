@@ -422,6 +422,11 @@ fc2t2_status sort_points_by_cell(const fc2t2_plan_s* pl, const void* x, int64_t 
     if (!sort_payload_ok(pl)) return FC2T2_EUNSUPPORTED;
     const uint32_t* pa = (const uint32_t*)x;
     const uint32_t* pb = (const uint32_t*)extra;
+    if (!extra)   // the coordinates only: pay_out [N][dim]
+      return pl->dim == 2 ? onesweep_passes<2>(keys, keys_out, vals_out, (uint32_t)N, npass, c, pa, 2, nullptr,
+                                               (uint32_t*)pay_out, s)
+                          : onesweep_passes<3>(keys, keys_out, vals_out, (uint32_t)N, npass, c, pa, 3, nullptr,
+                                               (uint32_t*)pay_out, s);
     return pl->dim == 2 ? onesweep_passes<3>(keys, keys_out, vals_out, (uint32_t)N, npass, c, pa, 2, pb,
                                              (uint32_t*)pay_out, s)
                         : onesweep_passes<4>(keys, keys_out, vals_out, (uint32_t)N, npass, c, pa, 3, pb,

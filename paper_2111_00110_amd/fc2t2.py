@@ -25,7 +25,7 @@ M2L_PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x2": 3, "bf16x3": 4, "separable"
 FIT = {"taylor": 0, "lsq": 0x100}   # M2L tensor: derivatives, or least-squares fit (section 3.1)
 IO = {"f32": 0, "f64": 1}
 OP = {"expand": 0, "eval_backward": 1, "expand_backward": 2, "ray_integral_backward": 3,
-      "ray_root_backward": 4}
+      "ray_root_backward": 4, "eval_sorted": 5}
 ROOT_SAVED = 12
 ROOT_SMOOTH, ROOT_FACE, ROOT_GRAZING = 0, 1, 2   # kind of a ray-root hit, saved[:, 10]
 
@@ -81,6 +81,10 @@ def lib() -> ctypes.CDLL:
     L.fc2t2_expand.argtypes = [vp, vp, vp, i64, vp, vp, sz, vp]
     L.fc2t2_eval.restype = i32
     L.fc2t2_eval.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
+    L.fc2t2_eval_sorted.restype = i32
+    L.fc2t2_eval_sorted.argtypes = [vp, vp, vp, i64, vp, vp, sz, vp]
+    L.fc2t2_eval_backward_sorted.restype = i32
+    L.fc2t2_eval_backward_sorted.argtypes = [vp, vp, i64, vp, vp, vp, vp, sz, i32, vp]
     L.fc2t2_eval_backward.restype = i32
     L.fc2t2_eval_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]
     L.fc2t2_expand_backward.restype = i32
@@ -248,6 +252,37 @@ class Plan:
         self._debug_domain("queries")
         return y, g, hs
 
+    @property
+    def sorted_queries(self) -> bool:
+        """Whether eval_sorted / eval_backward_sorted apply (FP32 IO, one channel)."""
+        return self.io == "f32" and self.C == 1
+
+    def eval_sorted(self, Lt: torch.Tensor, q: torch.Tensor, ws: Optional[torch.Tensor] = None):
+        """y at the queries taken in cell order; returns (y, ws), ws holding the sorted queries for
+        eval_backward_sorted."""
+        M = q.shape[0]
+        q = self._t(q, (M, self.dim), "q")
+        Lt = self._t(Lt, self.local_shape(), "L")
+        if ws is None:
+            ws = self.workspace("eval_sorted", M)
+        y = torch.empty((M, self.C), dtype=self.dtype, device=self.device)
+        _check(lib().fc2t2_eval_sorted(self.handle, _ptr(Lt), _ptr(q), M, _ptr(y), _ptr(ws), ws.numel(), _stream()),
+               "fc2t2_eval_sorted")
+        self._debug_domain("queries")
+        return y, ws
+
+    def eval_backward_sorted(self, Lt, M: int, gy, ws, gL: torch.Tensor, gq: Optional[torch.Tensor] = None,
+                             accumulate: bool = True):
+        """gL, gq += (accumulate) or = (otherwise) the cotangents of L and q, from the sorted queries
+        an eval_sorted call left in ws."""
+        gy = self._t(gy, (M, self.C), "gy")
+        assert gL.is_contiguous() and tuple(gL.shape) == self.local_shape() and gL.dtype == self.dtype
+        if gq is not None:
+            assert gq.is_contiguous() and tuple(gq.shape) == (M, self.dim) and gq.dtype == self.dtype
+        _check(lib().fc2t2_eval_backward_sorted(self.handle, _ptr(Lt), M, _ptr(gy), _ptr(gL), _ptr(gq), _ptr(ws),
+                                                ws.numel(), 1 if accumulate else 0, _stream()),
+               "fc2t2_eval_backward_sorted")
+
     def out_of_domain(self, reset: bool = False) -> int:
         """Points outside [lo, hi]^dim met by expand (sources) and eval (queries) since the plan was
         made or last reset; they were binned into the nearest boundary cell.  Synchronises."""
@@ -390,8 +425,11 @@ class Explicit(torch.autograd.Function):
     @staticmethod
     def forward(ctx, plan: Plan, p, w, q):
         Lt = plan.expand(p, w)
-        y, _, _ = plan.eval(Lt, q)
-        ctx.plan = plan
+        if plan.sorted_queries:   # queries sorted once, in the forward; the backward reuses them
+            y, ws = plan.eval_sorted(Lt, q)
+        else:
+            (y, _, _), ws = plan.eval(Lt, q), None
+        ctx.plan, ctx.ws = plan, ws
         ctx.save_for_backward(p, w, q, Lt)
         return y
 
@@ -406,7 +444,11 @@ class Explicit(torch.autograd.Function):
         gp = torch.empty_like(p) if need_p else None
         gw = torch.empty_like(w) if need_w else None
         gL = torch.empty(plan.local_shape(), dtype=plan.dtype, device=q.device) if (need_p or need_w) else None
-        plan.eval_backward(Lt, q, gy, gL, gq, accumulate=False)
+        if ctx.ws is not None and gL is not None:
+            plan.eval_backward_sorted(Lt, q.shape[0], gy, ctx.ws, gL, gq, accumulate=False)
+        else:
+            plan.eval_backward(Lt, q, gy, gL, gq, accumulate=False)
+        ctx.ws = None
         if gL is not None:
             plan.expand_backward(gL, p, w, gp, gw, accumulate=False)
         return None, gp, gw, gq

@@ -287,3 +287,58 @@ def test_eval_hessian_matches_checker(F, d, io):
     assert rel(hs.cpu().numpy(), want) < tol
     assert rel(g.cpu().numpy(), fmm.l2p_grad(geo, L0, x["q"])) < tol
     assert rel(y.cpu().numpy(), fmm.l2p(geo, L0, x["q"])) < (1e-12 if io == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("d,io_kernel", [(2, ("gaussian", 0.03)), (3, ("imq", 0.1))])
+def test_sorted_query_path_matches_checker_and_unsorted(F, d, io_kernel):
+    """fc2t2_eval_sorted + fc2t2_eval_backward_sorted (queries sorted once, q_bar fused into the
+    transpose of L2P) against the checker at the contract, and bitwise equal to the unsorted
+    calls (same formulas, same per-cell summation order); overwrite and accumulate; M = 0."""
+    kern, par = io_kernel
+    lo, hi = (0.0, 1.0) if d == 2 else (-1.0, 1.0)
+    wl = W.Workload("s", d, 32 if d == 2 else 16, lo, hi, 4, kern, par, 5000, 7001, 0, "f32", "explicit", "uniform")
+    x = W.make(wl, seed=14)
+    geo, ker = oracle_geometry(wl), oracle_kernel(wl)
+    plan = _plan(F, wl)
+    p, w, q, gy = (_dev(x[k]) for k in ("p", "w", "q", "gy"))
+    Lt = plan.expand(p, w)
+    y_s, ws = plan.eval_sorted(Lt, q)
+    gL_s, gq_s = plan.new_local().fill_(5.0), torch.empty_like(q).fill_(5.0)
+    plan.eval_backward_sorted(Lt, wl.M, gy, ws, gL_s, gq_s, accumulate=False)
+    y_u, _, _ = plan.eval(Lt, q)
+    gL_u, gq_u = plan.new_local(), torch.zeros_like(q)
+    plan.eval_backward(Lt, q, gy, gL_u, gq_u)
+    torch.cuda.synchronize()
+    assert torch.equal(y_s, y_u)
+    assert torch.equal(gL_s, gL_u)
+    assert torch.equal(gq_s, gq_u)
+    plan.eval_backward_sorted(Lt, wl.M, gy, ws, gL_s, gq_s, accumulate=True)
+    assert torch.allclose(gL_s, 2 * gL_u, rtol=1e-6, atol=0) and torch.allclose(gq_s, 2 * gq_u, rtol=1e-6, atol=0)
+    L0 = fmm.expand(geo, ker, x["p"], x["w"])
+    assert rel(y_s.cpu().numpy(), fmm.l2p(geo, L0, x["q"])) < 1e-5
+    gq_ref = np.einsum("mc,mcj->mj", x["gy"].astype(np.float64), fmm.l2p_grad(geo, L0, x["q"]))
+    assert rel(gq_u.cpu().numpy(), gq_ref) < 1e-4
+    G = fmm.l2p_T(geo, x["q"], x["gy"])
+    from helpers import scaled_cotangent
+    assert rel(gL_u.cpu().numpy(), scaled_cotangent(geo, G, plan.P_pad)) < 1e-5
+    # no queries: overwrite zeroes gL
+    y0, ws0 = plan.eval_sorted(Lt, q[:0])
+    gL0 = plan.new_local().fill_(1.0)
+    plan.eval_backward_sorted(Lt, 0, gy[:0], ws0, gL0, None, accumulate=False)
+    assert y0.shape == (0, 1) and float(gL0.abs().max()) == 0.0
+
+
+def test_explicit_autograd_uses_sorted_queries(F):
+    """The autograd wrapper (sorted-query path for FP32, one channel) against the unsorted calls."""
+    wl = W.workload("explicit2d", N=1 << 14, M=1 << 13, n=64)
+    x = W.make(wl, seed=15)
+    plan = _plan(F, wl)
+    assert plan.sorted_queries
+    p, w, q = (_dev(x[k]).requires_grad_(True) for k in ("p", "w", "q"))
+    y = F.Explicit.apply(plan, p, w, q)
+    (y * _dev(x["gy"])).sum().backward()
+    got = _run_gpu(F, plan, x)
+    assert np.array_equal(y.detach().cpu().numpy(), got["y"])
+    assert rel(w.grad.cpu().numpy(), got["gw"]) < 1e-6
+    assert rel(p.grad.cpu().numpy(), got["gp"]) < 1e-6
+    assert np.array_equal(q.grad.cpu().numpy(), got["gq"])

@@ -159,6 +159,19 @@ int fc2t2_plan_levels(fc2t2_plan plan);
 fc2t2_status fc2t2_out_of_domain(fc2t2_plan plan, int64_t* count, int reset, hipStream_t stream);
 size_t fc2t2_local_numel(fc2t2_plan plan);    /* C * n^dim * P_pad elements */
 
+/* Sorts by cell (of sources, queries, ray records) whose decoupled look-back gave up waiting on
+ * this plan since its creation or the last reset, counted on the device; same calling rules as
+ * fc2t2_out_of_domain.  A failed sort leaves every cell empty for the stages after it (their
+ * per-cell outputs are zero, per-point outputs in sorted order are not written), so a non-zero
+ * count means the outputs of the calls since the last read are not valid. */
+fc2t2_status fc2t2_sort_failures(fc2t2_plan plan, int64_t* count, int reset, hipStream_t stream);
+
+/* Test aid for the failure path above, process-wide: enable != 0 makes tile 1 of every one-sweep
+ * pass withhold its published counts and shortens the look-back's bounded wait to a few polls, so
+ * the tiles after it give up (every kernel still ends normally); enable = 0 restores normal
+ * sorting.  Calls made while it is enabled do not produce valid results. */
+void fc2t2_debug_sort_fault(int enable);
+
 /* Ray roots that fc2t2_ray_root classified as grazing (FC2T2_ROOT_GRAZING) on this plan since
  * its creation or the last reset, counted on the device; same calling rules as
  * fc2t2_out_of_domain. */

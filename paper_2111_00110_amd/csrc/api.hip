@@ -43,7 +43,7 @@ fc2t2_status bin_and_sort(const fc2t2_plan_s* pl, const void* x, int64_t count, 
   fc2t2_status st = sort_points_by_cell(pl, x, count, b.keys, b.keys_sorted, b.perm, b.scratch, s, extra,
                                         extra ? b.pay : nullptr, ood);
   if (st) return st;
-  return launch_cell_starts(b.keys_sorted, count, pl->G, b.starts, s);
+  return launch_cell_starts(b.keys_sorted, count, pl->G, b.starts, s, sort_err_word(b.scratch, count), pl->sort_fail);
 }
 
 // The next occupancy stamp of a plan (1..255).
@@ -198,7 +198,9 @@ fc2t2_status eval_backward_impl(fc2t2_plan plan, const void* L, const void* q, i
       // q_bar in cell order (rows from cache, scattered writes of q_bar) in 2-D; in input order
       // (scattered row reads, contiguous writes) in 3-D, where the wider scattered writes
       // measured slower
-      if (plan->dim == 2) return launch_qgrad_sorted(plan, L, sb.pay, sb.keys_sorted, sb.perm, M, gq, stream, acc);
+      if (plan->dim == 2)
+        return launch_qgrad_sorted(plan, L, sb.pay, sb.keys_sorted, sb.perm, M, gq, stream, acc,
+                                   sort_err_word(sb.scratch, M));
       return launch_l2p_qgrad(plan, L, q, M, gy, gq, stream, acc);
     }
     StageScope t(plan, FC2T2_STAGE_L2P_T, stream);
@@ -316,11 +318,12 @@ fc2t2_status fc2t2_eval_sorted(fc2t2_plan plan, const void* L, const void* q, in
     st = sort_points_by_cell(plan, q, M, b.keys, b.keys_sorted, b.perm, b.scratch, stream, nullptr, b.pay,
                              plan->ood);
     if (st) return st;
-    st = launch_cell_starts(b.keys_sorted, M, plan->G, b.starts, stream);
+    st = launch_cell_starts(b.keys_sorted, M, plan->G, b.starts, stream, sort_err_word(b.scratch, M),
+                            plan->sort_fail);
   }
   if (st) return st;
   StageScope t(plan, FC2T2_STAGE_L2P, stream);
-  return launch_l2p_sorted(plan, L, b.pay, b.keys_sorted, b.perm, M, y, stream);
+  return launch_l2p_sorted(plan, L, b.pay, b.keys_sorted, b.perm, M, y, stream, sort_err_word(b.scratch, M));
 }
 
 fc2t2_status fc2t2_eval_backward_sorted(fc2t2_plan plan, const void* L, int64_t M, const void* gy, void* gL,

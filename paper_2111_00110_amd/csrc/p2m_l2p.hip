@@ -234,10 +234,10 @@ __global__ void __launch_bounds__(256) qgrad_sorted_kernel(const float* __restri
                                                            const uint32_t* __restrict__ keys,
                                                            const uint32_t* __restrict__ perm, int64_t count, int n,
                                                            float lo, float h, float inv_h, float* __restrict__ gq,
-                                                           int accumulate) {
+                                                           int accumulate, const uint32_t* __restrict__ err) {
   constexpr int D = S::D, Ppad = S::Ppad, W = D + 1;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= count) return;
+  if (r >= count || *err) return;   // a failed sort: the records are not valid
   const int64_t cell = keys[r];
   int ic[3];
   decode_cell<D, float>(cell, n, ic);
@@ -264,10 +264,11 @@ template <class S>
 __global__ void __launch_bounds__(256) l2p_sorted_kernel(const float* __restrict__ grid, const float* __restrict__ pay,
                                                          const uint32_t* __restrict__ keys,
                                                          const uint32_t* __restrict__ perm, int64_t count, int n,
-                                                         float lo, float h, float inv_h, float* __restrict__ y) {
+                                                         float lo, float h, float inv_h, float* __restrict__ y,
+                                                         const uint32_t* __restrict__ err) {
   constexpr int D = S::D, Ppad = S::Ppad;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= count) return;
+  if (r >= count || *err) return;   // a failed sort: the records are not valid
   const int64_t cell = keys[r];
   int ic[3];
   decode_cell<D, float>(cell, n, ic);
@@ -440,7 +441,8 @@ fc2t2_status launch_p2m_T(const fc2t2_plan_s* pl, const void* GM0, const void* p
 }
 
 fc2t2_status launch_qgrad_sorted(const fc2t2_plan_s* pl, const void* L, const void* pay, const uint32_t* keys,
-                                 const uint32_t* perm, int64_t M, void* gq, hipStream_t s, bool accumulate) {
+                                 const uint32_t* perm, int64_t M, void* gq, hipStream_t s, bool accumulate,
+                                 const uint32_t* err) {
   if (pl->io != FC2T2_IO_F32 || pl->C != 1) return FC2T2_EUNSUPPORTED;
   if (M == 0) return FC2T2_OK;
   fc2t2_status st = FC2T2_EUNSUPPORTED;
@@ -448,7 +450,8 @@ fc2t2_status launch_qgrad_sorted(const fc2t2_plan_s* pl, const void* L, const vo
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {
     using S = decltype(shape);
     hipLaunchKernelGGL((qgrad_sorted_kernel<S>), grid, dim3(256), 0, s, (const float*)L, (const float*)pay, keys, perm,
-                       M, pl->n, (float)pl->lo, (float)pl->h0, (float)(1.0 / pl->h0), (float*)gq, accumulate ? 1 : 0);
+                       M, pl->n, (float)pl->lo, (float)pl->h0, (float)(1.0 / pl->h0), (float*)gq, accumulate ? 1 : 0,
+                       err);
     st = FC2T2_OK;
   });
   if (st != FC2T2_OK) return st;
@@ -457,7 +460,7 @@ fc2t2_status launch_qgrad_sorted(const fc2t2_plan_s* pl, const void* L, const vo
 }
 
 fc2t2_status launch_l2p_sorted(const fc2t2_plan_s* pl, const void* L, const void* pay, const uint32_t* keys,
-                               const uint32_t* perm, int64_t M, void* y, hipStream_t s) {
+                               const uint32_t* perm, int64_t M, void* y, hipStream_t s, const uint32_t* err) {
   if (pl->io != FC2T2_IO_F32 || pl->C != 1) return FC2T2_EUNSUPPORTED;
   if (M == 0) return FC2T2_OK;
   fc2t2_status st = FC2T2_EUNSUPPORTED;
@@ -465,7 +468,7 @@ fc2t2_status launch_l2p_sorted(const fc2t2_plan_s* pl, const void* L, const void
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {
     using S = decltype(shape);
     hipLaunchKernelGGL((l2p_sorted_kernel<S>), grid, dim3(256), 0, s, (const float*)L, (const float*)pay, keys, perm,
-                       M, pl->n, (float)pl->lo, (float)pl->h0, (float)(1.0 / pl->h0), (float*)y);
+                       M, pl->n, (float)pl->lo, (float)pl->h0, (float)(1.0 / pl->h0), (float*)y, err);
     st = FC2T2_OK;
   });
   if (st != FC2T2_OK) return st;

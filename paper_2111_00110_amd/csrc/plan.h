@@ -14,6 +14,7 @@ struct fc2t2_plan_s {
   unsigned long long* ood = nullptr;   // device counter: points outside the domain (expand, eval)
   unsigned long long* grazing = nullptr;   // device counter: grazing ray roots (ray root); the
                                            //   second word of the ood allocation
+  unsigned long long* sort_fail = nullptr; // device counter: sorts whose look-back gave up; third word
   double lo, hi, param;
   double h0;                      // finest cell width
   int64_t G;                      // finest cells
@@ -96,8 +97,14 @@ fc2t2_status sort_points_by_cell(const fc2t2_plan_s* pl, const void* x, int64_t 
                                  const void* extra = nullptr, void* pay_out = nullptr,
                                  unsigned long long* ood = nullptr);
 bool sort_payload_ok(const fc2t2_plan_s* pl);
+// err: the sort's failure word (sort_err_word); when set, every cell comes out empty and
+// *fail_ctr is incremented.
 fc2t2_status launch_cell_starts(const uint32_t* keys_sorted, int64_t N, int64_t G,
-                                uint32_t* starts, hipStream_t s);
+                                uint32_t* starts, hipStream_t s, const uint32_t* err,
+                                unsigned long long* fail_ctr);
+// The failure word of the sort whose scratch (for N records) is `scratch`: non-zero after a
+// pass whose look-back gave up; the sorted arrays are then not valid.
+const uint32_t* sort_err_word(const void* scratch, int64_t N);
 int key_bits_for(int64_t G);
 
 // ---- p2m_l2p.hip
@@ -135,11 +142,12 @@ fc2t2_status launch_p2m_T(const fc2t2_plan_s* pl, const void* GM0, const void* p
 // q_bar from queries sorted with their data (FP32, one channel): pay [M][dim + 1], keys the
 // sorted cells, perm the input indices; gq[perm[r]] += (or =) gy grad f(q) / h.
 fc2t2_status launch_qgrad_sorted(const fc2t2_plan_s* pl, const void* L, const void* pay, const uint32_t* keys,
-                                 const uint32_t* perm, int64_t M, void* gq, hipStream_t s, bool accumulate = true);
+                                 const uint32_t* perm, int64_t M, void* gq, hipStream_t s, bool accumulate,
+                                 const uint32_t* err);
 // L2P over queries sorted with their coordinates (FP32, one channel): pay [M][dim], keys the
 // sorted cells, perm the input indices; y[perm[r]] = f(q_r).
 fc2t2_status launch_l2p_sorted(const fc2t2_plan_s* pl, const void* L, const void* pay, const uint32_t* keys,
-                               const uint32_t* perm, int64_t M, void* y, hipStream_t s);
+                               const uint32_t* perm, int64_t M, void* y, hipStream_t s, const uint32_t* err);
 // Transpose of L2P fused with q_bar over the same sorted queries: gL (+)= per-cell sums of
 // gy[perm[r]] (q_r - c)^k / k!, and gq[perm[r]] (+)= gy grad f(q_r) (one pass, one channel).
 fc2t2_status launch_l2p_T_qgrad_sorted(const fc2t2_plan_s* pl, const void* L, const void* pay, const uint32_t* starts,

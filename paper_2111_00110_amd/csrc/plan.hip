@@ -460,12 +460,13 @@ fc2t2_status fc2t2_plan_create(const fc2t2_grid* grid, const fc2t2_kernel* kerne
   };
 
   // ---- device counters: out-of-domain points, grazing ray roots
-  if (hipMalloc((void**)&pl->ood, 2 * sizeof(unsigned long long)) != hipSuccess) {
+  if (hipMalloc((void**)&pl->ood, 3 * sizeof(unsigned long long)) != hipSuccess) {
     pl->ood = nullptr;
     return fail(FC2T2_ENOMEM);
   }
   pl->grazing = pl->ood + 1;
-  if (hipMemsetAsync(pl->ood, 0, 2 * sizeof(unsigned long long), stream) != hipSuccess) return fail(FC2T2_EHIP);
+  pl->sort_fail = pl->ood + 2;
+  if (hipMemsetAsync(pl->ood, 0, 3 * sizeof(unsigned long long), stream) != hipSuccess) return fail(FC2T2_EHIP);
 
   // ---- host tables
   const int P = pl->P, Ppad = pl->Ppad;
@@ -620,6 +621,11 @@ fc2t2_status fc2t2_out_of_domain(fc2t2_plan plan, int64_t* count, int reset, hip
 fc2t2_status fc2t2_grazing_roots(fc2t2_plan plan, int64_t* count, int reset, hipStream_t stream) {
   if (!plan || !count) return FC2T2_EINVAL;
   return read_counter(plan->grazing, count, reset, stream);
+}
+
+fc2t2_status fc2t2_sort_failures(fc2t2_plan plan, int64_t* count, int reset, hipStream_t stream) {
+  if (!plan || !count) return FC2T2_EINVAL;
+  return read_counter(plan->sort_fail, count, reset, stream);
 }
 
 int fc2t2_plan_P(fc2t2_plan plan) { return plan ? plan->P : -1; }

@@ -912,7 +912,7 @@ fc2t2_status ray_integral_backward_t(const fc2t2_plan_s* pl, const T* o, const T
   FC2T2_LAUNCH_CHECK();
   fc2t2_status st = radix_sort_pairs(b.keys, b.keys_sorted, b.perm, slots, key_bits_for(pl->G + 1), b.scratch, s);
   if (st) return st;
-  st = launch_cell_starts(b.keys_sorted, slots, pl->G, b.starts, s);
+  st = launch_cell_starts(b.keys_sorted, slots, pl->G, b.starts, s, sort_err_word(b.scratch, slots), pl->sort_fail);
   if (st) return st;
   st = FC2T2_EUNSUPPORTED;
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {
@@ -978,7 +978,7 @@ fc2t2_status ray_root_backward_t(const fc2t2_plan_s* pl, const T* saved, const i
   FC2T2_LAUNCH_CHECK();
   fc2t2_status st = radix_sort_pairs(b.keys, b.keys_sorted, b.perm, R, key_bits_for(pl->G + 1), b.scratch, s);
   if (st) return st;
-  st = launch_cell_starts(b.keys_sorted, R, pl->G, b.starts, s);
+  st = launch_cell_starts(b.keys_sorted, R, pl->G, b.starts, s, sort_err_word(b.scratch, R), pl->sort_fail);
   if (st) return st;
   st = FC2T2_EUNSUPPORTED;
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {

@@ -31,6 +31,11 @@ constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValMask = kFlagAgg - 1u;
 constexpr int kMaxPayload = 4;            // payload words per item
 constexpr uint32_t kMaxSpins = 1u << 22;   // bounded wait: a predecessor that never publishes sets err
+// Test aid (fc2t2_debug_sort_fault): the spin limit of the look-back and a tile that withholds
+// its published counts, so that the bounded wait gives up on purpose and every kernel still
+// ends normally.
+uint32_t g_max_spins = kMaxSpins;
+uint32_t g_withhold_tile = 0xFFFFFFFFu;
 
 // Sums the histogram blocks' counts in kSlices slices per pass: block (pass, slice), thread
 // digit, writes sums[slice][pass][digit] (the sweep adds the slices).  Also clears the error word.
@@ -138,7 +143,8 @@ __global__ void __launch_bounds__(kThreads) onesweep_kernel(const uint32_t* __re
                                                             uint32_t* __restrict__ vals_out, uint32_t* __restrict__ err,
                                                             const uint32_t* __restrict__ pa, int na,
                                                             const uint32_t* __restrict__ pb,
-                                                            uint32_t* __restrict__ pay_out) {
+                                                            uint32_t* __restrict__ pay_out, uint32_t max_spins,
+                                                            uint32_t withhold_tile) {
   constexpr int kItems = SweepShape<PW>::kItems, kWaveRun = SweepShape<PW>::kWaveRun;
   constexpr int kTile = SweepShape<PW>::kTile;
   __shared__ uint32_t wcount[kWaves][kBins];
@@ -204,7 +210,8 @@ __global__ void __launch_bounds__(kThreads) onesweep_kernel(const uint32_t* __re
     cnt += t;
   }
   uint32_t* my = status + (size_t)tile * kBins + tid;
-  store_status(my, (tile == 0 ? kFlagInc : kFlagAgg) | cnt);
+  const bool publish = tile != withhold_tile;
+  if (publish) store_status(my, (tile == 0 ? kFlagInc : kFlagAgg) | cnt);
   uint32_t excl;
   block_exclusive_scan(cnt, excl, scan_sh);
   s_excl[tid] = excl;
@@ -235,14 +242,14 @@ __global__ void __launch_bounds__(kThreads) onesweep_kernel(const uint32_t* __re
       if (done) break;
       t -= used;
       if (stall) {
-        if (++spins > kMaxSpins) {
+        if (++spins > max_spins) {
           atomicOr(err, 1u);
           break;
         }
         __builtin_amdgcn_s_sleep(1);
       }
     }
-    store_status(my, kFlagInc | (prefix + cnt));
+    if (publish) store_status(my, kFlagInc | (prefix + cnt));
   }
   uint32_t dtot = 0;
 #pragma unroll
@@ -283,10 +290,19 @@ __global__ void __launch_bounds__(kThreads) onesweep_kernel(const uint32_t* __re
   }
 }
 
+// Cell starts of a sorted key array.  After a failed sort (err set) every cell is empty, so no
+// later stage reads the unsorted records, and the plan's failure counter is incremented once.
 __global__ void __launch_bounds__(256) cell_starts_kernel(const uint32_t* __restrict__ keys, int64_t N,
-                                                          int64_t G, uint32_t* __restrict__ starts) {
+                                                          int64_t G, uint32_t* __restrict__ starts,
+                                                          const uint32_t* __restrict__ err,
+                                                          unsigned long long* __restrict__ fail_ctr) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c > G) return;
+  if (err && *err) {
+    starts[c] = 0u;
+    if (c == 0 && fail_ctr) atomicAdd(fail_ctr, 1ull);
+    return;
+  }
   int64_t lo = 0, hi = N;   // first position with key >= c
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
@@ -348,7 +364,7 @@ fc2t2_status onesweep_passes(const uint32_t* keys_in, uint32_t* keys_out, uint32
     const uint32_t tiles = (uint32_t)ceil_div(N, SweepShape<PW>::kTile);
     hipLaunchKernelGGL((onesweep_kernel<PW>), dim3(tiles), dim3(kThreads), 0, s, kin, vin, N, 8 * pass,
                        c.ghist + pass * kBins, c.status + (size_t)pass * c.max_tiles * kBins, kout, vout, c.err,
-                       pa, na, pb, pout);
+                       pa, na, pb, pout, g_max_spins, g_withhold_tile);
     FC2T2_LAUNCH_CHECK();
     kin = kout;
     vin = vout;
@@ -437,13 +453,22 @@ fc2t2_status sort_points_by_cell(const fc2t2_plan_s* pl, const void* x, int64_t 
 
 bool sort_payload_ok(const fc2t2_plan_s* pl) { return pl->io == FC2T2_IO_F32 && pl->C == 1; }
 
+const uint32_t* sort_err_word(const void* scratch, int64_t N) {
+  return N > 0 ? carve_scratch((void*)scratch, N).err : nullptr;
+}
+
 fc2t2_status launch_cell_starts(const uint32_t* keys_sorted, int64_t N, int64_t G, uint32_t* starts,
-                                hipStream_t s) {
+                                hipStream_t s, const uint32_t* err, unsigned long long* fail_ctr) {
   const int threads = 256;
   hipLaunchKernelGGL(cell_starts_kernel, dim3((unsigned)ceil_div(G + 1, threads)), dim3(threads), 0, s,
-                     keys_sorted, N, G, starts);
+                     keys_sorted, N, G, starts, err, fail_ctr);
   FC2T2_LAUNCH_CHECK();
   return FC2T2_OK;
 }
 
 }  // namespace fc2t2
+
+extern "C" void fc2t2_debug_sort_fault(int enable) {
+  g_max_spins = enable ? 64u : kMaxSpins;
+  g_withhold_tile = enable ? 1u : 0xFFFFFFFFu;
+}

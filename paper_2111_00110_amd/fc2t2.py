@@ -73,6 +73,10 @@ def lib() -> ctypes.CDLL:
     L.fc2t2_out_of_domain.argtypes = [vp, ctypes.POINTER(i64), i32, vp]
     L.fc2t2_grazing_roots.restype = i32
     L.fc2t2_grazing_roots.argtypes = [vp, ctypes.POINTER(i64), i32, vp]
+    L.fc2t2_sort_failures.restype = i32
+    L.fc2t2_sort_failures.argtypes = [vp, ctypes.POINTER(i64), i32, vp]
+    L.fc2t2_debug_sort_fault.restype = None
+    L.fc2t2_debug_sort_fault.argtypes = [i32]
     L.fc2t2_local_numel.restype = sz
     L.fc2t2_local_numel.argtypes = [vp]
     L.fc2t2_workspace_size.restype = sz
@@ -300,18 +304,30 @@ class Plan:
                "fc2t2_grazing_roots")
         return int(c.value)
 
+    def sort_failures(self, reset: bool = False) -> int:
+        """Sorts by cell whose look-back gave up on this plan since it was made or last reset (the
+        outputs of the calls since then are not valid).  Synchronises."""
+        c = ctypes.c_int64(0)
+        _check(lib().fc2t2_sort_failures(self.handle, ctypes.byref(c), 1 if reset else 0, _stream()),
+               "fc2t2_sort_failures")
+        return int(c.value)
+
     @staticmethod
     def root_kind(saved: torch.Tensor) -> torch.Tensor:
         """Kind of each ray-root hit (ROOT_SMOOTH, ROOT_FACE, ROOT_GRAZING) from the saved record."""
         return saved[:, 10].to(torch.int32)
 
     def _debug_domain(self, what: str):
-        # debug mode (FC2T2_DEBUG=1): fail on points outside the domain, at the call that met them
+        # debug mode (FC2T2_DEBUG=1): fail on points outside the domain and on failed sorts, at the
+        # call that met them
         if os.environ.get("FC2T2_DEBUG", "0") not in ("", "0"):
             n = self.out_of_domain(reset=True)
             if n:
                 raise FC2T2Error("%d %s outside the domain [%g, %g]^%d (binned into boundary cells)"
                                  % (n, what, self.lo, self.hi, self.dim))
+            f = self.sort_failures(reset=True)
+            if f:
+                raise FC2T2Error("%d sort(s) by cell failed (look-back gave up); outputs are not valid" % f)
 
     def eval_backward(self, Lt, q, gy, gL: Optional[torch.Tensor] = None, gq: Optional[torch.Tensor] = None,
                       accumulate: bool = True):

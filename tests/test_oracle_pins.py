@@ -730,3 +730,117 @@ def test_sampled_moment_cotangents_equal_full_transpose(d, n, K):
     gw2, gp2 = fmm.p2m_T(geo, full, p, w)
     assert np.abs(gw - gw2).max() <= 1e-12 * np.abs(gw2).max()
     assert np.abs(gp - gp2).max() <= 1e-12 * np.abs(gp2).max()
+
+
+# ---------------------------------------------------------------------------------------
+# Volumetric rendering layer (sections 6.1.2 and 6.2.2)
+
+from oracle import volume  # noqa: E402
+
+
+def test_mexp_is_the_l2_projection_of_exp():
+    """The transmittance polynomial is the L2-best degree-4 fit of exp(-x) on [0, 5]: its residual
+    is orthogonal to 1, x, ..., x^4 (scipy quad), and it stays within the fit's error of exp."""
+    from scipy import integrate
+    m = volume.mexp_coefficients()
+    assert len(m) == 5
+    for j in range(5):
+        v, _ = integrate.quad(lambda x: (math.exp(-x) - np.polynomial.polynomial.polyval(x, m)) * x ** j,
+                              0.0, 5.0, epsabs=1e-13, epsrel=1e-12, limit=200)
+        assert abs(v) < 1e-11, j
+    x = np.linspace(0, 5, 2001)
+    err = np.abs(np.polynomial.polynomial.polyval(x, m) - np.exp(-x))
+    assert err.max() < 0.06 and err.mean() < 0.02
+
+
+def _volume_field(rng, geo, dens=0.8):
+    L0 = 0.3 * rng.standard_normal((4,) + (geo.n,) * 3 + (geo.P,))
+    L0[0, ..., 0] = dens + 0.2 * rng.random((geo.n,) * 3)      # positive density
+    return L0
+
+
+def test_volume_forward_matches_pointwise_quadrature():
+    """The cell-by-cell polynomial algebra (line to polynomial, integral, composition with the
+    fit, products) against pointwise evaluation of the locals at Gauss-Legendre nodes, with the
+    depth at each node integrated separately: the same model by another route."""
+    rng = np.random.default_rng(50)
+    geo = fmm.Geometry(3, 8, -1, 1, 3)
+    L0 = _volume_field(rng, geo, dens=2.0)
+    o, r = _rays(rng, 6)
+    bg = np.array([0.1, 0.2, 0.3])
+    got = volume.render(geo, L0, o, r, 0.0, 4.0, bg)
+    m = volume.mexp_coefficients()
+    xg, wg = np.polynomial.legendre.leggauss(30)
+    assert got["stopped"].any() and not got["stopped"].all()
+    for i in range(6):
+        D, y, stopped = 0.0, np.zeros(3), False
+        for cell, ta, tb in rays.segments(geo, o[i], r[i], 0.0, 4.0):
+            s = tb - ta
+            c = geo.centre(0, np.asarray(cell))
+            f = lambda u: fmm.monomials(o[i][None] + (ta + np.atleast_1d(u))[:, None] * r[i][None] - c, geo.idx) \
+                @ L0[(slice(None),) + cell].T                          # [nodes, 4]
+            u = 0.5 * s * (xg + 1)
+            vals = f(u)
+            S = np.array([D + 0.5 * ui * np.sum(wg * f(0.5 * ui * (xg + 1))[:, 0]) for ui in u])
+            T = np.polynomial.polynomial.polyval(S, m)
+            y += 0.5 * s * np.einsum("n,nk->k", wg * vals[:, 0] * T, vals[:, 1:])
+            D += 0.5 * s * np.sum(wg * vals[:, 0])
+            if D > volume.STOP_DEPTH:
+                stopped = True
+                break
+        y += bg * (0.0 if stopped else np.polynomial.polynomial.polyval(D, m))
+        assert stopped == got["stopped"][i]
+        np.testing.assert_allclose(got["y"][i], y, rtol=1e-11, atol=1e-12)
+
+
+def test_volume_constant_field_closed_form():
+    """Constant density s0 and colour c0 along a ray through the box: S grows linearly, so
+    y = c0 int_0^{D_end} mexp(x) dx + c_bg mexp(D_end); with a dense medium the traversal stops
+    after the cell where the depth passes 4.5 and the background is not seen."""
+    geo = fmm.Geometry(3, 8, -1, 1, 2)
+    m = volume.mexp_coefficients()
+    M = np.polynomial.polynomial.polyint(m)
+    c0 = np.array([0.2, 0.5, 0.7])
+    bg = np.array([1.0, 0.5, 0.25])
+    o = np.array([[-2.0, 0.1, 0.3]])
+    r = np.array([[1.0, 0.0, 0.0]])
+    for s0, stop_cell in ((0.3, None), (5.0, 3)):
+        L0 = np.zeros((4,) + (8,) * 3 + (geo.P,))
+        L0[0, ..., 0] = s0
+        L0[1:, ..., 0] = c0[:, None, None, None]
+        got = volume.render(geo, L0, o, r, 0.0, 4.0, bg)
+        if stop_cell is None:
+            D = s0 * 2.0
+            want = c0 * np.polynomial.polynomial.polyval(D, M) + bg * np.polynomial.polynomial.polyval(D, m)
+            assert not got["stopped"][0]
+        else:
+            D = s0 * 0.25 * (stop_cell + 1)          # depth at the exit of the stopping cell
+            want = c0 * np.polynomial.polynomial.polyval(D, M)
+            assert got["stopped"][0]
+        assert abs(got["D_end"][0] - D) < 1e-13
+        np.testing.assert_allclose(got["y"][0], want, rtol=1e-13)
+
+
+@pytest.mark.parametrize("dens,bgv", [(0.8, (0.3, -0.2, 0.5)), (2.5, (0.0, 0.0, 0.0))])
+def test_volume_backward_matches_finite_differences(dens, bgv):
+    """The backward (colour insertion, and the density insertion with the running integral of
+    c sigma mexp'(S)) against central differences of the forward on entries of all four
+    channels; with a medium thin enough to see the background and one dense enough to stop."""
+    rng = np.random.default_rng(51)
+    geo = fmm.Geometry(3, 4, -1, 1, 2)
+    L0 = _volume_field(rng, geo, dens=dens)
+    o, r = _rays(rng, 3)
+    bg = np.array(bgv)
+    gy = rng.standard_normal((3, 3))
+    fwd = volume.render(geo, L0, o, r, 0.0, 4.0, bg)
+    G = volume.render_T(geo, L0, o, r, 0.0, 4.0, fwd, gy, bg)
+    loss = lambda L: float(np.sum(gy * volume.render(geo, L, o, r, 0.0, 4.0, bg)["y"]))
+    flat = np.flatnonzero(np.abs(G) > 0)
+    picks = rng.choice(flat, size=24, replace=False)
+    eps = 1e-6
+    for f in picks:
+        e = np.zeros(L0.size)
+        e[f] = eps
+        e = e.reshape(L0.shape)
+        fd = (loss(L0 + e) - loss(L0 - e)) / (2 * eps)
+        assert abs(fd - G.flat[f]) < 1e-6 * max(1.0, abs(fd)), (np.unravel_index(f, L0.shape), fd, G.flat[f])

@@ -119,7 +119,8 @@ typedef enum {
   FC2T2_OP_EXPAND_BACKWARD = 2,      /* count = N sources */
   FC2T2_OP_RAY_INTEGRAL_BACKWARD = 3,/* count = R rays */
   FC2T2_OP_RAY_ROOT_BACKWARD = 4,    /* count = R rays */
-  FC2T2_OP_EVAL_SORTED = 5           /* count = M queries (fc2t2_eval_sorted's records) */
+  FC2T2_OP_EVAL_SORTED = 5,          /* count = M queries (fc2t2_eval_sorted's records) */
+  FC2T2_OP_RAY_VOLUME_BACKWARD = 6   /* count = R rays */
 } fc2t2_op;
 
 /* Status text (static storage). */
@@ -290,6 +291,36 @@ fc2t2_status fc2t2_ray_root_at(fc2t2_plan plan, const void* L, const void* o, co
 fc2t2_status fc2t2_ray_root_backward(fc2t2_plan plan, const void* saved, const int32_t* hit,
                                      int64_t R, const void* gt, const void* gn, void* gL,
                                      void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Volumetric rendering (section 6.1.2; dim 3, C == 4: channel 0 the density sigma, channels
+ * 1..3 the colour c = (R, G, B); K <= 5).  Per ray, with S the optical depth from the entry
+ * point of the clipped ray and mexp the degree-4 polynomial closest to exp(-x) in L2 on
+ * [0, 5] standing in for the transmittance exp(-S):
+ *   y[r][k] = int T sigma c_k dt + bg[k] T_end,    T = mexp(S),
+ * computed exactly cell by cell (every factor is a polynomial of t inside a cell).  The walk
+ * ends after the first cell whose exit depth exceeds FC2T2_VOLUME_STOP_DEPTH (the fit is used
+ * below 5 only); T_end = 0 then, else mexp(total depth).  o, r [R][3] (r need not be unit);
+ * bg: host array of 3 doubles, the background colour (section 6.2.2), or NULL for black.
+ * Outputs y [R][3] and, when trans is not NULL, trans [R] = T_end (IO type).  The density is
+ * used as the expansion gives it (a caller keeps it non-negative, e.g. through non-negative
+ * density weights). */
+#define FC2T2_VOLUME_STOP_DEPTH 4.5
+fc2t2_status fc2t2_ray_volume(fc2t2_plan plan, const void* L, const void* o, const void* r,
+                              double t0, double t1, int64_t R, const double* bg, void* y,
+                              void* trans, hipStream_t stream);
+
+/* Backward of fc2t2_ray_volume (section 6.2.2) as the exact derivative of its forward, the
+ * stop decision held fixed: with gy [R][3] the colour cotangents, gL += for colour channel k
+ * the integrals of gy_k sigma T mono, and for the density channel the integrals of H mono with
+ *   H(t) = c_y T + int_t^end c_y sigma mexp'(S) + [walk did not stop] (gy . bg) mexp'(S_end),
+ * c_y = sum_k gy_k c_k (a change of density at t changes the depth at every later point);
+ * mono = (q - centre)^k / k! in cell units.  L is the forward's expansion (the derivative
+ * depends on it); workspace FC2T2_OP_RAY_VOLUME_BACKWARD.  EUNSUPPORTED when
+ * R (3 n + 4) > 2^32. */
+fc2t2_status fc2t2_ray_volume_backward(fc2t2_plan plan, const void* L, const void* o,
+                                       const void* r, double t0, double t1, int64_t R,
+                                       const double* bg, const void* gy, void* gL, void* ws,
+                                       size_t ws_bytes, hipStream_t stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc): fc2t2_ray_root_backward with its scratch in a

@@ -70,14 +70,16 @@ def _cell_polys(geo, L0, cell, d, r):
 
 def render(geo: fmm.Geometry, L0: np.ndarray, o, r, t0: float, t1: float, bg=(0.0, 0.0, 0.0)) -> dict:
     """Per ray: colour y [R, 3], exit transmittance T_end [R], exit depth D_end [R], whether the
-    traversal stopped [R], and G [R, 3] = int c_k sigma mexp'(S) over the traversal (kept for
-    the backward).  L0 has four channels (density, R, G, B), physical units."""
+    traversal stopped [R], G [R, 3] = int c_k sigma mexp'(S) over the traversal (kept for
+    the backward), and margin [R] = the smallest |exit depth - STOP_DEPTH| over the cells
+    visited (how far the stop decision is from flipping).  L0 has four channels (density, R,
+    G, B), physical units."""
     m = mexp_coefficients()
     mp = npoly.polyder(m)
     bg = np.asarray(bg, dtype=np.float64)
     R = len(o)
     out = {"y": np.zeros((R, 3)), "T_end": np.zeros(R), "D_end": np.zeros(R),
-           "stopped": np.zeros(R, dtype=bool), "G": np.zeros((R, 3))}
+           "stopped": np.zeros(R, dtype=bool), "G": np.zeros((R, 3)), "margin": np.full(R, np.inf)}
     for ri in range(R):
         D = 0.0
         y = np.zeros(3)
@@ -96,6 +98,7 @@ def render(geo: fmm.Geometry, L0: np.ndarray, o, r, t0: float, t1: float, bg=(0.
                 y[k] += _int0(npoly.polymul(cs, T), s)
                 G[k] += _int0(npoly.polymul(cs, Tp), s)
             D = float(npoly.polyval(s, S))
+            out["margin"][ri] = min(out["margin"][ri], abs(D - STOP_DEPTH))
             if D > STOP_DEPTH:
                 stopped = True
                 break

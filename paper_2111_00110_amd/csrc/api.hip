@@ -259,6 +259,7 @@ size_t fc2t2_workspace_size(fc2t2_plan plan, int op, int64_t count) {
     case FC2T2_OP_RAY_INTEGRAL_BACKWARD: return ray_integral_bwd_ws(plan, count);
     case FC2T2_OP_RAY_ROOT_BACKWARD: return ray_root_bwd_ws(plan, count);
     case FC2T2_OP_EVAL_SORTED: return ws_eval_sorted(plan, count);
+    case FC2T2_OP_RAY_VOLUME_BACKWARD: return ray_volume_bwd_ws(plan, count);
   }
   return 0;
 }

@@ -1,6 +1,8 @@
 // Internal plan state and the launchers each translation unit provides.
 #pragma once
 
+#include <vector>
+
 #include "common.h"
 
 namespace fc2t2 {
@@ -59,7 +61,10 @@ inline size_t pyramid_elems(const fc2t2_plan_s* pl, int first) {
   return s;
 }
 
-// ---- plan.hip: stage timing
+// ---- plan.hip
+// Gauss-Legendre nodes t and weights w of the Q-point rule on [-1, 1].
+void gauss_legendre(int Q, std::vector<double>& t, std::vector<double>& w);
+// stage timing
 void stage_begin(const fc2t2_plan_s* pl, int stage, hipStream_t s);
 void stage_end(const fc2t2_plan_s* pl, int stage, hipStream_t s);
 void stage_timer_destroy(fc2t2_plan_s* pl);
@@ -224,5 +229,9 @@ void noalloc_setup(fc2t2_plan_s* pl);
 fc2t2_status ray_root_backward(const fc2t2_plan_s* pl, const void* saved, const int32_t* hit,
                                int64_t R, const void* gt, const void* gn, void* gL, void* ws,
                                hipStream_t s);
+
+
+// ---- volume.hip
+size_t ray_volume_bwd_ws(const fc2t2_plan_s* pl, int64_t R);
 
 }  // namespace fc2t2

@@ -183,6 +183,10 @@ __global__ void pack_m2l_kernel(int dim, int K, int P, int Ppad, int levels, int
   out[tid] = (T)v;
 }
 
+}  // namespace
+
+namespace fc2t2 {
+
 // Gauss-Legendre nodes and weights on [-1, 1]: Newton's method on P_Q from the usual cosine
 // guesses, P_Q by the three-term recurrence.
 void gauss_legendre(int Q, std::vector<double>& t, std::vector<double>& w) {
@@ -217,6 +221,10 @@ void gauss_legendre(int Q, std::vector<double>& t, std::vector<double>& w) {
     w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
   }
 }
+
+}  // namespace fc2t2
+
+namespace {
 
 // Weighted least-squares projection for the fitted tensors: nodes u [J][3] (cell units, tensor
 // Gauss-Legendre with K + 2 nodes per dimension on [-1/2, 1/2]) and Pi [P][J] with

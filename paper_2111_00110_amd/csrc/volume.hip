@@ -1,0 +1,479 @@
+// Volumetric rendering on the finest-level local expansions (section 6.1.2) and its backward
+// (section 6.2.2); dim 3, four channels: density sigma (channel 0) and colour c = (R, G, B)
+// (channels 1..3).
+//
+// Along a ray, y = int T sigma c dt + bg T_end with T = mexp(S) and S the optical depth from
+// the entry point; mexp is the degree-4 polynomial closest to exp(-x) in L2 on [0, 5].  Inside
+// one cell every factor is a polynomial of the normalised segment parameter x in [0, 1]:
+// sigma and c of degree K (line to polynomial, section 5.1.1), S of degree K + 1 and T of
+// degree 4 (K + 1), so c sigma T has degree 6K + 4 and the N = 3K + 3 point Gauss-Legendre
+// rule integrates it exactly (up to rounding): no sampling along the ray.  The walk stops
+// after the first cell whose exit depth exceeds 4.5 (the fit is used below 5 only); then
+// T_end = 0, else T_end = mexp(D_end).
+//
+// Backward: the exact derivative of this forward.  Colour channel k receives
+//   y_bar_k int mono sigma T dt,
+// the density channel int mono H dt with
+//   H(t) = c_y(t) T(t) + E - Gb - int_{t_a}^t c_y sigma mexp'(S),    c_y = sum_k y_bar_k c_k,
+// E = int over the whole walk of c_y sigma mexp'(S), plus (y_bar . bg) mexp'(D_end) when the
+// walk did not stop, and Gb the same integral up to the cell's entry: a change of sigma at t
+// changes S at every later point.  mono = u^k / k! in cell units u = (q - centre) / h, so the
+// output is the cotangent of the cell-scaled rows.  The running integral inside the cell is
+// built as a polynomial (degree 5K + 4 in x) so that H is exact at the quadrature nodes.  The
+// stop decision is not differentiated.
+//
+// Records: one per segment (cell as the sort key; [ta, tb], entry depth and Gb as payload),
+// sorted by cell and reduced per cell with the ray insertion's segmented reduction.  Every
+// per-segment quantity runs in FP64 (the vector FP64 and FP32 rates are equal without packed
+// FP32); only the expansion rows and the output rows use the IO type.
+#include <math.h>
+
+#include <vector>
+
+#include "plan.h"
+#include "raywalk.h"
+#include "segreduce.h"
+
+using namespace fc2t2;
+
+namespace {
+
+constexpr int kMaxNodes = 18;        // 3K + 3 for K <= 5
+constexpr double kStopDepth = FC2T2_VOLUME_STOP_DEPTH;
+constexpr double kMexpRange = 5.0;   // mexp fits exp(-x) on [0, kMexpRange]
+
+struct VolumeConsts {
+  double m[5];                         // mexp, low to high degree in x
+  double mp[4];                        // its derivative
+  double x[kMaxNodes], w[kMaxNodes];   // Gauss-Legendre nodes and weights on [0, 1]
+  double bg[3];                        // background colour
+};
+
+// The degree-4 polynomial closest to exp(-x) in L2 on [0, 5].  In t = x / 5 the shifted
+// Legendre polynomials Q_j(t) = P_j(2t - 1) are orthogonal on [0, 1] with <Q_j, Q_j> =
+// 1 / (2j + 1), so the projection is sum_j (2j + 1) <exp(-5t), Q_j> Q_j.  The inner products
+// come from a 40-point Gauss-Legendre rule (exact to rounding for this entire integrand).
+void mexp_fit(double (&m)[5]) {
+  std::vector<double> t, w;
+  gauss_legendre(40, t, w);
+  double Q[5][5] = {};   // Q[j][k]: coefficient of t^k; Q_{j+1} = ((2j+1)(2t-1) Q_j - j Q_{j-1}) / (j+1)
+  Q[0][0] = 1.0;
+  Q[1][0] = -1.0;
+  Q[1][1] = 2.0;
+  for (int j = 1; j < 4; ++j)
+    for (int k = 0; k < 5; ++k)
+      Q[j + 1][k] = ((2.0 * j + 1.0) * ((k ? 2.0 * Q[j][k - 1] : 0.0) - Q[j][k]) - j * Q[j - 1][k]) / (j + 1.0);
+  double c[5] = {};
+  for (int j = 0; j < 5; ++j) {
+    double a = 0.0;
+    for (size_t i = 0; i < t.size(); ++i) {
+      const double tt = 0.5 * (1.0 + t[i]);
+      double q = 0.0;
+      for (int k = 4; k >= 0; --k) q = q * tt + Q[j][k];
+      a += 0.5 * w[i] * exp(-kMexpRange * tt) * q;
+    }
+    a *= 2.0 * j + 1.0;
+    for (int k = 0; k < 5; ++k) c[k] += a * Q[j][k];
+  }
+  for (int k = 0; k < 5; ++k) m[k] = c[k] / pow(kMexpRange, k);
+}
+
+VolumeConsts volume_consts(int K, const double* bg) {
+  VolumeConsts vc = {};
+  mexp_fit(vc.m);
+  for (int k = 0; k < 4; ++k) vc.mp[k] = (k + 1) * vc.m[k + 1];
+  std::vector<double> t, w;
+  gauss_legendre(3 * K + 3, t, w);
+  for (int i = 0; i < 3 * K + 3; ++i) {
+    vc.x[i] = 0.5 * (1.0 + t[i]);
+    vc.w[i] = 0.5 * w[i];
+  }
+  for (int k = 0; k < 3; ++k) vc.bg[k] = bg ? bg[k] : 0.0;
+  return vc;
+}
+
+// Horner evaluation of the first N coefficients of c.
+template <int N, int CAP>
+__device__ __forceinline__ double poly_at(const double (&c)[CAP], double x) {
+  static_assert(N <= CAP, "coefficients");
+  double v = c[N - 1];
+#pragma unroll
+  for (int m = N - 2; m >= 0; --m) v = v * x + c[m];
+  return v;
+}
+
+__device__ __forceinline__ double mexp_at(const VolumeConsts& vc, double s) {
+  return (((vc.m[4] * s + vc.m[3]) * s + vc.m[2]) * s + vc.m[1]) * s + vc.m[0];
+}
+__device__ __forceinline__ double mexp_d(const VolumeConsts& vc, double s) {
+  return ((vc.mp[3] * s + vc.mp[2]) * s + vc.mp[1]) * s + vc.mp[0];
+}
+
+// Entry offset of the segment from the cell centre and the direction, both in cell units.
+__device__ __forceinline__ void seg_local(const double (&o)[3], const double (&r)[3], double ta, const int (&cc)[3],
+                                          double lo, double h, double (&d)[3], double (&q)[3]) {
+  const double ih = 1.0 / h;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    d[j] = (o[j] + ta * r[j] - (lo + (cc[j] + 0.5) * h)) * ih;
+    q[j] = r[j] * ih;
+  }
+}
+
+// Optical depth on the segment in x: S(x) = D + s int_0^x sigma, from sigma's coefficients.
+template <int K>
+__device__ __forceinline__ void depth_poly(const double (&bs)[6], double D, double s, double (&sx)[K + 2]) {
+  sx[0] = D;
+#pragma unroll
+  for (int m = 0; m <= K; ++m) sx[m + 1] = s * bs[m] / (m + 1);
+}
+
+// ---------------------------------------------------------------------------------------
+// Forward: one thread per ray.
+template <class S, typename T>
+__global__ void __launch_bounds__(64) volume_kernel(const T* __restrict__ L, const T* __restrict__ O,
+                                                    const T* __restrict__ Rd, int64_t R, double t0, double t1,
+                                                    double lo, double hi, double h, int n, int64_t G,
+                                                    VolumeConsts vc, T* __restrict__ y, T* __restrict__ trans) {
+  constexpr int K = S::K, Ppad = S::Ppad, NQ = 3 * K + 3;
+  static_assert(NQ <= kMaxNodes, "quadrature nodes");
+  const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ray >= R) return;
+  double o[3], r[3];
+  load3(O, ray, o);
+  load3(Rd, ray, r);
+  Dda dda;
+  dda.init(o, r, t0, t1, lo, hi, h, n);
+  const int64_t cs = G * Ppad;   // channel stride
+  double D = 0.0, y0 = 0.0, y1 = 0.0, y2 = 0.0;
+  bool stopped = false;
+  int64_t cell;
+  int cc[3];
+  double ta, tb;
+  while (dda.next(cell, cc, ta, tb)) {
+    const double sl = tb - ta;
+    double d[3], q[3];
+    seg_local(o, r, ta, cc, lo, h, d, q);
+    const T* row = L + cell * Ppad;
+    double bs[6], b0[6], b1[6], b2[6];
+    segment_poly<S>(row, d, q, sl, bs);
+    segment_poly<S>(row + cs, d, q, sl, b0);
+    segment_poly<S>(row + 2 * cs, d, q, sl, b1);
+    segment_poly<S>(row + 3 * cs, d, q, sl, b2);
+    double sx[K + 2];
+    depth_poly<K>(bs, D, sl, sx);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const double x = vc.x[i];
+      const double a = sl * vc.w[i] * poly_at<K + 1>(bs, x) * mexp_at(vc, poly_at<K + 2>(sx, x));
+      y0 += a * poly_at<K + 1>(b0, x);
+      y1 += a * poly_at<K + 1>(b1, x);
+      y2 += a * poly_at<K + 1>(b2, x);
+    }
+    D = poly_at<K + 2>(sx, 1.0);
+    if (D > kStopDepth) {
+      stopped = true;
+      break;
+    }
+  }
+  const double Tend = stopped ? 0.0 : mexp_at(vc, D);
+  y[3 * ray] = (T)(y0 + vc.bg[0] * Tend);
+  y[3 * ray + 1] = (T)(y1 + vc.bg[1] * Tend);
+  y[3 * ray + 2] = (T)(y2 + vc.bg[2] * Tend);
+  if (trans) trans[ray] = (T)Tend;
+}
+
+// ---------------------------------------------------------------------------------------
+// Backward records: the forward's walk again, with the colour cotangents folded into c_y.
+// Slot ray * maxseg + j holds segment j: key = its cell, rec[2 slot] = (ta, tb),
+// rec[2 slot + 1] = (entry depth, Gb); unused slots get the key G (sorted after every cell).
+// E[ray] receives the walk's total of int c_y sigma mexp'(S) plus the background term.
+template <class S, typename T>
+__global__ void __launch_bounds__(64) volume_records_kernel(const T* __restrict__ L, const T* __restrict__ O,
+                                                            const T* __restrict__ Rd, int64_t R, double t0,
+                                                            double t1, double lo, double hi, double h, int n,
+                                                            int64_t G, VolumeConsts vc, const T* __restrict__ gy,
+                                                            int maxseg, uint32_t* __restrict__ keys,
+                                                            double2* __restrict__ rec, double* __restrict__ E) {
+  constexpr int K = S::K, Ppad = S::Ppad, NQ = 3 * K + 3;
+  const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ray >= R) return;
+  double o[3], r[3];
+  load3(O, ray, o);
+  load3(Rd, ray, r);
+  const double g0 = (double)gy[3 * ray], g1 = (double)gy[3 * ray + 1], g2 = (double)gy[3 * ray + 2];
+  Dda dda;
+  dda.init(o, r, t0, t1, lo, hi, h, n);
+  const int64_t cs = G * Ppad;
+  double D = 0.0, Gb = 0.0;
+  bool stopped = false;
+  int64_t cell;
+  int cc[3];
+  double ta, tb;
+  int j = 0;
+  const int64_t base = ray * maxseg;
+  while (j < maxseg && dda.next(cell, cc, ta, tb)) {
+    const double sl = tb - ta;
+    double d[3], q[3];
+    seg_local(o, r, ta, cc, lo, h, d, q);
+    const T* row = L + cell * Ppad;
+    double bs[6], b0[6], b1[6], b2[6];
+    segment_poly<S>(row, d, q, sl, bs);
+    segment_poly<S>(row + cs, d, q, sl, b0);
+    segment_poly<S>(row + 2 * cs, d, q, sl, b1);
+    segment_poly<S>(row + 3 * cs, d, q, sl, b2);
+    double cy[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) cy[m] = g0 * b0[m] + g1 * b1[m] + g2 * b2[m];
+    double sx[K + 2];
+    depth_poly<K>(bs, D, sl, sx);
+    keys[base + j] = (uint32_t)cell;
+    rec[2 * (base + j)] = make_double2(ta, tb);
+    rec[2 * (base + j) + 1] = make_double2(D, Gb);
+    ++j;
+    double gseg = 0.0;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const double x = vc.x[i];
+      gseg += vc.w[i] * poly_at<K + 1>(cy, x) * poly_at<K + 1>(bs, x) * mexp_d(vc, poly_at<K + 2>(sx, x));
+    }
+    Gb += sl * gseg;
+    D = poly_at<K + 2>(sx, 1.0);
+    if (D > kStopDepth) {
+      stopped = true;
+      break;
+    }
+  }
+  for (; j < maxseg; ++j) keys[base + j] = (uint32_t)G;
+  const double gbg = g0 * vc.bg[0] + g1 * vc.bg[1] + g2 * vc.bg[2];
+  E[ray] = Gb + (stopped ? 0.0 : gbg * mexp_d(vc, D));
+}
+
+// Per record: the segment's contribution to one channel's cotangent row.
+template <class S, typename T>
+struct VolumeInsert {
+  static constexpr int K = S::K, NQ = 3 * K + 3;
+  static constexpr int NT = 3 * K + 4;   // mexp'(S(x)): degree 3 (K + 1)
+  static constexpr int NC = 2 * K + 1;   // c_y sigma
+  static constexpr int NG = 5 * K + 4;   // c_y sigma mexp'(S)
+  const T* __restrict__ L;
+  const T* __restrict__ O;
+  const T* __restrict__ Rd;
+  const double2* __restrict__ rec;
+  const double* __restrict__ E;
+  const T* __restrict__ gy;
+  int maxseg, n;
+  int64_t G;
+  double lo, h;
+  VolumeConsts vc;
+
+  __device__ __forceinline__ void operator()(uint32_t slot, const T (&)[3], int ch, T (&v)[S::P],
+                                             int64_t cell) const {
+    constexpr int Ppad = S::Ppad;
+    const int64_t ray = slot / maxseg;
+    double o[3], r[3];
+    load3(O, ray, o);
+    load3(Rd, ray, r);
+    const double2 tt = rec[2 * (int64_t)slot], de = rec[2 * (int64_t)slot + 1];
+    const double sl = tt.y - tt.x;
+    int cc[3];
+    decode_cell<3, T>(cell, n, cc);
+    double d[3], q[3];
+    seg_local(o, r, tt.x, cc, lo, h, d, q);
+    const T* row = L + cell * Ppad;
+    const int64_t cs = G * Ppad;
+    double bs[6];
+    segment_poly<S>(row, d, q, sl, bs);
+    double sx[K + 2];
+    depth_poly<K>(bs, de.x, sl, sx);
+    double a[NQ];
+    if (ch == 0) {
+      const double g0 = (double)gy[3 * ray], g1 = (double)gy[3 * ray + 1], g2 = (double)gy[3 * ray + 2];
+      double b0[6], b1[6], b2[6], cy[6];
+      segment_poly<S>(row + cs, d, q, sl, b0);
+      segment_poly<S>(row + 2 * cs, d, q, sl, b1);
+      segment_poly<S>(row + 3 * cs, d, q, sl, b2);
+#pragma unroll
+      for (int m = 0; m < 6; ++m) cy[m] = g0 * b0[m] + g1 * b1[m] + g2 * b2[m];
+      // tp = mexp'(S(x)) by Horner over polynomials
+      double tp[NT];
+#pragma unroll
+      for (int m = 0; m < NT; ++m) tp[m] = 0.0;
+      tp[0] = vc.mp[3];
+#pragma unroll
+      for (int deg = 2; deg >= 0; --deg) {
+        double nt[NT];
+#pragma unroll
+        for (int m = 0; m < NT; ++m) nt[m] = 0.0;
+#pragma unroll
+        for (int i = 0; i < NT; ++i)
+#pragma unroll
+          for (int k = 0; k < K + 2; ++k)
+            if (i + k < NT) nt[i + k] += tp[i] * sx[k];
+        nt[0] += vc.mp[deg];
+#pragma unroll
+        for (int m = 0; m < NT; ++m) tp[m] = nt[m];
+      }
+      double cz[NC];
+#pragma unroll
+      for (int m = 0; m < NC; ++m) cz[m] = 0.0;
+#pragma unroll
+      for (int i = 0; i <= K; ++i)
+#pragma unroll
+        for (int k = 0; k <= K; ++k) cz[i + k] += cy[i] * bs[k];
+      // run(x) = s int_0^x c_y sigma mexp'(S)
+      double run[NG + 1];
+#pragma unroll
+      for (int m = 0; m <= NG; ++m) run[m] = 0.0;
+#pragma unroll
+      for (int i = 0; i < NC; ++i)
+#pragma unroll
+        for (int k = 0; k < NT; ++k)
+          if (i + k < NG) run[i + k + 1] += cz[i] * tp[k];
+#pragma unroll
+      for (int m = 1; m <= NG; ++m) run[m] *= sl / m;
+      const double c0 = E[ray] - de.y;
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) {
+        const double x = vc.x[i];
+        const double H = poly_at<K + 1>(cy, x) * mexp_at(vc, poly_at<K + 2>(sx, x)) + c0 - poly_at<NG + 1>(run, x);
+        a[i] = sl * vc.w[i] * H;
+      }
+    } else {
+      const double g = (double)gy[3 * ray + ch - 1];
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) {
+        const double x = vc.x[i];
+        a[i] = g * sl * vc.w[i] * poly_at<K + 1>(bs, x) * mexp_at(vc, poly_at<K + 2>(sx, x));
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < S::P; ++k) v[k] = T(0);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const double xs = sl * vc.x[i];
+      T u[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) u[j] = (T)(d[j] + q[j] * xs);
+      T mono[S::P];
+      monomials<S>(u, mono);
+      const T ai = (T)a[i];
+#pragma unroll
+      for (int k = 0; k < S::P; ++k) v[k] += ai * mono[k];
+    }
+  }
+};
+
+bool volume_ok(const fc2t2_plan_s* pl) { return pl->dim == 3 && pl->C == 4; }
+
+}  // namespace
+
+namespace fc2t2 {
+
+size_t ray_volume_bwd_ws(const fc2t2_plan_s* pl, int64_t R) {
+  Carve c(nullptr);
+  carve_records(c, pl, R * maxseg_for(pl), 2);
+  c.take<double>(R);
+  return c.off;
+}
+
+}  // namespace fc2t2
+
+namespace {
+
+fc2t2_status launch_volume(const fc2t2_plan_s* pl, const void* L, const void* o, const void* r, double t0, double t1,
+                           int64_t R, const double* bg, void* y, void* trans, hipStream_t s) {
+  if (R == 0) return FC2T2_OK;
+  const VolumeConsts vc = volume_consts(pl->K, bg);
+  fc2t2_status st = FC2T2_EUNSUPPORTED;
+  const dim3 grid((unsigned)ceil_div(R, 64));
+  dispatch_shape(pl->dim, pl->K, [&](auto shape) {
+    using S = decltype(shape);
+    if constexpr (S::D == 3) {
+      if (pl->io == FC2T2_IO_F64)
+        hipLaunchKernelGGL((volume_kernel<S, double>), grid, dim3(64), 0, s, (const double*)L, (const double*)o,
+                           (const double*)r, R, t0, t1, pl->lo, pl->hi, pl->h0, pl->n, pl->G, vc, (double*)y,
+                           (double*)trans);
+      else
+        hipLaunchKernelGGL((volume_kernel<S, float>), grid, dim3(64), 0, s, (const float*)L, (const float*)o,
+                           (const float*)r, R, t0, t1, pl->lo, pl->hi, pl->h0, pl->n, pl->G, vc, (float*)y,
+                           (float*)trans);
+      st = FC2T2_OK;
+    }
+  });
+  if (st) return st;
+  FC2T2_LAUNCH_CHECK();
+  return FC2T2_OK;
+}
+
+template <typename T>
+fc2t2_status volume_backward_t(const fc2t2_plan_s* pl, const T* L, const T* o, const T* r, double t0, double t1,
+                               int64_t R, const double* bg, const T* gy, T* gL, void* ws, hipStream_t s) {
+  const int maxseg = maxseg_for(pl);
+  const int64_t slots = R * maxseg;
+  Carve c(ws);
+  RecordBufs b = carve_records(c, pl, slots, 2);
+  double* E = c.take<double>(R);
+  const VolumeConsts vc = volume_consts(pl->K, bg);
+  fc2t2_status st = FC2T2_EUNSUPPORTED;
+  dispatch_shape(pl->dim, pl->K, [&](auto shape) {
+    using S = decltype(shape);
+    if constexpr (S::D == 3) {
+      hipLaunchKernelGGL((volume_records_kernel<S, T>), dim3((unsigned)ceil_div(R, 64)), dim3(64), 0, s, L, o, r, R,
+                         t0, t1, pl->lo, pl->hi, pl->h0, pl->n, pl->G, vc, gy, maxseg, b.keys, b.rec, E);
+      st = FC2T2_OK;
+    }
+  });
+  if (st) return st;
+  FC2T2_LAUNCH_CHECK();
+  st = radix_sort_pairs(b.keys, b.keys_sorted, b.perm, slots, key_bits_for(pl->G + 1), b.scratch, s);
+  if (st) return st;
+  st = launch_cell_starts(b.keys_sorted, slots, pl->G, b.starts, s, sort_err_word(b.scratch, slots), pl->sort_fail);
+  if (st) return st;
+  st = FC2T2_EUNSUPPORTED;
+  dispatch_shape(pl->dim, pl->K, [&](auto shape) {
+    using S = decltype(shape);
+    if constexpr (S::D == 3) {
+      VolumeInsert<S, T> fn{L, o, r, b.rec, E, gy, maxseg, pl->n, pl->G, pl->lo, pl->h0, vc};
+      // a ray crosses about 2.3 n cells: records per occupied cell are few
+      st = launch_reduce_cells<S, T>(pl, b.starts, b.perm, R * 2 * pl->n, gL, true, fn, s);
+    }
+  });
+  return st;
+}
+
+bool bad_rays(int64_t R) { return R < 0 || R > 0x7FFFFFFFll; }
+
+}  // namespace
+
+extern "C" {
+
+fc2t2_status fc2t2_ray_volume(fc2t2_plan plan, const void* L, const void* o, const void* r, double t0, double t1,
+                              int64_t R, const double* bg, void* y, void* trans, hipStream_t stream) {
+  if (!plan || !L || bad_rays(R) || !isfinite(t0) || !isfinite(t1)) return FC2T2_EINVAL;
+  if (R > 0 && (!o || !r || !y)) return FC2T2_EINVAL;
+  if (bg && !(isfinite(bg[0]) && isfinite(bg[1]) && isfinite(bg[2]))) return FC2T2_EINVAL;
+  if (!volume_ok(plan) || plan->K > 5) return FC2T2_EUNSUPPORTED;
+  StageScope tm(plan, FC2T2_STAGE_RAY, stream);
+  return launch_volume(plan, L, o, r, t0, t1, R, bg, y, trans, stream);
+}
+
+fc2t2_status fc2t2_ray_volume_backward(fc2t2_plan plan, const void* L, const void* o, const void* r, double t0,
+                                       double t1, int64_t R, const double* bg, const void* gy, void* gL, void* ws,
+                                       size_t ws_bytes, hipStream_t stream) {
+  if (!plan || !L || !gL || bad_rays(R) || !isfinite(t0) || !isfinite(t1)) return FC2T2_EINVAL;
+  if (R > 0 && (!o || !r || !gy)) return FC2T2_EINVAL;
+  if (bg && !(isfinite(bg[0]) && isfinite(bg[1]) && isfinite(bg[2]))) return FC2T2_EINVAL;
+  if (!volume_ok(plan) || plan->K > 5) return FC2T2_EUNSUPPORTED;
+  if (R * (int64_t)maxseg_for(plan) > 0xFFFFFFFFll) return FC2T2_EUNSUPPORTED;
+  if (R == 0) return FC2T2_OK;
+  if (!ws || ws_bytes < ray_volume_bwd_ws(plan, R)) return FC2T2_EWORKSPACE;
+  StageScope tm(plan, FC2T2_STAGE_RAY_T, stream);
+  return plan->io == FC2T2_IO_F64
+             ? volume_backward_t<double>(plan, (const double*)L, (const double*)o, (const double*)r, t0, t1, R, bg,
+                                         (const double*)gy, (double*)gL, ws, stream)
+             : volume_backward_t<float>(plan, (const float*)L, (const float*)o, (const float*)r, t0, t1, R, bg,
+                                        (const float*)gy, (float*)gL, ws, stream);
+}
+
+}  // extern "C"

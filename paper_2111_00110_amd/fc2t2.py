@@ -25,7 +25,8 @@ M2L_PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x2": 3, "bf16x3": 4, "separable"
 FIT = {"taylor": 0, "lsq": 0x100}   # M2L tensor: derivatives, or least-squares fit (section 3.1)
 IO = {"f32": 0, "f64": 1}
 OP = {"expand": 0, "eval_backward": 1, "expand_backward": 2, "ray_integral_backward": 3,
-      "ray_root_backward": 4, "eval_sorted": 5}
+      "ray_root_backward": 4, "eval_sorted": 5, "ray_volume_backward": 6}
+VOLUME_STOP_DEPTH = 4.5   # the volume walk ends after the first cell exiting deeper than this
 ROOT_SAVED = 12
 ROOT_SMOOTH, ROOT_FACE, ROOT_GRAZING = 0, 1, 2   # kind of a ray-root hit, saved[:, 10]
 
@@ -105,6 +106,10 @@ def lib() -> ctypes.CDLL:
     L.fc2t2_ray_root.argtypes = [vp, vp, vp, vp, dbl, dbl, i64, dbl, vp, vp, vp, vp, vp]
     L.fc2t2_ray_root_at.restype = i32
     L.fc2t2_ray_root_at.argtypes = [vp, vp, vp, vp, dbl, dbl, i64, vp, vp, vp, vp, vp, vp]
+    L.fc2t2_ray_volume.restype = i32
+    L.fc2t2_ray_volume.argtypes = [vp, vp, vp, vp, dbl, dbl, i64, vp, vp, vp, vp]
+    L.fc2t2_ray_volume_backward.restype = i32
+    L.fc2t2_ray_volume_backward.argtypes = [vp, vp, vp, vp, dbl, dbl, i64, vp, vp, vp, vp, sz, vp]
     L.fc2t2_m2l.restype = i32
     L.fc2t2_m2l.argtypes = [vp, i32, i32, vp, vp, i32, vp]
     L.fc2t2_level_numel.restype = sz
@@ -381,6 +386,41 @@ class Plan:
                                                  _ptr(gy), _ptr(gL), _ptr(ws), ws.numel(), _stream()),
                "fc2t2_ray_integral_backward")
 
+    @staticmethod
+    def _bg(bg):
+        """Background colour as a host array of 3 doubles (None: black)."""
+        if bg is None:
+            return None
+        vals = [float(v) for v in bg]
+        assert len(vals) == 3, "bg has three components"
+        return (ctypes.c_double * 3)(*vals)
+
+    def ray_volume(self, Lt, o, r, t0: float, t1: float, bg=None, with_trans: bool = False):
+        """Volumetric rendering (four channels: density, R, G, B): colour y [R, 3], and the exit
+        transmittance [R] as well with with_trans."""
+        R = o.shape[0]
+        o = self._t(o, (R, 3), "o")
+        r = self._t(r, (R, 3), "r")
+        Lt = self._t(Lt, self.local_shape(), "L")
+        y = torch.empty((R, 3), dtype=self.dtype, device=self.device)
+        tr = torch.empty(R, dtype=self.dtype, device=self.device) if with_trans else None
+        _check(lib().fc2t2_ray_volume(self.handle, _ptr(Lt), _ptr(o), _ptr(r), float(t0), float(t1), R,
+                                      self._bg(bg), _ptr(y), _ptr(tr), _stream()), "fc2t2_ray_volume")
+        return (y, tr) if with_trans else y
+
+    def ray_volume_backward(self, Lt, o, r, t0: float, t1: float, gy, gL, bg=None):
+        """gL += the cotangent of the four channels of Lt from colour cotangents gy [R, 3]."""
+        R = o.shape[0]
+        o = self._t(o, (R, 3), "o")
+        r = self._t(r, (R, 3), "r")
+        Lt = self._t(Lt, self.local_shape(), "L")
+        gy = self._t(gy, (R, 3), "gy")
+        assert gL.is_contiguous() and tuple(gL.shape) == self.local_shape() and gL.dtype == self.dtype
+        ws = self.workspace("ray_volume_backward", R)
+        _check(lib().fc2t2_ray_volume_backward(self.handle, _ptr(Lt), _ptr(o), _ptr(r), float(t0), float(t1), R,
+                                               self._bg(bg), _ptr(gy), _ptr(gL), _ptr(ws), ws.numel(), _stream()),
+               "fc2t2_ray_volume_backward")
+
     def ray_root(self, Lt, o, r, t0: float, t1: float, level_frac: float = 0.5,
                  tau: Optional[torch.Tensor] = None):
         """First upward crossing of level_frac * max f along each ray, or of the given per-ray
@@ -492,6 +532,32 @@ class RayIntegral(torch.autograd.Function):
         gw = torch.empty_like(w) if ctx.needs_input_grad[2] else None
         plan.expand_backward(gL, p, w, gp, gw, accumulate=False)
         return None, gp, gw, None, None, None, None
+
+
+class RayVolume(torch.autograd.Function):
+    """Colour of each ray through the density and colour fields of one four-channel expansion
+    (section 6.1.2: channel 0 the density, channels 1..3 R, G, B), with the backward of
+    section 6.2.2 as the exact derivative of the forward.  Keeping the density non-negative
+    (e.g. non-negative density weights) is the caller's part."""
+
+    @staticmethod
+    def forward(ctx, plan: Plan, p, w, o, r, t0: float, t1: float, bg=None):
+        Lt = plan.expand(p, w)
+        y = plan.ray_volume(Lt, o, r, t0, t1, bg)
+        ctx.plan, ctx.t0, ctx.t1, ctx.bg = plan, t0, t1, bg
+        ctx.save_for_backward(p, w, o, r, Lt)
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        plan = ctx.plan
+        p, w, o, r, Lt = ctx.saved_tensors
+        gL = plan.new_local()
+        plan.ray_volume_backward(Lt, o, r, ctx.t0, ctx.t1, gy.contiguous(), gL, ctx.bg)
+        gp = torch.empty_like(p) if ctx.needs_input_grad[1] else None
+        gw = torch.empty_like(w) if ctx.needs_input_grad[2] else None
+        plan.expand_backward(gL, p, w, gp, gw, accumulate=False)
+        return None, gp, gw, None, None, None, None, None
 
 
 class RayRoot(torch.autograd.Function):

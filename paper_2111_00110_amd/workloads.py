@@ -3,8 +3,10 @@
 This module only draws random inputs.  It holds none of the method's arithmetic, so the
 GPU path and the FP64 CPU checker can both consume the same arrays.
 
-Five workloads mirror the paper's shapes (section 3.3 benchmarks; section 4.3 SDF fitting
-with N = 8 m sources and M = 10 m targets; sections 5-6 rays through a level-6 grid):
+Six workloads mirror the paper's shapes (section 3.3 benchmarks; section 4.3 SDF fitting
+with N = 8 m sources and M = 10 m targets; sections 5-6 rays through a level-6 grid; the
+volumetric layer's experiment with a level-6 expansion, 8 m sources and 100,000 rays per
+iteration):
 
   explicit2d_small   2-D, N = M = 4096, Gaussian sigma = 0.05, 16^2 grid, K = 4, FP64
   explicit2d         2-D, N = M = 2^20, Gaussian sigma = 0.01, 256^2 grid, K = 6, FP32
@@ -14,6 +16,11 @@ with N = 8 m sources and M = 10 m targets; sections 5-6 rays through a level-6 g
                      128^3 grid, K = 4
   ray_root3d         3-D shell sources N = 2^23, 65,536 rays, Gaussian sigma = 0.015,
                      128^3 grid, K = 5
+  volume3d           3-D shell sources N = 2^23 with four channels (density, R, G, B),
+                     100,000 rays, Gaussian sigma = 0.02, 64^3 grid, K = 4; density weights
+                     0.006 |N(0, 1)| (non-negative, as the paper keeps them), so a ray through
+                     the shell gathers an optical depth of a few units and some rays end in
+                     the medium while others reach the background
 
 Draw order with numpy's PCG64 (default_rng(seed)), all in FP64, then one cast to the
 workload's IO precision: sources, weights, queries (or ray origins, then aim jitter),
@@ -41,10 +48,11 @@ class Workload:
     M: int                  # queries (explicit layer)
     R: int                  # rays (ray layers)
     io: str                 # "f32" | "f64"
-    layer: str              # "explicit" | "ray_integral" | "ray_root"
+    layer: str              # "explicit" | "ray_integral" | "ray_root" | "volume"
     sources: str            # "uniform" | "shell"
     t0: float = 0.0         # ray parameter range
     t1: float = 4.0
+    dens: float = 1.0       # volume: density weights are dens * |N(0, 1)|
 
 
 WORKLOADS = {
@@ -58,6 +66,8 @@ WORKLOADS = {
                                1 << 22, 0, 65536, "f32", "ray_integral", "shell"),
     "ray_root3d": Workload("ray_root3d", 3, 128, -1.0, 1.0, 5, "gaussian", 0.015,
                            1 << 23, 0, 65536, "f32", "ray_root", "shell"),
+    "volume3d": Workload("volume3d", 3, 64, -1.0, 1.0, 4, "gaussian", 0.02,
+                         1 << 23, 0, 100_000, "f32", "volume", "shell", dens=0.006),
 }
 
 
@@ -79,7 +89,9 @@ def make(wl: Workload, seed: int = 0, channels: int = 1) -> dict:
     Returns a dict of numpy arrays in the workload's IO precision:
       p [N, d], w [N, C]; explicit: q [M, d], gy [M, C];
       ray_integral: o [R, 3], r [R, 3], gy [R, C];
-      ray_root: o, r, gt [R], gn [R, 3].
+      ray_root: o, r, gt [R], gn [R, 3];
+      volume: w [N, 4] (density, R, G, B; the density column dens * |N(0, 1)|), o, r,
+              gy [R, 3], bg [3] (the background colour, fixed).
     """
     rng = np.random.default_rng(seed)
     d = wl.dim
@@ -88,7 +100,11 @@ def make(wl: Workload, seed: int = 0, channels: int = 1) -> dict:
         p = rng.uniform(wl.lo, wl.hi, size=(wl.N, d))
     else:
         p = _shell(rng, wl.N)
+    if wl.layer == "volume":
+        channels = 4
     w = rng.standard_normal((wl.N, channels))
+    if wl.layer == "volume":
+        w[:, 0] = wl.dens * np.abs(w[:, 0])
     if wl.layer == "explicit":
         out["q"] = rng.uniform(wl.lo, wl.hi, size=(wl.M, d))
     else:
@@ -107,6 +123,9 @@ def make(wl: Workload, seed: int = 0, channels: int = 1) -> dict:
         out["gy"] = rng.standard_normal((wl.M, channels))
     elif wl.layer == "ray_integral":
         out["gy"] = rng.standard_normal((wl.R, channels))
+    elif wl.layer == "volume":
+        out["gy"] = rng.standard_normal((wl.R, 3))
+        out["bg"] = np.array([0.2, 0.4, 0.6])
     else:
         out["gt"] = rng.standard_normal(wl.R)
         out["gn"] = rng.standard_normal((wl.R, 3))

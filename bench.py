@@ -17,8 +17,8 @@ Prints one JSON line with
   * the same step with the other M2L forms (BF16x3, plain FP32 on the matrix cores) with their
     errors, i.e. FP16x3 against FP32 at equal accuracy;
   * the FP64 direct-sum checker timed on the host's cores on a bounded sample (cpu_baseline);
-  * the other workloads (2-D explicit, line integral, ray root, small FP64 case) under
-    "other_workloads".
+  * the other workloads (2-D explicit, line integral, ray root, volumetric rendering, small
+    FP64 case) under "other_workloads".
 """
 from __future__ import annotations
 
@@ -142,7 +142,8 @@ class Runner:
     def plan(self, m2l):
         from paper_2111_00110_amd import fc2t2
         wl = self.wl
-        return fc2t2.Plan(wl.dim, wl.n, wl.lo, wl.hi, wl.kernel, wl.param, wl.K, m2l=m2l, io=wl.io, fit=self.fit)
+        return fc2t2.Plan(wl.dim, wl.n, wl.lo, wl.hi, wl.kernel, wl.param, wl.K, m2l=m2l, io=wl.io, fit=self.fit,
+                          channels=4 if wl.layer == "volume" else 1)
 
     def step_fn(self, plan):
         torch, wl, t = self.torch, self.wl, self.t
@@ -178,6 +179,17 @@ class Runner:
                 y = plan.ray_integral(Lt, o, r, wl.t0, wl.t1)
                 gL.zero_()
                 plan.ray_integral_backward(o, r, wl.t0, wl.t1, gy, gL)
+                plan.expand_backward(gL, p, w, gp, gw, accumulate=False)
+                return y
+        elif wl.layer == "volume":
+            o, r, gy = t["o"], t["r"], t["gy"]
+            bg = tuple(float(v) for v in self.x["bg"])
+
+            def step():
+                plan.expand(p, w, out=Lt)
+                y = plan.ray_volume(Lt, o, r, wl.t0, wl.t1, bg)
+                gL.zero_()
+                plan.ray_volume_backward(Lt, o, r, wl.t0, wl.t1, gy, gL, bg)
                 plan.expand_backward(gL, p, w, gp, gw, accumulate=False)
                 return y
         else:
@@ -414,7 +426,8 @@ def other_workload(name, m2l, steps, warmup, threads):
            "config": {"dim": wl.dim, "N": wl.N, "M": wl.M, "R": wl.R, "grid": "%d^%d" % (wl.n, wl.dim), "K": wl.K,
                       "kernel": "%s %g" % (wl.kernel, wl.param), "io": wl.io,
                       "outputs": {"explicit": "y, w_bar, p_bar, q_bar" if wl.io == "f32" else "y (forward only)",
-                                  "ray_integral": "y, w_bar, p_bar", "ray_root": "t*, grad f(q*), w_bar, p_bar"}[wl.layer]},
+                                  "ray_integral": "y, w_bar, p_bar", "ray_root": "t*, grad f(q*), w_bar, p_bar",
+                                  "volume": "colour y, w_bar, p_bar (four channels)"}[wl.layer]},
            "stages_ms_per_step": {k: round(v[0], 4) for k, v in st.items()}}
     if form != "f64":
         out["m2l_mfma"] = m2l_lines(wl, st, form, flops)
@@ -461,7 +474,7 @@ def main():
     value = r.units / (ms * 1e-3)
 
     outputs = {"explicit": "y, w_bar, p_bar, q_bar", "ray_integral": "y (ray integrals), w_bar, p_bar",
-               "ray_root": "t*, grad f(q*), w_bar, p_bar"}[wl.layer]
+               "ray_root": "t*, grad f(q*), w_bar, p_bar", "volume": "colour y, w_bar, p_bar (four channels)"}[wl.layer]
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": r.unit, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
@@ -511,7 +524,7 @@ def main():
         del r, plan
         torch.cuda.empty_cache()
         others = {}
-        for name in ("explicit2d", "ray_integral3d", "ray_root3d", "explicit2d_small"):
+        for name in ("explicit2d", "ray_integral3d", "ray_root3d", "volume3d", "explicit2d_small"):
             if name == args.workload:
                 continue
             others[name] = other_workload(name, args.m2l,

@@ -18,12 +18,11 @@
 // E = int over the whole walk of c_y sigma mexp'(S), plus (y_bar . bg) mexp'(D_end) when the
 // walk did not stop, and Gb the same integral up to the cell's entry: a change of sigma at t
 // changes S at every later point.  mono = u^k / k! in cell units u = (q - centre) / h, so the
-// output is the cotangent of the cell-scaled rows.  The running integral inside the cell is
-// built as a polynomial (degree 5K + 4 in x) so that H is exact at the quadrature nodes.  The
-// stop decision is not differentiated.
+// output is the cotangent of the cell-scaled rows.  The stop decision is not differentiated.
 //
-// Records: one per segment (cell as the sort key; [ta, tb], entry depth and Gb as payload),
-// sorted by cell and reduced per cell with the ray insertion's segmented reduction.  Every
+// Records: one per segment (cell as the sort key; [ta, tb] and the segment's weights at K + 1
+// points as payload, see below), sorted by cell and reduced per cell with the ray insertion's
+// segmented reduction.  Every
 // per-segment quantity runs in FP64 (the vector FP64 and FP32 rates are equal without packed
 // FP32); only the expansion rows and the output rows use the IO type.
 #include <math.h>
@@ -184,17 +183,66 @@ __global__ void __launch_bounds__(64) volume_kernel(const T* __restrict__ L, con
 }
 
 // ---------------------------------------------------------------------------------------
-// Backward records: the forward's walk again, with the colour cotangents folded into c_y.
-// Slot ray * maxseg + j holds segment j: key = its cell, rec[2 slot] = (ta, tb),
-// rec[2 slot + 1] = (entry depth, Gb); unused slots get the key G (sorted after every cell).
-// E[ray] receives the walk's total of int c_y sigma mexp'(S) plus the background term.
+// Backward, per segment.  Every channel's cotangent row gets sum over the segment of
+// a(x) mono(u(x)) dx for a weight function a; mono(u(x)) is a polynomial of degree <= K in x,
+// so the segment's whole contribution is fixed by K + 1 numbers: the weights alpha_m at the
+// K + 1 Chebyshev-Lobatto points z_m of the segment, alpha_m = s int_0^1 a(x) l_m(x) dx with
+// l_m the Lagrange basis on the z_m; then the row gets sum_m alpha_m mono(u(z_m)).  With
+// Lam[m][i] = l_m(x_i) at the Gauss-Legendre nodes, Gam[m][i] = int_{x_i}^1 l_m and
+// beta_m = int_0^1 l_m (host constants):
+//   colour k:  alpha_m = y_bar_k s sum_i w_i (sigma T)(x_i) Lam[m][i];
+//   density:   alpha_m = s sum_i w_i (c_y T)(x_i) Lam[m][i] - s^2 sum_i w_i g(x_i) Gam[m][i]
+//                        + s (E - Gb) beta_m,        g = c_y sigma mexp'(S),
+// where the middle term is the running integral of g with the order of integration swapped
+// (int_0^1 l_m(x) int_0^x g = int_0^1 g(y) int_y^1 l_m); every integrand has degree <= 6K + 4,
+// so each sum is exact.  The records pass computes the alphas (E, the ray's total, is added
+// in the reduction, which runs after the whole walk).
+struct VolumeProj {
+  double lam[6][kMaxNodes];   // l_m(x_i)
+  double gam[6][kMaxNodes];   // int_{x_i}^1 l_m
+  double beta[6];             // int_0^1 l_m
+};
+
+VolumeProj volume_proj(int K, const VolumeConsts& vc) {
+  VolumeProj vp = {};
+  double z[6];
+  for (int m = 0; m <= K; ++m) z[m] = lobatto_node(K, m);
+  auto ell = [&](int m, double x) {
+    double v = 1.0;
+    for (int j = 0; j <= K; ++j)
+      if (j != m) v *= (x - z[j]) / (z[m] - z[j]);
+    return v;
+  };
+  std::vector<double> t, w;
+  gauss_legendre(8, t, w);   // exact for the degree-K basis
+  auto integral = [&](int m, double a, double b) {
+    double acc = 0.0;
+    for (size_t k = 0; k < t.size(); ++k) acc += w[k] * ell(m, a + 0.5 * (b - a) * (1.0 + t[k]));
+    return 0.5 * (b - a) * acc;
+  };
+  for (int m = 0; m <= K; ++m) {
+    for (int i = 0; i < 3 * K + 3; ++i) {
+      vp.lam[m][i] = ell(m, vc.x[i]);
+      vp.gam[m][i] = integral(m, vc.x[i], 1.0);
+    }
+    vp.beta[m] = integral(m, 0.0, 1.0);
+  }
+  return vp;
+}
+
+// Records: the forward's walk again, with the colour cotangents folded into c_y.  Slot
+// ray * maxseg + j holds segment j: key = its cell; rec[(K + 2) slot] = (ta, tb), then
+// (alpha_m of the density without the E term, alpha_m of sigma T without y_bar_k) for
+// m = 0..K; unused slots get the key G (sorted after every cell).  E[ray] receives the walk's
+// total of int c_y sigma mexp'(S), plus (y_bar . bg) mexp'(D_end) when the walk did not stop.
 template <class S, typename T>
 __global__ void __launch_bounds__(64) volume_records_kernel(const T* __restrict__ L, const T* __restrict__ O,
                                                             const T* __restrict__ Rd, int64_t R, double t0,
                                                             double t1, double lo, double hi, double h, int n,
-                                                            int64_t G, VolumeConsts vc, const T* __restrict__ gy,
-                                                            int maxseg, uint32_t* __restrict__ keys,
-                                                            double2* __restrict__ rec, double* __restrict__ E) {
+                                                            int64_t G, VolumeConsts vc, VolumeProj vp,
+                                                            const T* __restrict__ gy, int maxseg,
+                                                            uint32_t* __restrict__ keys, double2* __restrict__ rec,
+                                                            double* __restrict__ E) {
   constexpr int K = S::K, Ppad = S::Ppad, NQ = 3 * K + 3;
   const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (ray >= R) return;
@@ -227,16 +275,30 @@ __global__ void __launch_bounds__(64) volume_records_kernel(const T* __restrict_
     for (int m = 0; m < 6; ++m) cy[m] = g0 * b0[m] + g1 * b1[m] + g2 * b2[m];
     double sx[K + 2];
     depth_poly<K>(bs, D, sl, sx);
-    keys[base + j] = (uint32_t)cell;
-    rec[2 * (base + j)] = make_double2(ta, tb);
-    rec[2 * (base + j) + 1] = make_double2(D, Gb);
-    ++j;
+    double ad[K + 1], as[K + 1];
+#pragma unroll
+    for (int m = 0; m <= K; ++m) ad[m] = as[m] = 0.0;
     double gseg = 0.0;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
       const double x = vc.x[i];
-      gseg += vc.w[i] * poly_at<K + 1>(cy, x) * poly_at<K + 1>(bs, x) * mexp_d(vc, poly_at<K + 2>(sx, x));
+      const double sg = poly_at<K + 1>(bs, x), cv = poly_at<K + 1>(cy, x), Sv = poly_at<K + 2>(sx, x);
+      const double Tv = mexp_at(vc, Sv), gi = cv * sg * mexp_d(vc, Sv);
+      gseg += vc.w[i] * gi;
+      const double hA = vc.w[i] * sl * cv * Tv, hB = vc.w[i] * sl * sl * gi, hS = vc.w[i] * sl * sg * Tv;
+#pragma unroll
+      for (int m = 0; m <= K; ++m) {
+        ad[m] += hA * vp.lam[m][i] - hB * vp.gam[m][i];
+        as[m] += hS * vp.lam[m][i];
+      }
     }
+    const int64_t slot = base + j;
+    keys[slot] = (uint32_t)cell;
+    double2* rr = rec + slot * (K + 2);
+    rr[0] = make_double2(ta, tb);
+#pragma unroll
+    for (int m = 0; m <= K; ++m) rr[1 + m] = make_double2(ad[m] - sl * Gb * vp.beta[m], as[m]);
+    ++j;
     Gb += sl * gseg;
     D = poly_at<K + 2>(sx, 1.0);
     if (D > kStopDepth) {
@@ -249,120 +311,108 @@ __global__ void __launch_bounds__(64) volume_records_kernel(const T* __restrict_
   E[ray] = Gb + (stopped ? 0.0 : gbg * mexp_d(vc, D));
 }
 
-// Per record: the segment's contribution to one channel's cotangent row.
-template <class S, typename T>
-struct VolumeInsert {
-  static constexpr int K = S::K, NQ = 3 * K + 3;
-  static constexpr int NT = 3 * K + 4;   // mexp'(S(x)): degree 3 (K + 1)
-  static constexpr int NC = 2 * K + 1;   // c_y sigma
-  static constexpr int NG = 5 * K + 4;   // c_y sigma mexp'(S)
-  const T* __restrict__ L;
-  const T* __restrict__ O;
-  const T* __restrict__ Rd;
-  const double2* __restrict__ rec;
-  const double* __restrict__ E;
-  const T* __restrict__ gy;
-  int maxseg, n;
-  int64_t G;
-  double lo, h;
-  VolumeConsts vc;
+// Per-cell reduction of the records into all four channels in one pass (a group of GROUP
+// lanes per cell, as the shared segmented reduction, but with the monomials of each record's
+// K + 1 points computed once for the four rows): density row += sum_m (alpha_m + s E beta_m)
+// mono(u_m); colour row k += y_bar_k sum_m alpha'_m mono(u_m).  Each lane sums a few records;
+// the group's partial rows are then added by a butterfly, and the rows are added into out.
+struct VolumeBeta {
+  double beta[6];
+};
 
-  __device__ __forceinline__ void operator()(uint32_t slot, const T (&)[3], int ch, T (&v)[S::P],
-                                             int64_t cell) const {
-    constexpr int Ppad = S::Ppad;
-    const int64_t ray = slot / maxseg;
-    double o[3], r[3];
-    load3(O, ray, o);
-    load3(Rd, ray, r);
-    const double2 tt = rec[2 * (int64_t)slot], de = rec[2 * (int64_t)slot + 1];
-    const double sl = tt.y - tt.x;
+template <class S, typename T, int GROUP>
+__global__ void __launch_bounds__(256) volume_reduce_kernel(const uint32_t* __restrict__ starts,
+                                                            const uint32_t* __restrict__ perm, int64_t G, int n,
+                                                            double lo, double h, const T* __restrict__ O,
+                                                            const T* __restrict__ Rd, const double2* __restrict__ rec,
+                                                            const double* __restrict__ E, const T* __restrict__ gy,
+                                                            int maxseg, VolumeBeta vb, T* __restrict__ out) {
+  constexpr int K = S::K, P = S::P, Ppad = S::Ppad;
+  constexpr int CPW = kWave / GROUP;
+  constexpr Lobatto<K> LB{};
+  const int lane = threadIdx.x & (kWave - 1);
+  const int lane_g = lane & (GROUP - 1);
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const int64_t wave_id = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t cs = G * Ppad;
+  for (int64_t c0 = wave_id * CPW; c0 < G; c0 += waves * CPW) {
+    const int64_t cell = c0 + lane / GROUP;
+    const bool valid = cell < G;
+    const uint32_t b = valid ? starts[cell] : 0u, e = valid ? starts[cell + 1] : 0u;
+    T acc[4][P];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int k = 0; k < P; ++k) acc[c][k] = T(0);
     int cc[3];
-    decode_cell<3, T>(cell, n, cc);
-    double d[3], q[3];
-    seg_local(o, r, tt.x, cc, lo, h, d, q);
-    const T* row = L + cell * Ppad;
-    const int64_t cs = G * Ppad;
-    double bs[6];
-    segment_poly<S>(row, d, q, sl, bs);
-    double sx[K + 2];
-    depth_poly<K>(bs, de.x, sl, sx);
-    double a[NQ];
-    if (ch == 0) {
-      const double g0 = (double)gy[3 * ray], g1 = (double)gy[3 * ray + 1], g2 = (double)gy[3 * ray + 2];
-      double b0[6], b1[6], b2[6], cy[6];
-      segment_poly<S>(row + cs, d, q, sl, b0);
-      segment_poly<S>(row + 2 * cs, d, q, sl, b1);
-      segment_poly<S>(row + 3 * cs, d, q, sl, b2);
+    decode_cell<3, T>(valid ? cell : 0, n, cc);
+    for (uint32_t ri = b + lane_g; ri < e; ri += GROUP) {
+      const uint32_t slot = perm[ri];
+      const int64_t ray = slot / maxseg;
+      double o[3], r[3];
+      load3(O, ray, o);
+      load3(Rd, ray, r);
+      const double2* rr = rec + (int64_t)slot * (K + 2);
+      const double2 tt = rr[0];
+      const double sl = tt.y - tt.x;
+      double d[3], q[3];
+      seg_local(o, r, tt.x, cc, lo, h, d, q);
+      const double es = sl * E[ray];
+      T tmp[P];
 #pragma unroll
-      for (int m = 0; m < 6; ++m) cy[m] = g0 * b0[m] + g1 * b1[m] + g2 * b2[m];
-      // tp = mexp'(S(x)) by Horner over polynomials
-      double tp[NT];
+      for (int k = 0; k < P; ++k) tmp[k] = T(0);
 #pragma unroll
-      for (int m = 0; m < NT; ++m) tp[m] = 0.0;
-      tp[0] = vc.mp[3];
+      for (int m = 0; m <= K; ++m) {
+        const double2 al = rr[1 + m];
+        const T a0 = (T)(al.x + es * vb.beta[m]), as = (T)al.y;
+        const double xs = sl * LB.x[m];
+        T u[3];
 #pragma unroll
-      for (int deg = 2; deg >= 0; --deg) {
-        double nt[NT];
+        for (int j = 0; j < 3; ++j) u[j] = (T)(d[j] + q[j] * xs);
+        T mono[P];
+        monomials<S>(u, mono);
 #pragma unroll
-        for (int m = 0; m < NT; ++m) nt[m] = 0.0;
-#pragma unroll
-        for (int i = 0; i < NT; ++i)
-#pragma unroll
-          for (int k = 0; k < K + 2; ++k)
-            if (i + k < NT) nt[i + k] += tp[i] * sx[k];
-        nt[0] += vc.mp[deg];
-#pragma unroll
-        for (int m = 0; m < NT; ++m) tp[m] = nt[m];
+        for (int k = 0; k < P; ++k) {
+          acc[0][k] += a0 * mono[k];
+          tmp[k] += as * mono[k];
+        }
       }
-      double cz[NC];
+      const T g0 = gy[3 * ray], g1 = gy[3 * ray + 1], g2 = gy[3 * ray + 2];
 #pragma unroll
-      for (int m = 0; m < NC; ++m) cz[m] = 0.0;
-#pragma unroll
-      for (int i = 0; i <= K; ++i)
-#pragma unroll
-        for (int k = 0; k <= K; ++k) cz[i + k] += cy[i] * bs[k];
-      // run(x) = s int_0^x c_y sigma mexp'(S)
-      double run[NG + 1];
-#pragma unroll
-      for (int m = 0; m <= NG; ++m) run[m] = 0.0;
-#pragma unroll
-      for (int i = 0; i < NC; ++i)
-#pragma unroll
-        for (int k = 0; k < NT; ++k)
-          if (i + k < NG) run[i + k + 1] += cz[i] * tp[k];
-#pragma unroll
-      for (int m = 1; m <= NG; ++m) run[m] *= sl / m;
-      const double c0 = E[ray] - de.y;
-#pragma unroll
-      for (int i = 0; i < NQ; ++i) {
-        const double x = vc.x[i];
-        const double H = poly_at<K + 1>(cy, x) * mexp_at(vc, poly_at<K + 2>(sx, x)) + c0 - poly_at<NG + 1>(run, x);
-        a[i] = sl * vc.w[i] * H;
-      }
-    } else {
-      const double g = (double)gy[3 * ray + ch - 1];
-#pragma unroll
-      for (int i = 0; i < NQ; ++i) {
-        const double x = vc.x[i];
-        a[i] = g * sl * vc.w[i] * poly_at<K + 1>(bs, x) * mexp_at(vc, poly_at<K + 2>(sx, x));
+      for (int k = 0; k < P; ++k) {
+        acc[1][k] += g0 * tmp[k];
+        acc[2][k] += g1 * tmp[k];
+        acc[3][k] += g2 * tmp[k];
       }
     }
 #pragma unroll
-    for (int k = 0; k < S::P; ++k) v[k] = T(0);
+    for (int off = GROUP / 2; off >= 1; off >>= 1)
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) {
-      const double xs = sl * vc.x[i];
-      T u[3];
+      for (int c = 0; c < 4; ++c)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) u[j] = (T)(d[j] + q[j] * xs);
-      T mono[S::P];
-      monomials<S>(u, mono);
-      const T ai = (T)a[i];
+        for (int k = 0; k < P; ++k) acc[c][k] += __shfl_xor(acc[c][k], off, GROUP);
+    if (valid && e > b) {
 #pragma unroll
-      for (int k = 0; k < S::P; ++k) v[k] += ai * mono[k];
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+          if (k % GROUP == lane_g) out[c * cs + cell * Ppad + k] += acc[c][k];
     }
   }
-};
+}
+
+template <class S, typename T, int GROUP>
+fc2t2_status launch_volume_reduce(const fc2t2_plan_s* pl, const uint32_t* starts, const uint32_t* perm, const T* o,
+                                  const T* r, const double2* rec, const double* E, const T* gy, int maxseg,
+                                  const VolumeBeta& vb, T* gL, hipStream_t s) {
+  const int threads = 256;
+  const int64_t need = ceil_div(pl->G * GROUP, threads);
+  const int64_t blocks = need < 16384 ? need : 16384;
+  hipLaunchKernelGGL((volume_reduce_kernel<S, T, GROUP>), dim3((unsigned)blocks), dim3(threads), 0, s, starts, perm,
+                     pl->G, pl->n, pl->lo, pl->h0, o, r, rec, E, gy, maxseg, vb, gL);
+  FC2T2_LAUNCH_CHECK();
+  return FC2T2_OK;
+}
 
 bool volume_ok(const fc2t2_plan_s* pl) { return pl->dim == 3 && pl->C == 4; }
 
@@ -372,7 +422,7 @@ namespace fc2t2 {
 
 size_t ray_volume_bwd_ws(const fc2t2_plan_s* pl, int64_t R) {
   Carve c(nullptr);
-  carve_records(c, pl, R * maxseg_for(pl), 2);
+  carve_records(c, pl, R * maxseg_for(pl), pl->K + 2);
   c.take<double>(R);
   return c.off;
 }
@@ -412,15 +462,16 @@ fc2t2_status volume_backward_t(const fc2t2_plan_s* pl, const T* L, const T* o, c
   const int maxseg = maxseg_for(pl);
   const int64_t slots = R * maxseg;
   Carve c(ws);
-  RecordBufs b = carve_records(c, pl, slots, 2);
+  RecordBufs b = carve_records(c, pl, slots, pl->K + 2);
   double* E = c.take<double>(R);
   const VolumeConsts vc = volume_consts(pl->K, bg);
+  const VolumeProj vp = volume_proj(pl->K, vc);
   fc2t2_status st = FC2T2_EUNSUPPORTED;
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {
     using S = decltype(shape);
     if constexpr (S::D == 3) {
       hipLaunchKernelGGL((volume_records_kernel<S, T>), dim3((unsigned)ceil_div(R, 64)), dim3(64), 0, s, L, o, r, R,
-                         t0, t1, pl->lo, pl->hi, pl->h0, pl->n, pl->G, vc, gy, maxseg, b.keys, b.rec, E);
+                         t0, t1, pl->lo, pl->hi, pl->h0, pl->n, pl->G, vc, vp, gy, maxseg, b.keys, b.rec, E);
       st = FC2T2_OK;
     }
   });
@@ -434,9 +485,14 @@ fc2t2_status volume_backward_t(const fc2t2_plan_s* pl, const T* L, const T* o, c
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {
     using S = decltype(shape);
     if constexpr (S::D == 3) {
-      VolumeInsert<S, T> fn{L, o, r, b.rec, E, gy, maxseg, pl->n, pl->G, pl->lo, pl->h0, vc};
-      // a ray crosses about 2.3 n cells: records per occupied cell are few
-      st = launch_reduce_cells<S, T>(pl, b.starts, b.perm, R * 2 * pl->n, gL, true, fn, s);
+      VolumeBeta vb;
+      for (int m = 0; m < 6; ++m) vb.beta[m] = vp.beta[m];
+      // a ray crosses about 2.3 n cells: lanes per cell from the mean records per cell
+      switch (reduce_group_for(R * 2 * pl->n, pl->G)) {
+        case 4: st = launch_volume_reduce<S, T, 4>(pl, b.starts, b.perm, o, r, b.rec, E, gy, maxseg, vb, gL, s); break;
+        case 16: st = launch_volume_reduce<S, T, 16>(pl, b.starts, b.perm, o, r, b.rec, E, gy, maxseg, vb, gL, s); break;
+        default: st = launch_volume_reduce<S, T, 64>(pl, b.starts, b.perm, o, r, b.rec, E, gy, maxseg, vb, gL, s); break;
+      }
     }
   });
   return st;

@@ -17,13 +17,14 @@ iteration):
   ray_root3d         3-D shell sources N = 2^23, 65,536 rays, Gaussian sigma = 0.015,
                      128^3 grid, K = 5
   volume3d           3-D shell sources N = 2^23 with four channels (density, R, G, B),
-                     100,000 rays, Gaussian sigma = 0.02, 64^3 grid, K = 4; density weights
-                     0.006 |N(0, 1)| (non-negative, as the paper keeps them), so a ray through
-                     the shell gathers an optical depth of a few units and some rays end in
-                     the medium while others reach the background
+                     100,000 rays aimed at uniform points of [-0.6, 0.6]^3 (camera rays over
+                     the object and around it), Gaussian sigma = 0.02, 64^3 grid, K = 4;
+                     density weights 0.009 |N(0, 1)| (non-negative, as the paper keeps them):
+                     a ray through both walls of the shell, or along one, ends in the medium,
+                     one that misses it reaches the background
 
 Draw order with numpy's PCG64 (default_rng(seed)), all in FP64, then one cast to the
-workload's IO precision: sources, weights, queries (or ray origins, then aim jitter),
+workload's IO precision: sources, weights, queries (or ray origins, then aim points),
 source jitter, cotangents.
 """
 from __future__ import annotations
@@ -53,6 +54,7 @@ class Workload:
     t0: float = 0.0         # ray parameter range
     t1: float = 4.0
     dens: float = 1.0       # volume: density weights are dens * |N(0, 1)|
+    aim: float = 0.1        # rays aim at uniform points of [-aim, aim]^3
 
 
 WORKLOADS = {
@@ -67,7 +69,7 @@ WORKLOADS = {
     "ray_root3d": Workload("ray_root3d", 3, 128, -1.0, 1.0, 5, "gaussian", 0.015,
                            1 << 23, 0, 65536, "f32", "ray_root", "shell"),
     "volume3d": Workload("volume3d", 3, 64, -1.0, 1.0, 4, "gaussian", 0.02,
-                         1 << 23, 0, 100_000, "f32", "volume", "shell", dens=0.006),
+                         1 << 23, 0, 100_000, "f32", "volume", "shell", dens=0.009, aim=0.6),
 }
 
 
@@ -110,7 +112,7 @@ def make(wl: Workload, seed: int = 0, channels: int = 1) -> dict:
     else:
         v = rng.standard_normal((wl.R, 3))
         o = 2.0 * v / np.linalg.norm(v, axis=1, keepdims=True)
-        aim = rng.uniform(-0.1, 0.1, size=(wl.R, 3))
+        aim = rng.uniform(-wl.aim, wl.aim, size=(wl.R, 3))
         r = -o + aim
         r = r / np.linalg.norm(r, axis=1, keepdims=True)
         out["o"] = o

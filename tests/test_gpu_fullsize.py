@@ -7,14 +7,16 @@
   of local cotangents, itself the transpose of L2P over every query);
 * ray layers (128^3): y or (t*, grad f) on sampled rays, and w_bar at sampled sources for the
   cotangents of a subsample of rays (ray insertion, or the implicit-function insertion, then
-  the whole expansion backward at full size).
+  the whole expansion backward at full size);
+* volumetric rendering (64^3, 2^23 four-channel sources, 10^5 rays): the colour of sampled
+  rays, and w_bar at sampled sources for the colour cotangents of those rays.
 
 Tolerances are the error contract: 1e-5 on values and w_bar, 1e-4 on the differentiated p_bar
 and q_bar."""
 import numpy as np
 import pytest
 
-from oracle import fmm, rays
+from oracle import fmm, rays, volume
 from paper_2111_00110_amd import workloads as W
 
 from helpers import oracle_geometry, oracle_kernel, rel
@@ -34,7 +36,8 @@ def F():
 
 
 def _plan(F, wl):
-    return F.Plan(wl.dim, wl.n, wl.lo, wl.hi, wl.kernel, wl.param, wl.K, m2l=BENCH_M2L, io=wl.io)
+    return F.Plan(wl.dim, wl.n, wl.lo, wl.hi, wl.kernel, wl.param, wl.K, m2l=BENCH_M2L, io=wl.io,
+                  channels=4 if wl.layer == "volume" else 1)
 
 
 def _dev(a):
@@ -85,9 +88,11 @@ def test_explicit_full_size_forward_and_backward(F, name):
 def _sparse_locals(geo, ker, Ms, cells):
     """Physical locals at the given cells inside an otherwise empty full-size array."""
     cells = np.unique(np.asarray(cells, dtype=np.int64).reshape(-1, geo.dim), axis=0)
-    L = np.zeros((1,) + (geo.n,) * geo.dim + (geo.P,))
+    C = Ms[0].shape[0]
+    L = np.zeros((C,) + (geo.n,) * geo.dim + (geo.P,))
     vals = fmm.locals_at_cells(geo, ker, Ms, cells)
-    L[(0,) + tuple(cells[:, j] for j in range(geo.dim))] = vals[0]
+    for c in range(C):
+        L[(c,) + tuple(cells[:, j] for j in range(geo.dim))] = vals[c]
     return L
 
 
@@ -154,3 +159,36 @@ def test_ray_root3d_full_size(F):
     isrc = W.subsample(11, 160, wl.N)
     want_gw, _ = _sampled_source_grads(geo, ker, G_L0, x["p"], x["w"], isrc)
     assert rel(gw[isrc], want_gw) < 1e-4
+
+
+def test_volume3d_full_size(F):
+    wl = W.workload("volume3d")
+    x = W.make(wl)
+    geo, ker = oracle_geometry(wl), oracle_kernel(wl)
+    plan = _plan(F, wl)
+    p, w, o, r = (_dev(x[k]) for k in ("p", "w", "o", "r"))
+    bg = tuple(float(v) for v in x["bg"])
+    Lt = plan.expand(p, w)
+    y, tr = plan.ray_volume(Lt, o, r, wl.t0, wl.t1, bg, with_trans=True)
+    y, tr = y.cpu().numpy(), tr.cpu().numpy()
+    # the medium: some rays end inside it, others reach the background
+    assert 0.05 < float(np.mean(tr == 0)) < 0.95
+    idx = W.subsample(12, 8, wl.R)
+    os_, rs = x["o"][idx], x["r"][idx]
+    Ms = fmm.moments_all_levels(geo, x["p"], x["w"])
+    L = _sparse_locals(geo, ker, Ms, _ray_cells(geo, os_, rs, wl.t0, wl.t1))
+    ref = volume.render(geo, L, os_, rs, wl.t0, wl.t1, np.array(bg))
+    ok = ref["margin"] > 1e-3          # stop decisions clear of rounding
+    assert ok.sum() >= 6
+    assert rel(y[idx][ok], ref["y"][ok]) < 1e-5
+    # backward of the sampled rays' colours through the whole expansion at full size
+    gys = np.where(ok[:, None], x["gy"][idx], 0.0).astype(np.float32)
+    gL = plan.new_local()
+    plan.ray_volume_backward(Lt, _dev(os_), _dev(rs), wl.t0, wl.t1, _dev(gys), gL, bg)
+    gw = torch.empty_like(w)
+    plan.expand_backward(gL, p, w, None, gw, accumulate=False)
+    gw = gw.cpu().numpy()
+    G_L0 = volume.render_T(geo, L, os_, rs, wl.t0, wl.t1, ref, gys, np.array(bg))
+    isrc = W.subsample(13, 160, wl.N)
+    want_gw, _ = _sampled_source_grads(geo, ker, G_L0, x["p"], x["w"], isrc)
+    assert rel(gw[isrc], want_gw) < 1e-5

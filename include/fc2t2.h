@@ -120,7 +120,8 @@ typedef enum {
   FC2T2_OP_RAY_INTEGRAL_BACKWARD = 3,/* count = R rays */
   FC2T2_OP_RAY_ROOT_BACKWARD = 4,    /* count = R rays */
   FC2T2_OP_EVAL_SORTED = 5,          /* count = M queries (fc2t2_eval_sorted's records) */
-  FC2T2_OP_RAY_VOLUME_BACKWARD = 6   /* count = R rays */
+  FC2T2_OP_RAY_VOLUME_BACKWARD = 6,  /* count = R rays */
+  FC2T2_OP_BIN_POINTS = 7            /* count = N points */
 } fc2t2_op;
 
 /* Status text (static storage). */
@@ -291,6 +292,20 @@ fc2t2_status fc2t2_ray_root_at(fc2t2_plan plan, const void* L, const void* o, co
 fc2t2_status fc2t2_ray_root_backward(fc2t2_plan plan, const void* saved, const int32_t* hit,
                                      int64_t R, const void* gt, const void* gn, void* gL,
                                      void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Binning (section 3.3: a point's finest box is the integer part of its scaled coordinates,
+ * clamped to the grid), as the expansion and the sorted evaluation do it: points x [N][dim]
+ * (IO type) sorted stably by the row-major index of their finest cell.  Outputs (caller-owned,
+ * uint32): keys_sorted [N] the cell indices in sorted order, perm [N] the input index of each
+ * sorted position (equal cells keep input order), starts [G + 1] the first sorted position of
+ * each cell (starts[G] = N), G = n^dim.  With pay_out (FP32 IO, one channel): the coordinates
+ * travel with the sort, pay_out [N][dim] in sorted order, or [N][dim + 1] with extra [N] (one
+ * value per point, e.g. a weight) appended.  Points outside the domain are counted
+ * (fc2t2_out_of_domain).  A failed look-back in the sort empties every cell and is counted
+ * (fc2t2_sort_failures).  Workspace FC2T2_OP_BIN_POINTS. */
+fc2t2_status fc2t2_bin_points(fc2t2_plan plan, const void* x, int64_t N, const void* extra,
+                              uint32_t* keys_sorted, uint32_t* perm, uint32_t* starts,
+                              void* pay_out, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Volumetric rendering (section 6.1.2; dim 3, C == 4: channel 0 the density sigma, channels
  * 1..3 the colour c = (R, G, B); K <= 5).  Per ray, with S the optical depth from the entry

@@ -101,6 +101,13 @@ size_t ws_eval_sorted(const fc2t2_plan_s* pl, int64_t M) {
   return c.off;
 }
 
+size_t ws_bin_points(int64_t N) {
+  Carve c(nullptr);
+  c.take<uint32_t>(N);
+  c.take<char>(radix_sort_scratch_bytes(N));
+  return c.off;
+}
+
 size_t ws_eval_backward(const fc2t2_plan_s* pl, int64_t M) {
   Carve c(nullptr);
   carve_sort(c, pl, M);
@@ -260,6 +267,7 @@ size_t fc2t2_workspace_size(fc2t2_plan plan, int op, int64_t count) {
     case FC2T2_OP_RAY_ROOT_BACKWARD: return ray_root_bwd_ws(plan, count);
     case FC2T2_OP_EVAL_SORTED: return ws_eval_sorted(plan, count);
     case FC2T2_OP_RAY_VOLUME_BACKWARD: return ray_volume_bwd_ws(plan, count);
+    case FC2T2_OP_BIN_POINTS: return ws_bin_points(count);
   }
   return 0;
 }
@@ -302,6 +310,28 @@ fc2t2_status fc2t2_eval(fc2t2_plan plan, const void* L, const void* q, int64_t M
   if (M > 0 && (!q || !y)) return FC2T2_EINVAL;
   StageScope t(plan, FC2T2_STAGE_L2P, stream);
   return launch_l2p(plan, L, q, M, y, grad, hess, stream);
+}
+
+fc2t2_status fc2t2_bin_points(fc2t2_plan plan, const void* x, int64_t N, const void* extra, uint32_t* keys_sorted,
+                              uint32_t* perm, uint32_t* starts, void* pay_out, void* ws, size_t ws_bytes,
+                              hipStream_t stream) {
+  if (!plan || !starts || bad_count(N)) return FC2T2_EINVAL;
+  if (N > 0 && (!x || !keys_sorted || !perm)) return FC2T2_EINVAL;
+  if (extra && !pay_out) return FC2T2_EINVAL;
+  if (pay_out && !sort_payload_ok(plan)) return FC2T2_EUNSUPPORTED;
+  if (plan->G > 0xFFFFFFFFll) return FC2T2_EUNSUPPORTED;
+  if (!ws || ws_bytes < ws_bin_points(N)) return FC2T2_EWORKSPACE;
+  Carve c(ws);
+  uint32_t* keys = c.take<uint32_t>(N);
+  void* scratch = c.take<char>(radix_sort_scratch_bytes(N));
+  StageScope t(plan, FC2T2_STAGE_SORT, stream);
+  if (N > 0) {
+    const fc2t2_status st = sort_points_by_cell(plan, x, N, keys, keys_sorted, perm, scratch, stream, extra, pay_out,
+                                                plan->ood);
+    if (st) return st;
+  }
+  return launch_cell_starts(keys_sorted, N, plan->G, starts, stream, N > 0 ? sort_err_word(scratch, N) : nullptr,
+                            plan->sort_fail);
 }
 
 fc2t2_status fc2t2_eval_sorted(fc2t2_plan plan, const void* L, const void* q, int64_t M, void* y, void* ws,

@@ -29,7 +29,6 @@ constexpr int kHistBlocks = 512;  // histogram blocks; each writes its own count
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValMask = kFlagAgg - 1u;
-constexpr int kMaxPayload = 4;            // payload words per item
 constexpr uint32_t kMaxSpins = 1u << 22;   // bounded wait: a predecessor that never publishes sets err
 // Test aid (fc2t2_debug_sort_fault): the spin limit of the look-back and a tile that withholds
 // its published counts, so that the bounded wait gives up on purpose and every kernel still
@@ -132,9 +131,12 @@ __device__ __forceinline__ void store_status(uint32_t* p, uint32_t v) {
 // publishes its digit counts, looks back over the preceding tiles' status words for its
 // global offsets (decoupled look-back), and writes each digit's items as one contiguous run
 // through an LDS staging copy in digit order.
-// Optional payload: PW 32-bit words per item travel with the key, read from pa (na words per
-// item) and pb (PW - na words per item), written to pay_out [N][PW].
-template <int PW>
+// Optional payload: PW 32-bit words per item, written to pay_out [N][PW]; read from pa (na words
+// per item) and pb (PW - na words per item), either staged with the key through LDS (GATHER
+// false: pa, pb indexed by input position) or fetched at write time by the item's original
+// index (GATHER true, the last pass: pa, pb are the unsorted inputs and vals carry the original
+// indices), so that earlier passes move only keys and indices.
+template <int PW, bool GATHER = false>
 __global__ void __launch_bounds__(kThreads) onesweep_kernel(const uint32_t* __restrict__ keys_in,
                                                             const uint32_t* __restrict__ vals_in, uint32_t N,
                                                             int shift, const uint32_t* __restrict__ ghist,
@@ -145,15 +147,16 @@ __global__ void __launch_bounds__(kThreads) onesweep_kernel(const uint32_t* __re
                                                             const uint32_t* __restrict__ pb,
                                                             uint32_t* __restrict__ pay_out, uint32_t max_spins,
                                                             uint32_t withhold_tile) {
-  constexpr int kItems = SweepShape<PW>::kItems, kWaveRun = SweepShape<PW>::kWaveRun;
-  constexpr int kTile = SweepShape<PW>::kTile;
+  constexpr int PS = GATHER ? 0 : PW;   // payload words staged through LDS
+  constexpr int kItems = SweepShape<PS>::kItems, kWaveRun = SweepShape<PS>::kWaveRun;
+  constexpr int kTile = SweepShape<PS>::kTile;
   __shared__ uint32_t wcount[kWaves][kBins];
   __shared__ uint32_t s_excl[kBins];
   __shared__ uint32_t s_gbase[kBins];
   __shared__ uint32_t scan_sh[kThreads];
   __shared__ uint32_t s_key[kTile];
   __shared__ uint32_t s_val[kTile];
-  __shared__ uint32_t s_pay[PW > 0 ? PW * kTile : 1];
+  __shared__ uint32_t s_pay[PS > 0 ? PS * kTile : 1];
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
@@ -170,8 +173,8 @@ __global__ void __launch_bounds__(kThreads) onesweep_kernel(const uint32_t* __re
     key[j] = ok ? keys_in[i] : 0u;
     val[j] = ok ? (vals_in ? vals_in[i] : i) : 0u;
   }
-  uint32_t pay[kItems][PW > 0 ? PW : 1];
-  if constexpr (PW > 0) {
+  uint32_t pay[kItems][PS > 0 ? PS : 1];
+  if constexpr (PS > 0) {
     const int nb = PW - na;
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
@@ -266,7 +269,7 @@ __global__ void __launch_bounds__(kThreads) onesweep_kernel(const uint32_t* __re
     const uint32_t lp = s_excl[digit] + wcount[wave][digit] + rank[j];
     s_key[lp] = key[j];
     s_val[lp] = val[j];
-    if constexpr (PW > 0) {
+    if constexpr (PS > 0) {
 #pragma unroll
       for (int w = 0; w < PW; ++w) s_pay[w * kTile + lp] = pay[j][w];
     }
@@ -281,9 +284,18 @@ __global__ void __launch_bounds__(kThreads) onesweep_kernel(const uint32_t* __re
     const uint32_t digit = (k >> shift) & (kBins - 1);
     const uint32_t pos = s_gbase[digit] + (t - s_excl[digit]);
     if (pos >= N) continue;   // only after a failed look-back (err set)
+    const uint32_t v = s_val[t];
     keys_out[pos] = k;
-    vals_out[pos] = s_val[t];
-    if constexpr (PW > 0) {
+    vals_out[pos] = v;
+    if constexpr (GATHER && PW > 0) {
+      // v is an original index (< N) unless an earlier pass failed (err set): its indices are
+      // then not a permutation, and the gather must not follow them out of the inputs
+      const bool in = v < N;
+      const int nb = PW - na;
+#pragma unroll
+      for (int w = 0; w < PW; ++w)
+        pay_out[(size_t)pos * PW + w] = !in ? 0u : (w < na ? pa[(size_t)v * na + w] : pb[(size_t)v * nb + (w - na)]);
+    } else if constexpr (PW > 0) {
 #pragma unroll
       for (int w = 0; w < PW; ++w) pay_out[(size_t)pos * PW + w] = s_pay[w * kTile + t];
     }
@@ -326,7 +338,7 @@ int key_bits_for(int64_t G) {
 namespace {
 
 struct SortScratch {
-  uint32_t *ktmp, *vtmp, *ptmp, *part, *ghist, *status, *err;
+  uint32_t *ktmp, *vtmp, *part, *ghist, *status, *err;
   uint32_t max_tiles;
 };
 constexpr int kPartWords = kHistBlocks * kMaxPasses * kBins;
@@ -339,8 +351,6 @@ SortScratch carve_scratch(void* scratch, int64_t N) {
   p += align256((size_t)N * 4);
   c.vtmp = (uint32_t*)p;
   p += align256((size_t)N * 4);
-  c.ptmp = (uint32_t*)p;
-  p += align256((size_t)N * 4 * kMaxPayload);
   c.part = (uint32_t*)p;                  // per histogram block: kMaxPasses x kBins counts
   p += align256((size_t)kPartWords * 4);
   c.ghist = (uint32_t*)p;                 // kSlices x kMaxPasses x kBins partial totals, then err
@@ -350,6 +360,8 @@ SortScratch carve_scratch(void* scratch, int64_t N) {
   return c;
 }
 
+// Passes of 8 bits; with a payload (PW > 0) the passes before the last move keys and indices
+// only, and the last gathers each item's payload from the inputs by its original index.
 template <int PW>
 fc2t2_status onesweep_passes(const uint32_t* keys_in, uint32_t* keys_out, uint32_t* vals_out, uint32_t N,
                              int npass, const SortScratch& c, const uint32_t* pa, int na, const uint32_t* pb,
@@ -358,19 +370,21 @@ fc2t2_status onesweep_passes(const uint32_t* keys_in, uint32_t* keys_out, uint32
   const uint32_t* vin = nullptr;
   for (int pass = 0; pass < npass; ++pass) {
     const bool to_out = ((npass - 1 - pass) % 2) == 0;
+    const bool last = pass == npass - 1;
     uint32_t* kout = to_out ? keys_out : c.ktmp;
     uint32_t* vout = to_out ? vals_out : c.vtmp;
-    uint32_t* pout = to_out ? pay_out : c.ptmp;
-    const uint32_t tiles = (uint32_t)ceil_div(N, SweepShape<PW>::kTile);
-    hipLaunchKernelGGL((onesweep_kernel<PW>), dim3(tiles), dim3(kThreads), 0, s, kin, vin, N, 8 * pass,
-                       c.ghist + pass * kBins, c.status + (size_t)pass * c.max_tiles * kBins, kout, vout, c.err,
-                       pa, na, pb, pout, g_max_spins, g_withhold_tile);
+    const uint32_t tiles = (uint32_t)ceil_div(N, SweepShape<0>::kTile);
+    if (PW > 0 && last)
+      hipLaunchKernelGGL((onesweep_kernel<PW, true>), dim3(tiles), dim3(kThreads), 0, s, kin, vin, N, 8 * pass,
+                         c.ghist + pass * kBins, c.status + (size_t)pass * c.max_tiles * kBins, kout, vout, c.err,
+                         pa, na, pb, pay_out, g_max_spins, g_withhold_tile);
+    else
+      hipLaunchKernelGGL((onesweep_kernel<0>), dim3(tiles), dim3(kThreads), 0, s, kin, vin, N, 8 * pass,
+                         c.ghist + pass * kBins, c.status + (size_t)pass * c.max_tiles * kBins, kout, vout, c.err,
+                         nullptr, 0, nullptr, nullptr, g_max_spins, g_withhold_tile);
     FC2T2_LAUNCH_CHECK();
     kin = kout;
     vin = vout;
-    pa = pout;   // later passes read the payload as written, PW words per item
-    na = PW;
-    pb = nullptr;
   }
   return FC2T2_OK;
 }
@@ -398,7 +412,7 @@ namespace fc2t2 {
 
 size_t radix_sort_scratch_bytes(int64_t N) {
   const int64_t tiles = ceil_div(N > 0 ? N : 1, kTileMin);
-  return align256((size_t)N * 4) * 2 + align256((size_t)N * 4 * kMaxPayload) + align256((size_t)kPartWords * 4) +
+  return align256((size_t)N * 4) * 2 + align256((size_t)kPartWords * 4) +
          align256((kSlices * kMaxPasses * kBins + 1) * 4) +
          align256((size_t)kMaxPasses * tiles * kBins * 4);
 }

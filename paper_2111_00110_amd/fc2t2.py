@@ -25,7 +25,7 @@ M2L_PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x2": 3, "bf16x3": 4, "separable"
 FIT = {"taylor": 0, "lsq": 0x100}   # M2L tensor: derivatives, or least-squares fit (section 3.1)
 IO = {"f32": 0, "f64": 1}
 OP = {"expand": 0, "eval_backward": 1, "expand_backward": 2, "ray_integral_backward": 3,
-      "ray_root_backward": 4, "eval_sorted": 5, "ray_volume_backward": 6}
+      "ray_root_backward": 4, "eval_sorted": 5, "ray_volume_backward": 6, "bin_points": 7}
 VOLUME_STOP_DEPTH = 4.5   # the volume walk ends after the first cell exiting deeper than this
 ROOT_SAVED = 12
 ROOT_SMOOTH, ROOT_FACE, ROOT_GRAZING = 0, 1, 2   # kind of a ray-root hit, saved[:, 10]
@@ -106,6 +106,8 @@ def lib() -> ctypes.CDLL:
     L.fc2t2_ray_root.argtypes = [vp, vp, vp, vp, dbl, dbl, i64, dbl, vp, vp, vp, vp, vp]
     L.fc2t2_ray_root_at.restype = i32
     L.fc2t2_ray_root_at.argtypes = [vp, vp, vp, vp, dbl, dbl, i64, vp, vp, vp, vp, vp, vp]
+    L.fc2t2_bin_points.restype = i32
+    L.fc2t2_bin_points.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
     L.fc2t2_ray_volume.restype = i32
     L.fc2t2_ray_volume.argtypes = [vp, vp, vp, vp, dbl, dbl, i64, vp, vp, vp, vp]
     L.fc2t2_ray_volume_backward.restype = i32
@@ -385,6 +387,26 @@ class Plan:
         _check(lib().fc2t2_ray_integral_backward(self.handle, _ptr(o), _ptr(r), float(t0), float(t1), R,
                                                  _ptr(gy), _ptr(gL), _ptr(ws), ws.numel(), _stream()),
                "fc2t2_ray_integral_backward")
+
+    def bin_points(self, x, extra=None, with_payload: bool = False):
+        """Stable sort of points by finest cell: (keys_sorted [N], perm [N], starts [G + 1]) as
+        int32 views of the library's uint32 outputs, plus the sorted payload with with_payload
+        (coordinates [N, dim], or [N, dim + 1] with extra [N] appended)."""
+        N = x.shape[0]
+        x = self._t(x, (N, self.dim), "x")
+        if extra is not None:
+            extra = self._t(extra, (N,), "extra")
+            with_payload = True
+        keys = torch.empty(N, dtype=torch.int32, device=self.device)
+        perm = torch.empty(N, dtype=torch.int32, device=self.device)
+        starts = torch.empty(self.n ** self.dim + 1, dtype=torch.int32, device=self.device)
+        pay = None
+        if with_payload:
+            pay = torch.empty((N, self.dim + (1 if extra is not None else 0)), dtype=self.dtype, device=self.device)
+        ws = self.workspace("bin_points", N)
+        _check(lib().fc2t2_bin_points(self.handle, _ptr(x), N, _ptr(extra), _ptr(keys), _ptr(perm), _ptr(starts),
+                                      _ptr(pay), _ptr(ws), ws.numel(), _stream()), "fc2t2_bin_points")
+        return (keys, perm, starts, pay) if with_payload else (keys, perm, starts)
 
     @staticmethod
     def _bg(bg):

@@ -256,10 +256,12 @@ def key_passes(G: int) -> int:
 
 def sort_bytes(count: int, dim: int, G: int, payload_words: int, itemsize: int = 4) -> int:
     """Algorithmic bytes of one sort of `count` points by cell: the cell key computed from the
-    coordinates (read d coordinates, write one key), every radix pass reading and writing key,
-    index and the carried payload words, and the cell starts written."""
-    per_pass = 2 * (8 + 4 * payload_words)
-    return count * (dim * itemsize + 4) + key_passes(G) * count * per_pass + (G + 1) * 4
+    coordinates (read d coordinates, write one key), every radix pass reading and writing key and
+    index, the payload words read once and written once in sorted order (the last pass gathers
+    them by original index), and the cell starts written."""
+    per_pass = 2 * 8
+    return (count * (dim * itemsize + 4) + key_passes(G) * count * per_pass + 2 * 4 * payload_words * count
+            + (G + 1) * 4)
 
 
 def pyramid_rows(dim: int, n: int) -> list:

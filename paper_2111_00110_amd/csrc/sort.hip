@@ -23,7 +23,7 @@ struct SweepShape {
   static constexpr int kWaveRun = kItems * kWave;
   static constexpr int kTile = kThreads * kItems;
 };
-constexpr int kHistBlocks = 512;  // histogram blocks; each writes its own counts (no atomics)
+constexpr int kHistBlocks = 2048;  // at most this many histogram blocks; each writes its own counts
 // Tile status words: value in the low 30 bits, flag in the top two (0 = not yet published,
 // 1 = the tile's own counts, 2 = counts of all tiles up to and including this one).
 constexpr uint32_t kFlagAgg = 1u << 30;
@@ -136,7 +136,7 @@ __device__ __forceinline__ void store_status(uint32_t* p, uint32_t v) {
 // false: pa, pb indexed by input position) or fetched at write time by the item's original
 // index (GATHER true, the last pass: pa, pb are the unsorted inputs and vals carry the original
 // indices), so that earlier passes move only keys and indices.
-template <int PW, bool GATHER = false>
+template <int PW, bool GATHER = false, int NA = PW>
 __global__ void __launch_bounds__(kThreads) onesweep_kernel(const uint32_t* __restrict__ keys_in,
                                                             const uint32_t* __restrict__ vals_in, uint32_t N,
                                                             int shift, const uint32_t* __restrict__ ghist,
@@ -276,6 +276,48 @@ __global__ void __launch_bounds__(kThreads) onesweep_kernel(const uint32_t* __re
   }
   __syncthreads();
   const uint32_t count = (N - tile0) < (uint32_t)kTile ? (N - tile0) : (uint32_t)kTile;
+  if constexpr (GATHER && PW > 0) {
+    // every item's position and original index first, then all of the thread's gathers in
+    // flight together, then the writes.  v is an original index (< N) unless an earlier pass
+    // failed (err set): the indices are then not a permutation, and the gather must not follow
+    // them out of the inputs.
+    constexpr int NB = PW - NA;
+    uint32_t pos[kItems], v[kItems], kk[kItems], pv[kItems][PW];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const uint32_t t = (uint32_t)j * kThreads + tid;
+      pos[j] = N;
+      v[j] = N;
+      kk[j] = 0u;
+      if (t < count) {
+        kk[j] = s_key[t];
+        const uint32_t digit = (kk[j] >> shift) & (kBins - 1);
+        pos[j] = s_gbase[digit] + (t - s_excl[digit]);
+        v[j] = s_val[t];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const bool in = v[j] < N;
+      const size_t vi = in ? v[j] : 0u;
+#pragma unroll
+      for (int w = 0; w < NA; ++w) pv[j][w] = pa[vi * NA + w];
+#pragma unroll
+      for (int w = 0; w < NB; ++w) pv[j][NA + w] = pb[vi * NB + w];
+      if (!in)
+#pragma unroll
+        for (int w = 0; w < PW; ++w) pv[j][w] = 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      if (pos[j] >= N) continue;   // past the tile's end, or after a failed look-back (err set)
+      keys_out[pos[j]] = kk[j];
+      vals_out[pos[j]] = v[j];
+#pragma unroll
+      for (int w = 0; w < PW; ++w) pay_out[(size_t)pos[j] * PW + w] = pv[j][w];
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     const uint32_t t = (uint32_t)j * kThreads + tid;
@@ -284,18 +326,9 @@ __global__ void __launch_bounds__(kThreads) onesweep_kernel(const uint32_t* __re
     const uint32_t digit = (k >> shift) & (kBins - 1);
     const uint32_t pos = s_gbase[digit] + (t - s_excl[digit]);
     if (pos >= N) continue;   // only after a failed look-back (err set)
-    const uint32_t v = s_val[t];
     keys_out[pos] = k;
-    vals_out[pos] = v;
-    if constexpr (GATHER && PW > 0) {
-      // v is an original index (< N) unless an earlier pass failed (err set): its indices are
-      // then not a permutation, and the gather must not follow them out of the inputs
-      const bool in = v < N;
-      const int nb = PW - na;
-#pragma unroll
-      for (int w = 0; w < PW; ++w)
-        pay_out[(size_t)pos * PW + w] = !in ? 0u : (w < na ? pa[(size_t)v * na + w] : pb[(size_t)v * nb + (w - na)]);
-    } else if constexpr (PW > 0) {
+    vals_out[pos] = s_val[t];
+    if constexpr (PW > 0) {
 #pragma unroll
       for (int w = 0; w < PW; ++w) pay_out[(size_t)pos * PW + w] = s_pay[w * kTile + t];
     }
@@ -341,7 +374,14 @@ struct SortScratch {
   uint32_t *ktmp, *vtmp, *part, *ghist, *status, *err;
   uint32_t max_tiles;
 };
-constexpr int kPartWords = kHistBlocks * kMaxPasses * kBins;
+// Histogram blocks for N keys and `words` status words to clear: about 8 items per thread, so
+// that a streaming read of 10^7 keys keeps enough loads in flight on every CU.
+int hist_blocks(int64_t N, int64_t words) {
+  const int64_t work = N > words ? N : words;
+  return (int)std::min<int64_t>(std::max<int64_t>(ceil_div(work, kThreads * 8), 1), kHistBlocks);
+}
+int64_t max_status_words(int64_t N) { return (int64_t)kMaxPasses * ceil_div(N > 0 ? N : 1, kTileMin) * kBins; }
+int64_t part_words(int64_t N) { return (int64_t)hist_blocks(N, max_status_words(N)) * kMaxPasses * kBins; }
 
 SortScratch carve_scratch(void* scratch, int64_t N) {
   SortScratch c;
@@ -352,7 +392,7 @@ SortScratch carve_scratch(void* scratch, int64_t N) {
   c.vtmp = (uint32_t*)p;
   p += align256((size_t)N * 4);
   c.part = (uint32_t*)p;                  // per histogram block: kMaxPasses x kBins counts
-  p += align256((size_t)kPartWords * 4);
+  p += align256((size_t)part_words(N) * 4);
   c.ghist = (uint32_t*)p;                 // kSlices x kMaxPasses x kBins partial totals, then err
   c.err = c.ghist + kSlices * kMaxPasses * kBins;
   p += align256((kSlices * kMaxPasses * kBins + 1) * 4);
@@ -362,7 +402,7 @@ SortScratch carve_scratch(void* scratch, int64_t N) {
 
 // Passes of 8 bits; with a payload (PW > 0) the passes before the last move keys and indices
 // only, and the last gathers each item's payload from the inputs by its original index.
-template <int PW>
+template <int PW, int NA = PW>
 fc2t2_status onesweep_passes(const uint32_t* keys_in, uint32_t* keys_out, uint32_t* vals_out, uint32_t N,
                              int npass, const SortScratch& c, const uint32_t* pa, int na, const uint32_t* pb,
                              uint32_t* pay_out, hipStream_t s) {
@@ -375,7 +415,7 @@ fc2t2_status onesweep_passes(const uint32_t* keys_in, uint32_t* keys_out, uint32
     uint32_t* vout = to_out ? vals_out : c.vtmp;
     const uint32_t tiles = (uint32_t)ceil_div(N, SweepShape<0>::kTile);
     if (PW > 0 && last)
-      hipLaunchKernelGGL((onesweep_kernel<PW, true>), dim3(tiles), dim3(kThreads), 0, s, kin, vin, N, 8 * pass,
+      hipLaunchKernelGGL((onesweep_kernel<PW, true, NA>), dim3(tiles), dim3(kThreads), 0, s, kin, vin, N, 8 * pass,
                          c.ghist + pass * kBins, c.status + (size_t)pass * c.max_tiles * kBins, kout, vout, c.err,
                          pa, na, pb, pay_out, g_max_spins, g_withhold_tile);
     else
@@ -395,8 +435,7 @@ fc2t2_status sort_prologue(const T* x, T lo, T scale, int n, uint32_t* keys, uin
                            unsigned long long* ood,
                            const SortScratch& c, hipStream_t s) {
   const uint32_t status_words = (uint32_t)npass * c.max_tiles * kBins;
-  const int64_t work = (int64_t)N > (int64_t)status_words ? (int64_t)N : (int64_t)status_words;
-  const int blocks = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(work, kThreads * 8), 1), kHistBlocks);
+  const int blocks = hist_blocks(N, status_words);
   hipLaunchKernelGGL((sort_hist_kernel<T, D>), dim3(blocks), dim3(kThreads), 0, s, x, lo, scale, n, keys, N, npass,
                      c.part, c.status, status_words, ood);
   FC2T2_LAUNCH_CHECK();
@@ -412,7 +451,7 @@ namespace fc2t2 {
 
 size_t radix_sort_scratch_bytes(int64_t N) {
   const int64_t tiles = ceil_div(N > 0 ? N : 1, kTileMin);
-  return align256((size_t)N * 4) * 2 + align256((size_t)kPartWords * 4) +
+  return align256((size_t)N * 4) * 2 + align256((size_t)part_words(N) * 4) +
          align256((kSlices * kMaxPasses * kBins + 1) * 4) +
          align256((size_t)kMaxPasses * tiles * kBins * 4);
 }
@@ -457,9 +496,9 @@ fc2t2_status sort_points_by_cell(const fc2t2_plan_s* pl, const void* x, int64_t 
                                                (uint32_t*)pay_out, s)
                           : onesweep_passes<3>(keys, keys_out, vals_out, (uint32_t)N, npass, c, pa, 3, nullptr,
                                                (uint32_t*)pay_out, s);
-    return pl->dim == 2 ? onesweep_passes<3>(keys, keys_out, vals_out, (uint32_t)N, npass, c, pa, 2, pb,
+    return pl->dim == 2 ? onesweep_passes<3, 2>(keys, keys_out, vals_out, (uint32_t)N, npass, c, pa, 2, pb,
                                              (uint32_t*)pay_out, s)
-                        : onesweep_passes<4>(keys, keys_out, vals_out, (uint32_t)N, npass, c, pa, 3, pb,
+                        : onesweep_passes<4, 3>(keys, keys_out, vals_out, (uint32_t)N, npass, c, pa, 3, pb,
                                              (uint32_t*)pay_out, s);
   }
   return onesweep_passes<0>(keys, keys_out, vals_out, (uint32_t)N, npass, c, nullptr, 0, nullptr, nullptr, s);

@@ -1,9 +1,9 @@
 """Binning and the stable sort by cell (section 3.3), through fc2t2_bin_points, bit-exact
 against numpy: the cell of each point (the integer part of its scaled coordinates in the IO
 precision, clamped to the grid), a stable argsort of the cell indices, the cell starts, and
-the payload carried through the sort.  Grids from 2^4 to 2^21 cells cover one pass and two
-and three passes of 8-bit digits and two passes of 9-bit digits; sizes from one point to
-several hundred tiles with a ragged last tile."""
+the payload carried through the sort.  Grids from 2^4 to 2^21 cells cover one, two and three
+passes of 8-bit digits; sizes from one point to several hundred tiles with a ragged last
+tile."""
 import numpy as np
 import pytest
 

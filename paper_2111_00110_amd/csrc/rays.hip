@@ -188,11 +188,11 @@ __device__ __forceinline__ double peval(const double (&c)[6], double x) {
 }
 
 template <int DEG>
-__device__ double solve_monotone(const double (&c)[6], double lo, double hi, double flo) {
+__device__ double solve_monotone(const double (&c)[6], double lo, double hi, double flo, double x0 = -1.0) {
   double dc[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int m = 0; m < DEG; ++m) dc[m] = (m + 1) * c[m + 1];
-  double x = 0.5 * (lo + hi);
+  double x = (x0 > lo && x0 < hi) ? x0 : 0.5 * (lo + hi);
   for (int it = 0; it < 200; ++it) {
     const double fx = peval<DEG>(c, x);
     if (fx == 0.0) return x;
@@ -247,6 +247,178 @@ __device__ int real_roots(const double (&c)[6], double a, double b, double (&out
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// Closed-form roots for degree <= 4 (section 5.1: the paper finds the roots of a box's quartic
+// with Ferrari's method): the quadratic formula in its cancellation-free form, Cardano's
+// formula for the cubic (trigonometric form when all three roots are real), and Ferrari's
+// reduction of the quartic to two quadratics through a positive root of its resolvent cubic.
+// Every real root is polished by three Newton steps on the original polynomial.  A leading
+// coefficient below 1e-8 of the largest other one is dropped first (on [0, 1] its term moves a
+// root of the rest by a relative 1e-8 at most, which the polish removes).  The closed forms are
+// used only where they are well conditioned on [0, 1]: a leading coefficient between 1e-8 and
+// 1e-2 of the largest other one (the roots that matter would sit behind the cancellation of
+// huge normalised coefficients), or a polished root that does not zero the polynomial to
+// 1e-9 of its coefficient sum, makes the caller use the derivative cascade instead.
+template <int DEG>
+__device__ __forceinline__ void newton_polish(const double (&c)[6], double& x) {
+#pragma unroll
+  for (int it = 0; it < 3; ++it) {
+    double v = c[DEG], d = 0.0;
+#pragma unroll
+    for (int m = DEG - 1; m >= 0; --m) { d = d * x + v; v = v * x + c[m]; }
+    if (d != 0.0) {
+      const double xn = x - v / d;
+      if (isfinite(xn)) x = xn;
+    }
+  }
+}
+
+// Real roots of x^2 + b x + c (appended to r at n).
+__device__ __forceinline__ void quad_roots(double b, double c, double* r, int& n) {
+  const double disc = b * b - 4.0 * c;
+  if (disc < 0.0) return;
+  const double q = -0.5 * (b + copysign(sqrt(disc), b));
+  if (q != 0.0) {
+    r[n++] = q;
+    r[n++] = c / q;
+  } else {
+    r[n++] = 0.0;   // b = c = 0
+  }
+}
+
+// Real roots of x^3 + a x^2 + b x + c; returns the count, the largest first when all are real.
+__device__ __forceinline__ int cubic_roots(double a, double b, double c, double* r) {
+  const double a3 = a / 3.0;
+  const double p = b - a * a3, q = (2.0 * a3 * a3 - b) * a3 + c;   // t^3 + p t + q, x = t - a/3
+  const double hq = 0.5 * q, tp = p / 3.0;
+  const double disc = hq * hq + tp * tp * tp;
+  if (disc > 0.0) {
+    // one real root: t = u - tp / u with u^3 = -q/2 - sign(q) sqrt(disc) (no cancellation)
+    const double u = cbrt(-hq - copysign(sqrt(disc), hq));
+    r[0] = (u != 0.0 ? u - tp / u : 0.0) - a3;
+    return 1;
+  }
+  if (tp == 0.0) {   // p = q = 0: a triple root
+    r[0] = -a3;
+    return 1;
+  }
+  const double m = sqrt(-tp);
+  const double arg = fmin(1.0, fmax(-1.0, -hq / (m * m * m)));
+  const double phi = acos(arg) / 3.0;
+  const double two_pi_3 = 2.0943951023931954923;
+  r[0] = 2.0 * m * cos(phi) - a3;
+  r[1] = 2.0 * m * cos(phi - two_pi_3) - a3;
+  r[2] = 2.0 * m * cos(phi + two_pi_3) - a3;
+  return 3;
+}
+
+// All real roots of the polynomial c of degree <= DEG (DEG <= 4), unsorted, unpolished; -1 where
+// the closed forms are not well conditioned.
+template <int DEG>
+__device__ int closed_form_roots_raw(const double (&c)[6], double (&r)[4]) {
+  static_assert(DEG <= 4, "closed forms exist up to degree 4");
+  if constexpr (DEG <= 0) {
+    return 0;
+  } else {
+    double big = 0.0;
+#pragma unroll
+    for (int m = 0; m < DEG; ++m) big = fmax(big, fabs(c[m]));
+    if (!(fabs(c[DEG]) > 1e-8 * big)) return closed_form_roots_raw<DEG - 1>(c, r);
+    if (!(fabs(c[DEG]) >= 1e-2 * big)) return -1;
+    int n = 0;
+    const double inv = 1.0 / c[DEG];
+    if constexpr (DEG == 1) {
+      r[n++] = -c[0] * inv;
+    } else if constexpr (DEG == 2) {
+      quad_roots(c[1] * inv, c[0] * inv, r, n);
+    } else if constexpr (DEG == 3) {
+      n = cubic_roots(c[2] * inv, c[1] * inv, c[0] * inv, r);
+    } else {
+      // Ferrari: x = y - a/4 gives y^4 + p y^2 + q y + s
+      const double a = c[3] * inv, b = c[2] * inv, cc = c[1] * inv, d = c[0] * inv;
+      const double a4 = 0.25 * a, aa = a4 * a4;
+      const double p = b - 6.0 * aa;
+      const double q = cc - 2.0 * b * a4 + 8.0 * aa * a4;
+      const double sq = d - cc * a4 + b * aa - 3.0 * aa * aa;
+      if (fabs(q) <= 1e-14 * (fabs(p) * fabs(p) + fabs(sq) + 1e-300)) {
+        // biquadratic: y^2 = z with z^2 + p z + s = 0
+        double z[2];
+        int nz = 0;
+        quad_roots(p, sq, z, nz);
+        for (int i = 0; i < nz; ++i)
+          if (z[i] >= 0.0) {
+            const double y = sqrt(z[i]);
+            r[n++] = y - a4;
+            if (n < 4 && y != 0.0) r[n++] = -y - a4;
+          }
+      } else {
+        // resolvent 8 m^3 + 8 p m^2 + (2 p^2 - 8 s) m - q^2 = 0 has a root m > 0 (its largest)
+        double mr[3];
+        const int nm = cubic_roots(p, 0.25 * p * p - sq, -0.125 * q * q, mr);
+        double m = mr[0];
+        for (int i = 1; i < nm; ++i) m = fmax(m, mr[i]);
+        if (m > 0.0) {
+          // y^4 + p y^2 + q y + s = (y^2 + p/2 + m)^2 - (w y - q / (2 w))^2 with w = sqrt(2 m)
+          const double w = sqrt(2.0 * m);
+          const double h0 = 0.5 * p + m, h1 = 0.5 * q / w;
+          double y[4];
+          int ny = 0;
+          quad_roots(w, h0 - h1, y, ny);
+          quad_roots(-w, h0 + h1, y, ny);
+          for (int i = 0; i < ny; ++i) r[n++] = y[i] - a4;
+        }
+      }
+    }
+    return n;
+  }
+}
+
+// The same, each root polished by Newton steps on the full polynomial; -1 where the closed
+// forms are not well conditioned or a polished root fails the residual check.
+template <int DEG>
+__device__ int closed_form_roots(const double (&c)[6], double (&r)[4]) {
+  const int n = closed_form_roots_raw<DEG>(c, r);
+  double sum = 0.0;
+#pragma unroll
+  for (int m = 0; m <= DEG; ++m) sum += fabs(c[m]);
+  for (int i = 0; i < n; ++i) {
+    newton_polish<DEG>(c, r[i]);
+    if (!(fabs(peval<DEG>(c, r[i])) <= 1e-9 * sum)) return -1;
+  }
+  return n;
+}
+
+// Real roots of c (degree <= DEG <= 4) strictly inside (a, b), ascending: the split points of
+// [a, b] into monotone pieces when c is a derivative.
+// Where the closed forms are not usable, or miss a sign change (an odd number of sign-changing
+// roots is needed when c changes sign over [a, b]), the derivative cascade answers.
+template <int DEG>
+__device__ int interior_roots_cf(const double (&c)[6], double a, double b, double (&out)[5]) {
+  double r[4];
+  const int n = closed_form_roots<DEG>(c, r);
+  if (n < 0) return real_roots<DEG>(c, a, b, out);
+  int cnt = 0;
+  for (int i = 0; i < n; ++i)
+    if (r[i] > a && r[i] < b) {
+      // insertion into the ascending list
+      int j = cnt++;
+      while (j > 0 && out[j - 1] > r[i]) { out[j] = out[j - 1]; --j; }
+      out[j] = r[i];
+    }
+  const double ca = peval<DEG>(c, a), cb = peval<DEG>(c, b);
+  if ((ca < 0.0 && cb > 0.0) || (ca > 0.0 && cb < 0.0)) {
+    // an odd number of sign changes inside: count the found roots that change sign
+    int changes = 0;
+    for (int i = 0; i < cnt; ++i) {
+      const double lo = 0.5 * ((i > 0 ? out[i - 1] : a) + out[i]);
+      const double hi = 0.5 * (out[i] + (i + 1 < cnt ? out[i + 1] : b));
+      if ((peval<DEG>(c, lo) < 0.0) != (peval<DEG>(c, hi) < 0.0)) ++changes;
+    }
+    if ((changes & 1) == 0) return real_roots<DEG>(c, a, b, out);
+  }
+  return cnt;
+}
+
 // Upper bound of the polynomial a on [0, s]: a_0 + sum_{m >= 1} max(0, a_m) s^m.
 template <int K>
 __device__ __forceinline__ double upper_bound(const double (&a)[6], double s) {
@@ -258,28 +430,42 @@ __device__ __forceinline__ double upper_bound(const double (&a)[6], double s) {
 
 // Called only for the few segments the bounds cannot rule out: kept out of line so that the
 // root cascade does not raise the register pressure of the traversal loop.
+// With closed_form (K <= 4) the critical points come from the closed forms, else from the
+// derivative cascade.
 template <class S>
-__device__ __noinline__ double seg_max(const double (&a)[6], double s) {
+__device__ __noinline__ double seg_max(const double (&a)[6], double s, int closed_form) {
   constexpr int K = S::K;
   double best = fmax(peval<K>(a, 0.0), peval<K>(a, s));
   double da[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int m = 0; m < K; ++m) da[m] = (m + 1) * a[m + 1];
   double crit[5];
-  const int nc = real_roots<K - 1>(da, 0.0, s, crit);
+  int nc;
+  if constexpr (K <= 4) {
+    nc = closed_form ? interior_roots_cf<K - 1>(da, 0.0, s, crit) : real_roots<K - 1>(da, 0.0, s, crit);
+  } else {
+    nc = real_roots<K - 1>(da, 0.0, s, crit);
+  }
   for (int i = 0; i < nc; ++i) best = fmax(best, peval<K>(a, crit[i]));
   return best;
 }
 
 // First v in (0, s] where g = a - tau goes from < 0 to >= 0 on a monotone piece; -1 if none.
+// With closed_form (K <= 4): critical points and the root on the piece from the closed forms
+// (the piece's root, polished, starts the safeguarded Newton iteration, which then ends at once).
 template <class S>
-__device__ __noinline__ double first_upward(const double (&g)[6], double s) {
+__device__ __noinline__ double first_upward(const double (&g)[6], double s, int closed_form) {
   constexpr int K = S::K;
   double dg[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int m = 0; m < K; ++m) dg[m] = (m + 1) * g[m + 1];
   double crit[5];
-  const int nc = real_roots<K - 1>(dg, 0.0, s, crit);
+  int nc;
+  if constexpr (K <= 4) {
+    nc = closed_form ? interior_roots_cf<K - 1>(dg, 0.0, s, crit) : real_roots<K - 1>(dg, 0.0, s, crit);
+  } else {
+    nc = real_roots<K - 1>(dg, 0.0, s, crit);
+  }
   double pts[7];
   int np = 0;
   pts[np++] = 0.0;
@@ -291,6 +477,14 @@ __device__ __noinline__ double first_upward(const double (&g)[6], double s) {
     const double f1 = peval<K>(g, pts[i + 1]);
     if (f0 < 0.0 && f1 >= 0.0) {
       if (f1 == 0.0) return pts[i + 1];
+      if constexpr (K <= 4) {
+        if (closed_form) {
+          double r[4];
+          const int n = closed_form_roots<K>(g, r);
+          for (int k = 0; k < n; ++k)   // (n = -1: no candidate; the bracketed iteration alone)
+            if (r[k] > pts[i] && r[k] < pts[i + 1]) return solve_monotone<K>(g, pts[i], pts[i + 1], f0, r[k]);
+        }
+      }
       return solve_monotone<K>(g, pts[i], pts[i + 1], f0);
     }
     f0 = f1;
@@ -327,6 +521,9 @@ __device__ __forceinline__ void root_gradients(const T* __restrict__ row_ptr, co
 }
 
 constexpr int kRootSub = 8;
+// Root finding for K <= 4: closed forms (1, the default) or the derivative cascade (0, a test
+// aid set by fc2t2_debug_root_cascade, so that the two can be compared on the same rays).
+int g_root_closed_form = 1;
 constexpr int kRootSmooth = FC2T2_ROOT_SMOOTH, kRootFace = FC2T2_ROOT_FACE, kRootGrazing = FC2T2_ROOT_GRAZING;
 
 // Bounds of each finest cell's polynomial over the whole cell: with u in [-1/2, 1/2]^3,
@@ -362,7 +559,7 @@ __global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, c
                                                       int32_t* __restrict__ hit, T* __restrict__ saved,
                                                       const float2* __restrict__ bounds,
                                                       unsigned long long* __restrict__ grazing,
-                                                      const T* __restrict__ tau_in) {
+                                                      const T* __restrict__ tau_in, int closed_form) {
   constexpr int P = S::P, Ppad = S::Ppad, K = S::K, SUB = kRootSub;
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t ray = gtid / SUB;
@@ -430,7 +627,7 @@ __global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, c
       double a[6];
       segment_poly<S>(row, d, q, tb - ta, a);
       // the exact segment maximum only matters when the segment can beat the best so far
-      if (upper_bound<K>(a, 1.0) > fmax_v) fmax_v = fmax(fmax_v, seg_max<S>(a, 1.0));
+      if (upper_bound<K>(a, 1.0) > fmax_v) fmax_v = fmax(fmax_v, seg_max<S>(a, 1.0, closed_form));
     }
   }
 #pragma unroll
@@ -493,7 +690,7 @@ __global__ void __launch_bounds__(64) ray_root_kernel(const T* __restrict__ L, c
         ev_face = true;
       }
       if (!found) {
-        const double v = upper_bound<K>(g, 1.0) < 0.0 ? -1.0 : first_upward<S>(g, 1.0);
+        const double v = upper_bound<K>(g, 1.0) < 0.0 ? -1.0 : first_upward<S>(g, 1.0, closed_form);
         if (v >= 0.0) {
           t_ev = ta + sl * v;
           ev_cell = cell;
@@ -736,12 +933,14 @@ fc2t2_status launch_ray_root(const fc2t2_plan_s* pl, const void* L, const void* 
         hipLaunchKernelGGL((cell_bounds_kernel<S, double>), bgrid, dim3(256), 0, s, (const double*)L, pl->G, bounds);
         hipLaunchKernelGGL((ray_root_kernel<S, double>), grid, dim3(64), 0, s, (const double*)L, (const double*)o,
                            (const double*)r, R, t0, t1, pl->lo, pl->hi, pl->h0, pl->n, frac, (double*)t,
-                           (double*)normal, hit, (double*)saved, bounds, pl->grazing, (const double*)tau_in);
+                           (double*)normal, hit, (double*)saved, bounds, pl->grazing, (const double*)tau_in,
+                           g_root_closed_form);
       } else {
         hipLaunchKernelGGL((cell_bounds_kernel<S, float>), bgrid, dim3(256), 0, s, (const float*)L, pl->G, bounds);
         hipLaunchKernelGGL((ray_root_kernel<S, float>), grid, dim3(64), 0, s, (const float*)L, (const float*)o,
                            (const float*)r, R, t0, t1, pl->lo, pl->hi, pl->h0, pl->n, frac, (float*)t,
-                           (float*)normal, hit, (float*)saved, bounds, pl->grazing, (const float*)tau_in);
+                           (float*)normal, hit, (float*)saved, bounds, pl->grazing, (const float*)tau_in,
+                           g_root_closed_form);
       }
       st = FC2T2_OK;
     }
@@ -801,6 +1000,8 @@ fc2t2_status ray_root_backward(const fc2t2_plan_s* pl, const void* saved, const 
 }  // namespace fc2t2
 
 extern "C" {
+
+void fc2t2_debug_root_cascade(int enable) { g_root_closed_form = enable ? 0 : 1; }
 
 static bool bad_rays(int64_t R) { return R < 0 || R > 0x7FFFFFFFll; }
 

@@ -78,6 +78,8 @@ def lib() -> ctypes.CDLL:
     L.fc2t2_sort_failures.argtypes = [vp, ctypes.POINTER(i64), i32, vp]
     L.fc2t2_debug_sort_fault.restype = None
     L.fc2t2_debug_sort_fault.argtypes = [i32]
+    L.fc2t2_debug_root_cascade.restype = None
+    L.fc2t2_debug_root_cascade.argtypes = [i32]
     L.fc2t2_local_numel.restype = sz
     L.fc2t2_local_numel.argtypes = [vp]
     L.fc2t2_workspace_size.restype = sz

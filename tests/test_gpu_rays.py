@@ -115,6 +115,32 @@ def test_ray_root_stage(F, io, K, n):
     assert rel(gL.cpu().numpy(), scaled_cotangent(geo, G, plan.P_pad)) < (1e-8 if io == "f64" else 1e-4)
 
 
+@pytest.mark.parametrize("io,K", [("f64", 4), ("f64", 3), ("f32", 4), ("f64", 2)])
+def test_ray_root_closed_forms_match_the_cascade(F, io, K):
+    """For K <= 4 the roots come from the closed forms (Ferrari, Cardano, the quadratic formula;
+    section 5.1).  On the same rays the derivative cascade gives the same hits and levels and
+    the same roots to rounding, and the closed-form hits match the checker's."""
+    wl = _wl(n=16, K=K, io=io, R=256, sigma=0.08)
+    x = W.make(wl, seed=31)
+    plan = _plan(F, wl)
+    geo, Lt, Lphys = _shared_locals(wl, x, plan)
+    o, r, L = _dev(x["o"]), _dev(x["r"]), _dev(Lt)
+    t1, n1, h1, s1 = (a.cpu().numpy() for a in plan.ray_root(L, o, r, 0.0, 4.0, 0.5))
+    F.lib().fc2t2_debug_root_cascade(1)
+    try:
+        t2, n2, h2, s2 = (a.cpu().numpy() for a in plan.ray_root(L, o, r, 0.0, 4.0, 0.5))
+    finally:
+        F.lib().fc2t2_debug_root_cascade(0)
+    assert np.array_equal(h1, h2) and h1.sum() > 0.8 * len(h1)
+    h = h1 == 1
+    tol = 1e-10 if io == "f64" else 1e-6
+    assert np.max(np.abs(t1[h] - t2[h])) < tol
+    assert np.max(np.abs(s1[:, 8] - s2[:, 8]) / np.abs(s2[:, 8])) < (1e-12 if io == "f64" else 1e-6)
+    ref = rays.ray_root(geo, Lphys, x["o"], x["r"], 0.0, 4.0)
+    assert np.array_equal(h1, ref["hit"])
+    assert np.max(np.abs(t1[h] - ref["t"][h])) < tol
+
+
 def test_ray_root_end_to_end(F):
     """Expansion + ray root + IFT backward through the autograd wrapper against the checker.
     The cotangents are zeroed on the few rays where the two sides disagree on the hit or its

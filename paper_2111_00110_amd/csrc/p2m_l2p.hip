@@ -109,6 +109,26 @@ struct QueryMonomialsGrad {
 // record r (sorted position) holds the coordinates (pay [M][D]); its input index perm[r] gives
 // the cotangent gy and where q_bar goes.  Each query is one record, so the gq writes do not
 // collide.
+// q_bar of one query, written (or added) as one vector access of D floats: the queries are
+// visited in cell order, so these are scattered, and one request per query instead of D.
+template <int D>
+struct alignas(4) FloatD {
+  float v[D];
+};
+template <int D>
+__device__ __forceinline__ void store_qgrad(float* __restrict__ dst, float s, const float (&g)[3], int accumulate) {
+  FloatD<D> o;
+#pragma unroll
+  for (int j = 0; j < D; ++j) o.v[j] = s * g[j];
+  FloatD<D>* p = reinterpret_cast<FloatD<D>*>(dst);
+  if (accumulate) {
+    const FloatD<D> old = *p;
+#pragma unroll
+    for (int j = 0; j < D; ++j) o.v[j] += old.v[j];
+  }
+  *p = o;
+}
+
 template <class S>
 struct SortedQueryGrad {
   const float* __restrict__ pay;
@@ -134,11 +154,7 @@ struct SortedQueryGrad {
       load_row<S::Ppad>(L + cell * S::Ppad, row);
       float val, g[3], hs[6];
       eval_poly<S, float, true, false>(row, pw, val, g, hs);
-#pragma unroll
-      for (int j = 0; j < D; ++j) {
-        const float gj = a * g[j] * inv_h;
-        gq[(int64_t)i * D + j] = accumulate ? gq[(int64_t)i * D + j] + gj : gj;
-      }
+      store_qgrad<D>(gq + (int64_t)i * D, a * inv_h, g, accumulate);
     }
     monomials<S>(u, v);
 #pragma unroll
@@ -253,8 +269,7 @@ __global__ void __launch_bounds__(256) qgrad_sorted_kernel(const float* __restri
   eval_poly<S, float, true, false>(c, pw, val, g, hs);
   const float a = rec[D];
   const int64_t i = perm[r];
-#pragma unroll
-  for (int j = 0; j < D; ++j) gq[i * D + j] = accumulate ? gq[i * D + j] + a * g[j] * inv_h : a * g[j] * inv_h;
+  store_qgrad<D>(gq + (int64_t)i * D, a * inv_h, g, accumulate);
 }
 
 // L2P over the queries in sorted order (FP32, one channel): record r holds the query's

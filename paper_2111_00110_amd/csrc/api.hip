@@ -31,17 +31,18 @@ SortBufs carve_sort(Carve& c, const fc2t2_plan_s* pl, int64_t count) {
   b.keys_sorted = c.take<uint32_t>(count);
   b.perm = c.take<uint32_t>(count);
   b.starts = c.take<uint32_t>(pl->G + 1);
-  b.pay = sort_payload_ok(pl) ? (void*)c.take<float>((size_t)count * (pl->dim + 1)) : nullptr;
+  b.pay = sort_payload_ok(pl) ? (void*)c.take<float>((size_t)count * (pl->dim + pl->C)) : nullptr;
   b.scratch = c.take<char>(radix_sort_scratch_bytes(count));
   return b;
 }
 
-// Sorts points by cell; with `extra` (one value per point) and a carved payload buffer, the
-// coordinates and that value are sorted along into b.pay.
+// Sorts points by cell; with `extra` (`words` values per point) and a carved payload buffer, the
+// coordinates and those values are sorted along into b.pay.
 fc2t2_status bin_and_sort(const fc2t2_plan_s* pl, const void* x, int64_t count, const SortBufs& b,
-                          hipStream_t s, const void* extra = nullptr, unsigned long long* ood = nullptr) {
+                          hipStream_t s, const void* extra = nullptr, unsigned long long* ood = nullptr,
+                          int words = 1) {
   fc2t2_status st = sort_points_by_cell(pl, x, count, b.keys, b.keys_sorted, b.perm, b.scratch, s, extra,
-                                        extra ? b.pay : nullptr, ood);
+                                        extra ? b.pay : nullptr, ood, words);
   if (st) return st;
   return launch_cell_starts(b.keys_sorted, count, pl->G, b.starts, s, sort_err_word(b.scratch, count), pl->sort_fail);
 }
@@ -189,7 +190,7 @@ fc2t2_status eval_backward_impl(fc2t2_plan plan, const void* L, const void* q, i
     Carve c(ws);
     SortBufs sb = carve_sort(c, plan, M);
     fc2t2_status st;
-    const bool carry = sb.pay != nullptr;
+    const bool carry = sb.pay != nullptr && plan->C == 1;   // the sorted q_bar pass is one channel
     {
       StageScope t(plan, FC2T2_STAGE_SORT, stream);
       st = bin_and_sort(plan, q, M, sb, stream, carry ? gy : nullptr);
@@ -292,7 +293,7 @@ fc2t2_status fc2t2_expand(fc2t2_plan plan, const void* p, const void* w, int64_t
   const bool carry = sb.pay != nullptr;   // sort the points' data along with the keys
   {
     StageScope t(plan, FC2T2_STAGE_SORT, stream);
-    st = bin_and_sort(plan, p, N, sb, stream, carry ? w : nullptr, plan->ood);
+    st = bin_and_sort(plan, p, N, sb, stream, carry ? w : nullptr, plan->ood, plan->C);
   }
   if (st) return st;
   {
@@ -327,7 +328,7 @@ fc2t2_status fc2t2_bin_points(fc2t2_plan plan, const void* x, int64_t N, const v
   StageScope t(plan, FC2T2_STAGE_SORT, stream);
   if (N > 0) {
     const fc2t2_status st = sort_points_by_cell(plan, x, N, keys, keys_sorted, perm, scratch, stream, extra, pay_out,
-                                                plan->ood);
+                                                plan->ood, 1);
     if (st) return st;
   }
   return launch_cell_starts(keys_sorted, N, plan->G, starts, stream, N > 0 ? sort_err_word(scratch, N) : nullptr,
@@ -338,7 +339,7 @@ fc2t2_status fc2t2_eval_sorted(fc2t2_plan plan, const void* L, const void* q, in
                                size_t ws_bytes, hipStream_t stream) {
   if (!plan || !L || bad_count(M)) return FC2T2_EINVAL;
   if (M > 0 && (!q || !y)) return FC2T2_EINVAL;
-  if (!sort_payload_ok(plan)) return FC2T2_EUNSUPPORTED;
+  if (!sort_payload_ok(plan) || plan->C != 1) return FC2T2_EUNSUPPORTED;
   if (!ws || ws_bytes < ws_eval_sorted(plan, M)) return FC2T2_EWORKSPACE;
   if (M == 0) return FC2T2_OK;
   Carve c(ws);
@@ -363,7 +364,7 @@ fc2t2_status fc2t2_eval_backward_sorted(fc2t2_plan plan, const void* L, int64_t 
   if (!plan || !gL || bad_count(M)) return FC2T2_EINVAL;
   if (M > 0 && !gy) return FC2T2_EINVAL;
   if (gq && !L) return FC2T2_EINVAL;
-  if (!sort_payload_ok(plan)) return FC2T2_EUNSUPPORTED;
+  if (!sort_payload_ok(plan) || plan->C != 1) return FC2T2_EUNSUPPORTED;
   if (!ws || ws_bytes < ws_eval_sorted(plan, M)) return FC2T2_EWORKSPACE;
   if (M == 0) return accumulate ? FC2T2_OK : launch_zero(plan, gL, (int64_t)grid_elems(plan, 0), stream);
   Carve c((void*)ws);

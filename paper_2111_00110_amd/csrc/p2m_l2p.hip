@@ -59,17 +59,17 @@ struct PointMonomials {
 // coordinates and its weight (one channel), indexed by sorted position.
 template <class S, typename T>
 struct SortedMonomials {
-  const T* __restrict__ pay;
+  const T* __restrict__ pay;   // [count][D + C]: coordinates, then the C values
   T inv_h;
-  __device__ __forceinline__ void operator()(uint32_t r, const T (&centre)[3], int, T (&v)[S::P],
+  int C;
+  __device__ __forceinline__ void operator()(uint32_t r, const T (&centre)[3], int ch, T (&v)[S::P],
                                              int64_t) const {
-    constexpr int W = S::D + 1;
-    const T* rec = pay + (size_t)r * W;
+    const T* rec = pay + (size_t)r * (S::D + C);
     T u[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int j = 0; j < S::D; ++j) u[j] = (rec[j] - centre[j]) * inv_h;
     monomials<S>(u, v);
-    const T a = rec[S::D];
+    const T a = rec[S::D + ch];
 #pragma unroll
     for (int k = 0; k < S::P; ++k) v[k] *= a;
   }
@@ -395,11 +395,11 @@ fc2t2_status launch_mark_cells(const fc2t2_plan_s* pl, const void* x, int64_t N,
 
 fc2t2_status launch_reduce_sorted(const fc2t2_plan_s* pl, const void* pay, int64_t count, const uint32_t* starts,
                                   void* out, bool accumulate, hipStream_t s, uint8_t* occ, uint8_t gen) {
-  if (pl->io != FC2T2_IO_F32 || pl->C != 1) return FC2T2_EUNSUPPORTED;
+  if (pl->io != FC2T2_IO_F32 || pl->C > 4) return FC2T2_EUNSUPPORTED;
   fc2t2_status st = FC2T2_EUNSUPPORTED;
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {
     using S = decltype(shape);
-    SortedMonomials<S, float> fn{(const float*)pay, (float)(1.0 / pl->h0)};
+    SortedMonomials<S, float> fn{(const float*)pay, (float)(1.0 / pl->h0), pl->C};
     // sources (the call that records occupancy) may crowd a few cells: let waves take those
     st = occ ? launch_reduce_cells<S, float, decltype(fn), true>(pl, starts, nullptr, count, (float*)out, accumulate,
                                                                   fn, s, occ, gen)

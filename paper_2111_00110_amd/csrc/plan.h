@@ -93,14 +93,15 @@ fc2t2_status radix_sort_pairs(const uint32_t* keys_in, uint32_t* keys_out, uint3
                               int64_t N, int key_bits, void* scratch, hipStream_t s);
 // starts[c] = first sorted position with key >= c, for c in [0, G]; starts[G] = N.
 // The same for points: keys (written to `keys`) are the linear finest-cell indices of x.
-// With pay_out, each point's coordinates and its one value in `extra` travel with it:
-// pay_out [N][dim + 1] receives them in sorted order (FP32, one channel: sort_payload_ok); with
-// pay_out and no `extra`, the coordinates alone: pay_out [N][dim].
+// With pay_out, each point's coordinates and its extra_words (1..4) values in `extra`
+// ([N][extra_words]) travel with it: pay_out [N][dim + extra_words] receives them in sorted order
+// (FP32: sort_payload_ok); with pay_out and no `extra`, the coordinates alone: pay_out [N][dim].
 // With ood, the points outside the domain are added to *ood.
 fc2t2_status sort_points_by_cell(const fc2t2_plan_s* pl, const void* x, int64_t N, uint32_t* keys,
                                  uint32_t* keys_out, uint32_t* vals_out, void* scratch, hipStream_t s,
                                  const void* extra = nullptr, void* pay_out = nullptr,
-                                 unsigned long long* ood = nullptr);
+                                 unsigned long long* ood = nullptr, int extra_words = 1);
+// FP32 points whose sorts can carry their coordinates and up to four values each.
 bool sort_payload_ok(const fc2t2_plan_s* pl);
 // err: the sort's failure word (sort_err_word); when set, every cell comes out empty and
 // *fail_ctr is incremented.
@@ -121,8 +122,8 @@ fc2t2_status launch_p2m(const fc2t2_plan_s* pl, const void* p, const void* w, in
 fc2t2_status launch_l2p_T(const fc2t2_plan_s* pl, const void* q, const void* gy, int64_t M,
                           const uint32_t* starts, const uint32_t* perm, void* gL, hipStream_t s,
                           bool accumulate = true);
-// P2M, or the transpose of L2P, from records sorted with their data (pay [count][dim + 1]:
-// coordinates and weight or cotangent; FP32, one channel).
+// P2M, or the transpose of L2P, from records sorted with their data (pay [count][dim + C]:
+// coordinates and the C weights or cotangents; FP32, C <= 4).
 fc2t2_status launch_reduce_sorted(const fc2t2_plan_s* pl, const void* pay, int64_t count, const uint32_t* starts,
                                   void* out, bool accumulate, hipStream_t s, uint8_t* occ = nullptr,
                                   uint8_t gen = 1);

@@ -469,7 +469,7 @@ fc2t2_status radix_sort_pairs(const uint32_t* keys_in, uint32_t* keys_out, uint3
 
 fc2t2_status sort_points_by_cell(const fc2t2_plan_s* pl, const void* x, int64_t N, uint32_t* keys,
                                  uint32_t* keys_out, uint32_t* vals_out, void* scratch, hipStream_t s,
-                                 const void* extra, void* pay_out, unsigned long long* ood) {
+                                 const void* extra, void* pay_out, unsigned long long* ood, int extra_words) {
   if (N == 0) return FC2T2_OK;
   if (N >= (int64_t)kValMask) return FC2T2_EUNSUPPORTED;
   const int key_bits = key_bits_for(pl->G);
@@ -496,15 +496,30 @@ fc2t2_status sort_points_by_cell(const fc2t2_plan_s* pl, const void* x, int64_t 
                                                (uint32_t*)pay_out, s)
                           : onesweep_passes<3>(keys, keys_out, vals_out, (uint32_t)N, npass, c, pa, 3, nullptr,
                                                (uint32_t*)pay_out, s);
-    return pl->dim == 2 ? onesweep_passes<3, 2>(keys, keys_out, vals_out, (uint32_t)N, npass, c, pa, 2, pb,
-                                             (uint32_t*)pay_out, s)
-                        : onesweep_passes<4, 3>(keys, keys_out, vals_out, (uint32_t)N, npass, c, pa, 3, pb,
-                                             (uint32_t*)pay_out, s);
+    // the coordinates and extra_words values per point: pay_out [N][dim + extra_words]
+    const uint32_t n = (uint32_t)N;
+    uint32_t* po = (uint32_t*)pay_out;
+    if (pl->dim == 2) {
+      switch (extra_words) {
+        case 1: return onesweep_passes<3, 2>(keys, keys_out, vals_out, n, npass, c, pa, 2, pb, po, s);
+        case 2: return onesweep_passes<4, 2>(keys, keys_out, vals_out, n, npass, c, pa, 2, pb, po, s);
+        case 3: return onesweep_passes<5, 2>(keys, keys_out, vals_out, n, npass, c, pa, 2, pb, po, s);
+        case 4: return onesweep_passes<6, 2>(keys, keys_out, vals_out, n, npass, c, pa, 2, pb, po, s);
+      }
+    } else {
+      switch (extra_words) {
+        case 1: return onesweep_passes<4, 3>(keys, keys_out, vals_out, n, npass, c, pa, 3, pb, po, s);
+        case 2: return onesweep_passes<5, 3>(keys, keys_out, vals_out, n, npass, c, pa, 3, pb, po, s);
+        case 3: return onesweep_passes<6, 3>(keys, keys_out, vals_out, n, npass, c, pa, 3, pb, po, s);
+        case 4: return onesweep_passes<7, 3>(keys, keys_out, vals_out, n, npass, c, pa, 3, pb, po, s);
+      }
+    }
+    return FC2T2_EUNSUPPORTED;
   }
   return onesweep_passes<0>(keys, keys_out, vals_out, (uint32_t)N, npass, c, nullptr, 0, nullptr, nullptr, s);
 }
 
-bool sort_payload_ok(const fc2t2_plan_s* pl) { return pl->io == FC2T2_IO_F32 && pl->C == 1; }
+bool sort_payload_ok(const fc2t2_plan_s* pl) { return pl->io == FC2T2_IO_F32 && pl->C <= 4; }
 
 const uint32_t* sort_err_word(const void* scratch, int64_t N) {
   return N > 0 ? carve_scratch((void*)scratch, N).err : nullptr;

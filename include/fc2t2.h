@@ -283,12 +283,14 @@ fc2t2_status fc2t2_ray_root_at(fc2t2_plan plan, const void* L, const void* o, co
                                double t0, double t1, int64_t R, const void* tau, void* t,
                                void* normal, int32_t* hit, void* saved, hipStream_t stream);
 
-/* Test aid: root finding of fc2t2_ray_root / fc2t2_ray_root_at for K <= 4 uses the closed
- * forms (section 5.1: Ferrari's method for the quartic, Cardano's for the cubic, the quadratic
- * formula, each root polished by Newton steps) by default; enable != 0 switches every later
- * call in the process to the derivative cascade used for K = 5 (critical points by recursion on
- * the derivatives, safeguarded Newton on monotone pieces), enable == 0 back.  Both give the
- * same roots to rounding; the switch lets a test compare them on the same rays. */
+/* Test aid: root finding of fc2t2_ray_root / fc2t2_ray_root_at solves every polynomial of degree
+ * <= 4 by closed forms by default (section 5.1: Ferrari's method for the quartic, Cardano's for
+ * the cubic, the quadratic formula, each root polished by Newton steps): for K <= 4 the segment
+ * polynomial's roots and critical points, for K = 5 its critical points (the root on each monotone
+ * piece then comes from the safeguarded iteration).  enable != 0 switches every later call in the
+ * process to the derivative cascade throughout (critical points by recursion on the derivatives,
+ * safeguarded Newton on monotone pieces), enable == 0 back.  Both give the same roots to
+ * rounding; the switch lets a test compare them on the same rays. */
 void fc2t2_debug_root_cascade(int enable);
 
 /* Backward of fc2t2_ray_root (section 5.2, implicit function theorem), tau held fixed:

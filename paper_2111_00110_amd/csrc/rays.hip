@@ -430,8 +430,8 @@ __device__ __forceinline__ double upper_bound(const double (&a)[6], double s) {
 
 // Called only for the few segments the bounds cannot rule out: kept out of line so that the
 // root cascade does not raise the register pressure of the traversal loop.
-// With closed_form (K <= 4) the critical points come from the closed forms, else from the
-// derivative cascade.
+// With closed_form the critical points (roots of the derivative, degree K - 1 <= 4) come from
+// the closed forms, else from the derivative cascade.
 template <class S>
 __device__ __noinline__ double seg_max(const double (&a)[6], double s, int closed_form) {
   constexpr int K = S::K;
@@ -441,7 +441,7 @@ __device__ __noinline__ double seg_max(const double (&a)[6], double s, int close
   for (int m = 0; m < K; ++m) da[m] = (m + 1) * a[m + 1];
   double crit[5];
   int nc;
-  if constexpr (K <= 4) {
+  if constexpr (K <= 5) {
     nc = closed_form ? interior_roots_cf<K - 1>(da, 0.0, s, crit) : real_roots<K - 1>(da, 0.0, s, crit);
   } else {
     nc = real_roots<K - 1>(da, 0.0, s, crit);
@@ -451,8 +451,9 @@ __device__ __noinline__ double seg_max(const double (&a)[6], double s, int close
 }
 
 // First v in (0, s] where g = a - tau goes from < 0 to >= 0 on a monotone piece; -1 if none.
-// With closed_form (K <= 4): critical points and the root on the piece from the closed forms
-// (the piece's root, polished, starts the safeguarded Newton iteration, which then ends at once).
+// With closed_form: the critical points from the closed forms (degree K - 1 <= 4), and for
+// K <= 4 the root on the piece too (polished, it starts the safeguarded Newton iteration, which
+// then ends at once); for K = 5 the piece's root comes from the safeguarded iteration alone.
 template <class S>
 __device__ __noinline__ double first_upward(const double (&g)[6], double s, int closed_form) {
   constexpr int K = S::K;
@@ -461,7 +462,7 @@ __device__ __noinline__ double first_upward(const double (&g)[6], double s, int 
   for (int m = 0; m < K; ++m) dg[m] = (m + 1) * g[m + 1];
   double crit[5];
   int nc;
-  if constexpr (K <= 4) {
+  if constexpr (K <= 5) {
     nc = closed_form ? interior_roots_cf<K - 1>(dg, 0.0, s, crit) : real_roots<K - 1>(dg, 0.0, s, crit);
   } else {
     nc = real_roots<K - 1>(dg, 0.0, s, crit);
@@ -521,7 +522,8 @@ __device__ __forceinline__ void root_gradients(const T* __restrict__ row_ptr, co
 }
 
 constexpr int kRootSub = 8;
-// Root finding for K <= 4: closed forms (1, the default) or the derivative cascade (0, a test
+// Root finding: closed forms (1, the default: every polynomial of degree <= 4, i.e. the roots of
+// g for K <= 4 and the critical points for K <= 5) or the derivative cascade throughout (0, a test
 // aid set by fc2t2_debug_root_cascade, so that the two can be compared on the same rays).
 int g_root_closed_form = 1;
 constexpr int kRootSmooth = FC2T2_ROOT_SMOOTH, kRootFace = FC2T2_ROOT_FACE, kRootGrazing = FC2T2_ROOT_GRAZING;

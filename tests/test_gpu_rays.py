@@ -115,11 +115,12 @@ def test_ray_root_stage(F, io, K, n):
     assert rel(gL.cpu().numpy(), scaled_cotangent(geo, G, plan.P_pad)) < (1e-8 if io == "f64" else 1e-4)
 
 
-@pytest.mark.parametrize("io,K", [("f64", 4), ("f64", 3), ("f32", 4), ("f64", 2)])
+@pytest.mark.parametrize("io,K", [("f64", 4), ("f64", 3), ("f32", 4), ("f64", 2), ("f64", 5), ("f32", 5)])
 def test_ray_root_closed_forms_match_the_cascade(F, io, K):
-    """For K <= 4 the roots come from the closed forms (Ferrari, Cardano, the quadratic formula;
-    section 5.1).  On the same rays the derivative cascade gives the same hits and levels and
-    the same roots to rounding, and the closed-form hits match the checker's."""
+    """For K <= 4 the roots, and for K <= 5 the critical points, come from the closed forms
+    (Ferrari, Cardano, the quadratic formula; section 5.1).  On the same rays the derivative
+    cascade gives the same hits and levels and the same roots to rounding, and the closed-form
+    hits match the checker's."""
     wl = _wl(n=16, K=K, io=io, R=256, sigma=0.08)
     x = W.make(wl, seed=31)
     plan = _plan(F, wl)

@@ -337,11 +337,11 @@ def dominant_roofline(r, plan, step, st, steps, m2l, flops):
     return dom, ms, y, roof
 
 
-def checker_sample(wl, x, idx):
+def checker_sample(wl, x, idx, fit="taylor"):
     """Step-by-step FP64 checker (locals cell by cell from the full moment pyramid) at sampled
     queries: y [S, C]."""
     from oracle import fmm, kernels
-    geo = fmm.Geometry(wl.dim, wl.n, wl.lo, wl.hi, wl.K, np.float32 if wl.io == "f32" else np.float64)
+    geo = fmm.Geometry(wl.dim, wl.n, wl.lo, wl.hi, wl.K, np.float32 if wl.io == "f32" else np.float64, fit)
     ker = kernels.make_kernel(wl.kernel, wl.param, wl.dim)
     qs = x["q"][idx]
     cells = geo.cell_index(qs)
@@ -358,7 +358,7 @@ def accuracy(r, y_gpu, sample, threads):
     idx = workloads.subsample(321, sample, wl.M)
     ker = kernels.make_kernel(wl.kernel, wl.param, wl.dim)
     yd = direct.explicit_y(ker, x["p"], x["w"], x["q"][idx], chunk=4, threads=threads)
-    yf = checker_sample(wl, x, idx)
+    yf = checker_sample(wl, x, idx, r.fit)
     yg = y_gpu[idx]
     eps_cfg = rel(yf, yd)
     vs_direct = rel(yg, yd)

@@ -311,11 +311,12 @@ __global__ void __launch_bounds__(64) volume_records_kernel(const T* __restrict_
   E[ray] = Gb + (stopped ? 0.0 : gbg * mexp_d(vc, D));
 }
 
-// Per-cell reduction of the records into all four channels in one pass (a group of GROUP
-// lanes per cell, as the shared segmented reduction, but with the monomials of each record's
-// K + 1 points computed once for the four rows): density row += sum_m (alpha_m + s E beta_m)
-// mono(u_m); colour row k += y_bar_k sum_m alpha'_m mono(u_m).  Each lane sums a few records;
-// the group's partial rows are then added by a butterfly, and the rows are added into out.
+// Per-cell reduction of the records into the four channel rows: density row += sum_m
+// (alpha_m + s E beta_m) mono(u_m); colour row k += y_bar_k sum_m alpha'_m mono(u_m).  A group
+// of GROUP lanes owns a cell; inside it, four neighbouring lanes share a record and take one row
+// each (so a lane holds P sums, not four rows), and the GROUP / 4 record lanes walk the cell's
+// records in a strided order, all of a record's gathers in flight together.  The record lanes'
+// partial rows are added by a butterfly, and the rows are written into out.
 struct VolumeBeta {
   double beta[6];
 };
@@ -328,25 +329,26 @@ __global__ void __launch_bounds__(256) volume_reduce_kernel(const uint32_t* __re
                                                             const double* __restrict__ E, const T* __restrict__ gy,
                                                             int maxseg, VolumeBeta vb, T* __restrict__ out) {
   constexpr int K = S::K, P = S::P, Ppad = S::Ppad;
+  constexpr int RL = GROUP / 4;   // record lanes per cell
+  static_assert(RL >= 1, "four lanes per record");
   constexpr int CPW = kWave / GROUP;
   constexpr Lobatto<K> LB{};
   const int lane = threadIdx.x & (kWave - 1);
   const int lane_g = lane & (GROUP - 1);
+  const int ch = lane_g & 3, rl = lane_g >> 2;   // this lane's row and record lane
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
   const int64_t wave_id = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t cs = G * Ppad;
   for (int64_t c0 = wave_id * CPW; c0 < G; c0 += waves * CPW) {
     const int64_t cell = c0 + lane / GROUP;
     const bool valid = cell < G;
-    const uint32_t b = valid ? starts[cell] : 0u, e = valid ? starts[cell + 1] : 0u;
-    T acc[4][P];
+    const uint32_t rb = valid ? starts[cell] : 0u, re = valid ? starts[cell + 1] : 0u;
+    T acc[P];
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int k = 0; k < P; ++k) acc[c][k] = T(0);
+    for (int k = 0; k < P; ++k) acc[k] = T(0);
     int cc[3];
     decode_cell<3, T>(valid ? cell : 0, n, cc);
-    for (uint32_t ri = b + lane_g; ri < e; ri += GROUP) {
+    for (uint32_t ri = rb + rl; ri < re; ri += RL) {
       const uint32_t slot = perm[ri];
       const int64_t ray = slot / maxseg;
       double o[3], r[3];
@@ -354,17 +356,18 @@ __global__ void __launch_bounds__(256) volume_reduce_kernel(const uint32_t* __re
       load3(Rd, ray, r);
       const double2* rr = rec + (int64_t)slot * (K + 2);
       const double2 tt = rr[0];
+      double2 al[K + 1];
+#pragma unroll
+      for (int m = 0; m <= K; ++m) al[m] = rr[1 + m];
+      const double e_ray = E[ray];
+      const T g = ch > 0 ? gy[3 * ray + ch - 1] : T(0);
       const double sl = tt.y - tt.x;
       double d[3], q[3];
       seg_local(o, r, tt.x, cc, lo, h, d, q);
-      const double es = sl * E[ray];
-      T tmp[P];
-#pragma unroll
-      for (int k = 0; k < P; ++k) tmp[k] = T(0);
+      const double es = sl * e_ray;
 #pragma unroll
       for (int m = 0; m <= K; ++m) {
-        const double2 al = rr[1 + m];
-        const T a0 = (T)(al.x + es * vb.beta[m]), as = (T)al.y;
+        const T w = ch == 0 ? (T)(al[m].x + es * vb.beta[m]) : g * (T)al[m].y;
         const double xs = sl * LB.x[m];
         T u[3];
 #pragma unroll
@@ -372,31 +375,17 @@ __global__ void __launch_bounds__(256) volume_reduce_kernel(const uint32_t* __re
         T mono[P];
         monomials<S>(u, mono);
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-          acc[0][k] += a0 * mono[k];
-          tmp[k] += as * mono[k];
-        }
-      }
-      const T g0 = gy[3 * ray], g1 = gy[3 * ray + 1], g2 = gy[3 * ray + 2];
-#pragma unroll
-      for (int k = 0; k < P; ++k) {
-        acc[1][k] += g0 * tmp[k];
-        acc[2][k] += g1 * tmp[k];
-        acc[3][k] += g2 * tmp[k];
+        for (int k = 0; k < P; ++k) acc[k] += w * mono[k];
       }
     }
 #pragma unroll
-    for (int off = GROUP / 2; off >= 1; off >>= 1)
+    for (int off = GROUP / 2; off >= 4; off >>= 1)
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
+      for (int k = 0; k < P; ++k) acc[k] += __shfl_xor(acc[k], off, GROUP);
+    if (valid && re > rb) {
 #pragma unroll
-        for (int k = 0; k < P; ++k) acc[c][k] += __shfl_xor(acc[c][k], off, GROUP);
-    if (valid && e > b) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int k = 0; k < P; ++k)
-          if (k % GROUP == lane_g) out[c * cs + cell * Ppad + k] += acc[c][k];
+      for (int k = 0; k < P; ++k)
+        if (k % RL == rl) out[ch * cs + cell * Ppad + k] += acc[k];
     }
   }
 }
@@ -487,10 +476,10 @@ fc2t2_status volume_backward_t(const fc2t2_plan_s* pl, const T* L, const T* o, c
     if constexpr (S::D == 3) {
       VolumeBeta vb;
       for (int m = 0; m < 6; ++m) vb.beta[m] = vp.beta[m];
-      // a ray crosses about 2.3 n cells: lanes per cell from the mean records per cell
+      // record lanes per cell from the mean records per cell (a ray crosses about 2.3 n cells),
+      // four lanes per record
       switch (reduce_group_for(R * 2 * pl->n, pl->G)) {
-        case 4: st = launch_volume_reduce<S, T, 4>(pl, b.starts, b.perm, o, r, b.rec, E, gy, maxseg, vb, gL, s); break;
-        case 16: st = launch_volume_reduce<S, T, 16>(pl, b.starts, b.perm, o, r, b.rec, E, gy, maxseg, vb, gL, s); break;
+        case 4: st = launch_volume_reduce<S, T, 16>(pl, b.starts, b.perm, o, r, b.rec, E, gy, maxseg, vb, gL, s); break;
         default: st = launch_volume_reduce<S, T, 64>(pl, b.starts, b.perm, o, r, b.rec, E, gy, maxseg, vb, gL, s); break;
       }
     }

@@ -59,8 +59,9 @@ __device__ __forceinline__ void load_row_f64(const T* __restrict__ src, double (
   for (int k = 0; k < S::P; ++k) c[k] = (double)src[k];
 }
 
-// Line integral: one thread per ray; each segment's integral is the three-point
-// Gauss-Legendre sum of the cell polynomial (exact for K <= 5), accumulated in FP64.
+// Line integral: kRayLanes lanes per ray, each over its sub-range of the clipped ray; each
+// piece's integral is the three-point Gauss-Legendre sum of the cell polynomial (exact for
+// K <= 5), accumulated in FP64, and the lanes' sums are added by a butterfly.
 template <class S, typename T>
 __global__ void __launch_bounds__(64) ray_integral_kernel(const T* __restrict__ L, const T* __restrict__ O,
                                                           const T* __restrict__ Rd, int64_t R, double t0,
@@ -68,70 +69,83 @@ __global__ void __launch_bounds__(64) ray_integral_kernel(const T* __restrict__ 
                                                           int64_t G, T* __restrict__ y, int C) {
   static_assert(S::K <= 5, "three Gauss-Legendre nodes integrate degree <= 5 exactly");
   constexpr int P = S::P, Ppad = S::Ppad, K = S::K;
-  const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ray = gid / kRayLanes;
+  const int l = (int)(gid % kRayLanes);
   const int ch = blockIdx.y;
-  if (ray >= R) return;
-  double o[3], r[3];
-  load3(O, ray, o);
-  load3(Rd, ray, r);
-  Dda dda;
-  dda.init(o, r, t0, t1, lo, hi, h, n);
-  const double ih = 1.0 / h;
-  const double q[3] = {r[0] * ih, r[1] * ih, r[2] * ih};
-  const T* __restrict__ Lc = L + (int64_t)ch * G * Ppad;
   double acc = 0.0;
-  int64_t cell;
-  int cc[3];
-  double ta, tb;
-  while (dda.next(cell, cc, ta, tb)) {
-    double row[P];
-    load_row_f64<S>(Lc + cell * Ppad, row);
-    double d[3];
+  double o[3], r[3], ta_r, tb_r;
+  if (ray < R) {
+    load3(O, ray, o);
+    load3(Rd, ray, r);
+  }
+  if (ray < R && ray_range(o, r, t0, t1, lo, hi, ta_r, tb_r)) {
+    Dda dda;
+    dda.init(o, r, lane_cut(ta_r, tb_r, l), lane_cut(ta_r, tb_r, l + 1), lo, hi, h, n);
+    const double ih = 1.0 / h;
+    const double q[3] = {r[0] * ih, r[1] * ih, r[2] * ih};
+    const T* __restrict__ Lc = L + (int64_t)ch * G * Ppad;
+    int64_t cell;
+    int cc[3];
+    double ta, tb;
+    while (dda.next(cell, cc, ta, tb)) {
+      double row[P];
+      load_row_f64<S>(Lc + cell * Ppad, row);
+      double d[3];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) d[j] = (o[j] + ta * r[j] - (lo + (cc[j] + 0.5) * h)) * ih;
-    double nodes[3], wt[3];
-    gl3(tb - ta, nodes, wt);
+      for (int j = 0; j < 3; ++j) d[j] = (o[j] + ta * r[j] - (lo + (cc[j] + 0.5) * h)) * ih;
+      double nodes[3], wt[3];
+      gl3(tb - ta, nodes, wt);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      double u[3];
+      for (int i = 0; i < 3; ++i) {
+        double u[3];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) u[j] = d[j] + q[j] * nodes[i];
-      double pw[3][K + 1];
-      power_table<S>(u, pw);
-      double val, g[3], hs[6];
-      eval_poly<S, double, false, false>(row, pw, val, g, hs);
-      acc += wt[i] * val;
+        for (int j = 0; j < 3; ++j) u[j] = d[j] + q[j] * nodes[i];
+        double pw[3][K + 1];
+        power_table<S>(u, pw);
+        double val, g[3], hs[6];
+        eval_poly<S, double, false, false>(row, pw, val, g, hs);
+        acc += wt[i] * val;
+      }
     }
   }
-  y[ray * C + ch] = (T)acc;
+#pragma unroll
+  for (int off = kRayLanes / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, kRayLanes);
+  if (ray < R && l == 0) y[ray * C + ch] = (T)acc;
 }
 
 // ---------------------------------------------------------------------------------------
-// Ray insertion records: slot ray * maxseg + j holds segment j of the ray (its cell as the
-// sort key, [ta, tb] as payload); unused slots get the key G (sorted after every cell).
+// Ray insertion records: lane l of ray i writes its pieces to its own slots
+// [(i kRayLanes + l) perlane, ...) (the cell as the sort key, [ta, tb] as payload); unused
+// slots get the key G (sorted after every cell).  The ray of a slot is slot / maxseg with
+// maxseg = kRayLanes perlane.
 template <typename T>
 __global__ void __launch_bounds__(256) ray_records_kernel(const T* __restrict__ O, const T* __restrict__ Rd,
                                                           int64_t R, double t0, double t1, double lo, double hi,
-                                                          double h, int n, int64_t G, int maxseg,
+                                                          double h, int n, int64_t G, int perlane,
                                                           uint32_t* __restrict__ keys, double2* __restrict__ rec) {
-  const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ray = gid / kRayLanes;
+  const int l = (int)(gid % kRayLanes);
   if (ray >= R) return;
-  double o[3], r[3];
+  double o[3], r[3], ta_r, tb_r;
   load3(O, ray, o);
   load3(Rd, ray, r);
-  Dda dda;
-  dda.init(o, r, t0, t1, lo, hi, h, n);
-  int64_t cell;
-  int cc[3];
-  double ta, tb;
   int j = 0;
-  const int64_t base = ray * maxseg;
-  while (j < maxseg && dda.next(cell, cc, ta, tb)) {
-    keys[base + j] = (uint32_t)cell;
-    rec[base + j] = make_double2(ta, tb);
-    ++j;
+  const int64_t base = gid * perlane;
+  if (ray_range(o, r, t0, t1, lo, hi, ta_r, tb_r)) {
+    Dda dda;
+    dda.init(o, r, lane_cut(ta_r, tb_r, l), lane_cut(ta_r, tb_r, l + 1), lo, hi, h, n);
+    int64_t cell;
+    int cc[3];
+    double ta, tb;
+    while (j < perlane && dda.next(cell, cc, ta, tb)) {
+      keys[base + j] = (uint32_t)cell;
+      rec[base + j] = make_double2(ta, tb);
+      ++j;
+    }
   }
-  for (; j < maxseg; ++j) keys[base + j] = (uint32_t)G;
+  for (; j < perlane; ++j) keys[base + j] = (uint32_t)G;
 }
 
 template <class S, typename T>
@@ -862,7 +876,7 @@ fc2t2_status launch_ray_integral(const fc2t2_plan_s* pl, const void* L, const vo
                                  double t1, int64_t R, void* y, hipStream_t s) {
   if (R == 0) return FC2T2_OK;
   fc2t2_status st = FC2T2_EUNSUPPORTED;
-  const dim3 grid((unsigned)ceil_div(R, 64), pl->C);
+  const dim3 grid((unsigned)ceil_div(R * kRayLanes, 64), pl->C);
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {
     using S = decltype(shape);
     if constexpr (S::D == 3) {
@@ -889,8 +903,8 @@ fc2t2_status ray_integral_backward_t(const fc2t2_plan_s* pl, const T* o, const T
   const int64_t slots = R * maxseg;
   Carve c(ws);
   RecordBufs b = carve_records(c, pl, slots, 1);
-  hipLaunchKernelGGL((ray_records_kernel<T>), dim3((unsigned)ceil_div(R, 256)), dim3(256), 0, s, o, r, R, t0, t1,
-                     pl->lo, pl->hi, pl->h0, pl->n, pl->G, maxseg, b.keys, b.rec);
+  hipLaunchKernelGGL((ray_records_kernel<T>), dim3((unsigned)ceil_div(R * kRayLanes, 256)), dim3(256), 0, s, o, r, R,
+                     t0, t1, pl->lo, pl->hi, pl->h0, pl->n, pl->G, perlane_for(pl), b.keys, b.rec);
   FC2T2_LAUNCH_CHECK();
   fc2t2_status st = radix_sort_pairs(b.keys, b.keys_sorted, b.perm, slots, key_bits_for(pl->G + 1), b.scratch, s);
   if (st) return st;

@@ -17,6 +17,7 @@ struct Dda {
   int cx, cy, cz, sx, sy, sz;
   double mx, my, mz;   // parameter of the next plane crossing per axis
   bool live;
+  bool at_plane;       // the last piece ended at a cell face (see next())
 
   __device__ static double plane_t(double lo, double h, int c, int st, double o, double r) {
     if (st == 0) return INFINITY;
@@ -65,18 +66,23 @@ struct Dda {
     if (!(tb > ta)) live = false;
     t = ta;
     t_end = tb;
+    at_plane = false;
     first_cell(lo, h, n, ox, rx, ta, cx, sx, mx);
     first_cell(lo, h, n, oy, ry, ta, cy, sy, my);
     first_cell(lo, h, n, oz, rz, ta, cz, sz, mz);
   }
 
-  // Next segment of positive length: cell index (row-major) and [ta, tb].
+  // Next segment of positive length: cell index (row-major) and [ta, tb].  at_plane is set when
+  // the segment ends at a cell face, including a face that lies within rounding past t_end (a
+  // cut between two lanes' sub-ranges can land a few ulps before a face; the segment then
+  // still ends its cell, and the next lane starts in the next cell).
   __device__ bool next(int64_t& cell, int (&cc)[3], double& ta, double& tb) {
     while (live && t < t_end) {
       const int j = (my < mx) ? ((mz < my) ? 2 : 1) : ((mz < mx) ? 2 : 0);
       const double tm = j == 0 ? mx : (j == 1 ? my : mz);
       const double tn = fmin(tm, t_end);
       const double t_prev = t;
+      at_plane = tm <= t_end + 1e-12 * fabs(t_end);
       cc[0] = cx; cc[1] = cy; cc[2] = cz;
       t = tn;
       if (tn < t_end) {
@@ -191,8 +197,36 @@ __device__ void segment_poly(const R* row, const double (&d)[3], const double (&
 }
 
 // ---------------------------------------------------------------------------------------
-// Segments a clipped ray can have in the finest grid: at most n cells along each axis.
-inline int maxseg_for(const fc2t2_plan_s* pl) { return 3 * pl->n + 4; }
+// Lanes per ray in the walking kernels: the clipped parameter range [ta, tb] of a ray is cut
+// into kRayLanes equal sub-ranges, walked by neighbouring lanes of one wave.  A cell crossed by
+// a cut is split into two pieces; each piece is integrated exactly, so the sum over a ray is
+// unchanged up to rounding.
+constexpr int kRayLanes = 8;
+
+// Clipped parameter range of a ray in the domain box; false if it misses the box.
+__device__ inline bool ray_range(const double (&o)[3], const double (&r)[3], double t0, double t1, double lo,
+                                 double hi, double& ta, double& tb) {
+  bool live = true;
+  ta = t0;
+  tb = t1;
+  Dda::start_axis(lo, hi, 0.0, 0, o[0], r[0], ta, tb, live);
+  Dda::start_axis(lo, hi, 0.0, 0, o[1], r[1], ta, tb, live);
+  Dda::start_axis(lo, hi, 0.0, 0, o[2], r[2], ta, tb, live);
+  return live && tb > ta;
+}
+
+// Cut c (0..kRayLanes) of [ta, tb]: lane l walks [cut(l), cut(l + 1)]; neighbours compute the
+// shared cut with the same expression, so the sub-ranges tile [ta, tb] exactly.
+__device__ __forceinline__ double lane_cut(double ta, double tb, int c) {
+  return c == 0 ? ta : (c == kRayLanes ? tb : ta + (tb - ta) * ((double)c / kRayLanes));
+}
+
+// Record slots per lane.  Along axis j a sub-range of length (tb - ta) / kRayLanes crosses at
+// most |r_j| (tb - ta) / (kRayLanes h) + 1 faces, and |r_j| (tb - ta) <= n h inside the box, so
+// a lane has at most 3 n / kRayLanes + 4 pieces; two more absorb rounding.  Lane l of ray i
+// owns slots [(i kRayLanes + l) perlane, ... + perlane).
+inline int perlane_for(const fc2t2_plan_s* pl) { return 3 * pl->n / kRayLanes + 6; }
+inline int maxseg_for(const fc2t2_plan_s* pl) { return kRayLanes * perlane_for(pl); }
 
 struct Carve {
   char* base;

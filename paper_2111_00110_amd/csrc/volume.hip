@@ -128,24 +128,45 @@ __device__ __forceinline__ void depth_poly(const double (&bs)[6], double D, doub
 }
 
 // ---------------------------------------------------------------------------------------
-// Forward: one thread per ray.
+// Lanes per ray.  kRayLanes neighbouring lanes walk the sub-ranges of one ray.  The optical
+// depth at a lane's start and the stop decision need the cells before it, so every lane first
+// walks its sub-range for the density alone: the depth it adds (dsum) and the largest depth,
+// relative to its start, at which one of its pieces leaves a cell (dmax; a piece that ends at a
+// cut inside a cell is not a cell exit, the ray's last piece is).  A scan over the lanes then
+// gives each lane its start depth and the largest exit depth of every cell before it; a lane
+// after a cell whose exit depth exceeds the threshold adds nothing, and the lane holding that
+// cell stops after it, as a walk of the whole ray would.
+__device__ __forceinline__ void depth_scan(double s, double m, int l, double& ex_s, double& ex_m, double& tot_s,
+                                           double& tot_m) {
+  // (sum, max) pairs combine as (a.s + b.s, max(a.m, a.s + b.m)), earlier lane first
+  double is = s, im = m;
+#pragma unroll
+  for (int off = 1; off < kRayLanes; off <<= 1) {
+    const double ps = __shfl_up(is, off, kRayLanes), pm = __shfl_up(im, off, kRayLanes);
+    if (l >= off) {
+      im = fmax(pm, ps + im);
+      is = ps + is;
+    }
+  }
+  tot_s = __shfl(is, kRayLanes - 1, kRayLanes);
+  tot_m = __shfl(im, kRayLanes - 1, kRayLanes);
+  ex_s = __shfl_up(is, 1, kRayLanes);
+  ex_m = __shfl_up(im, 1, kRayLanes);
+  if (l == 0) {
+    ex_s = 0.0;
+    ex_m = -INFINITY;
+  }
+}
+
+// The density pass of one lane over [a, b] (see above).
 template <class S, typename T>
-__global__ void __launch_bounds__(64) volume_kernel(const T* __restrict__ L, const T* __restrict__ O,
-                                                    const T* __restrict__ Rd, int64_t R, double t0, double t1,
-                                                    double lo, double hi, double h, int n, int64_t G,
-                                                    VolumeConsts vc, T* __restrict__ y, T* __restrict__ trans) {
-  constexpr int K = S::K, Ppad = S::Ppad, NQ = 3 * K + 3;
-  static_assert(NQ <= kMaxNodes, "quadrature nodes");
-  const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (ray >= R) return;
-  double o[3], r[3];
-  load3(O, ray, o);
-  load3(Rd, ray, r);
+__device__ void density_pass(const T* __restrict__ L, const double (&o)[3], const double (&r)[3], double a, double b,
+                             bool last_lane, double lo, double hi, double h, int n, double& dsum, double& dmax) {
+  constexpr int K = S::K, Ppad = S::Ppad;
   Dda dda;
-  dda.init(o, r, t0, t1, lo, hi, h, n);
-  const int64_t cs = G * Ppad;   // channel stride
-  double D = 0.0, y0 = 0.0, y1 = 0.0, y2 = 0.0;
-  bool stopped = false;
+  dda.init(o, r, a, b, lo, hi, h, n);
+  dsum = 0.0;
+  dmax = -INFINITY;
   int64_t cell;
   int cc[3];
   double ta, tb;
@@ -153,33 +174,86 @@ __global__ void __launch_bounds__(64) volume_kernel(const T* __restrict__ L, con
     const double sl = tb - ta;
     double d[3], q[3];
     seg_local(o, r, ta, cc, lo, h, d, q);
-    const T* row = L + cell * Ppad;
-    double bs[6], b0[6], b1[6], b2[6];
-    segment_poly<S>(row, d, q, sl, bs);
-    segment_poly<S>(row + cs, d, q, sl, b0);
-    segment_poly<S>(row + 2 * cs, d, q, sl, b1);
-    segment_poly<S>(row + 3 * cs, d, q, sl, b2);
+    double bs[6];
+    segment_poly<S>(L + cell * Ppad, d, q, sl, bs);
     double sx[K + 2];
-    depth_poly<K>(bs, D, sl, sx);
+    depth_poly<K>(bs, dsum, sl, sx);
+    dsum = poly_at<K + 2>(sx, 1.0);
+    if (dda.at_plane || last_lane) dmax = fmax(dmax, dsum);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Forward: kRayLanes lanes per ray (density pass, scan, then the lane's share of the colour
+// integral from its start depth); the lanes' colour sums are added by a butterfly.
+template <class S, typename T>
+__global__ void __launch_bounds__(64) volume_kernel(const T* __restrict__ L, const T* __restrict__ O,
+                                                    const T* __restrict__ Rd, int64_t R, double t0, double t1,
+                                                    double lo, double hi, double h, int n, int64_t G,
+                                                    VolumeConsts vc, T* __restrict__ y, T* __restrict__ trans) {
+  constexpr int K = S::K, Ppad = S::Ppad, NQ = 3 * K + 3;
+  static_assert(NQ <= kMaxNodes, "quadrature nodes");
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ray = gid / kRayLanes;
+  const int l = (int)(gid % kRayLanes);
+  const bool last_lane = l == kRayLanes - 1;
+  double o[3], r[3], ta_r = 0.0, tb_r = 0.0;
+  bool hit = false;
+  if (ray < R) {
+    load3(O, ray, o);
+    load3(Rd, ray, r);
+    hit = ray_range(o, r, t0, t1, lo, hi, ta_r, tb_r);
+  }
+  const double a = lane_cut(ta_r, tb_r, l), b = lane_cut(ta_r, tb_r, l + 1);
+  double dsum = 0.0, dmax = -INFINITY;
+  if (hit) density_pass<S>(L, o, r, a, b, last_lane, lo, hi, h, n, dsum, dmax);
+  double D, before_max, D_end, max_exit;
+  depth_scan(dsum, dmax, l, D, before_max, D_end, max_exit);
+  const int64_t cs = G * Ppad;   // channel stride
+  double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+  if (hit && !(before_max > kStopDepth)) {
+    Dda dda;
+    dda.init(o, r, a, b, lo, hi, h, n);
+    int64_t cell;
+    int cc[3];
+    double ta, tb;
+    while (dda.next(cell, cc, ta, tb)) {
+      const double sl = tb - ta;
+      double d[3], q[3];
+      seg_local(o, r, ta, cc, lo, h, d, q);
+      const T* row = L + cell * Ppad;
+      double bs[6], b0[6], b1[6], b2[6];
+      segment_poly<S>(row, d, q, sl, bs);
+      segment_poly<S>(row + cs, d, q, sl, b0);
+      segment_poly<S>(row + 2 * cs, d, q, sl, b1);
+      segment_poly<S>(row + 3 * cs, d, q, sl, b2);
+      double sx[K + 2];
+      depth_poly<K>(bs, D, sl, sx);
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) {
-      const double x = vc.x[i];
-      const double a = sl * vc.w[i] * poly_at<K + 1>(bs, x) * mexp_at(vc, poly_at<K + 2>(sx, x));
-      y0 += a * poly_at<K + 1>(b0, x);
-      y1 += a * poly_at<K + 1>(b1, x);
-      y2 += a * poly_at<K + 1>(b2, x);
-    }
-    D = poly_at<K + 2>(sx, 1.0);
-    if (D > kStopDepth) {
-      stopped = true;
-      break;
+      for (int i = 0; i < NQ; ++i) {
+        const double x = vc.x[i];
+        const double w = sl * vc.w[i] * poly_at<K + 1>(bs, x) * mexp_at(vc, poly_at<K + 2>(sx, x));
+        y0 += w * poly_at<K + 1>(b0, x);
+        y1 += w * poly_at<K + 1>(b1, x);
+        y2 += w * poly_at<K + 1>(b2, x);
+      }
+      D = poly_at<K + 2>(sx, 1.0);
+      if ((dda.at_plane || last_lane) && D > kStopDepth) break;
     }
   }
-  const double Tend = stopped ? 0.0 : mexp_at(vc, D);
-  y[3 * ray] = (T)(y0 + vc.bg[0] * Tend);
-  y[3 * ray + 1] = (T)(y1 + vc.bg[1] * Tend);
-  y[3 * ray + 2] = (T)(y2 + vc.bg[2] * Tend);
-  if (trans) trans[ray] = (T)Tend;
+#pragma unroll
+  for (int off = kRayLanes / 2; off >= 1; off >>= 1) {
+    y0 += __shfl_xor(y0, off, kRayLanes);
+    y1 += __shfl_xor(y1, off, kRayLanes);
+    y2 += __shfl_xor(y2, off, kRayLanes);
+  }
+  if (ray < R && l == 0) {
+    const double Tend = max_exit > kStopDepth ? 0.0 : mexp_at(vc, D_end);
+    y[3 * ray] = (T)(y0 + vc.bg[0] * Tend);
+    y[3 * ray + 1] = (T)(y1 + vc.bg[1] * Tend);
+    y[3 * ray + 2] = (T)(y2 + vc.bg[2] * Tend);
+    if (trans) trans[ray] = (T)Tend;
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -195,8 +269,8 @@ __global__ void __launch_bounds__(64) volume_kernel(const T* __restrict__ L, con
 //                        + s (E - Gb) beta_m,        g = c_y sigma mexp'(S),
 // where the middle term is the running integral of g with the order of integration swapped
 // (int_0^1 l_m(x) int_0^x g = int_0^1 g(y) int_y^1 l_m); every integrand has degree <= 6K + 4,
-// so each sum is exact.  The records pass computes the alphas (E, the ray's total, is added
-// in the reduction, which runs after the whole walk).
+// so each sum is exact.  The records pass computes the alphas (the E term, which needs the
+// ray's total, is added in the reduction, which runs after the whole walk).
 struct VolumeProj {
   double lam[6][kMaxNodes];   // l_m(x_i)
   double gam[6][kMaxNodes];   // int_{x_i}^1 l_m
@@ -230,85 +304,113 @@ VolumeProj volume_proj(int K, const VolumeConsts& vc) {
   return vp;
 }
 
-// Records: the forward's walk again, with the colour cotangents folded into c_y.  Slot
-// ray * maxseg + j holds segment j: key = its cell; rec[(K + 2) slot] = (ta, tb), then
-// (alpha_m of the density without the E term, alpha_m of sigma T without y_bar_k) for
-// m = 0..K; unused slots get the key G (sorted after every cell).  E[ray] receives the walk's
-// total of int c_y sigma mexp'(S), plus (y_bar . bg) mexp'(D_end) when the walk did not stop.
+// Records: the forward's walk again (density pass and scan first), with the colour cotangents
+// folded into c_y.  Lane l of ray i writes its pieces to the slots [(i kRayLanes + l) perlane,
+// ...): key = the cell; rec[(K + 2) slot] = (ta, tb), then (alpha_m of the density without the
+// E term, with Gb counted from the lane's start; alpha_m of sigma T without y_bar_k) for
+// m = 0..K; unused slots get the key G (sorted after every cell).  Ex[i kRayLanes + l]
+// receives E - Gb0, with E the ray's total of int c_y sigma mexp'(S) (plus (y_bar . bg)
+// mexp'(D_end) when the ray did not stop) and Gb0 the same integral over the lanes before l, so
+// that the reduction's term s Ex beta_m completes each record of the lane.
 template <class S, typename T>
 __global__ void __launch_bounds__(64) volume_records_kernel(const T* __restrict__ L, const T* __restrict__ O,
                                                             const T* __restrict__ Rd, int64_t R, double t0,
                                                             double t1, double lo, double hi, double h, int n,
                                                             int64_t G, VolumeConsts vc, VolumeProj vp,
-                                                            const T* __restrict__ gy, int maxseg,
+                                                            const T* __restrict__ gy, int perlane,
                                                             uint32_t* __restrict__ keys, double2* __restrict__ rec,
-                                                            double* __restrict__ E) {
+                                                            double* __restrict__ Ex) {
   constexpr int K = S::K, Ppad = S::Ppad, NQ = 3 * K + 3;
-  const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (ray >= R) return;
-  double o[3], r[3];
-  load3(O, ray, o);
-  load3(Rd, ray, r);
-  const double g0 = (double)gy[3 * ray], g1 = (double)gy[3 * ray + 1], g2 = (double)gy[3 * ray + 2];
-  Dda dda;
-  dda.init(o, r, t0, t1, lo, hi, h, n);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ray = gid / kRayLanes;
+  const int l = (int)(gid % kRayLanes);
+  const bool last_lane = l == kRayLanes - 1;
+  double o[3], r[3], ta_r = 0.0, tb_r = 0.0;
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  bool hit = false;
+  if (ray < R) {
+    load3(O, ray, o);
+    load3(Rd, ray, r);
+    g0 = (double)gy[3 * ray];
+    g1 = (double)gy[3 * ray + 1];
+    g2 = (double)gy[3 * ray + 2];
+    hit = ray_range(o, r, t0, t1, lo, hi, ta_r, tb_r);
+  }
+  const double a = lane_cut(ta_r, tb_r, l), b = lane_cut(ta_r, tb_r, l + 1);
+  double dsum = 0.0, dmax = -INFINITY;
+  if (hit) density_pass<S>(L, o, r, a, b, last_lane, lo, hi, h, n, dsum, dmax);
+  double D, before_max, D_end, max_exit;
+  depth_scan(dsum, dmax, l, D, before_max, D_end, max_exit);
   const int64_t cs = G * Ppad;
-  double D = 0.0, Gb = 0.0;
-  bool stopped = false;
-  int64_t cell;
-  int cc[3];
-  double ta, tb;
+  double Gb = 0.0;
   int j = 0;
-  const int64_t base = ray * maxseg;
-  while (j < maxseg && dda.next(cell, cc, ta, tb)) {
-    const double sl = tb - ta;
-    double d[3], q[3];
-    seg_local(o, r, ta, cc, lo, h, d, q);
-    const T* row = L + cell * Ppad;
-    double bs[6], b0[6], b1[6], b2[6];
-    segment_poly<S>(row, d, q, sl, bs);
-    segment_poly<S>(row + cs, d, q, sl, b0);
-    segment_poly<S>(row + 2 * cs, d, q, sl, b1);
-    segment_poly<S>(row + 3 * cs, d, q, sl, b2);
-    double cy[6];
+  const int64_t base = gid * perlane;
+  if (hit && !(before_max > kStopDepth)) {
+    Dda dda;
+    dda.init(o, r, a, b, lo, hi, h, n);
+    int64_t cell;
+    int cc[3];
+    double ta, tb;
+    while (j < perlane && dda.next(cell, cc, ta, tb)) {
+      const double sl = tb - ta;
+      double d[3], q[3];
+      seg_local(o, r, ta, cc, lo, h, d, q);
+      const T* row = L + cell * Ppad;
+      double bs[6], b0[6], b1[6], b2[6];
+      segment_poly<S>(row, d, q, sl, bs);
+      segment_poly<S>(row + cs, d, q, sl, b0);
+      segment_poly<S>(row + 2 * cs, d, q, sl, b1);
+      segment_poly<S>(row + 3 * cs, d, q, sl, b2);
+      double cy[6];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) cy[m] = g0 * b0[m] + g1 * b1[m] + g2 * b2[m];
-    double sx[K + 2];
-    depth_poly<K>(bs, D, sl, sx);
-    double ad[K + 1], as[K + 1];
+      for (int m = 0; m < 6; ++m) cy[m] = g0 * b0[m] + g1 * b1[m] + g2 * b2[m];
+      double sx[K + 2];
+      depth_poly<K>(bs, D, sl, sx);
+      double ad[K + 1], as[K + 1];
 #pragma unroll
-    for (int m = 0; m <= K; ++m) ad[m] = as[m] = 0.0;
-    double gseg = 0.0;
+      for (int m = 0; m <= K; ++m) ad[m] = as[m] = 0.0;
+      double gseg = 0.0;
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) {
-      const double x = vc.x[i];
-      const double sg = poly_at<K + 1>(bs, x), cv = poly_at<K + 1>(cy, x), Sv = poly_at<K + 2>(sx, x);
-      const double Tv = mexp_at(vc, Sv), gi = cv * sg * mexp_d(vc, Sv);
-      gseg += vc.w[i] * gi;
-      const double hA = vc.w[i] * sl * cv * Tv, hB = vc.w[i] * sl * sl * gi, hS = vc.w[i] * sl * sg * Tv;
+      for (int i = 0; i < NQ; ++i) {
+        const double x = vc.x[i];
+        const double sg = poly_at<K + 1>(bs, x), cv = poly_at<K + 1>(cy, x), Sv = poly_at<K + 2>(sx, x);
+        const double Tv = mexp_at(vc, Sv), gi = cv * sg * mexp_d(vc, Sv);
+        gseg += vc.w[i] * gi;
+        const double hA = vc.w[i] * sl * cv * Tv, hB = vc.w[i] * sl * sl * gi, hS = vc.w[i] * sl * sg * Tv;
 #pragma unroll
-      for (int m = 0; m <= K; ++m) {
-        ad[m] += hA * vp.lam[m][i] - hB * vp.gam[m][i];
-        as[m] += hS * vp.lam[m][i];
+        for (int m = 0; m <= K; ++m) {
+          ad[m] += hA * vp.lam[m][i] - hB * vp.gam[m][i];
+          as[m] += hS * vp.lam[m][i];
+        }
       }
-    }
-    const int64_t slot = base + j;
-    keys[slot] = (uint32_t)cell;
-    double2* rr = rec + slot * (K + 2);
-    rr[0] = make_double2(ta, tb);
+      const int64_t slot = base + j;
+      keys[slot] = (uint32_t)cell;
+      double2* rr = rec + slot * (K + 2);
+      rr[0] = make_double2(ta, tb);
 #pragma unroll
-    for (int m = 0; m <= K; ++m) rr[1 + m] = make_double2(ad[m] - sl * Gb * vp.beta[m], as[m]);
-    ++j;
-    Gb += sl * gseg;
-    D = poly_at<K + 2>(sx, 1.0);
-    if (D > kStopDepth) {
-      stopped = true;
-      break;
+      for (int m = 0; m <= K; ++m) rr[1 + m] = make_double2(ad[m] - sl * Gb * vp.beta[m], as[m]);
+      ++j;
+      Gb += sl * gseg;
+      D = poly_at<K + 2>(sx, 1.0);
+      if ((dda.at_plane || last_lane) && D > kStopDepth) break;
     }
   }
-  for (; j < maxseg; ++j) keys[base + j] = (uint32_t)G;
-  const double gbg = g0 * vc.bg[0] + g1 * vc.bg[1] + g2 * vc.bg[2];
-  E[ray] = Gb + (stopped ? 0.0 : gbg * mexp_d(vc, D));
+  if (ray < R)
+    for (; j < perlane; ++j) keys[base + j] = (uint32_t)G;
+  // the running integral at each lane's start, and the ray's total
+  double is = Gb;
+#pragma unroll
+  for (int off = 1; off < kRayLanes; off <<= 1) {
+    const double ps = __shfl_up(is, off, kRayLanes);
+    if (l >= off) is += ps;
+  }
+  const double gb_tot = __shfl(is, kRayLanes - 1, kRayLanes);
+  const double gb0 = is - Gb;
+  if (ray < R) {
+    const double gbg = g0 * vc.bg[0] + g1 * vc.bg[1] + g2 * vc.bg[2];
+    const double E = gb_tot + (max_exit > kStopDepth ? 0.0 : gbg * mexp_d(vc, D_end));
+    Ex[gid] = E - gb0;
+  }
 }
 
 // Per-cell reduction of the records into the four channel rows: density row += sum_m
@@ -326,8 +428,8 @@ __global__ void __launch_bounds__(256) volume_reduce_kernel(const uint32_t* __re
                                                             const uint32_t* __restrict__ perm, int64_t G, int n,
                                                             double lo, double h, const T* __restrict__ O,
                                                             const T* __restrict__ Rd, const double2* __restrict__ rec,
-                                                            const double* __restrict__ E, const T* __restrict__ gy,
-                                                            int maxseg, VolumeBeta vb, T* __restrict__ out) {
+                                                            const double* __restrict__ Ex, const T* __restrict__ gy,
+                                                            int perlane, VolumeBeta vb, T* __restrict__ out) {
   constexpr int K = S::K, P = S::P, Ppad = S::Ppad;
   constexpr int RL = GROUP / 4;   // record lanes per cell
   static_assert(RL >= 1, "four lanes per record");
@@ -350,7 +452,7 @@ __global__ void __launch_bounds__(256) volume_reduce_kernel(const uint32_t* __re
     decode_cell<3, T>(valid ? cell : 0, n, cc);
     for (uint32_t ri = rb + rl; ri < re; ri += RL) {
       const uint32_t slot = perm[ri];
-      const int64_t ray = slot / maxseg;
+      const int64_t lane_id = slot / perlane, ray = lane_id / kRayLanes;
       double o[3], r[3];
       load3(O, ray, o);
       load3(Rd, ray, r);
@@ -359,7 +461,7 @@ __global__ void __launch_bounds__(256) volume_reduce_kernel(const uint32_t* __re
       double2 al[K + 1];
 #pragma unroll
       for (int m = 0; m <= K; ++m) al[m] = rr[1 + m];
-      const double e_ray = E[ray];
+      const double e_ray = Ex[lane_id];
       const T g = ch > 0 ? gy[3 * ray + ch - 1] : T(0);
       const double sl = tt.y - tt.x;
       double d[3], q[3];
@@ -392,13 +494,13 @@ __global__ void __launch_bounds__(256) volume_reduce_kernel(const uint32_t* __re
 
 template <class S, typename T, int GROUP>
 fc2t2_status launch_volume_reduce(const fc2t2_plan_s* pl, const uint32_t* starts, const uint32_t* perm, const T* o,
-                                  const T* r, const double2* rec, const double* E, const T* gy, int maxseg,
+                                  const T* r, const double2* rec, const double* Ex, const T* gy, int perlane,
                                   const VolumeBeta& vb, T* gL, hipStream_t s) {
   const int threads = 256;
   const int64_t need = ceil_div(pl->G * GROUP, threads);
   const int64_t blocks = need < 16384 ? need : 16384;
   hipLaunchKernelGGL((volume_reduce_kernel<S, T, GROUP>), dim3((unsigned)blocks), dim3(threads), 0, s, starts, perm,
-                     pl->G, pl->n, pl->lo, pl->h0, o, r, rec, E, gy, maxseg, vb, gL);
+                     pl->G, pl->n, pl->lo, pl->h0, o, r, rec, Ex, gy, perlane, vb, gL);
   FC2T2_LAUNCH_CHECK();
   return FC2T2_OK;
 }
@@ -412,7 +514,7 @@ namespace fc2t2 {
 size_t ray_volume_bwd_ws(const fc2t2_plan_s* pl, int64_t R) {
   Carve c(nullptr);
   carve_records(c, pl, R * maxseg_for(pl), pl->K + 2);
-  c.take<double>(R);
+  c.take<double>(R * kRayLanes);
   return c.off;
 }
 
@@ -425,7 +527,7 @@ fc2t2_status launch_volume(const fc2t2_plan_s* pl, const void* L, const void* o,
   if (R == 0) return FC2T2_OK;
   const VolumeConsts vc = volume_consts(pl->K, bg);
   fc2t2_status st = FC2T2_EUNSUPPORTED;
-  const dim3 grid((unsigned)ceil_div(R, 64));
+  const dim3 grid((unsigned)ceil_div(R * kRayLanes, 64));
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {
     using S = decltype(shape);
     if constexpr (S::D == 3) {
@@ -452,15 +554,16 @@ fc2t2_status volume_backward_t(const fc2t2_plan_s* pl, const T* L, const T* o, c
   const int64_t slots = R * maxseg;
   Carve c(ws);
   RecordBufs b = carve_records(c, pl, slots, pl->K + 2);
-  double* E = c.take<double>(R);
+  double* Ex = c.take<double>(R * kRayLanes);
   const VolumeConsts vc = volume_consts(pl->K, bg);
   const VolumeProj vp = volume_proj(pl->K, vc);
   fc2t2_status st = FC2T2_EUNSUPPORTED;
   dispatch_shape(pl->dim, pl->K, [&](auto shape) {
     using S = decltype(shape);
     if constexpr (S::D == 3) {
-      hipLaunchKernelGGL((volume_records_kernel<S, T>), dim3((unsigned)ceil_div(R, 64)), dim3(64), 0, s, L, o, r, R,
-                         t0, t1, pl->lo, pl->hi, pl->h0, pl->n, pl->G, vc, vp, gy, maxseg, b.keys, b.rec, E);
+      hipLaunchKernelGGL((volume_records_kernel<S, T>), dim3((unsigned)ceil_div(R * kRayLanes, 64)), dim3(64), 0, s, L,
+                         o, r, R, t0, t1, pl->lo, pl->hi, pl->h0, pl->n, pl->G, vc, vp, gy, perlane_for(pl), b.keys,
+                         b.rec, Ex);
       st = FC2T2_OK;
     }
   });
@@ -479,8 +582,8 @@ fc2t2_status volume_backward_t(const fc2t2_plan_s* pl, const T* L, const T* o, c
       // record lanes per cell from the mean records per cell (a ray crosses about 2.3 n cells),
       // four lanes per record
       switch (reduce_group_for(R * 2 * pl->n, pl->G)) {
-        case 4: st = launch_volume_reduce<S, T, 16>(pl, b.starts, b.perm, o, r, b.rec, E, gy, maxseg, vb, gL, s); break;
-        default: st = launch_volume_reduce<S, T, 64>(pl, b.starts, b.perm, o, r, b.rec, E, gy, maxseg, vb, gL, s); break;
+        case 4: st = launch_volume_reduce<S, T, 16>(pl, b.starts, b.perm, o, r, b.rec, Ex, gy, perlane_for(pl), vb, gL, s); break;
+        default: st = launch_volume_reduce<S, T, 64>(pl, b.starts, b.perm, o, r, b.rec, Ex, gy, perlane_for(pl), vb, gL, s); break;
       }
     }
   });

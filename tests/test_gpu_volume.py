@@ -158,3 +158,38 @@ def test_volume_end_to_end_and_gradients(F):
     gw, gp = fmm.p2m_T(geo, fmm.expand_T(geo, ker, G), x["p"], w)
     assert rel(wd.grad.cpu().numpy(), gw) < 1e-4
     assert rel(p.grad.cpu().numpy(), gp) < 1e-4
+
+
+@pytest.mark.parametrize("n,dens", [(8, 2.5), (8, 4.0), (16, 6.0)])
+def test_volume_lane_cuts_on_cell_faces(F, n, dens):
+    """Rays along the axes across the whole box: each ray's parameter range is cut into equal
+    sub-ranges for the lanes that walk it, and with n a multiple of the lane count the cuts fall
+    on cell faces (up to rounding).  The stop decision must still be taken at every cell exit,
+    forward and backward."""
+    wl = _wl(n=n, K=4, io="f64", R=48)
+    geo = oracle_geometry(wl)
+    plan = _plan(F, wl)
+    rng = np.random.default_rng(90 + n)
+    Lt, L0 = _field(rng, geo, plan.P_pad, np.float64, dens)
+    o, r = [], []
+    for axis in range(3):
+        for sign in (1.0, -1.0):
+            for _ in range(wl.R // 6):
+                d = np.zeros(3)
+                d[axis] = sign
+                p = rng.uniform(-0.95, 0.95, 3)
+                p[axis] = -3.0 * sign
+                o.append(p)
+                r.append(d)
+    o, r = np.array(o), np.array(r)
+    bg = np.array([0.3, 0.6, 0.9])
+    ref = volume.render(geo, L0, o, r, 0.0, 10.0, bg)
+    ok = ref["margin"] > 1e-6
+    assert ok.sum() >= 0.9 * len(ok) and ref["stopped"][ok].any()
+    y = plan.ray_volume(_dev(Lt), _dev(o), _dev(r), 0.0, 10.0, bg).cpu().numpy()
+    assert np.max(np.abs(y[ok] - ref["y"][ok])) < 1e-10
+    gy = np.where(ok[:, None], rng.standard_normal((len(o), 3)), 0.0)
+    gL = plan.new_local()
+    plan.ray_volume_backward(_dev(Lt), _dev(o), _dev(r), 0.0, 10.0, _dev(gy), gL, bg)
+    G = volume.render_T(geo, L0, o, r, 0.0, 10.0, ref, gy, bg)
+    assert rel(gL.cpu().numpy(), scaled_cotangent(geo, G, plan.P_pad)) < 1e-9

@@ -164,10 +164,19 @@ class Runner:
             gq = torch.zeros_like(q)
 
             ws = plan.workspace("eval_sorted", q.shape[0])
+            side = torch.cuda.Stream()   # default priority
 
-            def step():   # queries sorted once (forward); the backward calls overwrite their outputs
+            def step():
+                # queries sorted once per step, on a second stream while the expansion is built
+                # (after the previous step's backward has read the records); the backward calls
+                # overwrite their outputs
+                main = torch.cuda.current_stream()
+                side.wait_stream(main)
+                with torch.cuda.stream(side):
+                    plan.sort_queries(q, ws)
                 plan.expand(p, w, out=Lt)
-                y, _ = plan.eval_sorted(Lt, q, ws)
+                main.wait_stream(side)
+                y = plan.eval_presorted(Lt, q.shape[0], ws)
                 plan.eval_backward_sorted(Lt, q.shape[0], gy, ws, gL, gq, accumulate=False)
                 plan.expand_backward(gL, p, w, gp, gw, accumulate=False)
                 return y

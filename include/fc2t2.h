@@ -203,6 +203,19 @@ fc2t2_status fc2t2_eval(fc2t2_plan plan, const void* L, const void* q, int64_t M
 fc2t2_status fc2t2_eval_sorted(fc2t2_plan plan, const void* L, const void* q, int64_t M, void* y,
                                void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* The two halves of fc2t2_eval_sorted (section 3.3 binning, then L2P of section 3), so that a
+ * caller can sort a step's queries on one stream while another builds the expansion:
+ * fc2t2_sort_queries bins and sorts q [M][dim] by cell into `ws` (the records described above;
+ * q is not read again), and fc2t2_eval_presorted evaluates y [M] (input order) from those
+ * records and L.  The second call must be ordered after the first (same stream, or an event);
+ * same plan, M and ws, ws not written in between.  Same support, workspace size and
+ * out-of-domain counting as fc2t2_eval_sorted; the records then serve
+ * fc2t2_eval_backward_sorted as well. */
+fc2t2_status fc2t2_sort_queries(fc2t2_plan plan, const void* q, int64_t M, void* ws, size_t ws_bytes,
+                                hipStream_t stream);
+fc2t2_status fc2t2_eval_presorted(fc2t2_plan plan, const void* L, int64_t M, void* y, const void* ws,
+                                  size_t ws_bytes, hipStream_t stream);
+
 /* fc2t2_eval_backward from the records an fc2t2_eval_sorted call left in `ws` (same plan, same
  * queries and M, ws not written in between; q is not read again): one pass over the sorted
  * queries gives gL (the transpose of L2P, per-cell sums) and gq [M][dim] = gy . grad f(q) (NULL

@@ -335,27 +335,43 @@ fc2t2_status fc2t2_bin_points(fc2t2_plan plan, const void* x, int64_t N, const v
                             plan->sort_fail);
 }
 
-fc2t2_status fc2t2_eval_sorted(fc2t2_plan plan, const void* L, const void* q, int64_t M, void* y, void* ws,
-                               size_t ws_bytes, hipStream_t stream) {
-  if (!plan || !L || bad_count(M)) return FC2T2_EINVAL;
-  if (M > 0 && (!q || !y)) return FC2T2_EINVAL;
+fc2t2_status fc2t2_sort_queries(fc2t2_plan plan, const void* q, int64_t M, void* ws, size_t ws_bytes,
+                                hipStream_t stream) {
+  if (!plan || bad_count(M)) return FC2T2_EINVAL;
+  if (M > 0 && !q) return FC2T2_EINVAL;
   if (!sort_payload_ok(plan) || plan->C != 1) return FC2T2_EUNSUPPORTED;
   if (!ws || ws_bytes < ws_eval_sorted(plan, M)) return FC2T2_EWORKSPACE;
   if (M == 0) return FC2T2_OK;
   Carve c(ws);
   const QueryRecords b = carve_query_records(c, plan, M);
-  fc2t2_status st;
-  {
-    StageScope t(plan, FC2T2_STAGE_SORT, stream);
-    st = sort_points_by_cell(plan, q, M, b.keys, b.keys_sorted, b.perm, b.scratch, stream, nullptr, b.pay,
-                             plan->ood);
-    if (st) return st;
-    st = launch_cell_starts(b.keys_sorted, M, plan->G, b.starts, stream, sort_err_word(b.scratch, M),
-                            plan->sort_fail);
-  }
+  StageScope t(plan, FC2T2_STAGE_SORT, stream);
+  fc2t2_status st = sort_points_by_cell(plan, q, M, b.keys, b.keys_sorted, b.perm, b.scratch, stream, nullptr,
+                                        b.pay, plan->ood);
   if (st) return st;
+  return launch_cell_starts(b.keys_sorted, M, plan->G, b.starts, stream, sort_err_word(b.scratch, M),
+                            plan->sort_fail);
+}
+
+fc2t2_status fc2t2_eval_presorted(fc2t2_plan plan, const void* L, int64_t M, void* y, const void* ws,
+                                  size_t ws_bytes, hipStream_t stream) {
+  if (!plan || !L || bad_count(M)) return FC2T2_EINVAL;
+  if (M > 0 && !y) return FC2T2_EINVAL;
+  if (!sort_payload_ok(plan) || plan->C != 1) return FC2T2_EUNSUPPORTED;
+  if (!ws || ws_bytes < ws_eval_sorted(plan, M)) return FC2T2_EWORKSPACE;
+  if (M == 0) return FC2T2_OK;
+  Carve c((void*)ws);
+  const QueryRecords b = carve_query_records(c, plan, M);
   StageScope t(plan, FC2T2_STAGE_L2P, stream);
   return launch_l2p_sorted(plan, L, b.pay, b.keys_sorted, b.perm, M, y, stream, sort_err_word(b.scratch, M));
+}
+
+fc2t2_status fc2t2_eval_sorted(fc2t2_plan plan, const void* L, const void* q, int64_t M, void* y, void* ws,
+                               size_t ws_bytes, hipStream_t stream) {
+  if (!plan || !L || bad_count(M)) return FC2T2_EINVAL;
+  if (M > 0 && (!q || !y)) return FC2T2_EINVAL;
+  fc2t2_status st = fc2t2_sort_queries(plan, q, M, ws, ws_bytes, stream);
+  if (st) return st;
+  return fc2t2_eval_presorted(plan, L, M, y, ws, ws_bytes, stream);
 }
 
 fc2t2_status fc2t2_eval_backward_sorted(fc2t2_plan plan, const void* L, int64_t M, const void* gy, void* gL,

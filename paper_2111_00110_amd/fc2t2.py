@@ -90,6 +90,10 @@ def lib() -> ctypes.CDLL:
     L.fc2t2_eval.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
     L.fc2t2_eval_sorted.restype = i32
     L.fc2t2_eval_sorted.argtypes = [vp, vp, vp, i64, vp, vp, sz, vp]
+    L.fc2t2_sort_queries.restype = i32
+    L.fc2t2_sort_queries.argtypes = [vp, vp, i64, vp, sz, vp]
+    L.fc2t2_eval_presorted.restype = i32
+    L.fc2t2_eval_presorted.argtypes = [vp, vp, i64, vp, vp, sz, vp]
     L.fc2t2_eval_backward_sorted.restype = i32
     L.fc2t2_eval_backward_sorted.argtypes = [vp, vp, i64, vp, vp, vp, vp, sz, i32, vp]
     L.fc2t2_eval_backward.restype = i32
@@ -283,6 +287,28 @@ class Plan:
                "fc2t2_eval_sorted")
         self._debug_domain("queries")
         return y, ws
+
+    def sort_queries(self, q: torch.Tensor, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """First half of eval_sorted: the queries binned and sorted by cell into ws (returned), on
+        the current stream.  eval_presorted then evaluates from ws; a caller can run this on a
+        side stream while the expansion is built."""
+        M = q.shape[0]
+        q = self._t(q, (M, self.dim), "q")
+        if ws is None:
+            ws = self.workspace("eval_sorted", M)
+        _check(lib().fc2t2_sort_queries(self.handle, _ptr(q), M, _ptr(ws), ws.numel(), _stream()),
+               "fc2t2_sort_queries")
+        return ws
+
+    def eval_presorted(self, Lt: torch.Tensor, M: int, ws: torch.Tensor) -> torch.Tensor:
+        """Second half of eval_sorted: y [M] (input order) from the records sort_queries left in ws
+        (ordered after it on the device)."""
+        Lt = self._t(Lt, self.local_shape(), "L")
+        y = torch.empty((M, self.C), dtype=self.dtype, device=self.device)
+        _check(lib().fc2t2_eval_presorted(self.handle, _ptr(Lt), M, _ptr(y), _ptr(ws), ws.numel(), _stream()),
+               "fc2t2_eval_presorted")
+        self._debug_domain("queries")
+        return y
 
     def eval_backward_sorted(self, Lt, M: int, gy, ws, gL: torch.Tensor, gq: Optional[torch.Tensor] = None,
                              accumulate: bool = True):
@@ -499,15 +525,37 @@ class Plan:
 
 # ---------------------------------------------------------------------------- autograd
 
+_side_streams = {}
+
+
+def _side_stream(device) -> "torch.cuda.Stream":
+    """A second stream per device (default priority) for work that overlaps the current
+    stream's."""
+    key = torch.device(device).index
+    if key not in _side_streams:
+        _side_streams[key] = torch.cuda.Stream(device=device)
+    return _side_streams[key]
+
+
 class Explicit(torch.autograd.Function):
     """y = f(q; p, w) (section 4) with the backward of section 4.1."""
 
     @staticmethod
     def forward(ctx, plan: Plan, p, w, q):
-        Lt = plan.expand(p, w)
-        if plan.sorted_queries:   # queries sorted once, in the forward; the backward reuses them
-            y, ws = plan.eval_sorted(Lt, q)
+        if plan.sorted_queries:
+            # queries sorted once, in the forward, on a side stream while the expansion is built;
+            # the backward reuses the sorted records
+            ws = plan.workspace("eval_sorted", q.shape[0])
+            main = torch.cuda.current_stream()
+            side = _side_stream(q.device)
+            side.wait_stream(main)
+            with torch.cuda.stream(side):
+                plan.sort_queries(q, ws)
+            Lt = plan.expand(p, w)
+            main.wait_stream(side)
+            y = plan.eval_presorted(Lt, q.shape[0], ws)
         else:
+            Lt = plan.expand(p, w)
             (y, _, _), ws = plan.eval(Lt, q), None
         ctx.plan, ctx.ws = plan, ws
         ctx.save_for_backward(p, w, q, Lt)

@@ -328,6 +328,39 @@ def test_sorted_query_path_matches_checker_and_unsorted(F, d, io_kernel):
     assert y0.shape == (0, 1) and float(gL0.abs().max()) == 0.0
 
 
+def test_query_sort_on_a_side_stream_matches_eval_sorted(F):
+    """fc2t2_sort_queries on a second stream while the expansion runs on the first, then
+    fc2t2_eval_presorted after the streams join: y and the backward from the sorted records are
+    bitwise those of fc2t2_eval_sorted, over three steps reusing one workspace."""
+    wl = W.workload("explicit3d_imq", N=1 << 15, M=50_001, n=32)
+    x = W.make(wl, seed=23)
+    plan = _plan(F, wl)
+    p, w, q, gy = (_dev(x[k]) for k in ("p", "w", "q", "gy"))
+    Lt = plan.expand(p, w)
+    y_ref, ws_ref = plan.eval_sorted(Lt, q)
+    gL_ref, gq_ref = plan.new_local(), torch.empty_like(q)
+    plan.eval_backward_sorted(Lt, wl.M, gy, ws_ref, gL_ref, gq_ref, accumulate=False)
+    ws = plan.workspace("eval_sorted", wl.M)
+    L2 = plan.new_local()
+    side = torch.cuda.Stream()
+    main = torch.cuda.current_stream()
+    for _ in range(3):
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            plan.sort_queries(q, ws)
+        plan.expand(p, w, out=L2)
+        main.wait_stream(side)
+        y = plan.eval_presorted(L2, wl.M, ws)
+        gL, gq = plan.new_local().fill_(3.0), torch.empty_like(q).fill_(3.0)
+        plan.eval_backward_sorted(L2, wl.M, gy, ws, gL, gq, accumulate=False)
+        torch.cuda.synchronize()
+        assert torch.equal(y, y_ref)
+        assert torch.equal(gL, gL_ref) and torch.equal(gq, gq_ref)
+    assert plan.sort_failures() == 0
+    e = plan.sort_queries(q[:0])
+    assert plan.eval_presorted(Lt, 0, e).shape == (0, 1)
+
+
 def test_explicit_autograd_uses_sorted_queries(F):
     """The autograd wrapper (sorted-query path for FP32, one channel) against the unsorted calls."""
     wl = W.workload("explicit2d", N=1 << 14, M=1 << 13, n=64)

@@ -87,10 +87,12 @@ struct StageScope {
 
 // ---- sort.hip
 // Stable LSD radix sort of (key, index) pairs by the low `key_bits` bits.  keys_in is
-// read only; keys_out/vals_out receive the sorted keys and the original indices.
+// read only; keys_out/vals_out receive the sorted keys and the original indices.  `frequent`
+// names a key expected many times (the records' unused-slot key), counted without contention.
 size_t radix_sort_scratch_bytes(int64_t N);
 fc2t2_status radix_sort_pairs(const uint32_t* keys_in, uint32_t* keys_out, uint32_t* vals_out,
-                              int64_t N, int key_bits, void* scratch, hipStream_t s);
+                              int64_t N, int key_bits, void* scratch, hipStream_t s,
+                              uint32_t frequent = 0xFFFFFFFFu);
 // starts[c] = first sorted position with key >= c, for c in [0, G]; starts[G] = N.
 // The same for points: keys (written to `keys`) are the linear finest-cell indices of x.
 // With pay_out, each point's coordinates and its extra_words (1..4) values in `extra`

@@ -115,10 +115,9 @@ __global__ void __launch_bounds__(64) ray_integral_kernel(const T* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------------------
-// Ray insertion records: lane l of ray i writes its pieces to its own slots
-// [(i kRayLanes + l) perlane, ...) (the cell as the sort key, [ta, tb] as payload); unused
-// slots get the key G (sorted after every cell).  The ray of a slot is slot / maxseg with
-// maxseg = kRayLanes perlane.
+// Ray insertion records: lane l of ray i writes its pieces to its own slots (ray_slot; the cell
+// as the sort key, [ta, tb] as payload); unused slots get the key G (sorted after every cell).
+// The ray of a slot is slot / maxseg with maxseg = kRayLanes perlane.
 template <typename T>
 __global__ void __launch_bounds__(256) ray_records_kernel(const T* __restrict__ O, const T* __restrict__ Rd,
                                                           int64_t R, double t0, double t1, double lo, double hi,
@@ -132,7 +131,6 @@ __global__ void __launch_bounds__(256) ray_records_kernel(const T* __restrict__ 
   load3(O, ray, o);
   load3(Rd, ray, r);
   int j = 0;
-  const int64_t base = gid * perlane;
   if (ray_range(o, r, t0, t1, lo, hi, ta_r, tb_r)) {
     Dda dda;
     dda.init(o, r, lane_cut(ta_r, tb_r, l), lane_cut(ta_r, tb_r, l + 1), lo, hi, h, n);
@@ -140,12 +138,13 @@ __global__ void __launch_bounds__(256) ray_records_kernel(const T* __restrict__ 
     int cc[3];
     double ta, tb;
     while (j < perlane && dda.next(cell, cc, ta, tb)) {
-      keys[base + j] = (uint32_t)cell;
-      rec[base + j] = make_double2(ta, tb);
+      const int64_t slot = ray_slot(ray, l, j, perlane);
+      keys[slot] = (uint32_t)cell;
+      rec[slot] = make_double2(ta, tb);
       ++j;
     }
   }
-  for (; j < perlane; ++j) keys[base + j] = (uint32_t)G;
+  for (; j < perlane; ++j) keys[ray_slot(ray, l, j, perlane)] = (uint32_t)G;
 }
 
 template <class S, typename T>
@@ -906,7 +905,8 @@ fc2t2_status ray_integral_backward_t(const fc2t2_plan_s* pl, const T* o, const T
   hipLaunchKernelGGL((ray_records_kernel<T>), dim3((unsigned)ceil_div(R * kRayLanes, 256)), dim3(256), 0, s, o, r, R,
                      t0, t1, pl->lo, pl->hi, pl->h0, pl->n, pl->G, perlane_for(pl), b.keys, b.rec);
   FC2T2_LAUNCH_CHECK();
-  fc2t2_status st = radix_sort_pairs(b.keys, b.keys_sorted, b.perm, slots, key_bits_for(pl->G + 1), b.scratch, s);
+  fc2t2_status st = radix_sort_pairs(b.keys, b.keys_sorted, b.perm, slots, key_bits_for(pl->G + 1), b.scratch, s,
+                                          (uint32_t)pl->G);
   if (st) return st;
   st = launch_cell_starts(b.keys_sorted, slots, pl->G, b.starts, s, sort_err_word(b.scratch, slots), pl->sort_fail);
   if (st) return st;
@@ -974,7 +974,8 @@ fc2t2_status ray_root_backward_t(const fc2t2_plan_s* pl, const T* saved, const i
   hipLaunchKernelGGL((root_keys_kernel<T>), dim3((unsigned)ceil_div(R, 256)), dim3(256), 0, s, saved, hit, R, pl->G,
                      b.keys);
   FC2T2_LAUNCH_CHECK();
-  fc2t2_status st = radix_sort_pairs(b.keys, b.keys_sorted, b.perm, R, key_bits_for(pl->G + 1), b.scratch, s);
+  fc2t2_status st = radix_sort_pairs(b.keys, b.keys_sorted, b.perm, R, key_bits_for(pl->G + 1), b.scratch, s,
+                                          (uint32_t)pl->G);
   if (st) return st;
   st = launch_cell_starts(b.keys_sorted, R, pl->G, b.starts, s, sort_err_word(b.scratch, R), pl->sort_fail);
   if (st) return st;

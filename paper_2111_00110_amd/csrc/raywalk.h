@@ -223,10 +223,15 @@ __device__ __forceinline__ double lane_cut(double ta, double tb, int c) {
 
 // Record slots per lane.  Along axis j a sub-range of length (tb - ta) / kRayLanes crosses at
 // most |r_j| (tb - ta) / (kRayLanes h) + 1 faces, and |r_j| (tb - ta) <= n h inside the box, so
-// a lane has at most 3 n / kRayLanes + 4 pieces; two more absorb rounding.  Lane l of ray i
-// owns slots [(i kRayLanes + l) perlane, ... + perlane).
+// a lane has at most 3 n / kRayLanes + 4 pieces; two more absorb rounding.  Piece j of lane l of
+// ray i is slot (i perlane + j) kRayLanes + l: a ray owns maxseg = kRayLanes perlane consecutive
+// slots (its ray is slot / maxseg, its lane slot % kRayLanes), and the lanes' j-th records are
+// neighbours, so a wave's record writes fill whole lines.
 inline int perlane_for(const fc2t2_plan_s* pl) { return 3 * pl->n / kRayLanes + 6; }
 inline int maxseg_for(const fc2t2_plan_s* pl) { return kRayLanes * perlane_for(pl); }
+__host__ __device__ inline int64_t ray_slot(int64_t ray, int lane, int j, int perlane) {
+  return ((ray * perlane + j) * kRayLanes) + lane;
+}
 
 struct Carve {
   char* base;

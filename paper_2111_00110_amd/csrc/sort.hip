@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(kThreads) sort_hist_sum_kernel(const uint32_t*
 template <typename T, int D>
 __global__ void __launch_bounds__(kThreads) sort_hist_kernel(const T* __restrict__ x, T lo, T scale, int n,
                                                              uint32_t* __restrict__ keys, uint32_t N, int npass,
-                                                             uint32_t* __restrict__ ghist,
+                                                             uint32_t frequent, uint32_t* __restrict__ ghist,
                                                              uint32_t* __restrict__ status, uint32_t status_words,
                                                              unsigned long long* __restrict__ ood) {
   __shared__ uint32_t h[kMaxPasses][kBins];
@@ -66,6 +66,7 @@ __global__ void __launch_bounds__(kThreads) sort_hist_kernel(const T* __restrict
   __syncthreads();
   const uint32_t stride = gridDim.x * kThreads;
   constexpr int kBatch = 8;   // points per thread per round, loaded before any is used
+  uint32_t nfreq = 0;         // keys equal to `frequent`, counted here and added once
   for (uint32_t i0 = blockIdx.x * kThreads + tid; i0 < N; i0 += kBatch * stride) {
     uint32_t key[kBatch];
 #pragma unroll
@@ -90,9 +91,15 @@ __global__ void __launch_bounds__(kThreads) sort_hist_kernel(const T* __restrict
 #pragma unroll
     for (int b = 0; b < kBatch; ++b) {
       if (i0 + b * stride >= N) continue;
+      if (key[b] == frequent) {
+        ++nfreq;
+        continue;
+      }
       for (int ps = 0; ps < npass; ++ps) atomicAdd(&h[ps][(key[b] >> (8 * ps)) & (kBins - 1)], 1u);
     }
   }
+  if (nfreq)
+    for (int ps = 0; ps < npass; ++ps) atomicAdd(&h[ps][(frequent >> (8 * ps)) & (kBins - 1)], nfreq);
   __syncthreads();
   uint32_t* mine = ghist + (size_t)blockIdx.x * kMaxPasses * kBins;   // this block's counts
   for (int ps = 0; ps < npass; ++ps) mine[ps * kBins + tid] = h[ps][tid];
@@ -429,15 +436,18 @@ fc2t2_status onesweep_passes(const uint32_t* keys_in, uint32_t* keys_out, uint32
   return FC2T2_OK;
 }
 
-// Histogram (and keys from points when x is given) for npass passes of 8 bits.
+// Histogram (and keys from points when x is given) for npass passes of 8 bits; `frequent` is a
+// key the caller expects many times (counted per thread instead of by shared-memory atomics on
+// one address), or kNoKey.
+constexpr uint32_t kNoKey = 0xFFFFFFFFu;
 template <typename T, int D>
 fc2t2_status sort_prologue(const T* x, T lo, T scale, int n, uint32_t* keys, uint32_t N, int npass,
                            unsigned long long* ood,
-                           const SortScratch& c, hipStream_t s) {
+                           const SortScratch& c, hipStream_t s, uint32_t frequent = kNoKey) {
   const uint32_t status_words = (uint32_t)npass * c.max_tiles * kBins;
   const int blocks = hist_blocks(N, status_words);
   hipLaunchKernelGGL((sort_hist_kernel<T, D>), dim3(blocks), dim3(kThreads), 0, s, x, lo, scale, n, keys, N, npass,
-                     c.part, c.status, status_words, ood);
+                     frequent, c.part, c.status, status_words, ood);
   FC2T2_LAUNCH_CHECK();
   hipLaunchKernelGGL(sort_hist_sum_kernel, dim3(npass, kSlices), dim3(kThreads), 0, s, c.part, blocks, c.ghist,
                      c.err);
@@ -457,12 +467,13 @@ size_t radix_sort_scratch_bytes(int64_t N) {
 }
 
 fc2t2_status radix_sort_pairs(const uint32_t* keys_in, uint32_t* keys_out, uint32_t* vals_out,
-                              int64_t N, int key_bits, void* scratch, hipStream_t s) {
+                              int64_t N, int key_bits, void* scratch, hipStream_t s, uint32_t frequent) {
   if (N == 0) return FC2T2_OK;
   if (N >= (int64_t)kValMask || key_bits > 8 * kMaxPasses) return FC2T2_EUNSUPPORTED;
   const SortScratch c = carve_scratch(scratch, N);
   const int npass = (key_bits + 7) / 8;
-  fc2t2_status st = sort_prologue<float, 1>(nullptr, 0.f, 0.f, 0, (uint32_t*)keys_in, (uint32_t)N, npass, nullptr, c, s);
+  fc2t2_status st =
+      sort_prologue<float, 1>(nullptr, 0.f, 0.f, 0, (uint32_t*)keys_in, (uint32_t)N, npass, nullptr, c, s, frequent);
   if (st) return st;
   return onesweep_passes<0>(keys_in, keys_out, vals_out, (uint32_t)N, npass, c, nullptr, 0, nullptr, nullptr, s);
 }

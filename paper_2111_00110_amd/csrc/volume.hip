@@ -305,10 +305,10 @@ VolumeProj volume_proj(int K, const VolumeConsts& vc) {
 }
 
 // Records: the forward's walk again (density pass and scan first), with the colour cotangents
-// folded into c_y.  Lane l of ray i writes its pieces to the slots [(i kRayLanes + l) perlane,
-// ...): key = the cell; rec[(K + 2) slot] = (ta, tb), then (alpha_m of the density without the
-// E term, with Gb counted from the lane's start; alpha_m of sigma T without y_bar_k) for
-// m = 0..K; unused slots get the key G (sorted after every cell).  Ex[i kRayLanes + l]
+// folded into c_y.  Lane l of ray i writes its pieces to its own slots (ray_slot): key = the
+// cell; rec[(K + 2) slot] = (ta, tb), then (alpha_m of the density without the E term, with Gb
+// counted from the lane's start; alpha_m of sigma T without y_bar_k) for m = 0..K; unused
+// slots get the key G (sorted after every cell).  Ex[i kRayLanes + l]
 // receives E - Gb0, with E the ray's total of int c_y sigma mexp'(S) (plus (y_bar . bg)
 // mexp'(D_end) when the ray did not stop) and Gb0 the same integral over the lanes before l, so
 // that the reduction's term s Ex beta_m completes each record of the lane.
@@ -344,7 +344,6 @@ __global__ void __launch_bounds__(64) volume_records_kernel(const T* __restrict_
   const int64_t cs = G * Ppad;
   double Gb = 0.0;
   int j = 0;
-  const int64_t base = gid * perlane;
   if (hit && !(before_max > kStopDepth)) {
     Dda dda;
     dda.init(o, r, a, b, lo, hi, h, n);
@@ -383,7 +382,7 @@ __global__ void __launch_bounds__(64) volume_records_kernel(const T* __restrict_
           as[m] += hS * vp.lam[m][i];
         }
       }
-      const int64_t slot = base + j;
+      const int64_t slot = ray_slot(ray, l, j, perlane);
       keys[slot] = (uint32_t)cell;
       double2* rr = rec + slot * (K + 2);
       rr[0] = make_double2(ta, tb);
@@ -396,7 +395,7 @@ __global__ void __launch_bounds__(64) volume_records_kernel(const T* __restrict_
     }
   }
   if (ray < R)
-    for (; j < perlane; ++j) keys[base + j] = (uint32_t)G;
+    for (; j < perlane; ++j) keys[ray_slot(ray, l, j, perlane)] = (uint32_t)G;
   // the running integral at each lane's start, and the ray's total
   double is = Gb;
 #pragma unroll
@@ -452,7 +451,7 @@ __global__ void __launch_bounds__(256) volume_reduce_kernel(const uint32_t* __re
     decode_cell<3, T>(valid ? cell : 0, n, cc);
     for (uint32_t ri = rb + rl; ri < re; ri += RL) {
       const uint32_t slot = perm[ri];
-      const int64_t lane_id = slot / perlane, ray = lane_id / kRayLanes;
+      const int64_t ray = slot / ((int64_t)perlane * kRayLanes), lane_id = ray * kRayLanes + slot % kRayLanes;
       double o[3], r[3];
       load3(O, ray, o);
       load3(Rd, ray, r);
@@ -569,7 +568,8 @@ fc2t2_status volume_backward_t(const fc2t2_plan_s* pl, const T* L, const T* o, c
   });
   if (st) return st;
   FC2T2_LAUNCH_CHECK();
-  st = radix_sort_pairs(b.keys, b.keys_sorted, b.perm, slots, key_bits_for(pl->G + 1), b.scratch, s);
+  st = radix_sort_pairs(b.keys, b.keys_sorted, b.perm, slots, key_bits_for(pl->G + 1), b.scratch, s,
+                                          (uint32_t)pl->G);
   if (st) return st;
   st = launch_cell_starts(b.keys_sorted, slots, pl->G, b.starts, s, sort_err_word(b.scratch, slots), pl->sort_fail);
   if (st) return st;

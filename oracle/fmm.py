@@ -4,7 +4,7 @@ Follows section 3 of the paper (derivation of eq. (2), the single-level algorith
 multilevel M2M / L2L shifts, the M2L convolution with its parity window and near-field
 hole) and section 4.1 (the explicit layer's vector-Jacobian products), in physical units.
 
-Readings taken where the paper is silent or inconsistent (each is listed in the design doc):
+Readings taken where the paper is silent or inconsistent (each one stated here):
 
 * Sign (section 3 derivation): phi(q, p) = psi(q - p).  With moments
   M[n] = sum w (p - c_p)^n / n! and locals L[k] = d^k f(c_q), the M2L tensor is

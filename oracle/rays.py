@@ -8,7 +8,8 @@
 * Ray insertion, 'line2taylor' (section 6.2.1): the cotangent of the locals of a cell is
   gy * I_k with I_k = int_0^s (d + r u)^k / k! du.  The paper prints this insertion
   without the 1/k!; we keep 1/k! so that it is the segment integral of the same
-  monomials P2M inserts (reading listed in the design doc).
+  monomials P2M inserts (a reading of the paper, taken where its formula and its P2M
+  disagree).
 * Ray root (section 5.1.2): tau = frac * max of f along the clipped ray, then the first
   parameter where f - tau changes sign from - to +, cell by cell in ray order.  A root on
   a cell face belongs to the earlier cell; tangent roots are ignored; a ray with

@@ -20,11 +20,11 @@
 // changes S at every later point.  mono = u^k / k! in cell units u = (q - centre) / h, so the
 // output is the cotangent of the cell-scaled rows.  The stop decision is not differentiated.
 //
-// Records: one per segment (cell as the sort key; [ta, tb] and the segment's weights at K + 1
-// points as payload, see below), sorted by cell and reduced per cell with the ray insertion's
-// segmented reduction.  Every
-// per-segment quantity runs in FP64 (the vector FP64 and FP32 rates are equal without packed
-// FP32); only the expansion rows and the output rows use the IO type.
+// Records: one per piece of the walk (a cell's segment, or its part on one of the lanes that
+// share a ray; cell as the sort key; [ta, tb] and the piece's weights at K + 1 points as payload,
+// see below), sorted by cell and reduced per cell into the four rows.  Every per-piece quantity
+// runs in FP64 (the vector FP64 and FP32 rates are equal without packed FP32); only the
+// expansion rows and the output rows use the IO type.
 #include <math.h>
 
 #include <vector>

@@ -916,8 +916,11 @@ fc2t2_status ray_integral_backward_t(const fc2t2_plan_s* pl, const T* o, const T
     if constexpr (S::D == 3) {
       SegmentInsert<S, T> fn{o, r, b.rec, gy, maxseg, pl->C, 1.0 / pl->h0};
       // records per occupied cell are few (a ray crosses a cell once): the number of real
-      // segments is about 2.3 n per ray
-      st = launch_reduce_cells<S, T>(pl, b.starts, b.perm, R * 2 * pl->n, gL, true, fn, s);
+      // segments is about 2.3 n per ray; below 12 per cell on average, two lanes per cell (a
+      // shorter butterfly) are faster than four
+      const int64_t recs = R * 2 * pl->n;
+      st = recs < 12 * pl->G ? launch_reduce_cells_g<S, T, 2, false>(pl, b.starts, b.perm, gL, true, fn, s, nullptr, 0)
+                             : launch_reduce_cells<S, T>(pl, b.starts, b.perm, recs, gL, true, fn, s);
     }
   });
   return st;

@@ -158,10 +158,13 @@ __device__ __forceinline__ void depth_scan(double s, double m, int l, double& ex
   }
 }
 
-// The density pass of one lane over [a, b] (see above).
+// The density pass of one lane over [a, b] (see above).  With `cache`, piece j's density
+// polynomial is also left in the first three double2 of its record slot (ray_slot(ray, l, j)),
+// where the records pass reads it back instead of evaluating the density row again.
 template <class S, typename T>
 __device__ void density_pass(const T* __restrict__ L, const double (&o)[3], const double (&r)[3], double a, double b,
-                             bool last_lane, double lo, double hi, double h, int n, double& dsum, double& dmax) {
+                             bool last_lane, double lo, double hi, double h, int n, double& dsum, double& dmax,
+                             double2* __restrict__ cache = nullptr, int64_t ray = 0, int l = 0, int perlane = 0) {
   constexpr int K = S::K, Ppad = S::Ppad;
   Dda dda;
   dda.init(o, r, a, b, lo, hi, h, n);
@@ -170,12 +173,20 @@ __device__ void density_pass(const T* __restrict__ L, const double (&o)[3], cons
   int64_t cell;
   int cc[3];
   double ta, tb;
+  int j = 0;
   while (dda.next(cell, cc, ta, tb)) {
     const double sl = tb - ta;
     double d[3], q[3];
     seg_local(o, r, ta, cc, lo, h, d, q);
     double bs[6];
     segment_poly<S>(L + cell * Ppad, d, q, sl, bs);
+    if (cache && j < perlane) {
+      double2* cb = cache + ray_slot(ray, l, j, perlane) * (K + 2);
+      cb[0] = make_double2(bs[0], bs[1]);
+      cb[1] = make_double2(bs[2], bs[3]);
+      cb[2] = make_double2(bs[4], bs[5]);
+    }
+    ++j;
     double sx[K + 2];
     depth_poly<K>(bs, dsum, sl, sx);
     dsum = poly_at<K + 2>(sx, 1.0);
@@ -338,7 +349,7 @@ __global__ void __launch_bounds__(64) volume_records_kernel(const T* __restrict_
   }
   const double a = lane_cut(ta_r, tb_r, l), b = lane_cut(ta_r, tb_r, l + 1);
   double dsum = 0.0, dmax = -INFINITY;
-  if (hit) density_pass<S>(L, o, r, a, b, last_lane, lo, hi, h, n, dsum, dmax);
+  if (hit) density_pass<S>(L, o, r, a, b, last_lane, lo, hi, h, n, dsum, dmax, rec, ray, l, perlane);
   double D, before_max, D_end, max_exit;
   depth_scan(dsum, dmax, l, D, before_max, D_end, max_exit);
   const int64_t cs = G * Ppad;
@@ -354,9 +365,14 @@ __global__ void __launch_bounds__(64) volume_records_kernel(const T* __restrict_
       const double sl = tb - ta;
       double d[3], q[3];
       seg_local(o, r, ta, cc, lo, h, d, q);
+      const int64_t slot = ray_slot(ray, l, j, perlane);
+      double2* rr = rec + slot * (K + 2);
       const T* row = L + cell * Ppad;
       double bs[6], b0[6], b1[6], b2[6];
-      segment_poly<S>(row, d, q, sl, bs);
+      {
+        const double2 c0 = rr[0], c1 = rr[1], c2 = rr[2];   // the density pass's polynomial
+        bs[0] = c0.x; bs[1] = c0.y; bs[2] = c1.x; bs[3] = c1.y; bs[4] = c2.x; bs[5] = c2.y;
+      }
       segment_poly<S>(row + cs, d, q, sl, b0);
       segment_poly<S>(row + 2 * cs, d, q, sl, b1);
       segment_poly<S>(row + 3 * cs, d, q, sl, b2);
@@ -382,9 +398,7 @@ __global__ void __launch_bounds__(64) volume_records_kernel(const T* __restrict_
           as[m] += hS * vp.lam[m][i];
         }
       }
-      const int64_t slot = ray_slot(ray, l, j, perlane);
       keys[slot] = (uint32_t)cell;
-      double2* rr = rec + slot * (K + 2);
       rr[0] = make_double2(ta, tb);
 #pragma unroll
       for (int m = 0; m <= K; ++m) rr[1 + m] = make_double2(ad[m] - sl * Gb * vp.beta[m], as[m]);
